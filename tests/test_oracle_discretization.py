@@ -1,0 +1,170 @@
+"""Pins of the oracle's discretisation: ghost formulas, the regular stencil,
+exactness of every row on the quartics, PLG lattice structure and merging
+postconditions (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import discretize as D
+from oracle.fields import Field
+from oracle.geometry import CUT, EXTERIOR
+from oracle.merging import THETA
+from paper_2410_05865_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "ghost_formulas.txt")
+
+
+def _avg_monomial(k, a, b):
+    """exact mean of t^k over [a, b]"""
+    return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+
+
+def _ghost_rows():
+    rows = []
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        bc, g = t[0], int(t[1])
+        c = [float(v) for v in t[2:7]]
+        den = float(t[7])
+        tag = t[8] if len(t) > 8 else ""
+        rows.append((bc, g, c, den, tag))
+    return rows
+
+
+@pytest.mark.parametrize("row", _ghost_rows(), ids=lambda r: f"{r[0]}{r[1]}{r[4]}")
+def test_ghost_formulas_exact_on_quartics(row):
+    """Cells of width 1: interior i-3..i = [-4,-3]..[-1,0], wall face at 0,
+    ghost 1 = [0,1], ghost 2 = [1,2]; exact averages of t^k, k <= 4."""
+    bc, g, c, den, tag = row
+    ok = True
+    for k in range(5):
+        cells = [_avg_monomial(k, a, a + 1) for a in (-4, -3, -2, -1)]
+        # face datum at t = 0: <phi> (Dirichlet) or h dphi/dn with n = +e (Neumann), h = 1
+        face = 0.0 ** k if bc == "dirichlet" else (float(k == 1))
+        ghost = _avg_monomial(k, g - 1, g)
+        val = (np.dot(c[:4], cells) + c[4] * face) / den
+        ok &= abs(val - ghost) < 1e-12
+    if tag == "printed":
+        assert not ok, "the printed coefficient should fail to reproduce constants"
+    else:
+        assert ok
+
+
+def test_regular_stencil_exact_to_degree_five():
+    for k in range(7):
+        cells = [_avg_monomial(k, a - 0.5, a + 0.5) for a in (-2, -1, 0, 1, 2)]
+        val = np.dot(np.array([-1, 16, -30, 16, -1]) / 12.0, cells)
+        exact = (_avg_monomial(k - 2, -0.5, 0.5) * k * (k - 1)) if k >= 2 else 0.0
+        if k <= 5:
+            assert val == pytest.approx(exact, abs=1e-13)
+        else:
+            assert abs(val - exact) > 1e-3
+
+
+def _quartic():
+    return Field(inputs.poly_field([(4, 0, 0, 1.0), (0, 2, 2, -2.0), (1, 1, 1, 1.0), (0, 0, 0, 1.0),
+                                    (0, 3, 0, 0.5), (1, 0, 3, -0.7), (2, 2, 0, 0.3), (0, 0, 1, 2.0)]))
+
+
+@pytest.fixture(scope="module")
+def sphere16():
+    dom, _ = inputs.sphere_workload(16)
+    return D.Level(dom, 16)
+
+
+@pytest.fixture(scope="module")
+def ellipsoid32_mixed():
+    dom = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    dom.wall_bc = (0, 1, 0, 0, 1, 0)      # two Neumann walls
+    return D.Level(dom, 32)
+
+
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+def test_every_row_exact_on_quartics(which, request):
+    lv = request.getfixturevalue(which)
+    P = _quartic()
+    r = lv.rhs(P.laplacian_desc(), P)
+    ex = lv.region_average(P)
+    res = lv.L @ ex - r
+    scale = np.max(np.abs(r)) + np.max(np.abs(lv.L).sum(axis=1)) * np.max(np.abs(ex))
+    assert np.max(np.abs(res)) < 1e-13 * scale
+
+
+def test_rows_not_exact_beyond_degree_four(sphere16):
+    lv = sphere16
+    P = Field({"kind": "poly", "terms": [(3, 2, 0, 1.0), (0, 0, 0, 0.0)]})
+    # degree 5 terms: skip the builder's degree check by constructing directly
+    r = lv.rhs(P.laplacian_desc(), P)
+    ex = lv.region_average(P)
+    res = lv.L @ ex - r
+    m1 = lv.phi1_mask()
+    assert np.max(np.abs(res[m1])) < 1e-9          # regular rows: exact to degree 5
+    assert np.max(np.abs(res[~m1])) > 1e-6         # PLG rows: degree 4 only
+
+
+def _is_triangular_lattice(coords, q):
+    """coords: 35 (i,j,k) cells.  Checks for per-axis numberings p_d making
+    the set {(p_0[k0], p_1[k1], p_2[k2]) : k0+k1+k2 <= 4} (Sec. 4.1)."""
+    S = set(map(tuple, coords))
+    if len(S) != 35 or tuple(q) not in S:
+        return False
+    # the numbering is recovered from multiplicities: along axis d the value
+    # with k_d = t appears C(6 - t, 2) times
+    need = {15: 0, 10: 1, 6: 2, 3: 3, 1: 4}
+    p = []
+    for d in range(3):
+        vals, cnt = np.unique(np.array(coords)[:, d], return_counts=True)
+        if sorted(cnt.tolist()) != [1, 3, 6, 10, 15]:
+            return False
+        order = [None] * 5
+        for v, c in zip(vals, cnt):
+            order[need[int(c)]] = int(v)
+        p.append(order)
+    T = {(p[0][a], p[1][b], p[2][c]) for a in range(5) for b in range(5) for c in range(5)
+         if a + b + c <= 4}
+    return T == S
+
+
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+def test_plg_lattices_are_poised_triangular_lattices(which, request):
+    lv = request.getfixturevalue(which)
+    for r, (cells, coefs) in list(lv.plg.items())[::7]:
+        p = int(lv.unknowns[r])
+        lat = cells[:35]
+        coords = [lv.ijk(c) for c in lat]
+        assert _is_triangular_lattice([tuple(int(v) for v in t) for t in coords],
+                                      tuple(int(v) for v in lv.ijk(p)))
+        assert all(lv.host[c] == c for c in lat)              # every site carries an unknown
+        A = np.array([lv._target_frame_cell_avg(p, lv.groups[c]) for c in lat])
+        assert np.linalg.cond(A) < 1e9                         # poised
+
+
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+def test_merging_postconditions(which, request):
+    lv = request.getfixturevalue(which)
+    geo = lv.geo
+    h3 = geo.h ** 3
+    total = 0.0
+    for host, mem in lv.groups.items():
+        vol = sum(geo.vol[m] for m in mem)
+        total += vol
+        assert vol >= THETA * h3 * (1 - 1e-12)                # every merged cell is theta-proper
+        assert geo.cls[host] != EXTERIOR
+    assert total == pytest.approx(float(np.sum(geo.vol)), rel=1e-14)   # volume conserved
+    small = [p for p in geo.cut if geo.vol[p] < THETA * h3]
+    assert all(lv.host[p] != p or len(lv.groups[p]) > 1 for p in small)
+
+
+def test_phi1_rule(sphere16):
+    lv = sphere16
+    n = lv.n
+    for p in lv.unknowns[::13]:
+        p = int(p)
+        if not lv.is_phi1[p]:
+            continue
+        cols, walls = lv.regular_row(p)
+        assert 10 <= len(cols) <= 19         # 13-point star; fewer distinct cells at walls
+        assert all(lv.plain[c] for c in cols)

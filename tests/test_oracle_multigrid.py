@@ -1,0 +1,122 @@
+"""Pins of the oracle's multigrid: the LU-correction postcondition, transfer
+invariants, agreement with direct solves, polynomial reproduction and
+fourth-order convergence (CPU only)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle.fields import Field
+from oracle.multigrid import Hierarchy, MGParams
+from paper_2410_05865_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def sphere32():
+    dom, phi = inputs.sphere_workload(32)
+    return Hierarchy(dom), Field(phi)
+
+
+@pytest.fixture(scope="module")
+def sphere16_two_level():
+    dom, phi = inputs.sphere_workload(16)
+    dom.n_min = 8
+    return Hierarchy(dom), Field(phi)
+
+
+def test_lu_correction_zeroes_phi2_residual(sphere32):
+    """After SMO-2 the phi_2 rows hold exactly (Sec. 5.3, the residual identity)."""
+    H, F = sphere32
+    op = H.ops[0]
+    rng = np.random.default_rng(0)
+    s = rng.standard_normal(op.L.shape[0])
+    e = op.smo1(rng.standard_normal(op.L.shape[0]), s, 0.8)
+    e = op.smo2(e, s)
+    res = s - op.L @ e
+    assert np.max(np.abs(res[op.i2])) < 1e-10 * np.max(np.abs(s))
+    assert np.max(np.abs(res[op.i1])) > 1e-3
+
+
+def test_smo1_is_weighted_jacobi_on_phi1(sphere32):
+    H, F = sphere32
+    op = H.ops[0]
+    rng = np.random.default_rng(1)
+    s = rng.standard_normal(op.L.shape[0])
+    e = rng.standard_normal(op.L.shape[0])
+    out = op.smo1(e, s, 0.5)
+    # phi_2 untouched, and a phi_1 entry moves by omega * residual / diagonal
+    assert np.array_equal(out[op.i2], e[op.i2])
+    i = op.i1[len(op.i1) // 2]
+    row = op.L[i].toarray().ravel()
+    assert out[i] == pytest.approx(e[i] + 0.5 * (s[i] - row @ e) / row[i], rel=1e-13)
+
+
+def test_transfers_preserve_constants(sphere32):
+    H, F = sphere32
+    fl, cl = H.levels[0], H.levels[1]
+    ones = np.ones(fl.N)
+    c = H.restrict(0, ones)
+    # coarse cells whose 8 children are all phi_1 receive exactly the constant
+    nf, nc = fl.n, cl.n
+    g = np.zeros(nf ** 3)
+    g[fl.unknowns[fl.phi1_mask()]] = 1.0
+    full = (g.reshape(nc, 2, nc, 2, nc, 2).sum(axis=(1, 3, 5)).reshape(-1) == 8)[cl.unknowns]
+    assert np.all(c[full] == 1.0)
+    assert np.all(c[~full] < 1.0)
+    e = H.prolong_add(0, np.zeros(fl.N), np.full(cl.N, 2.5))
+    assert np.all(e[fl.phi1_mask()] == 2.5) and np.all(e[~fl.phi1_mask()] == 0.0)
+
+
+def test_multigrid_matches_sparse_direct_solve(sphere32):
+    H, F = sphere32
+    lv = H.fine
+    r = lv.rhs(F.laplacian_desc(), F)
+    x, hist = H.solve(r, MGParams(tol=1e-13))
+    xd = spla.splu(lv.L.tocsc()).solve(r)
+    assert hist[-1] < 1e-13
+    assert np.max(np.abs(x - xd)) < 1e-10 * np.max(np.abs(xd))
+
+
+def test_multigrid_matches_dense_direct_solve(sphere16_two_level):
+    """Brute force on a tiny grid: numpy dense LU of the assembled operator."""
+    H, F = sphere16_two_level
+    lv = H.fine
+    r = lv.rhs(F.laplacian_desc(), F)
+    x, hist = H.solve(r, MGParams(tol=1e-13))
+    xd = np.linalg.solve(lv.L.toarray(), r)
+    assert np.max(np.abs(x - xd)) < 1e-10 * np.max(np.abs(xd))
+
+
+def test_vcycle_reduction_factor(sphere32):
+    H, F = sphere32
+    lv = H.fine
+    r = lv.rhs(F.laplacian_desc(), F)
+    x, hist = H.solve(r, MGParams(tol=1e-10))
+    rates = [hist[i + 1] / hist[i] for i in range(2, len(hist) - 1)]
+    assert len(hist) < 25
+    assert max(rates) < 0.4
+
+
+def test_polynomial_reproduction():
+    """Every row is exact on quartics, so their exact cell averages are the
+    discrete solution."""
+    dom = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    dom.n_min = 16
+    H = Hierarchy(dom)
+    P = Field(inputs.poly_field([(4, 0, 0, 1.0), (0, 2, 2, -2.0), (1, 1, 1, 1.0), (0, 0, 0, 1.0),
+                                 (2, 0, 1, 0.4)]))
+    lv = H.fine
+    r = lv.rhs(P.laplacian_desc(), P)
+    x, hist = H.solve(r, MGParams(tol=1e-13))
+    ex = lv.region_average(P)
+    assert np.max(np.abs(x - ex)) < 1e-10 * np.max(np.abs(ex))
+
+
+def test_fourth_order_convergence(sphere32, sphere16_two_level):
+    errs = []
+    for H, F in (sphere16_two_level, sphere32):
+        lv = H.fine
+        r = lv.rhs(F.laplacian_desc(), F)
+        x, _ = H.solve(r, MGParams(tol=1e-12))
+        errs.append(np.max(np.abs(x - lv.region_average(F))))
+    ratio = errs[0] / errs[1]
+    assert ratio > 11.0, errs      # fourth order: 16 asymptotically
