@@ -1,0 +1,191 @@
+/*
+ * cutcell.h -- C ABI of the MI355X fourth-order cut-cell multigrid Poisson solver.
+ *
+ * Problem (paper Sec. 1 and Sec. 2.3): Delta phi = f in Omega, N phi = g on the
+ * boundary, with Omega = R \ (union of ellipsoids), R = x_O + [0, n h]^3 and N the
+ * Dirichlet (identity) or Neumann (outward normal derivative) operator.  The
+ * unknowns are cell averages over the cut cells C_i ∩ Omega of the Cartesian grid
+ * (Sec. 2.2); the discrete system is L phi = r := f - N g (Sec. 2.4), solved by
+ * the modified multigrid of Sec. 5.3 (weighted Jacobi on regular cells, exact
+ * LU-correction on FV-PLG cells, piecewise-constant transfers, LU bottom solve).
+ *
+ * Conventions
+ *   - Cell arrays have n^3 entries (n of the level), linear index i + n (j + n k),
+ *     x fastest, FP64.  On output exterior cells hold 0 and cells merged into a
+ *     host cell hold 0 on coarse levels; on level 0 the solution of a merged cell
+ *     is the host's value (cc_solve fills it).
+ *   - Device pointers are caller-owned; the library never frees them.  Work runs
+ *     on the stream given to cc_build (NULL: a library-created stream); calls that
+ *     return host data synchronise that stream, others are asynchronous.
+ *   - Every function returns CC_OK (0) or a negative status; cc_last_error() gives
+ *     a thread-local message.  Inputs are validated on the host before any launch.
+ *   - The problem handle owns geometry, per-level rows, factorizations and
+ *     workspaces; it is not thread-safe (one caller at a time).
+ */
+#ifndef CUTCELL_H
+#define CUTCELL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,     /* bad argument */
+  CC_ENOMEM = -2,     /* host or device allocation failed */
+  CC_EDEVICE = -3,    /* HIP error, or no device (host-only handle) */
+  CC_EGEOM = -4,      /* geometry outside the supported class (see cc_build) */
+  CC_EPLG = -5,       /* no poised lattice for some cell */
+  CC_ESINGULAR = -6,  /* a pivot below the threshold in a factorization */
+  CC_ENOCONV = -7     /* max_iter V-cycles without reaching tol */
+};
+
+enum { CC_DIRICHLET = 0, CC_NEUMANN = 1 };
+enum { CC_FP64 = 0, CC_MIXED = 1 };
+
+/* An ellipsoid { x : (x-c)^T R diag(axes^-2) R^T (x-c) <= 1 } removed from the box.
+ * rot is row-major 3x3; its column j is the direction of semi-axis j. */
+typedef struct cc_obstacle {
+  double center[3];
+  double axes[3];
+  double rot[9];
+  int bc;             /* CC_DIRICHLET or CC_NEUMANN on this obstacle's surface */
+} cc_obstacle;
+
+/* Grid and domain (Sec. 2.2).  Walls ordered -x,+x,-y,+y,-z,+z. */
+typedef struct cc_domain {
+  int n;              /* cells per axis on the finest level */
+  double origin[3];   /* x_O */
+  double h;           /* cell size; must equal 1/n */
+  int wall_bc[6];
+  int n_obst;
+  const cc_obstacle* obst;
+} cc_domain;
+
+/* Method parameters (Sec. 4.2 theta; Sec. 5.3 omega, nu1, nu2, eps, I_max). */
+typedef struct cc_params {
+  double theta;       /* merging threshold, default 0.1 */
+  double omega;       /* Jacobi weight, default 0.8 */
+  int nu1, nu2;       /* smoothing steps, default 3, 3 */
+  int n_min;          /* coarsen while n/2 >= n_min, default 16 */
+  int max_iter;       /* I_max, default 200 */
+  double tol;         /* eps on max-norm relative residual, default 1e-10 */
+  int precision;      /* CC_FP64 or CC_MIXED */
+  int leaf_size;      /* nested-dissection leaf size, default 64 */
+  int device;         /* HIP device ordinal; -1 builds a host-only handle */
+  int use_graph;      /* capture the V-cycle in a hipGraph (default 1) */
+} cc_params;
+
+/* Analytic fields (problem data).  data layout by kind:
+ *   CC_FIELD_POLY    n_terms x (a0, a1, a2, coef): sum coef x^a0 y^a1 z^a2, degree <= 4
+ *   CC_FIELD_SINPROD (amp, k0, k1, k2, p0, p1, p2): amp prod_d sin(k_d x_d + p_d)
+ *   CC_FIELD_EXPCOS  (amp, a, b, c, p): amp exp(a x + b y) cos(c z + p)
+ *   CC_FIELD_GAUSS   n_terms x (amp, mu0, mu1, mu2, sigma)
+ * The library copies what it needs; data may be freed after the call. */
+enum { CC_FIELD_ZERO = 0, CC_FIELD_POLY = 1, CC_FIELD_SINPROD = 2, CC_FIELD_EXPCOS = 3,
+       CC_FIELD_GAUSS = 4 };
+enum { CC_VALUE = 0, CC_LAPLACIAN = 1 };
+typedef struct cc_field {
+  int kind;
+  int n_terms;
+  const double* data;
+} cc_field;
+
+typedef struct cc_problem cc_problem;
+
+#define CC_HISTORY_MAX 256
+typedef struct cc_solve_info {
+  int iterations;                       /* V-cycles applied */
+  double rel_residual;                  /* final max|r - L phi| / max|r| */
+  int history_len;
+  double history[CC_HISTORY_MAX];       /* relative residual before each V-cycle */
+  double seconds;                       /* wall time of the call */
+} cc_solve_info;
+
+typedef struct cc_level_info {
+  int n;
+  long long n_unknowns;   /* cells carrying an unknown (hosts included) */
+  long long n_phi2;       /* FV-PLG rows (N_2) */
+  long long n_cut;        /* cut cells */
+  long long n_merged;     /* cells absorbed into a host */
+  long long lu_vars;      /* variables of the level's factorization */
+  long long lu_entries;   /* FP64 entries of the stored supernodal factors */
+  int lu_nodes;           /* supernodes */
+  int lu_depth;           /* levels of the supernode tree */
+  double setup_seconds;
+} cc_level_info;
+
+/* Fill p with the defaults listed above. */
+void cc_default_params(cc_params* p);
+
+/* Build geometry, merging, rows and factorizations of every level (Secs. 2-5):
+ * classification and moments (exact ellipsoids), cell merging, the phi_1/phi_2
+ * split, FV-PLG stencils and least-squares rows, nested dissection and the LU of
+ * L22 on levels m < M and of L on level M, then the device upload.
+ * Supported geometry: every obstacle's bounding sphere keeps the wall layer free
+ * and meets no cell that another obstacle's bounding sphere meets, on every
+ * level (else CC_EGEOM).  stream: hipStream_t or NULL.  *out owned by the caller
+ * until cc_destroy. */
+int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out);
+
+int cc_num_levels(const cc_problem* p);
+int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info);
+
+/* r = f - N g on level 0 (Sec. 2.4): cell averages of f (f_mode CC_VALUE) or of
+ * Delta f (CC_LAPLACIAN) over each unknown's cell, minus the wall-ghost and FV-PLG
+ * boundary-site terms of the data g (Dirichlet: the value of g; Neumann: the
+ * outward normal derivative of g).  r_dev: device, n^3. */
+int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g,
+                    double* r_dev);
+
+/* Multigrid (Sec. 5.3): phi <- phi + VCycle(r - L phi) until the max-norm relative
+ * residual < tol or max_iter.  phi_dev is the initial guess on entry and the
+ * solution on exit (merged cells hold their host's value).  info may be NULL.
+ * Returns CC_ENOCONV (with phi holding the last iterate) if tol is not reached. */
+int cc_solve(cc_problem* p, const double* r_dev, double* phi_dev, cc_solve_info* info);
+
+/* Parity hooks, one per step of the V-cycle, on level `level` arrays (n_m^3):
+ *   cc_apply:      y = L x on unknown cells, 0 elsewhere (Sec. 2.4)
+ *   cc_residual:   s = r - L x on unknown cells; *maxabs = max |s| (host)
+ *   cc_smo1:       one SMO-1 sweep on phi_1 cells: e <- e + omega D^-1 (s - L e)
+ *   cc_smo2:       one SMO-2 LU-correction: e_2 <- L22^-1 (s_2 - L21 e_1)
+ *   cc_restrict:   s_c = 2^-3 sum over children of (s - L e) on phi_1 children
+ *   cc_prolong_add: e_f += e_c(parent) on phi_1 cells of level `level`
+ *   cc_bottom_solve: e = L^(M)^-1 s on the coarsest level
+ *   cc_vcycle:     e = VCycle(s) from level `level` down (e is overwritten) */
+int cc_apply(cc_problem* p, int level, const double* x_dev, double* y_dev);
+int cc_residual(cc_problem* p, int level, const double* r_dev, const double* x_dev,
+                double* s_dev, double* maxabs);
+int cc_smo1(cc_problem* p, int level, const double* s_dev, double* e_dev);
+int cc_smo2(cc_problem* p, int level, const double* s_dev, double* e_dev);
+int cc_restrict(cc_problem* p, int level, const double* s_dev, const double* e_dev,
+                double* sc_dev);
+int cc_prolong_add(cc_problem* p, int level, const double* ec_dev, double* ef_dev);
+int cc_bottom_solve(cc_problem* p, const double* s_dev, double* e_dev);
+int cc_vcycle(cc_problem* p, int level, const double* s_dev, double* e_dev);
+
+/* Host copies of a level's integer decisions and rows (Sec. 2.2-2.4), for
+ * exact comparison.  Any pointer may be NULL.
+ *   type[n^3]: 0 no unknown, 1 phi_1, 2 phi_2;  host[n^3]: -1 exterior, else the
+ *   cell whose unknown covers this cell;  volfrac[n^3]: |C_i ∩ Omega| / h^3.
+ *   PLG rows: row_cell[N2], cols[N2*35] (cell indices), vals[N2*35]. */
+int cc_export_cells(const cc_problem* p, int level, unsigned char* type, int* host,
+                    double* volfrac);
+int cc_export_plg(const cc_problem* p, int level, int* row_cell, int* cols, double* vals);
+
+/* Host check of a level's factorization (L22 on levels m < M, L on the
+ * coarsest level): solves with the stored supernodal factors for a random
+ * right-hand side and returns max|A x - b| / max|b|.  Diagnostic only. */
+int cc_selfcheck_lu(const cc_problem* p, int level, double* rel_residual);
+
+/* Timing hook: average device time in ms of `reps` back-to-back launches of the
+ * level-0 SMO-1 kernel (HIP events on the problem's stream). */
+int cc_time_smoother(cc_problem* p, int reps, double* ms_per_launch);
+
+void cc_destroy(cc_problem* p);
+const char* cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUTCELL_H */

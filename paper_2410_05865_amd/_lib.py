@@ -1,0 +1,287 @@
+"""ctypes binding of libcutcell.so (include/cutcell.h): argument marshalling only.
+
+Device arrays are torch tensors (float64, contiguous, on the GPU); every step of
+the solve runs in the library's HIP kernels.  There is no fallback: if the
+shared library is missing, `load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcutcell.so")
+
+CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_EGEOM, CC_EPLG, CC_ESINGULAR, CC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
+CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4}
+CC_VALUE, CC_LAPLACIAN = 0, 1
+HISTORY_MAX = 256
+
+EXPORTED = [
+    "cc_default_params", "cc_build", "cc_num_levels", "cc_get_level_info", "cc_assemble_rhs", "cc_solve",
+    "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
+    "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_time_smoother", "cc_destroy",
+    "cc_last_error",
+]
+
+
+class CcObstacle(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("axes", C.c_double * 3), ("rot", C.c_double * 9), ("bc", C.c_int)]
+
+
+class CcDomain(C.Structure):
+    _fields_ = [("n", C.c_int), ("origin", C.c_double * 3), ("h", C.c_double), ("wall_bc", C.c_int * 6),
+                ("n_obst", C.c_int), ("obst", C.POINTER(CcObstacle))]
+
+
+class CcParams(C.Structure):
+    _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("n_min", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
+                ("leaf_size", C.c_int), ("device", C.c_int), ("use_graph", C.c_int)]
+
+
+class CcField(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n_terms", C.c_int), ("data", C.POINTER(C.c_double))]
+
+
+class CcSolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("rel_residual", C.c_double), ("history_len", C.c_int),
+                ("history", C.c_double * HISTORY_MAX), ("seconds", C.c_double)]
+
+
+class CcLevelInfo(C.Structure):
+    _fields_ = [("n", C.c_int), ("n_unknowns", C.c_longlong), ("n_phi2", C.c_longlong), ("n_cut", C.c_longlong),
+                ("n_merged", C.c_longlong), ("lu_vars", C.c_longlong), ("lu_entries", C.c_longlong),
+                ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double)]
+
+
+class CutCellError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cutcell error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def load() -> C.CDLL:
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_05865_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    P = C.POINTER
+    lib.cc_default_params.argtypes = [P(CcParams)]
+    lib.cc_default_params.restype = None
+    lib.cc_build.argtypes = [P(CcDomain), P(CcParams), vp, P(vp)]
+    lib.cc_num_levels.argtypes = [vp]
+    lib.cc_get_level_info.argtypes = [vp, C.c_int, P(CcLevelInfo)]
+    lib.cc_assemble_rhs.argtypes = [vp, P(CcField), C.c_int, P(CcField), vp]
+    lib.cc_solve.argtypes = [vp, vp, vp, P(CcSolveInfo)]
+    lib.cc_apply.argtypes = [vp, C.c_int, vp, vp]
+    lib.cc_residual.argtypes = [vp, C.c_int, vp, vp, vp, P(C.c_double)]
+    for name in ("cc_smo1", "cc_smo2", "cc_prolong_add", "cc_vcycle"):
+        getattr(lib, name).argtypes = [vp, C.c_int, vp, vp]
+    lib.cc_restrict.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.cc_bottom_solve.argtypes = [vp, vp, vp]
+    lib.cc_export_cells.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.cc_export_plg.argtypes = [vp, C.c_int, vp, vp, vp]
+    lib.cc_selfcheck_lu.argtypes = [vp, C.c_int, P(C.c_double)]
+    lib.cc_time_smoother.argtypes = [vp, C.c_int, P(C.c_double)]
+    lib.cc_destroy.argtypes = [vp]
+    lib.cc_destroy.restype = None
+    lib.cc_last_error.restype = C.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != CC_OK:
+        raise CutCellError(rc, load().cc_last_error().decode())
+
+
+def default_params() -> CcParams:
+    p = CcParams()
+    load().cc_default_params(C.byref(p))
+    return p
+
+
+def _field(desc: Optional[dict]):
+    """cc_field from an inputs.* field descriptor; returns (struct, keep-alive)."""
+    if desc is None:
+        desc = inputs.zero_field()
+    k = desc["kind"]
+    if k == "zero":
+        data = np.zeros(1)
+        nt = 0
+    elif k == "poly":
+        data = np.array(desc["terms"], dtype=np.float64).reshape(-1)
+        nt = len(desc["terms"])
+    elif k == "sinprod":
+        data = np.array([desc["amp"], *desc["k"], *desc["p"]], dtype=np.float64)
+        nt = 1
+    elif k == "expcos":
+        data = np.array([desc["amp"], desc["a"], desc["b"], desc["c"], desc["p"]], dtype=np.float64)
+        nt = 1
+    elif k == "gauss":
+        data = np.array([[a, *m, s] for a, m, s in zip(desc["amp"], desc["mu"], desc["sigma"])],
+                        dtype=np.float64).reshape(-1)
+        nt = len(desc["amp"])
+    else:
+        raise ValueError(k)
+    data = np.ascontiguousarray(data)
+    f = CcField(CC_FIELD[k], nt, data.ctypes.data_as(C.POINTER(C.c_double)))
+    return f, data
+
+
+def _ptr(t, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A built cut-cell problem (geometry, rows, factorizations, device data)."""
+
+    def __init__(self, domain: inputs.Domain, params: Optional[CcParams] = None, stream=None,
+                 device: int = 0, **overrides):
+        lib = load()
+        prm = params if params is not None else default_params()
+        prm.n_min = domain.n_min
+        prm.device = device
+        for k, v in overrides.items():
+            setattr(prm, k, v)
+        obs = (CcObstacle * max(1, len(domain.obstacles)))()
+        for t, o in enumerate(domain.obstacles):
+            obs[t].center[:] = [float(v) for v in o.center]
+            obs[t].axes[:] = [float(v) for v in o.axes]
+            obs[t].rot[:] = [float(v) for v in np.asarray(o.rot).reshape(-1)]
+            obs[t].bc = int(o.bc)
+        dom = CcDomain()
+        dom.n = domain.n
+        dom.origin[:] = [float(v) for v in domain.origin]
+        dom.h = 1.0 / domain.n
+        dom.wall_bc[:] = [int(v) for v in domain.wall_bc]
+        dom.n_obst = len(domain.obstacles)
+        dom.obst = obs
+        h = C.c_void_p()
+        st = C.c_void_p(stream) if stream is not None else None
+        _check(lib.cc_build(C.byref(dom), C.byref(prm), st, C.byref(h)))
+        self._h = h
+        self.params = prm
+        self.domain = domain
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- info
+    @property
+    def num_levels(self) -> int:
+        return load().cc_num_levels(self._h)
+
+    def level_info(self, level: int) -> dict:
+        info = CcLevelInfo()
+        _check(load().cc_get_level_info(self._h, level, C.byref(info)))
+        return {f: getattr(info, f) for f, _ in CcLevelInfo._fields_}
+
+    def n(self, level: int = 0) -> int:
+        return self.level_info(level)["n"]
+
+    def export_cells(self, level: int = 0):
+        n = self.n(level)
+        typ = np.zeros(n ** 3, dtype=np.uint8)
+        host = np.zeros(n ** 3, dtype=np.int32)
+        vf = np.zeros(n ** 3, dtype=np.float64)
+        _check(load().cc_export_cells(self._h, level, typ.ctypes.data_as(C.c_void_p),
+                                      host.ctypes.data_as(C.c_void_p), vf.ctypes.data_as(C.c_void_p)))
+        return typ, host, vf
+
+    def export_plg(self, level: int = 0):
+        N2 = self.level_info(level)["n_phi2"]
+        cell = np.zeros(N2, dtype=np.int32)
+        cols = np.zeros(N2 * 35, dtype=np.int32)
+        vals = np.zeros(N2 * 35, dtype=np.float64)
+        _check(load().cc_export_plg(self._h, level, cell.ctypes.data_as(C.c_void_p),
+                                    cols.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p)))
+        return cell, cols.reshape(N2, 35), vals.reshape(N2, 35)
+
+    def selfcheck_lu(self, level: int) -> float:
+        v = C.c_double()
+        _check(load().cc_selfcheck_lu(self._h, level, C.byref(v)))
+        return v.value
+
+    # -------------------------------------------------------------- device
+    def assemble_rhs(self, f: dict, g: Optional[dict], r, f_mode: int = CC_VALUE):
+        fs, fk = _field(f)
+        gs, gk = _field(g)
+        _check(load().cc_assemble_rhs(self._h, C.byref(fs), f_mode, C.byref(gs), _ptr(r, self.n() ** 3)))
+
+    def solve(self, r, phi) -> dict:
+        n3 = self.n() ** 3
+        info = CcSolveInfo()
+        rc = load().cc_solve(self._h, _ptr(r, n3), _ptr(phi, n3), C.byref(info))
+        out = {"iterations": info.iterations, "rel_residual": info.rel_residual,
+               "history": list(info.history[:info.history_len]), "seconds": info.seconds,
+               "converged": rc == CC_OK}
+        if rc not in (CC_OK, CC_ENOCONV):
+            _check(rc)
+        return out
+
+    def apply(self, level, x, y):
+        n3 = self.n(level) ** 3
+        _check(load().cc_apply(self._h, level, _ptr(x, n3), _ptr(y, n3)))
+
+    def residual(self, level, r, x, s) -> float:
+        n3 = self.n(level) ** 3
+        m = C.c_double()
+        _check(load().cc_residual(self._h, level, _ptr(r, n3), _ptr(x, n3), _ptr(s, n3), C.byref(m)))
+        return m.value
+
+    def smo1(self, level, s, e):
+        n3 = self.n(level) ** 3
+        _check(load().cc_smo1(self._h, level, _ptr(s, n3), _ptr(e, n3)))
+
+    def smo2(self, level, s, e):
+        n3 = self.n(level) ** 3
+        _check(load().cc_smo2(self._h, level, _ptr(s, n3), _ptr(e, n3)))
+
+    def restrict(self, level, s, e, sc):
+        n3 = self.n(level) ** 3
+        _check(load().cc_restrict(self._h, level, _ptr(s, n3), _ptr(e, n3), _ptr(sc, self.n(level + 1) ** 3)))
+
+    def prolong_add(self, level, ec, ef):
+        _check(load().cc_prolong_add(self._h, level, _ptr(ec, self.n(level + 1) ** 3), _ptr(ef, self.n(level) ** 3)))
+
+    def bottom_solve(self, s, e):
+        M = self.num_levels - 1
+        n3 = self.n(M) ** 3
+        _check(load().cc_bottom_solve(self._h, _ptr(s, n3), _ptr(e, n3)))
+
+    def vcycle(self, level, s, e):
+        n3 = self.n(level) ** 3
+        _check(load().cc_vcycle(self._h, level, _ptr(s, n3), _ptr(e, n3)))
+
+    def time_smoother(self, reps: int = 20) -> float:
+        v = C.c_double()
+        _check(load().cc_time_smoother(self._h, reps, C.byref(v)))
+        return v.value

@@ -1,0 +1,923 @@
+// C ABI of the solver (include/cutcell.h): build, right-hand side, multigrid
+// solve and per-step hooks.  Orchestrates the host setup (level.cpp, mf_lu.cpp)
+// and the device kernels (kernels.hip) on one HIP stream.
+#include <hip/hip_runtime.h>
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "level.hpp"
+#include "mf_lu.hpp"
+#include "quadrature.hpp"
+
+namespace cc {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+#define HIPCHK(expr)                                                                                \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess) fail(CC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+  } while (0)
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Regular-row entries of a phi_1 cell (coefficients times 12 h^2), same tables
+// as the device stencil.
+void regular_entries(int n, const int bc[6], int i, int j, int k, std::map<int, double>& row) {
+  int ii[3] = {i, j, k};
+  long stride[3] = {1, n, (long)n * n};
+  long c = i + (long)n * (j + (long)n * k);
+  for (int d = 0; d < 3; ++d) {
+    int t = ii[d];
+    long s = stride[d];
+    int blo = bc[2 * d], bhi = bc[2 * d + 1];
+    auto add = [&](long off, double v) { row[(int)(c + off * s)] += v; };
+    if (t >= 2 && t <= n - 3) {
+      add(-2, -1.0); add(-1, 16.0); add(0, -30.0); add(1, 16.0); add(2, -1.0);
+    } else if (t == n - 1) {
+      if (bhi == 0) { add(-3, 21.0 / 12); add(-2, -139.0 / 12); add(-1, 545.0 / 12); add(0, -1087.0 / 12); }
+      else { add(-3, 0.1); add(-2, -1.5); add(-1, 15.9); add(0, -14.5); }
+    } else if (t == n - 2) {
+      if (bhi == 0) { add(-2, -15.0 / 12); add(-1, 209.0 / 12); add(0, -403.0 / 12); add(1, 269.0 / 12); }
+      else { add(-2, -1.1); add(-1, 16.5); add(0, -30.9); add(1, 15.5); }
+    } else if (t == 0) {
+      if (blo == 0) { add(3, 21.0 / 12); add(2, -139.0 / 12); add(1, 545.0 / 12); add(0, -1087.0 / 12); }
+      else { add(3, 0.1); add(2, -1.5); add(1, 15.9); add(0, -14.5); }
+    } else {  // t == 1
+      if (blo == 0) { add(2, -15.0 / 12); add(1, 209.0 / 12); add(0, -403.0 / 12); add(-1, 269.0 / 12); }
+      else { add(2, -1.1); add(1, 16.5); add(0, -30.9); add(-1, 15.5); }
+    }
+  }
+}
+
+// Wall-datum coefficient (times 12 h^2) of a regular row at layer t of axis
+// length n next to a wall of condition bc: Dirichlet datum <g>, Neumann datum
+// <dphi/dn> (outward).  0 if not next to that wall.
+double wall_coef(int layer, int bc, double h) {
+  if (layer == 0) return bc == CC_DIRICHLET ? 55.0 : 13.2 * h;
+  if (layer == 1) return bc == CC_DIRICHLET ? -5.0 : -1.2 * h;
+  return 0.0;
+}
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) fail(CC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct DevLU {
+  LuDev d{};
+  std::vector<LuTasks> tasks;  // per height
+  int height = 0;
+};
+
+struct DevLevel {
+  StencilLevel st{};
+  PlgRows plg{};
+  DevLU lu;
+  double* s = nullptr;
+  double* e = nullptr;
+  double* et = nullptr;
+  int2* absorbed = nullptr;
+  int n_absorbed = 0;
+};
+
+}  // namespace
+
+}  // namespace cc
+
+struct cc_problem {
+  cc::DomainSpec dom;
+  cc_params prm{};
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<std::unique_ptr<cc::LevelHost>> lv;
+  std::vector<cc::SupernodalLU> lu;
+  std::vector<cc::CSR> lu_mat;
+  std::vector<double> setup_s;
+  std::vector<cc::DevLevel> dev;
+  cc::DevBuf buf;
+  unsigned long long* d_norm = nullptr;
+  double* s0 = nullptr;
+  double* e0 = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  const double* g_r = nullptr;
+  double* g_phi = nullptr;
+};
+
+namespace cc {
+namespace {
+
+void check_level(const cc_problem* p, int level) {
+  if (!p) fail(CC_EINVAL, "null problem");
+  if (level < 0 || level >= (int)p->lv.size()) fail(CC_EINVAL, "level out of range");
+}
+void need_device(const cc_problem* p) {
+  if (p->device < 0) fail(CC_EDEVICE, "host-only problem handle (built with device = -1)");
+}
+
+// ---------------------------------------------------------------- build
+void build_lu_matrix(const LevelHost& L, bool bottom, CSR& A, std::vector<std::array<int, 3>>& xyz,
+                     std::vector<int>& var_cell_orig) {
+  const int n = L.n;
+  std::vector<int> idx_of(L.type.size(), -1);
+  const std::vector<int>& vars = bottom ? L.unknowns : L.phi2;
+  for (size_t t = 0; t < vars.size(); ++t) idx_of[vars[t]] = (int)t;
+  std::vector<int> plg_row(L.type.size(), -1);
+  for (size_t r = 0; r < L.phi2.size(); ++r) plg_row[L.phi2[r]] = (int)r;
+  A.n = (int)vars.size();
+  A.ptr.assign(A.n + 1, 0);
+  A.col.clear();
+  A.val.clear();
+  xyz.resize(A.n);
+  var_cell_orig = vars;
+  const double s12 = 1.0 / (12.0 * L.h * L.h);
+  for (int t = 0; t < A.n; ++t) {
+    int c = vars[t];
+    int i, j, k;
+    L.ijk(c, i, j, k);
+    xyz[t] = {i, j, k};
+    std::map<int, double> row;
+    if (L.type[c] == kPhi1) {
+      regular_entries(n, L.wall_bc, i, j, k, row);
+      for (auto& kv : row) kv.second *= s12;
+    } else {
+      int r = plg_row[c];
+      for (int q = 0; q < kPLG; ++q) row[L.plg_cols[(size_t)r * kPLG + q]] += L.plg_vals[(size_t)r * kPLG + q];
+    }
+    for (auto& kv : row) {
+      int col = idx_of[kv.first];
+      if (col < 0) {
+        if (bottom) fail(CC_EINVAL, "bottom row references a cell without an unknown");
+        continue;  // L21 entry
+      }
+      A.col.push_back(col);
+      A.val.push_back(kv.second);
+    }
+    A.ptr[t + 1] = (int)A.col.size();
+  }
+}
+
+void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var_orig_cell, DevLU& D) {
+  DevBuf& B = P->buf;
+  const int ns = (int)F.nodes.size();
+  std::vector<int> var_cell(F.n), nbase(ns), np(ns), nq(ns);
+  std::vector<long long> oM(ns), oV(ns), oW(ns), oU(ns), oP(ns);
+  for (int v = 0; v < F.n; ++v) var_cell[v] = var_orig_cell[F.perm[v]];
+  std::vector<int> piv(F.Pivbuf.size());
+  for (int s = 0; s < ns; ++s) {
+    const SnNode& nd = F.nodes[s];
+    nbase[s] = nd.base;
+    np[s] = nd.p;
+    nq[s] = nd.q;
+    oM[s] = nd.offM;
+    oV[s] = nd.offV;
+    oW[s] = nd.offW;
+    oU[s] = nd.offU;
+    oP[s] = nd.offPiv;
+    for (int j = 0; j < nd.p; ++j) piv[nd.offPiv + j] = nd.base + F.Pivbuf[nd.offPiv + j];
+  }
+  LuDev& d = D.d;
+  d.n = F.n;
+  d.var_cell = B.upload(var_cell);
+  d.M = B.upload(F.Mbuf);
+  d.V = B.upload(F.Vbuf);
+  d.W = B.upload(F.Wbuf);
+  d.U = B.upload(F.Ubuf);
+  d.piv = B.upload(piv);
+  d.nbase = B.upload(nbase);
+  d.np = B.upload(np);
+  d.nq = B.upload(nq);
+  d.offM = B.upload(oM);
+  d.offV = B.upload(oV);
+  d.offW = B.upload(oW);
+  d.offU = B.upload(oU);
+  d.offPiv = B.upload(oP);
+  d.y = B.alloc<double>(F.n);
+  d.z = B.alloc<double>(F.n);
+  d.x = B.alloc<double>(F.n);
+  D.height = F.max_height;
+  D.tasks.assign(F.max_height + 1, LuTasks{});
+  for (int h = 0; h <= F.max_height; ++h) {
+    std::vector<int2> ft;
+    std::map<int, std::vector<int2>> vmap;
+    for (int s = 0; s < ns; ++s) {
+      const SnNode& nd = F.nodes[s];
+      if (nd.height != h) continue;
+      for (int r = 0; r < nd.p; ++r) ft.push_back(make_int2(s, r));
+      for (int r = 0; r < nd.q; ++r) vmap[F.Ubuf[nd.offU + r]].push_back(make_int2(s, r));
+    }
+    std::vector<int> vvar, vptr = {0};
+    std::vector<int2> vent;
+    for (auto& kv : vmap) {
+      vvar.push_back(kv.first);
+      for (auto& e : kv.second) vent.push_back(e);
+      vptr.push_back((int)vent.size());
+    }
+    LuTasks& T = D.tasks[h];
+    T.nF = (int)ft.size();
+    T.ftask = B.upload(ft);
+    T.nVar = (int)vvar.size();
+    T.vvar = B.upload(vvar);
+    T.vptr = B.upload(vptr);
+    T.ventry = B.upload(vent);
+  }
+}
+
+void upload(cc_problem* P) {
+  DevBuf& B = P->buf;
+  const int M = (int)P->lv.size() - 1;
+  P->dev.resize(P->lv.size());
+  for (int m = 0; m <= M; ++m) {
+    const LevelHost& L = *P->lv[m];
+    DevLevel& D = P->dev[m];
+    D.st.n = L.n;
+    D.st.inv12h2 = 1.0 / (12.0 * L.h * L.h);
+    for (int a = 0; a < 6; ++a) D.st.bc[a] = L.wall_bc[a];
+    D.st.type = B.upload(L.type);
+    const int N2 = (int)L.phi2.size();
+    std::vector<int> cols((size_t)N2 * kPLG);
+    std::vector<double> vals((size_t)N2 * kPLG);
+    std::vector<uint64_t> mask(N2, 0);
+    for (int r = 0; r < N2; ++r)
+      for (int t = 0; t < kPLG; ++t) {
+        int c = L.plg_cols[(size_t)r * kPLG + t];
+        cols[(size_t)t * N2 + r] = c;
+        vals[(size_t)t * N2 + r] = L.plg_vals[(size_t)r * kPLG + t];
+        if (L.type[c] == kPhi2) mask[r] |= (1ull << t);
+      }
+    D.plg.N2 = N2;
+    D.plg.cell = B.upload(L.phi2);
+    D.plg.cols = B.upload(cols);
+    D.plg.vals = B.upload(vals);
+    D.plg.phi2 = B.upload(mask);
+    const SupernodalLU& F = P->lu[m];
+    std::vector<int> nd(N2, 0);
+    if (m < M)
+      for (int r = 0; r < N2; ++r) nd[r] = F.iperm[r];
+    D.plg.nd = B.upload(nd);
+    std::vector<int> orig = (m < M) ? L.phi2 : L.unknowns;
+    upload_lu(P, F, orig, D.lu);
+    size_t n3 = (size_t)L.n * L.n * L.n;
+    D.s = B.alloc<double>(n3);
+    D.e = B.alloc<double>(n3);
+    D.et = B.alloc<double>(n3);
+    std::vector<int2> ab;
+    for (size_t c = 0; c < n3; ++c)
+      if (L.host[c] >= 0 && L.host[c] != (int)c) ab.push_back(make_int2((int)c, L.host[c]));
+    D.n_absorbed = (int)ab.size();
+    D.absorbed = B.upload(ab);
+  }
+  P->d_norm = B.alloc<unsigned long long>(1);
+  size_t n3 = (size_t)P->lv[0]->n * P->lv[0]->n * P->lv[0]->n;
+  P->s0 = B.alloc<double>(n3);
+  P->e0 = B.alloc<double>(n3);
+}
+
+// ---------------------------------------------------------------- solve steps
+void smo2(cc_problem* P, int m, const double* s, double* e) {
+  DevLevel& D = P->dev[m];
+  if (D.plg.N2 == 0) return;
+  launch_plg_b2(D.plg, s, e, D.lu.d.y, P->stream);
+  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward(D.lu.d, D.lu.tasks[h], P->stream);
+  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward(D.lu.d, D.lu.tasks[h], e, P->stream);
+}
+
+void bottom(cc_problem* P, const double* s, double* e) {
+  int M = (int)P->dev.size() - 1;
+  DevLevel& D = P->dev[M];
+  long long n3 = (long long)D.st.n * D.st.n * D.st.n;
+  launch_zero(e, n3, P->stream);
+  launch_gather(D.lu.d.n, D.lu.d.var_cell, s, D.lu.d.y, P->stream);
+  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward(D.lu.d, D.lu.tasks[h], P->stream);
+  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward(D.lu.d, D.lu.tasks[h], e, P->stream);
+}
+
+// e = VCycle(s) on level m (e overwritten); tmp is a work array of the level.
+void vcycle(cc_problem* P, int m, const double* s, double* e, double* tmp) {
+  const int M = (int)P->dev.size() - 1;
+  if (m == M) {
+    bottom(P, s, e);
+    return;
+  }
+  DevLevel& D = P->dev[m];
+  const long long n3 = (long long)D.st.n * D.st.n * D.st.n;
+  const double om = P->prm.omega;
+  launch_zero(e, n3, P->stream);
+  double* cur = e;
+  double* oth = tmp;
+  for (int it = 0; it < P->prm.nu1; ++it) {
+    launch_smo1(D.st, om, s, cur, oth, P->stream);
+    std::swap(cur, oth);
+    smo2(P, m, s, cur);
+  }
+  DevLevel& C = P->dev[m + 1];
+  launch_restrict(D.st, C.st, s, cur, C.s, P->stream);
+  vcycle(P, m + 1, C.s, C.e, C.et);
+  launch_prolong_add(D.st, C.st.n, C.e, cur, P->stream);
+  for (int it = 0; it < P->prm.nu2; ++it) {
+    launch_smo1(D.st, om, s, cur, oth, P->stream);
+    std::swap(cur, oth);
+    smo2(P, m, s, cur);
+  }
+  if (cur != e) HIPCHK(hipMemcpyAsync(e, cur, n3 * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+}
+
+void residual(cc_problem* P, int m, const double* r, const double* x, double* s) {
+  DevLevel& D = P->dev[m];
+  launch_stencil_residual(D.st, r, x, s, P->stream);
+  launch_plg_residual(D.plg, r, x, s, 0, P->stream);
+}
+
+double read_norm(cc_problem* P) {
+  unsigned long long bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, P->d_norm, sizeof(bits), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  double v;
+  std::memcpy(&v, &bits, sizeof(v));
+  return v;
+}
+
+// one outer iteration after the initial residual: phi += VCycle(s0); s0 = r - L phi; |s0|
+void outer_step(cc_problem* P, const double* r, double* phi) {
+  DevLevel& D0 = P->dev[0];
+  long long n3 = (long long)D0.st.n * D0.st.n * D0.st.n;
+  vcycle(P, 0, P->s0, P->e0, D0.et);
+  launch_add_unknowns(D0.st, P->e0, phi, P->stream);
+  residual(P, 0, r, phi, P->s0);
+  launch_zero_u64(P->d_norm, P->stream);
+  launch_maxabs(P->s0, n3, P->d_norm, P->stream);
+}
+
+FieldDesc to_desc(const cc_field* f) {
+  FieldDesc d;
+  if (!f) return d;
+  d.kind = f->kind;
+  d.n_terms = f->n_terms;
+  int per = 0;
+  switch (f->kind) {
+    case CC_FIELD_ZERO: per = 0; break;
+    case CC_FIELD_POLY: per = 4 * f->n_terms; break;
+    case CC_FIELD_SINPROD: per = 7; break;
+    case CC_FIELD_EXPCOS: per = 5; break;
+    case CC_FIELD_GAUSS: per = 5 * f->n_terms; break;
+    default: fail(CC_EINVAL, "unknown field kind");
+  }
+  if (per > kFieldMax || per < 0) fail(CC_EINVAL, "field has too many terms");
+  if (per > 0 && !f->data) fail(CC_EINVAL, "field data is NULL");
+  for (int i = 0; i < per; ++i) d.d[i] = f->data[i];
+  if (f->kind == CC_FIELD_POLY)
+    for (int t = 0; t < f->n_terms; ++t) {
+      int a = (int)d.d[4 * t], b = (int)d.d[4 * t + 1], c = (int)d.d[4 * t + 2];
+      if (a < 0 || b < 0 || c < 0 || a + b + c > 4) fail(CC_EINVAL, "polynomial field of degree > 4");
+    }
+  return d;
+}
+
+// average of a field (value, or d/dn = side * d/dx_axis) over a wall face square
+double face_average(const LevelHost& L, const FieldDesc& g, int cell, int axis, int side, bool normal_deriv) {
+  static thread_local std::vector<double> gx, gw;
+  if (gx.empty()) gauss_legendre(8, gx, gw);
+  int ii[3];
+  L.ijk(cell, ii[0], ii[1], ii[2]);
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = L.origin[a] + L.h * ii[a];
+    hi[a] = lo[a] + L.h;
+  }
+  double xw = L.origin[axis] + (side > 0 ? L.n * L.h : 0.0);
+  int a1 = (axis + 1) % 3, a2 = (axis + 2) % 3;
+  double acc = 0.0;
+  for (int p = 0; p < 8; ++p)
+    for (int q = 0; q < 8; ++q) {
+      double x[3];
+      x[axis] = xw;
+      x[a1] = 0.5 * (lo[a1] + hi[a1]) + 0.5 * L.h * gx[p];
+      x[a2] = 0.5 * (lo[a2] + hi[a2]) + 0.5 * L.h * gx[q];
+      double v;
+      if (normal_deriv) {
+        double gr[3];
+        field_grad(g, x[0], x[1], x[2], gr);
+        v = side * gr[axis];
+      } else {
+        v = field_value(g, x[0], x[1], x[2], 0);
+      }
+      acc += gw[p] * gw[q] * v;
+    }
+  return 0.25 * acc;
+}
+
+}  // namespace
+}  // namespace cc
+
+using namespace cc;
+
+template <class F>
+static int guard(F&& f) {
+  try {
+    f();
+    return CC_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return CC_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CC_EINVAL;
+  }
+}
+
+extern "C" {
+
+const char* cc_last_error(void) { return g_last_error.c_str(); }
+
+void cc_default_params(cc_params* p) {
+  if (!p) return;
+  p->theta = 0.1;
+  p->omega = 0.8;
+  p->nu1 = 3;
+  p->nu2 = 3;
+  p->n_min = 16;
+  p->max_iter = 200;
+  p->tol = 1e-10;
+  p->precision = CC_FP64;
+  p->leaf_size = 64;
+  p->device = 0;
+  p->use_graph = 1;
+}
+
+int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out) {
+  return guard([&] {
+    if (!dom || !prm || !out) fail(CC_EINVAL, "null argument");
+    *out = nullptr;
+    if (dom->n < 8) fail(CC_EINVAL, "n must be at least 8");
+    if (std::fabs(dom->h * dom->n - 1.0) > 1e-12) fail(CC_EINVAL, "h must equal 1/n");
+    if (dom->n_obst < 0 || (dom->n_obst > 0 && !dom->obst)) fail(CC_EINVAL, "bad obstacle list");
+    if (!(prm->theta > 0 && prm->theta < 0.5)) fail(CC_EINVAL, "theta must lie in (0, 1/2)");
+    if (!(prm->omega > 0 && prm->omega < 2)) fail(CC_EINVAL, "omega must lie in (0, 2)");
+    if (prm->nu1 < 0 || prm->nu2 < 0 || prm->max_iter < 0 || prm->n_min < 8 || prm->leaf_size < 1)
+      fail(CC_EINVAL, "bad multigrid parameters");
+    for (int a = 0; a < 6; ++a)
+      if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
+    auto P = std::make_unique<cc_problem>();
+    P->prm = *prm;
+    P->device = prm->device;
+    DomainSpec& D = P->dom;
+    D.n = dom->n;
+    D.h = dom->h;
+    for (int a = 0; a < 3; ++a) D.origin[a] = dom->origin[a];
+    for (int a = 0; a < 6; ++a) D.wall_bc[a] = dom->wall_bc[a];
+    for (int t = 0; t < dom->n_obst; ++t) {
+      const cc_obstacle& o = dom->obst[t];
+      Obstacle ob;
+      for (int a = 0; a < 3; ++a) {
+        ob.c[a] = o.center[a];
+        ob.axes[a] = o.axes[a];
+        if (!(o.axes[a] > 0)) fail(CC_EINVAL, "semi-axes must be positive");
+      }
+      for (int a = 0; a < 9; ++a) ob.rot[a] = o.rot[a];
+      if (o.bc != CC_DIRICHLET && o.bc != CC_NEUMANN) fail(CC_EINVAL, "bad obstacle bc");
+      ob.bc = o.bc;
+      ob.R = std::max(ob.axes[0], std::max(ob.axes[1], ob.axes[2]));
+      ob.q = ellipsoid_quadric(ob.c, ob.axes, ob.rot);
+      D.obst.push_back(ob);
+    }
+    std::vector<int> sizes = {D.n};
+    while (sizes.back() % 2 == 0 && sizes.back() / 2 >= prm->n_min) sizes.push_back(sizes.back() / 2);
+    const int M = (int)sizes.size() - 1;
+    P->lv.resize(sizes.size());
+    P->lu.resize(sizes.size());
+    P->lu_mat.resize(sizes.size());
+    P->setup_s.resize(sizes.size());
+    for (int m = 0; m <= M; ++m) {
+      double t0 = now_s();
+      P->lv[m] = std::make_unique<LevelHost>();
+      P->lv[m]->build(D, sizes[m], prm->theta);
+      std::vector<std::array<int, 3>> xyz;
+      std::vector<int> orig;
+      build_lu_matrix(*P->lv[m], m == M, P->lu_mat[m], xyz, orig);
+      factorize(P->lu_mat[m], xyz, prm->leaf_size, P->lu[m]);
+      P->setup_s[m] = now_s() - t0;
+    }
+    if (P->device >= 0) {
+      HIPCHK(hipSetDevice(P->device));
+      if (stream) {
+        P->stream = (hipStream_t)stream;
+      } else {
+        HIPCHK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+        P->own_stream = true;
+      }
+      upload(P.get());
+    }
+    *out = P.release();
+  });
+}
+
+int cc_num_levels(const cc_problem* p) { return p ? (int)p->lv.size() : 0; }
+
+int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
+  return guard([&] {
+    check_level(p, level);
+    if (!info) fail(CC_EINVAL, "null info");
+    const LevelHost& L = *p->lv[level];
+    info->n = L.n;
+    info->n_unknowns = (long long)L.unknowns.size();
+    info->n_phi2 = (long long)L.phi2.size();
+    info->n_cut = (long long)L.cut.size();
+    info->n_merged = L.n_merged;
+    info->lu_vars = p->lu[level].n;
+    info->lu_entries = p->lu[level].entries();
+    info->lu_nodes = (int)p->lu[level].nodes.size();
+    info->lu_depth = p->lu[level].max_height + 1;
+    info->setup_seconds = p->setup_s[level];
+  });
+}
+
+int cc_export_cells(const cc_problem* p, int level, unsigned char* type, int* host, double* volfrac) {
+  return guard([&] {
+    check_level(p, level);
+    const LevelHost& L = *p->lv[level];
+    size_t n3 = L.type.size();
+    double h3 = L.h * L.h * L.h;
+    for (size_t c = 0; c < n3; ++c) {
+      if (type) type[c] = L.type[c];
+      if (host) host[c] = L.host[c];
+      if (volfrac) volfrac[c] = L.vol[c] / h3;
+    }
+  });
+}
+
+int cc_export_plg(const cc_problem* p, int level, int* row_cell, int* cols, double* vals) {
+  return guard([&] {
+    check_level(p, level);
+    const LevelHost& L = *p->lv[level];
+    if (row_cell) std::copy(L.phi2.begin(), L.phi2.end(), row_cell);
+    if (cols) std::copy(L.plg_cols.begin(), L.plg_cols.end(), cols);
+    if (vals) std::copy(L.plg_vals.begin(), L.plg_vals.end(), vals);
+  });
+}
+
+int cc_selfcheck_lu(const cc_problem* p, int level, double* rel_residual) {
+  return guard([&] {
+    check_level(p, level);
+    if (!rel_residual) fail(CC_EINVAL, "null output");
+    *rel_residual = p->lu[level].n ? selfcheck(p->lu_mat[level], p->lu[level], 12345u) : 0.0;
+  });
+}
+
+int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g, double* r_dev) {
+  return guard([&] {
+    if (!p || !r_dev) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    if (f_mode != CC_VALUE && f_mode != CC_LAPLACIAN) fail(CC_EINVAL, "bad f_mode");
+    FieldDesc fd = to_desc(f), gd = to_desc(g);
+    const LevelHost& L = *p->lv[0];
+    const int n = L.n;
+    const double h = L.h;
+    const size_t n3 = (size_t)n * n * n;
+    launch_cell_average(n, h, L.origin, fd, f_mode, 8, r_dev, p->stream);
+    std::vector<double> r(n3);
+    HIPCHK(hipMemcpyAsync(r.data(), r_dev, n3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const double s12 = 1.0 / (12.0 * h * h);
+    const double h3 = h * h * h;
+    // per cut cell: integral of f over the cut region and the patch datum of g
+    // (Dirichlet: <<g>>, Neumann: h <<dg/dn>>), from one quadrature pass
+    std::vector<int> cuts;
+    for (const auto& kv : L.cut) cuts.push_back(kv.first);
+    std::vector<double> cut_int(cuts.size()), cut_dat(cuts.size());
+#pragma omp parallel for schedule(dynamic, 8)
+    for (long t = 0; t < (long)cuts.size(); ++t) {
+      int m = cuts[t];
+      const CutData& cd = L.cut.at(m);
+      int bc = p->dom.obst[cd.obst].bc;
+      int ii[3];
+      L.ijk(m, ii[0], ii[1], ii[2]);
+      double lo[3], hi[3];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = L.origin[a] + h * ii[a];
+        hi[a] = lo[a] + h;
+      }
+      NodeSet vn;
+      SurfaceSet sn;
+      region_rules(lo, hi, 3, p->dom.obst[cd.obst].q, kQuadOrder, vn, &sn);
+      double s = 0.0;
+      for (size_t q = 0; q < vn.size(); ++q)
+        s += vn.w[q] * field_value(fd, vn.x[3 * q], vn.x[3 * q + 1], vn.x[3 * q + 2], f_mode);
+      cut_int[t] = s;
+      double acc = 0.0, area = 0.0;
+      for (size_t q = 0; q < sn.w.size(); ++q) {
+        const double* x = &sn.x[3 * q];
+        double v;
+        if (bc == CC_DIRICHLET) {
+          v = field_value(gd, x[0], x[1], x[2], 0);
+        } else {
+          double gr[3];
+          field_grad(gd, x[0], x[1], x[2], gr);
+          v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
+        }
+        acc += sn.w[q] * v;
+        area += sn.w[q];
+      }
+      cut_dat[t] = (area > 0) ? acc / area * (bc == CC_NEUMANN ? h : 1.0) : 0.0;
+    }
+    std::map<int, size_t> cut_pos;
+    for (size_t t = 0; t < cuts.size(); ++t) cut_pos[cuts[t]] = t;
+    auto cell_integral = [&](int m) -> double {
+      auto it = cut_pos.find(m);
+      return (it == cut_pos.end()) ? r[m] * h3 : cut_int[it->second];
+    };
+    std::vector<int> special;
+    for (int c : L.unknowns)
+      if (L.cut.count(c) || L.groups.count(c)) special.push_back(c);
+    std::vector<double> fbar(special.size());
+#pragma omp parallel for schedule(dynamic, 8)
+    for (long t = 0; t < (long)special.size(); ++t) {
+      int c = special[t];
+      std::vector<int> tmp;
+      const std::vector<int>& mem = L.members(c, tmp);
+      double tot = 0.0, vol = 0.0;
+      for (int m : mem) {
+        tot += cell_integral(m);
+        vol += L.vol[m];
+      }
+      fbar[t] = tot / vol;
+    }
+    std::vector<double> out = r;
+    for (size_t t = 0; t < special.size(); ++t) out[special[t]] = fbar[t];
+    for (size_t c = 0; c < n3; ++c)
+      if (L.host[c] != (int)c) out[c] = 0.0;
+    // wall-ghost terms of regular rows
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long t = 0; t < (long)L.unknowns.size(); ++t) {
+      int c = L.unknowns[t];
+      if (L.type[c] != kPhi1) continue;
+      int ii[3];
+      L.ijk(c, ii[0], ii[1], ii[2]);
+      double corr = 0.0;
+      for (int d = 0; d < 3; ++d)
+        for (int side : {-1, 1}) {
+          int layer = side > 0 ? n - 1 - ii[d] : ii[d];
+          if (layer > 1) continue;
+          int bc = L.wall_bc[2 * d + (side > 0 ? 1 : 0)];
+          double dat = face_average(L, gd, c, d, side, bc == CC_NEUMANN);
+          corr += wall_coef(layer, bc, h) * s12 * dat;
+        }
+      out[c] -= corr;
+    }
+    // boundary sites of FV-PLG rows
+    const int N2 = (int)L.phi2.size();
+    std::vector<double> pcorr(N2, 0.0);
+    std::vector<std::vector<size_t>> by_row(N2);
+    for (size_t s = 0; s < L.sites.size(); ++s) by_row[L.sites[s].row].push_back(s);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (long rr = 0; rr < N2; ++rr) {
+      double corr = 0.0;
+      for (size_t si : by_row[rr]) {
+        const Site& st = L.sites[si];
+        double dat;
+        if (st.kind == 'W') {
+          dat = face_average(L, gd, st.cell, st.axis, st.side, st.bc == CC_NEUMANN);
+          if (st.bc == CC_NEUMANN) dat *= h;
+        } else {
+          dat = cut_dat[cut_pos.at(st.cell)];
+        }
+        corr += st.coef * dat;
+      }
+      pcorr[rr] = corr;
+    }
+    for (int rr = 0; rr < N2; ++rr) out[L.phi2[rr]] -= pcorr[rr];
+    HIPCHK(hipMemcpyAsync(r_dev, out.data(), n3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_apply(cc_problem* p, int level, const double* x, double* y) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (!x || !y) fail(CC_EINVAL, "null array");
+    DevLevel& D = p->dev[level];
+    launch_stencil_apply(D.st, x, y, p->stream);
+    launch_plg_residual(D.plg, nullptr, x, y, 1, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_residual(cc_problem* p, int level, const double* r, const double* x, double* s, double* maxabs) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (!r || !x || !s) fail(CC_EINVAL, "null array");
+    DevLevel& D = p->dev[level];
+    residual(p, level, r, x, s);
+    launch_zero_u64(p->d_norm, p->stream);
+    launch_maxabs(s, (long long)D.st.n * D.st.n * D.st.n, p->d_norm, p->stream);
+    double v = read_norm(p);
+    if (maxabs) *maxabs = v;
+  });
+}
+
+int cc_smo1(cc_problem* p, int level, const double* s, double* e) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (!s || !e) fail(CC_EINVAL, "null array");
+    DevLevel& D = p->dev[level];
+    long long n3 = (long long)D.st.n * D.st.n * D.st.n;
+    launch_smo1(D.st, p->prm.omega, s, e, D.et, p->stream);
+    HIPCHK(hipMemcpyAsync(e, D.et, n3 * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_smo2(cc_problem* p, int level, const double* s, double* e) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (!s || !e) fail(CC_EINVAL, "null array");
+    if (level == (int)p->lv.size() - 1) fail(CC_EINVAL, "the coarsest level has no LU-correction");
+    smo2(p, level, s, e);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_restrict(cc_problem* p, int level, const double* s, const double* e, double* sc) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
+    if (!s || !e || !sc) fail(CC_EINVAL, "null array");
+    launch_restrict(p->dev[level].st, p->dev[level + 1].st, s, e, sc, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_prolong_add(cc_problem* p, int level, const double* ec, double* ef) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
+    if (!ec || !ef) fail(CC_EINVAL, "null array");
+    launch_prolong_add(p->dev[level].st, p->dev[level + 1].st.n, ec, ef, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_bottom_solve(cc_problem* p, const double* s, double* e) {
+  return guard([&] {
+    if (!p || !s || !e) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    bottom(p, s, e);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_vcycle(cc_problem* p, int level, const double* s, double* e) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (!s || !e) fail(CC_EINVAL, "null array");
+    vcycle(p, level, s, e, p->dev[level].et);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
+  int conv = 0;
+  int rc = guard([&] {
+    if (!p || !r || !phi) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    double t0 = now_s();
+    DevLevel& D0 = p->dev[0];
+    long long n3 = (long long)D0.st.n * D0.st.n * D0.st.n;
+    launch_zero_u64(p->d_norm, p->stream);
+    launch_maxabs(r, n3, p->d_norm, p->stream);
+    double rn = read_norm(p);
+    if (!std::isfinite(rn)) fail(CC_EINVAL, "non-finite right-hand side");
+    launch_mask_unknowns(D0.st, phi, p->stream);
+    residual(p, 0, r, phi, p->s0);
+    launch_zero_u64(p->d_norm, p->stream);
+    launch_maxabs(p->s0, n3, p->d_norm, p->stream);
+    double rel = (rn > 0) ? read_norm(p) / rn : 0.0;
+    int it = 0;
+    std::vector<double> hist = {rel};
+    bool use_graph = p->prm.use_graph != 0;
+    if (use_graph && (p->g_r != r || p->g_phi != phi || !p->gexec)) {
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+      }
+      HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+      outer_step(p, r, phi);
+      HIPCHK(hipStreamEndCapture(p->stream, &p->graph));
+      HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+      p->g_r = r;
+      p->g_phi = phi;
+    }
+    while (rel >= p->prm.tol && it < p->prm.max_iter) {
+      if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
+      if (use_graph)
+        HIPCHK(hipGraphLaunch(p->gexec, p->stream));
+      else
+        outer_step(p, r, phi);
+      rel = read_norm(p) / rn;
+      ++it;
+      hist.push_back(rel);
+    }
+    launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (info) {
+      info->iterations = it;
+      info->rel_residual = rel;
+      info->history_len = (int)std::min<size_t>(hist.size(), CC_HISTORY_MAX);
+      for (int i = 0; i < info->history_len; ++i) info->history[i] = hist[i];
+      info->seconds = now_s() - t0;
+    }
+    conv = (rel < p->prm.tol) ? 1 : 0;
+  });
+  if (rc == CC_OK && !conv) {
+    set_last_error("max_iter reached before tol");
+    return CC_ENOCONV;
+  }
+  return rc;
+}
+
+int cc_time_smoother(cc_problem* p, int reps, double* ms) {
+  return guard([&] {
+    if (!p || !ms || reps <= 0) fail(CC_EINVAL, "bad argument");
+    need_device(p);
+    DevLevel& D = p->dev[0];
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    double* x0 = p->e0;
+    double* x1 = D.et;
+    launch_smo1(D.st, p->prm.omega, p->s0, x0, x1, p->stream);
+    HIPCHK(hipEventRecord(a, p->stream));
+    for (int i = 0; i < reps; ++i) {
+      launch_smo1(D.st, p->prm.omega, p->s0, x0, x1, p->stream);
+      std::swap(x0, x1);
+    }
+    HIPCHK(hipEventRecord(b, p->stream));
+    HIPCHK(hipEventSynchronize(b));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, a, b));
+    *ms = t / reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  });
+}
+
+void cc_destroy(cc_problem* p) {
+  if (!p) return;
+  if (p->device >= 0) {
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->buf.release();
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+  }
+  delete p;
+}
+
+}  // extern "C"

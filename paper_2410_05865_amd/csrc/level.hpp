@@ -1,0 +1,107 @@
+// Host construction of one grid level (Secs. 2.2-2.4, 4.1-4.2): cell
+// classification and moments, merging, the phi_1/phi_2 split, FV-PLG stencils
+// and their weighted least-squares rows, and the sparse blocks the solver needs.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <vector>
+
+#include "common.hpp"
+#include "fields.hpp"
+#include "quadrature.hpp"
+
+namespace cc {
+
+struct Obstacle {
+  double c[3], axes[3], rot[9];
+  int bc;
+  double R;   // bounding-sphere radius
+  Quadric q;
+};
+
+struct DomainSpec {
+  int n;
+  double origin[3];
+  double h;
+  int wall_bc[6];
+  std::vector<Obstacle> obst;
+};
+
+enum : int8_t { kExterior = 0, kInterior = 1, kCut = 2 };
+enum : uint8_t { kNone = 0, kPhi1 = 1, kPhi2 = 2 };
+
+struct CutData {
+  int obst;
+  double vol;          // absolute
+  double m[N4];        // <xi^a> over the cut cell, own frame
+  double area;         // absolute patch area
+  double sm[N4];       // <<xi^a>> over the patch
+  double sn[3][N3];    // <<n_d xi^a>> over the patch, |a| <= 3
+};
+
+// A boundary site of an FV-PLG row: irregular patch of cut cell `cell`
+// (kind 'S') or the wall face (axis, side) of a stencil cell (kind 'W').
+struct Site {
+  int row;        // phi_2 row index
+  char kind;
+  int cell;
+  int bc;
+  int axis, side;
+  double coef;    // coefficient of the site datum in the row
+};
+
+constexpr int kPLG = 35;
+
+struct LevelHost {
+  int n = 0;
+  double h = 0, origin[3] = {0, 0, 0};
+  int wall_bc[6] = {};
+  const DomainSpec* dom = nullptr;
+
+  std::vector<int8_t> cls;       // n^3
+  std::vector<double> vol;       // n^3 absolute volume
+  std::vector<int> owner;        // n^3 obstacle claiming the cell, -1 if none
+  std::map<int, CutData> cut;    // cut cells
+  std::vector<int> host;         // n^3: -1 exterior, else the cell carrying the unknown
+  std::map<int, std::vector<int>> groups;  // hosts of merged groups -> sorted members
+  std::vector<uint8_t> plain;    // n^3 plain interior unknown
+  std::vector<uint8_t> type;     // n^3 kNone / kPhi1 / kPhi2
+  std::vector<int> unknowns;     // sorted cells carrying an unknown
+  std::vector<int> phi2;         // sorted phi_2 cells (row order)
+  std::vector<int> plg_cols;     // N2 x 35 stencil cells (lattice order)
+  std::vector<double> plg_vals;  // N2 x 35 coefficients (include 1/h^2)
+  std::vector<Site> sites;       // boundary sites of all rows
+  long long n_merged = 0;
+
+  int idx(int i, int j, int k) const { return i + n * (j + n * k); }
+  void ijk(int p, int& i, int& j, int& k) const {
+    i = p % n;
+    j = (p / n) % n;
+    k = p / (n * n);
+  }
+  const std::vector<int>& members(int p, std::vector<int>& tmp) const;
+
+  void build(const DomainSpec& d, int n_level, double theta);
+
+  // Regular-row wall data term of a phi_1 cell: coefficients multiplying the wall
+  // datum of each (axis, side) it touches; used by the right-hand side.
+  double face_area(int p, int d, int side) const;
+
+ private:
+  void claim();
+  void classify();
+  void merge(double theta);
+  void split();
+  void rows();
+  bool regular_ok(int p) const;
+  void plg_select(int p, int cells[kPLG]) const;
+  void plg_row(int p, int row, const int cells[kPLG], double vals[kPLG], std::vector<Site>& out) const;
+  void group_moments(int target, int cell, double out[N4]) const;
+};
+
+// Binomial shift of own-frame moments to a frame displaced by delta (grid units):
+// out_a = <(xi + delta)^a> given m_b = <xi^b>.
+void shift_moments4(const double m[N4], const int delta[3], double out[N4]);
+void shift_moments3(const double m[N3], const int delta[3], double out[N3]);
+
+}  // namespace cc
