@@ -178,6 +178,12 @@ int cc_export_plg(const cc_problem* p, int level, int* row_cell, int* cols, doub
  * right-hand side and returns max|A x - b| / max|b|.  Diagnostic only. */
 int cc_selfcheck_lu(const cc_problem* p, int level, double* rel_residual);
 
+/* Supernode structure of a level's factorization (postorder): first variable,
+ * size p, number of later variables q, height in the tree (leaves 0) and parent
+ * (-1 for roots).  Arrays hold lu_nodes entries (cc_level_info); NULL skips. */
+int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* nq, int* height,
+                       int* parent);
+
 /* Timing hook: average device time in ms of `reps` back-to-back launches of the
  * level-0 SMO-1 kernel (HIP events on the problem's stream). */
 int cc_time_smoother(cc_problem* p, int reps, double* ms_per_launch);

@@ -25,7 +25,7 @@ HISTORY_MAX = 256
 EXPORTED = [
     "cc_default_params", "cc_build", "cc_num_levels", "cc_get_level_info", "cc_assemble_rhs", "cc_solve",
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
-    "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_time_smoother", "cc_destroy",
+    "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_smoother", "cc_destroy",
     "cc_last_error",
 ]
 
@@ -95,6 +95,7 @@ def load() -> C.CDLL:
     lib.cc_export_cells.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.cc_export_plg.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.cc_selfcheck_lu.argtypes = [vp, C.c_int, P(C.c_double)]
+    lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_time_smoother.argtypes = [vp, C.c_int, P(C.c_double)]
     lib.cc_destroy.argtypes = [vp]
     lib.cc_destroy.restype = None
@@ -224,6 +225,13 @@ class Problem:
         _check(load().cc_export_plg(self._h, level, cell.ctypes.data_as(C.c_void_p),
                                     cols.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p)))
         return cell, cols.reshape(N2, 35), vals.reshape(N2, 35)
+
+    def export_lu_nodes(self, level: int = 0):
+        k = self.level_info(level)["lu_nodes"]
+        arr = {name: np.zeros(k, dtype=np.int32) for name in ("base", "p", "q", "height", "parent")}
+        _check(load().cc_export_lu_nodes(self._h, level, *[arr[nm].ctypes.data_as(C.c_void_p)
+                                                            for nm in ("base", "p", "q", "height", "parent")]))
+        return arr
 
     def selfcheck_lu(self, level: int) -> float:
         v = C.c_double()

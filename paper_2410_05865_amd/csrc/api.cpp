@@ -601,6 +601,21 @@ int cc_selfcheck_lu(const cc_problem* p, int level, double* rel_residual) {
   });
 }
 
+int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* nq, int* height, int* parent) {
+  return guard([&] {
+    check_level(p, level);
+    const SupernodalLU& F = p->lu[level];
+    for (size_t s = 0; s < F.nodes.size(); ++s) {
+      const SnNode& nd = F.nodes[s];
+      if (base) base[s] = nd.base;
+      if (np) np[s] = nd.p;
+      if (nq) nq[s] = nd.q;
+      if (height) height[s] = nd.height;
+      if (parent) parent[s] = nd.parent;
+    }
+  });
+}
+
 int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g, double* r_dev) {
   return guard([&] {
     if (!p || !r_dev) fail(CC_EINVAL, "null argument");
