@@ -19,7 +19,8 @@ ARCH = os.environ.get("CUTCELL_ARCH", "gfx950")
 
 # packed FP32 instructions stay off (the compiler must not form v_pk_*_f32)
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wno-unused-command-line-argument"]
+# hardware FP64 atomic add on device memory (coarse-grained allocations only)
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-munsafe-fp-atomics", "-Wno-unused-command-line-argument"]
 
 
 def _hipcc() -> str:

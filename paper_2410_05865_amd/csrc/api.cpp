@@ -192,13 +192,17 @@ void build_lu_matrix(const LevelHost& L, bool bottom, CSR& A, std::vector<std::a
   }
 }
 
-void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var_orig_cell, DevLU& D) {
+// Device copy of a factorization.  Equations of each node are stored in its
+// pivot order: position base + j holds equation base + piv[j]; row_pos maps an
+// equation (ND index) to its position.
+void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var_orig_cell, DevLU& D,
+               std::vector<int>& row_pos) {
   DevBuf& B = P->buf;
   const int ns = (int)F.nodes.size();
-  std::vector<int> var_cell(F.n), nbase(ns), np(ns), nq(ns);
-  std::vector<long long> oM(ns), oV(ns), oW(ns), oU(ns), oP(ns);
+  std::vector<int> var_cell(F.n), row_cell(F.n), nbase(ns), np(ns), nq(ns);
+  std::vector<long long> oM(ns), oV(ns), oW(ns), oU(ns);
   for (int v = 0; v < F.n; ++v) var_cell[v] = var_orig_cell[F.perm[v]];
-  std::vector<int> piv(F.Pivbuf.size());
+  row_pos.assign(F.n, 0);
   for (int s = 0; s < ns; ++s) {
     const SnNode& nd = F.nodes[s];
     nbase[s] = nd.base;
@@ -208,17 +212,23 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
     oV[s] = nd.offV;
     oW[s] = nd.offW;
     oU[s] = nd.offU;
-    oP[s] = nd.offPiv;
-    for (int j = 0; j < nd.p; ++j) piv[nd.offPiv + j] = nd.base + F.Pivbuf[nd.offPiv + j];
+    for (int j = 0; j < nd.p; ++j) {
+      int eq = nd.base + F.Pivbuf[nd.offPiv + j];
+      row_pos[eq] = nd.base + j;
+      row_cell[nd.base + j] = var_cell[eq];
+    }
   }
+  std::vector<int> Uf(F.Ubuf.size());
+  for (size_t e = 0; e < F.Ubuf.size(); ++e) Uf[e] = row_pos[F.Ubuf[e]];
   LuDev& d = D.d;
   d.n = F.n;
   d.var_cell = B.upload(var_cell);
+  d.row_cell = B.upload(row_cell);
   d.M = B.upload(F.Mbuf);
   d.V = B.upload(F.Vbuf);
   d.W = B.upload(F.Wbuf);
   d.U = B.upload(F.Ubuf);
-  d.piv = B.upload(piv);
+  d.Uf = B.upload(Uf);
   d.nbase = B.upload(nbase);
   d.np = B.upload(np);
   d.nq = B.upload(nq);
@@ -226,35 +236,36 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
   d.offV = B.upload(oV);
   d.offW = B.upload(oW);
   d.offU = B.upload(oU);
-  d.offPiv = B.upload(oP);
   d.y = B.alloc<double>(F.n);
   d.z = B.alloc<double>(F.n);
   d.x = B.alloc<double>(F.n);
   D.height = F.max_height;
   D.tasks.assign(F.max_height + 1, LuTasks{});
+  // g lanes per row: the largest power of two with about 8 entries per lane
+  auto lanes_for = [](double len) {
+    int g = 1;
+    while (g < 64 && 16.0 * g <= len) g <<= 1;
+    return g;
+  };
   for (int h = 0; h <= F.max_height; ++h) {
-    std::vector<int2> ft;
-    std::map<int, std::vector<int2>> vmap;
+    std::vector<LuTask> ft, bt;
     for (int s = 0; s < ns; ++s) {
       const SnNode& nd = F.nodes[s];
       if (nd.height != h) continue;
-      for (int r = 0; r < nd.p; ++r) ft.push_back(make_int2(s, r));
-      for (int r = 0; r < nd.q; ++r) vmap[F.Ubuf[nd.offU + r]].push_back(make_int2(s, r));
-    }
-    std::vector<int> vvar, vptr = {0};
-    std::vector<int2> vent;
-    for (auto& kv : vmap) {
-      vvar.push_back(kv.first);
-      for (auto& e : kv.second) vent.push_back(e);
-      vptr.push_back((int)vent.size());
+      int gf = lanes_for(nd.p), lgf = 0;
+      while ((1 << lgf) < gf) ++lgf;
+      for (int r = 0; r < nd.p + nd.q; r += 64 / gf)
+        ft.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, lgf, 0});
+      int gb = lanes_for(0.5 * nd.p + nd.q), lgb = 0;
+      while ((1 << lgb) < gb) ++lgb;
+      for (int r = 0; r < nd.p; r += 64 / gb)
+        bt.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, lgb, 0});
     }
     LuTasks& T = D.tasks[h];
     T.nF = (int)ft.size();
     T.ftask = B.upload(ft);
-    T.nVar = (int)vvar.size();
-    T.vvar = B.upload(vvar);
-    T.vptr = B.upload(vptr);
-    T.ventry = B.upload(vent);
+    T.nB = (int)bt.size();
+    T.btask = B.upload(bt);
   }
 }
 
@@ -286,12 +297,13 @@ void upload(cc_problem* P) {
     D.plg.vals = B.upload(vals);
     D.plg.phi2 = B.upload(mask);
     const SupernodalLU& F = P->lu[m];
+    std::vector<int> orig = (m < M) ? L.phi2 : L.unknowns;
+    std::vector<int> row_pos;
+    upload_lu(P, F, orig, D.lu, row_pos);
     std::vector<int> nd(N2, 0);
     if (m < M)
-      for (int r = 0; r < N2; ++r) nd[r] = F.iperm[r];
+      for (int r = 0; r < N2; ++r) nd[r] = row_pos[F.iperm[r]];
     D.plg.nd = B.upload(nd);
-    std::vector<int> orig = (m < M) ? L.phi2 : L.unknowns;
-    upload_lu(P, F, orig, D.lu);
     size_t n3 = (size_t)L.n * L.n * L.n;
     D.s = B.alloc<double>(n3);
     D.e = B.alloc<double>(n3);
@@ -322,7 +334,7 @@ void bottom(cc_problem* P, const double* s, double* e) {
   DevLevel& D = P->dev[M];
   long long n3 = (long long)D.st.n * D.st.n * D.st.n;
   launch_zero(e, n3, P->stream);
-  launch_gather(D.lu.d.n, D.lu.d.var_cell, s, D.lu.d.y, P->stream);
+  launch_gather(D.lu.d.n, D.lu.d.row_cell, s, D.lu.d.y, P->stream);
   for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward(D.lu.d, D.lu.tasks[h], P->stream);
   for (int h = D.lu.height; h >= 0; --h) launch_lu_backward(D.lu.d, D.lu.tasks[h], e, P->stream);
 }

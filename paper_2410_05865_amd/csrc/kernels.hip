@@ -83,12 +83,23 @@ __device__ __forceinline__ double regular_row(const StencilLevel& L, const doubl
   return a;
 }
 
+// 1D grid over 64 x 4 x 1 cell tiles, z fastest: concurrently resident blocks
+// work on a narrow range of (x, y) columns, so the +-2 z-neighbour planes are
+// re-read from cache (measured faster than x- or y-fastest orders).
+__device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
+  const int b = blockIdx.x;
+  k = b % n;
+  const int r = b / n;
+  const int ny = (n + 3) / 4;
+  j = (r % ny) * 4 + threadIdx.y;
+  i = (r / ny) * 64 + threadIdx.x;
+}
+
 __global__ void k_smo1(StencilLevel L, double omega, const double* __restrict__ s, const double* __restrict__ ein,
                        double* __restrict__ eout) {
   const int n = L.n;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
   long c = i + (long)n * (j + (long)n * k);
   double v = ein[c];
@@ -103,9 +114,8 @@ __global__ void k_smo1(StencilLevel L, double omega, const double* __restrict__ 
 __global__ void k_stencil_residual(StencilLevel L, const double* __restrict__ r, const double* __restrict__ x,
                                    double* __restrict__ s, int apply) {
   const int n = L.n;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
   long c = i + (long)n * (j + (long)n * k);
   double v = 0.0;
@@ -143,9 +153,8 @@ __global__ void k_plg_b2(PlgRows P, const double* __restrict__ s, const double* 
 __global__ void k_restrict(StencilLevel F, StencilLevel C, const double* __restrict__ s,
                            const double* __restrict__ e, double* __restrict__ sc) {
   const int nc = C.n, nf = F.n;
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  int J = blockIdx.y * blockDim.y + threadIdx.y;
-  int K = blockIdx.z;
+  int I, J, K;
+  tile_ijk(nc, I, J, K);
   if (I >= nc || J >= nc) return;
   long cc = I + (long)nc * (J + (long)nc * K);
   double acc = 0.0;
@@ -165,9 +174,8 @@ __global__ void k_restrict(StencilLevel F, StencilLevel C, const double* __restr
 
 __global__ void k_prolong_add(StencilLevel F, int nc, const double* __restrict__ ec, double* __restrict__ ef) {
   const int n = F.n;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
   long c = i + (long)n * (j + (long)n * k);
   if (F.type[c] == 1) ef[c] += ec[(i >> 1) + (long)nc * ((j >> 1) + (long)nc * (k >> 1))];
@@ -179,55 +187,87 @@ __global__ void k_gather(int n, const int* __restrict__ var_cell, const double* 
   if (v < n) y[v] = src[var_cell[v]];
 }
 
-// Forward supernodal sweep of one height: F-row tasks z = L11^-1 P y_F and
-// variable tasks y_v -= sum (L21 L11^-1) P y_F, one wavefront per task.
-__global__ void k_lu_forward(LuDev F, LuTasks T) {
+// Supernodal sweeps.  Rows of every node are stored row-major; the node's
+// equations are numbered in pivot order, so its right-hand side is contiguous.
+// A task is one wavefront handling 64/g rows of one node with g lanes per row:
+// (node, first row, log2 g).
+
+// acc += sum_{j in [j0, j1), j = gl mod g} a[j] * b[j], four independent chains
+__device__ __forceinline__ double lane_dot(const double* __restrict__ a, const double* __restrict__ b, int j0,
+                                           int j1, int gl, int g) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = j0 + gl;
+  for (; j + 3 * g < j1; j += 4 * g) {
+    s0 += a[j] * b[j];
+    s1 += a[j + g] * b[j + g];
+    s2 += a[j + 2 * g] * b[j + 2 * g];
+    s3 += a[j + 3 * g] * b[j + 3 * g];
+  }
+  for (; j < j1; j += g) s0 += a[j] * b[j];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// Forward sweep of one height: z_F = L11^-1 y_F on the node's rows, and
+// y_U -= (L21 L11^-1) y_F accumulated atomically into the later equations.
+__global__ void k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   int lane = threadIdx.x % kWave;
-  if (wave < T.nF) {
-    int2 t = T.ftask[wave];
-    int s = t.x, r = t.y, p = F.np[s];
-    const double* Mr = F.M + F.offM[s] + (long)r * p;
-    const int* piv = F.piv + F.offPiv[s];
-    double acc = 0.0;
-    for (int j = lane; j < r; j += kWave) acc += Mr[j] * F.y[piv[j]];
-    acc = wave_sum(acc);
-    if (lane == 0) F.z[F.nbase[s] + r] = acc + F.y[piv[r]];
-  } else if (wave < T.nF + T.nVar) {
-    int t = wave - T.nF;
-    double acc = 0.0;
-    for (int e = T.vptr[t]; e < T.vptr[t + 1]; ++e) {
-      int2 en = T.ventry[e];
-      int s = en.x, r = en.y, p = F.np[s];
-      const double* Vr = F.V + F.offV[s] + (long)r * p;
-      const int* piv = F.piv + F.offPiv[s];
-      for (int j = lane; j < p; j += kWave) acc += Vr[j] * F.y[piv[j]];
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) F.y[T.vvar[t]] -= acc;
+  if (wave >= ntasks) return;
+  const LuTask t = tasks[wave];
+  const int lg = t.lg, g = 1 << lg;
+  const int sub = lane >> lg, gl = lane & (g - 1);
+  const int p = t.p, q = t.q, base = t.base;
+  const int i = t.row0 + sub;
+  const bool valid = i < p + q;
+  const double* yF = F.y + base;
+  double acc = 0.0;
+  if (valid) {
+    if (i < p)
+      acc = lane_dot(F.M + t.offM + (long)i * p, yF, 0, i, gl, g);
+    else
+      acc = lane_dot(F.V + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
+  }
+  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && gl == 0) {
+    if (i < p)
+      F.z[base + i] = acc + yF[i];
+    else
+      atomicAdd(&F.y[F.Uf[t.offU + (i - p)]], -acc);
   }
 }
 
 // Backward sweep of one height: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered
 // to the grid array `out` through var_cell.
-__global__ void k_lu_backward(LuDev F, LuTasks T, double* __restrict__ out) {
+__global__ void k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, double* __restrict__ out) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   int lane = threadIdx.x % kWave;
-  if (wave >= T.nF) return;
-  int2 t = T.ftask[wave];
-  int s = t.x, r = t.y, p = F.np[s], q = F.nq[s], base = F.nbase[s];
-  const double* Mr = F.M + F.offM[s] + (long)r * p;
+  if (wave >= ntasks) return;
+  const LuTask t = tasks[wave];
+  const int lg = t.lg, g = 1 << lg;
+  const int sub = lane >> lg, gl = lane & (g - 1);
+  const int p = t.p, q = t.q, base = t.base;
+  const int i = t.row0 + sub;
+  const bool valid = i < p;
   double acc = 0.0;
-  for (int j = r + lane; j < p; j += kWave) acc += Mr[j] * F.z[base + j];
-  if (q > 0) {
-    const double* Wr = F.W + F.offW[s] + (long)r * q;
-    const int* U = F.U + F.offU[s];
-    for (int j = lane; j < q; j += kWave) acc -= Wr[j] * F.x[U[j]];
+  if (valid) {
+    acc = lane_dot(F.M + t.offM + (long)i * p, F.z + base, i, p, gl, g);
+    if (q > 0) {
+      const double* Wr = F.W + t.offVW + (long)i * q;
+      const int* U = F.U + t.offU;
+      double s0 = 0.0, s1 = 0.0;
+      int j = gl;
+      for (; j + g < q; j += 2 * g) {
+        s0 += Wr[j] * F.x[U[j]];
+        s1 += Wr[j + g] * F.x[U[j + g]];
+      }
+      for (; j < q; j += g) s0 += Wr[j] * F.x[U[j]];
+      acc -= s0 + s1;
+    }
   }
-  acc = wave_sum(acc);
-  if (lane == 0) {
-    F.x[base + r] = acc;
-    out[F.var_cell[base + r]] = acc;
+  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && gl == 0) {
+    F.x[base + i] = acc;
+    out[F.var_cell[base + i]] = acc;
   }
 }
 
@@ -299,6 +339,7 @@ __global__ void k_cell_average(int n, double h, double ox, double oy, double oz,
 }
 
 inline dim3 grid3(int n) { return dim3((n + 63) / 64, (n + 3) / 4, n); }
+inline dim3 grid_tiles(int n) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n); }
 const dim3 kBlock3(64, 4, 1);
 inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs); }
 
@@ -306,13 +347,13 @@ inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs)
 
 void launch_smo1(const StencilLevel& L, double omega, const double* s, const double* e_in, double* e_out,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_smo1, grid3(L.n), kBlock3, 0, st, L, omega, s, e_in, e_out);
+  hipLaunchKernelGGL(k_smo1, grid_tiles(L.n), kBlock3, 0, st, L, omega, s, e_in, e_out);
 }
 void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil_residual, grid3(L.n), kBlock3, 0, st, L, r, x, s, 0);
+  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, r, x, s, 0);
 }
 void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil_residual, grid3(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
+  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
 }
 void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only,
                          hipStream_t st) {
@@ -321,10 +362,10 @@ void launch_plg_residual(const PlgRows& P, const double* r, const double* x, dou
 }
 void launch_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, const double* e, double* sc,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict, grid3(C.n), kBlock3, 0, st, F, C, s, e, sc);
+  hipLaunchKernelGGL(k_restrict, grid_tiles(C.n), kBlock3, 0, st, F, C, s, e, sc);
 }
 void launch_prolong_add(const StencilLevel& F, int nc, const double* ec, double* ef, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_add, grid3(F.n), kBlock3, 0, st, F, nc, ec, ef);
+  hipLaunchKernelGGL(k_prolong_add, grid_tiles(F.n), kBlock3, 0, st, F, nc, ec, ef);
 }
 void launch_plg_b2(const PlgRows& P, const double* s, const double* e, double* y, hipStream_t st) {
   if (P.N2 == 0) return;
@@ -335,13 +376,13 @@ void launch_gather(int n, const int* var_cell, const double* src, double* y, hip
   hipLaunchKernelGGL(k_gather, dim3(blocks(n, 256)), dim3(256), 0, st, n, var_cell, src, y);
 }
 void launch_lu_forward(const LuDev& F, const LuTasks& T, hipStream_t st) {
-  long long waves = (long long)T.nF + T.nVar;
-  if (waves == 0) return;
-  hipLaunchKernelGGL(k_lu_forward, dim3(blocks(waves * kWave, 256)), dim3(256), 0, st, F, T);
+  if (T.nF > 0)
+    hipLaunchKernelGGL(k_lu_forward, dim3(blocks((long long)T.nF * kWave, 256)), dim3(256), 0, st, F, T.ftask, T.nF);
 }
 void launch_lu_backward(const LuDev& F, const LuTasks& T, double* out, hipStream_t st) {
-  if (T.nF == 0) return;
-  hipLaunchKernelGGL(k_lu_backward, dim3(blocks((long long)T.nF * kWave, 256)), dim3(256), 0, st, F, T, out);
+  if (T.nB == 0) return;
+  hipLaunchKernelGGL(k_lu_backward, dim3(blocks((long long)T.nB * kWave, 256)), dim3(256), 0, st, F, T.btask, T.nB,
+                     out);
 }
 void launch_zero(double* p, long long count, hipStream_t st) {
   if (count == 0) return;

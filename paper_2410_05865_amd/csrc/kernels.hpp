@@ -31,11 +31,12 @@ struct PlgRows {
 struct LuDev {
   int n;                 // variables
   const int* var_cell;   // n: grid cell of each variable (ND order)
+  const int* row_cell;   // n: grid cell of the equation stored at each position
   const double* M;
   const double* V;
   const double* W;
-  const int* U;
-  const int* piv;        // per node: absolute variable of pivoted row j
+  const int* U;           // later variables of each node (backward)
+  const int* Uf;          // their equation positions in pivot order (forward)
   const int* nbase;
   const int* np;
   const int* nq;
@@ -49,14 +50,23 @@ struct LuDev {
   double* x;
 };
 
-// Task lists of one height: F-row tasks (node, row) and variable tasks.
+// Task lists of one height.  A task is one wavefront: (node, first row,
+// log2 g, unused) taking 64/g rows with g lanes per row.  Forward rows are those
+// of [L11^-1 ; L21 L11^-1] (p + q rows); their L21 part is accumulated
+// atomically into the later equations.  Backward rows are those of
+// [U11^-1 | U11^-1 U12] (p rows).
+struct LuTask {
+  long long offM;         // node's M block
+  long long offVW;        // node's V block (forward) or W block (backward)
+  long long offU;         // node's later-variable list
+  int base, p, q;         // node's first variable, size, later variables
+  int row0, lg, pad;      // first row of this task, log2 lanes per row
+};
 struct LuTasks {
-  int nF;                 // F-row tasks
-  const int2* ftask;      // (node, row)
-  int nVar;               // forward variable tasks
-  const int* vvar;        // variable index
-  const int* vptr;        // nVar + 1
-  const int2* ventry;     // (node, row of V)
+  int nF;                 // forward tasks
+  const LuTask* ftask;
+  int nB;                 // backward tasks
+  const LuTask* btask;
 };
 
 void launch_smo1(const StencilLevel& L, double omega, const double* s, const double* e_in, double* e_out,
@@ -70,7 +80,7 @@ void launch_restrict(const StencilLevel& F, const StencilLevel& C, const double*
 void launch_prolong_add(const StencilLevel& F, int nc, const double* ec, double* ef, hipStream_t st);
 void launch_plg_b2(const PlgRows& P, const double* s, const double* e, double* y, hipStream_t st);
 void launch_gather(int n, const int* var_cell, const double* src, double* y, hipStream_t st);
-void launch_lu_forward(const LuDev& F, const LuTasks& T, hipStream_t st);
+void launch_lu_forward(const LuDev& F, const LuTasks& T, hipStream_t st);  // GEMV tasks + reduction
 void launch_lu_backward(const LuDev& F, const LuTasks& T, double* out, hipStream_t st);
 void launch_zero(double* p, long long count, hipStream_t st);
 void launch_zero_u64(unsigned long long* p, hipStream_t st);

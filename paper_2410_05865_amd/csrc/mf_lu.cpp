@@ -36,7 +36,11 @@ struct Builder {
       t[id].F = verts;
       return id;
     }
-    // axis of largest extent with at least two distinct coordinates
+    // Candidate cuts: a few planes per axis (quantiles of the coordinates);
+    // for each, the vertex separator is the smaller of the two one-sided sets
+    // (vertices of one side adjacent to the other).  The smallest separator
+    // with both halves holding at least 30% of the rest wins; ties keep the
+    // earlier candidate (largest-extent axis first, median first).
     int order[3] = {0, 1, 2};
     int ext[3];
     for (int a = 0; a < 3; ++a) {
@@ -48,37 +52,78 @@ struct Builder {
       ext[a] = hi - lo;
     }
     std::stable_sort(order, order + 3, [&](int x, int y) { return ext[x] > ext[y]; });
-    int axis = order[0];
-    if (ext[axis] == 0) {
+    if (ext[order[0]] == 0) {
       std::sort(verts.begin(), verts.end());
       t[id].F = verts;
       return id;
     }
-    std::vector<int> cs(verts.size());
-    for (size_t i = 0; i < verts.size(); ++i) cs[i] = (*xyz)[verts[i]][axis];
-    std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
-    int c = cs[cs.size() / 2];
-    int mn = *std::min_element(cs.begin(), cs.end());
-    if (c == mn) {  // keep both sides non-empty
-      int nxt = INT32_MAX;
-      for (int x : cs)
-        if (x > mn) nxt = std::min(nxt, x);
-      c = nxt;
+    static const double kQuant[5] = {0.5, 0.42, 0.58, 0.35, 0.65};
+    const size_t nv = verts.size();
+    size_t best_size = SIZE_MAX;
+    int best_axis = -1, best_c = 0, best_side = 1;
+    std::vector<int> cs(nv);
+    for (int oa = 0; oa < 3; ++oa) {
+      int axis = order[oa];
+      if (ext[axis] == 0) continue;
+      for (size_t i = 0; i < nv; ++i) cs[i] = (*xyz)[verts[i]][axis];
+      std::sort(cs.begin(), cs.end());
+      int nq = (oa == 0) ? 5 : 1;
+      for (int qi = 0; qi < nq; ++qi) {
+        int c = cs[std::min(nv - 1, (size_t)(kQuant[qi] * nv))];
+        if (c == cs[0]) {
+          auto it = std::upper_bound(cs.begin(), cs.end(), cs[0]);
+          if (it == cs.end()) continue;
+          c = *it;
+        }
+        for (int v : verts) mark[v] = ((*xyz)[v][axis] < c) ? 1 : 2;
+        size_t nl = 0, sl = 0, sr = 0;
+        for (int v : verts) {
+          bool left = mark[v] == 1;
+          nl += left;
+          for (int w : (*adj)[v])
+            if (mark[w] != 0 && mark[w] != mark[v]) {
+              (left ? sl : sr)++;
+              break;
+            }
+        }
+        for (int v : verts) mark[v] = 0;
+        size_t nr = nv - nl;
+        for (int side = 1; side <= 2; ++side) {
+          size_t sep = side == 1 ? sl : sr;
+          size_t a = (side == 1 ? nl : nr) - sep, b = (side == 1 ? nr : nl);
+          size_t rest = a + b;
+          if (rest == 0) continue;
+          bool balanced = a >= 0.3 * rest && b >= 0.3 * rest;
+          if (!balanced && !(best_axis < 0 && qi == 0 && oa == 0)) continue;
+          if (sep < best_size) {
+            best_size = sep;
+            best_axis = axis;
+            best_c = c;
+            best_side = side;
+          }
+        }
+      }
     }
-    for (int v : verts) mark[v] = ((*xyz)[v][axis] < c) ? 1 : 2;
+    if (best_axis < 0) {
+      std::sort(verts.begin(), verts.end());
+      t[id].F = verts;
+      return id;
+    }
+    for (int v : verts) mark[v] = ((*xyz)[v][best_axis] < best_c) ? 1 : 2;
     std::vector<int> L, R, S;
     for (int v : verts) {
-      if (mark[v] == 2) {
-        R.push_back(v);
-        continue;
-      }
+      bool mine = mark[v] == best_side;
       bool touches = false;
-      for (int w : (*adj)[v])
-        if (mark[w] == 2) {
-          touches = true;
-          break;
-        }
-      (touches ? S : L).push_back(v);
+      if (mine)
+        for (int w : (*adj)[v])
+          if (mark[w] != 0 && mark[w] != mark[v]) {
+            touches = true;
+            break;
+          }
+      if (touches)
+        S.push_back(v);
+      else
+        (mark[v] == 1 ? L : R).push_back(v);
     }
     for (int v : verts) mark[v] = 0;
     std::sort(S.begin(), S.end());
