@@ -19,7 +19,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-SMOOTHER_BYTES_PER_CELL = 24   # read e and s, write e' (FP64), over the n^3 grid
+SMOOTHER_BYTES_PER_CELL = 25   # read e, s and the cell type, write e (FP64), over the n^3 grid
 
 
 def _cpu_baseline(n_sample: int, gpu_cycles: int, n_target: int, N_target: int):
@@ -103,7 +103,7 @@ def main():
             infos.append(P.solve(r, x))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        ms_smoother = P.time_smoother(args.smoother_reps)
+        ms_smoother, _ = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
         torch.cuda.synchronize()
     ms = (t1 - t0) * 1000.0 / args.steps
     cycles = infos[-1]["iterations"]

@@ -70,7 +70,7 @@ typedef struct cc_params {
   int n_min;          /* coarsen while n/2 >= n_min, default 16 */
   int max_iter;       /* I_max, default 200 */
   double tol;         /* eps on max-norm relative residual, default 1e-10 */
-  int precision;      /* CC_FP64 or CC_MIXED */
+  int precision;      /* CC_FP64 or CC_MIXED (FP32 V-cycles, see cc_solve) */
   int leaf_size;      /* nested-dissection leaf size, default 64 */
   int device;         /* HIP device ordinal; -1 builds a host-only handle */
   int use_graph;      /* capture the V-cycle in a hipGraph (default 1) */
@@ -141,8 +141,34 @@ int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field
 /* Multigrid (Sec. 5.3): phi <- phi + VCycle(r - L phi) until the max-norm relative
  * residual < tol or max_iter.  phi_dev is the initial guess on entry and the
  * solution on exit (merged cells hold their host's value).  info may be NULL.
- * Returns CC_ENOCONV (with phi holding the last iterate) if tol is not reached. */
+ * Returns CC_ENOCONV (with phi holding the last iterate) if tol is not reached.
+ *
+ * precision CC_MIXED (set at cc_build) runs the same iteration as defect
+ * correction: the residual s = r - L phi, its max-norm and the update of phi
+ * stay FP64; each V-cycle runs in FP32 on d = s / max|s| (smoothers, FV-PLG rows,
+ * LU-correction with FP32 copies of the factors, transfers), except the bottom
+ * solve, which stays FP64; then phi += max|s| * e.  The stopping test is the FP64
+ * one, so the result meets the same tolerance.  FP32 copies of the rows and
+ * factors are made at cc_build; FP32 work arrays at the first mixed solve. */
 int cc_solve(cc_problem* p, const double* r_dev, double* phi_dev, cc_solve_info* info);
+
+/* Switch the precision of later cc_solve / cc_solve_batched calls (CC_FP64 or
+ * CC_MIXED); the build-time value is cc_params.precision. */
+int cc_set_precision(cc_problem* p, int precision);
+
+/* Several right-hand sides on one geometry: r_dev and phi_dev hold nrhs arrays of
+ * n^3 at a stride of n^3 (batch-major).  Groups of up to CC_BATCH_MAX
+ * right-hand sides run together: every kernel of the V-cycle processes the whole
+ * group in one launch, and the LU-correction reads each factor entry once for
+ * the group.  A group iterates until every member meets tol (members that meet it
+ * early keep receiving V-cycles).  info, if not NULL, has nrhs entries; each
+ * member's iterations count the V-cycles of its group.  Work arrays for a group
+ * are allocated at the first call (3 arrays per level of min(nrhs, CC_BATCH_MAX)
+ * * n_m^3 values in the working precision, plus one FP64 array of the finest
+ * level), grown by a later call with more right-hand sides, and kept until
+ * cc_destroy.  Returns CC_ENOCONV if some member misses tol. */
+#define CC_BATCH_MAX 64
+int cc_solve_batched(cc_problem* p, int nrhs, const double* r_dev, double* phi_dev, cc_solve_info* info);
 
 /* Parity hooks, one per step of the V-cycle, on level `level` arrays (n_m^3):
  *   cc_apply:      y = L x on unknown cells, 0 elsewhere (Sec. 2.4)
@@ -184,9 +210,21 @@ int cc_selfcheck_lu(const cc_problem* p, int level, double* rel_residual);
 int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* nq, int* height,
                        int* parent);
 
-/* Timing hook: average device time in ms of `reps` back-to-back launches of the
- * level-0 SMO-1 kernel (HIP events on the problem's stream). */
-int cc_time_smoother(cc_problem* p, int reps, double* ms_per_launch);
+/* Timing hook for roofline figures: average device time in ms of `reps`
+ * back-to-back launches (HIP events on the problem's stream) of
+ *   CC_TIME_SMO1      the level-0 SMO-1 kernel, FP64 (25 bytes per cell: e, s,
+ *                     the cell type and e')
+ *   CC_TIME_SMO1_F32  the same in FP32 (13 bytes per cell)
+ *   CC_TIME_LU        the level-0 LU-correction sweeps (all forward and backward
+ *                     launches of one correction, FP64)
+ *   CC_TIME_LU_F32    the same with the FP32 factors
+ *   CC_TIME_COPY      a plain copy of n^3 doubles (16 bytes per cell), the
+ *                     reference for memory-traffic counters
+ * *bytes (may be NULL) receives the algorithmic bytes moved per launch (per
+ * correction for the LU sweeps).  The timed kernels overwrite the library's
+ * level-0 work arrays only. */
+enum { CC_TIME_SMO1 = 0, CC_TIME_SMO1_F32 = 1, CC_TIME_LU = 2, CC_TIME_LU_F32 = 3, CC_TIME_COPY = 4 };
+int cc_time_kernel(cc_problem* p, int which, int reps, double* ms_per_launch, double* bytes);
 
 void cc_destroy(cc_problem* p);
 const char* cc_last_error(void);

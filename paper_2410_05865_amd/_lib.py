@@ -20,13 +20,17 @@ LIB_PATH = os.path.join(HERE, "libcutcell.so")
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_EGEOM, CC_EPLG, CC_ESINGULAR, CC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4}
 CC_VALUE, CC_LAPLACIAN = 0, 1
+CC_DIRICHLET, CC_NEUMANN = 0, 1
+CC_FP64, CC_MIXED = 0, 1
 HISTORY_MAX = 256
+BATCH_MAX = 64
+CC_TIME_SMO1, CC_TIME_SMO1_F32, CC_TIME_LU, CC_TIME_LU_F32, CC_TIME_COPY = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "cc_default_params", "cc_build", "cc_num_levels", "cc_get_level_info", "cc_assemble_rhs", "cc_solve",
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
-    "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_smoother", "cc_destroy",
-    "cc_last_error",
+    "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
+    "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision",
 ]
 
 
@@ -76,6 +80,9 @@ def load() -> C.CDLL:
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_05865_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (same soname), so torch's streams and allocations are valid in it
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     P = C.POINTER
@@ -96,7 +103,9 @@ def load() -> C.CDLL:
     lib.cc_export_plg.argtypes = [vp, C.c_int, vp, vp, vp]
     lib.cc_selfcheck_lu.argtypes = [vp, C.c_int, P(C.c_double)]
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
-    lib.cc_time_smoother.argtypes = [vp, C.c_int, P(C.c_double)]
+    lib.cc_set_precision.argtypes = [vp, C.c_int]
+    lib.cc_solve_batched.argtypes = [vp, C.c_int, vp, vp, P(CcSolveInfo)]
+    lib.cc_time_kernel.argtypes = [vp, C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
     lib.cc_destroy.argtypes = [vp]
     lib.cc_destroy.restype = None
     lib.cc_last_error.restype = C.c_char_p
@@ -244,15 +253,39 @@ class Problem:
         gs, gk = _field(g)
         _check(load().cc_assemble_rhs(self._h, C.byref(fs), f_mode, C.byref(gs), _ptr(r, self.n() ** 3)))
 
+    @staticmethod
+    def _info(info: CcSolveInfo, rc: int) -> dict:
+        return {"iterations": info.iterations, "rel_residual": info.rel_residual,
+                "history": list(info.history[:info.history_len]), "seconds": info.seconds,
+                "converged": rc == CC_OK}
+
+    def set_precision(self, precision: int):
+        _check(load().cc_set_precision(self._h, precision))
+        self.params.precision = precision
+
     def solve(self, r, phi) -> dict:
         n3 = self.n() ** 3
         info = CcSolveInfo()
         rc = load().cc_solve(self._h, _ptr(r, n3), _ptr(phi, n3), C.byref(info))
-        out = {"iterations": info.iterations, "rel_residual": info.rel_residual,
-               "history": list(info.history[:info.history_len]), "seconds": info.seconds,
-               "converged": rc == CC_OK}
         if rc not in (CC_OK, CC_ENOCONV):
             _check(rc)
+        return self._info(info, rc)
+
+    def solve_batched(self, r, phi) -> list:
+        """r, phi: (nrhs, n^3) contiguous float64 device tensors (batch-major)."""
+        n3 = self.n() ** 3
+        if r.dim() != 2 or r.shape[1] != n3 or phi.shape != r.shape:
+            raise ValueError("expected (nrhs, n^3) tensors of equal shape")
+        nrhs = r.shape[0]
+        infos = (CcSolveInfo * nrhs)()
+        rc = load().cc_solve_batched(self._h, nrhs, _ptr(r), _ptr(phi), infos)
+        if rc not in (CC_OK, CC_ENOCONV):
+            _check(rc)
+        out = []
+        for b in range(nrhs):
+            d = self._info(infos[b], CC_OK)
+            d["converged"] = infos[b].rel_residual < self.params.tol
+            out.append(d)
         return out
 
     def apply(self, level, x, y):
@@ -289,7 +322,9 @@ class Problem:
         n3 = self.n(level) ** 3
         _check(load().cc_vcycle(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
-    def time_smoother(self, reps: int = 20) -> float:
+    def time_kernel(self, which: int, reps: int = 20):
+        """(ms per launch, algorithmic bytes per launch) of a timing hook."""
         v = C.c_double()
-        _check(load().cc_time_smoother(self._h, reps, C.byref(v)))
-        return v.value
+        b = C.c_double()
+        _check(load().cc_time_kernel(self._h, which, reps, C.byref(v), C.byref(b)))
+        return v.value, b.value

@@ -8,9 +8,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -114,6 +116,45 @@ struct DevLevel {
   int n_absorbed = 0;
 };
 
+inline long long cube(int n) { return (long long)n * n * n; }
+
+// Arrays of the V-cycle in working precision T for nb right-hand sides: per
+// level s, e, et (nb * n^3 each), factorization work vectors (nb per variable;
+// FP64 on the coarsest level), the FP64 outer residual and per-RHS norms, and
+// the captured outer iteration.
+template <class T>
+struct Work {
+  int nb = 0;
+  std::vector<T*> s, e, et;
+  std::vector<LuDev> lu;
+  double* s0 = nullptr;
+  unsigned long long* norm = nullptr;
+  DevBuf own;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double* g_r = nullptr;
+  double* g_phi = nullptr;
+  int g_nb = 0;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    g_r = nullptr;
+    g_phi = nullptr;
+    g_nb = 0;
+  }
+  void release() {
+    drop_graph();
+    own.release();
+    s.clear();
+    e.clear();
+    et.clear();
+    lu.clear();
+    nb = 0;
+  }
+};
+
 }  // namespace
 
 }  // namespace cc
@@ -133,10 +174,10 @@ struct cc_problem {
   unsigned long long* d_norm = nullptr;
   double* s0 = nullptr;
   double* e0 = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  const double* g_r = nullptr;
-  double* g_phi = nullptr;
+  cc::Work<double> w64;         // FP64, one right-hand side (arrays of dev[])
+  cc::Work<float> w32;          // mixed precision, one right-hand side
+  cc::Work<double> wb64;        // batched
+  cc::Work<float> wb32;
 };
 
 namespace cc {
@@ -195,23 +236,15 @@ void build_lu_matrix(const LevelHost& L, bool bottom, CSR& A, std::vector<std::a
 // Device copy of a factorization.  Equations of each node are stored in its
 // pivot order: position base + j holds equation base + piv[j]; row_pos maps an
 // equation (ND index) to its position.
-void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var_orig_cell, DevLU& D,
+void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var_orig_cell, bool fp32, DevLU& D,
                std::vector<int>& row_pos) {
   DevBuf& B = P->buf;
   const int ns = (int)F.nodes.size();
-  std::vector<int> var_cell(F.n), row_cell(F.n), nbase(ns), np(ns), nq(ns);
-  std::vector<long long> oM(ns), oV(ns), oW(ns), oU(ns);
+  std::vector<int> var_cell(F.n), row_cell(F.n);
   for (int v = 0; v < F.n; ++v) var_cell[v] = var_orig_cell[F.perm[v]];
   row_pos.assign(F.n, 0);
   for (int s = 0; s < ns; ++s) {
     const SnNode& nd = F.nodes[s];
-    nbase[s] = nd.base;
-    np[s] = nd.p;
-    nq[s] = nd.q;
-    oM[s] = nd.offM;
-    oV[s] = nd.offV;
-    oW[s] = nd.offW;
-    oU[s] = nd.offU;
     for (int j = 0; j < nd.p; ++j) {
       int eq = nd.base + F.Pivbuf[nd.offPiv + j];
       row_pos[eq] = nd.base + j;
@@ -229,49 +262,91 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
   d.W = B.upload(F.Wbuf);
   d.U = B.upload(F.Ubuf);
   d.Uf = B.upload(Uf);
-  d.nbase = B.upload(nbase);
-  d.np = B.upload(np);
-  d.nq = B.upload(nq);
-  d.offM = B.upload(oM);
-  d.offV = B.upload(oV);
-  d.offW = B.upload(oW);
-  d.offU = B.upload(oU);
+  if (fp32) {
+    d.M32 = B.upload(std::vector<float>(F.Mbuf.begin(), F.Mbuf.end()));
+    d.V32 = B.upload(std::vector<float>(F.Vbuf.begin(), F.Vbuf.end()));
+    d.W32 = B.upload(std::vector<float>(F.Wbuf.begin(), F.Wbuf.end()));
+  }
   d.y = B.alloc<double>(F.n);
   d.z = B.alloc<double>(F.n);
   d.x = B.alloc<double>(F.n);
   D.height = F.max_height;
-  D.tasks.assign(F.max_height + 1, LuTasks{});
   // g lanes per row: the largest power of two with about 8 entries per lane
   auto lanes_for = [](double len) {
     int g = 1;
     while (g < 64 && 16.0 * g <= len) g <<= 1;
     return g;
   };
+  auto log2i = [](int g) {
+    int l = 0;
+    while ((1 << l) < g) ++l;
+    return l;
+  };
+  D.tasks.assign(F.max_height + 1, LuTasks{});
   for (int h = 0; h <= F.max_height; ++h) {
-    std::vector<LuTask> ft, bt;
+    std::vector<LuTask> ft, bt, fm, bm;
     for (int s = 0; s < ns; ++s) {
       const SnNode& nd = F.nodes[s];
       if (nd.height != h) continue;
-      int gf = lanes_for(nd.p), lgf = 0;
-      while ((1 << lgf) < gf) ++lgf;
+      const int gf = lanes_for(nd.p), lgf = log2i(gf);
       for (int r = 0; r < nd.p + nd.q; r += 64 / gf)
         ft.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, lgf, 0});
-      int gb = lanes_for(0.5 * nd.p + nd.q), lgb = 0;
-      while ((1 << lgb) < gb) ++lgb;
+      const int gb = lanes_for(0.5 * nd.p + nd.q), lgb = log2i(gb);
       for (int r = 0; r < nd.p; r += 64 / gb)
         bt.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, lgb, 0});
+      // multi-RHS: kMrRows consecutive rows of one node per wavefront
+      for (int r = 0; r < nd.p + nd.q; r += kMrRows)
+        fm.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, 0, 0});
+      for (int r = 0; r < nd.p; r += kMrRows)
+        bm.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, 0, 0});
     }
     LuTasks& T = D.tasks[h];
     T.nF = (int)ft.size();
-    T.ftask = B.upload(ft);
     T.nB = (int)bt.size();
+    T.ftask = B.upload(ft);
     T.btask = B.upload(bt);
+    T.nFm = (int)fm.size();
+    T.nBm = (int)bm.size();
+    T.ftask_m = B.upload(fm);
+    T.btask_m = B.upload(bm);
   }
+}
+
+// Allocate a Work for nb right-hand sides (FP64 outer arrays, level arrays in
+// T, factorization vectors in T on levels m < M and FP64 on the coarsest).
+template <class T>
+void alloc_work(cc_problem* P, Work<T>& W, int nb) {
+  W.release();
+  const int M = (int)P->dev.size() - 1;
+  W.nb = nb;
+  for (int m = 0; m <= M; ++m) {
+    const long long n3 = cube(P->dev[m].st.n);
+    W.s.push_back(W.own.template alloc<T>((size_t)n3 * nb));
+    W.e.push_back(W.own.template alloc<T>((size_t)n3 * nb));
+    W.et.push_back(W.own.template alloc<T>((size_t)n3 * nb));
+    LuDev d = P->dev[m].lu.d;
+    const size_t nv = (size_t)std::max(d.n, 1) * nb;
+    d.y = d.z = d.x = nullptr;
+    d.y32 = d.z32 = d.x32 = nullptr;
+    if (std::is_same<T, float>::value && m < M) {
+      d.y32 = W.own.template alloc<float>(nv);
+      d.z32 = W.own.template alloc<float>(nv);
+      d.x32 = W.own.template alloc<float>(nv);
+    } else {
+      d.y = W.own.template alloc<double>(nv);
+      d.z = W.own.template alloc<double>(nv);
+      d.x = W.own.template alloc<double>(nv);
+    }
+    W.lu.push_back(d);
+  }
+  W.s0 = W.own.template alloc<double>((size_t)cube(P->dev[0].st.n) * nb);
+  W.norm = W.own.template alloc<unsigned long long>((size_t)nb);
 }
 
 void upload(cc_problem* P) {
   DevBuf& B = P->buf;
   const int M = (int)P->lv.size() - 1;
+
   P->dev.resize(P->lv.size());
   for (int m = 0; m <= M; ++m) {
     const LevelHost& L = *P->lv[m];
@@ -295,11 +370,12 @@ void upload(cc_problem* P) {
     D.plg.cell = B.upload(L.phi2);
     D.plg.cols = B.upload(cols);
     D.plg.vals = B.upload(vals);
+    D.plg.vals32 = B.upload(std::vector<float>(vals.begin(), vals.end()));
     D.plg.phi2 = B.upload(mask);
     const SupernodalLU& F = P->lu[m];
     std::vector<int> orig = (m < M) ? L.phi2 : L.unknowns;
     std::vector<int> row_pos;
-    upload_lu(P, F, orig, D.lu, row_pos);
+    upload_lu(P, F, orig, m < M, D.lu, row_pos);
     std::vector<int> nd(N2, 0);
     if (m < M)
       for (int r = 0; r < N2; ++r) nd[r] = row_pos[F.iperm[r]];
@@ -318,81 +394,188 @@ void upload(cc_problem* P) {
   size_t n3 = (size_t)P->lv[0]->n * P->lv[0]->n * P->lv[0]->n;
   P->s0 = B.alloc<double>(n3);
   P->e0 = B.alloc<double>(n3);
+  // FP64 single right-hand side: the level arrays themselves
+  Work<double>& W = P->w64;
+  W.nb = 1;
+  for (int m = 0; m <= M; ++m) {
+    W.s.push_back(P->dev[m].s);
+    W.e.push_back(P->dev[m].e);
+    W.et.push_back(P->dev[m].et);
+    W.lu.push_back(P->dev[m].lu.d);
+  }
+  W.s0 = P->s0;
+  W.norm = P->d_norm;
 }
 
 // ---------------------------------------------------------------- solve steps
-void smo2(cc_problem* P, int m, const double* s, double* e) {
+template <class T>
+T* vec_y(const LuDev& F);
+template <>
+double* vec_y<double>(const LuDev& F) { return F.y; }
+template <>
+float* vec_y<float>(const LuDev& F) { return F.y32; }
+
+// SMO-2 on level m < M: b_2 = s_2 - L21 e_1, e_2 = L22^-1 b_2 (Sec. 5.3)
+template <class T>
+void smo2(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, int nb) {
   DevLevel& D = P->dev[m];
   if (D.plg.N2 == 0) return;
-  launch_plg_b2(D.plg, s, e, D.lu.d.y, P->stream);
-  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward(D.lu.d, D.lu.tasks[h], P->stream);
-  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward(D.lu.d, D.lu.tasks[h], e, P->stream);
+  const LuDev& F = W.lu[m];
+  const long long n3 = cube(D.st.n);
+  launch_plg_b2<T>(D.plg, s, e, vec_y<T>(F), n3, nb, P->stream);
+  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<T>(F, D.lu.tasks[h], nb, P->stream);
+  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward<T, T>(F, D.lu.tasks[h], e, n3, nb, P->stream);
 }
 
-void bottom(cc_problem* P, const double* s, double* e) {
-  int M = (int)P->dev.size() - 1;
+// e = L^(M)^-1 s on the coarsest level, in FP64 whatever T is
+template <class T>
+void bottom(cc_problem* P, const Work<T>& W, const T* s, T* e, int nb) {
+  const int M = (int)P->dev.size() - 1;
   DevLevel& D = P->dev[M];
-  long long n3 = (long long)D.st.n * D.st.n * D.st.n;
-  launch_zero(e, n3, P->stream);
-  launch_gather(D.lu.d.n, D.lu.d.row_cell, s, D.lu.d.y, P->stream);
-  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward(D.lu.d, D.lu.tasks[h], P->stream);
-  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward(D.lu.d, D.lu.tasks[h], e, P->stream);
+  const LuDev& F = W.lu[M];
+  const long long n3 = cube(D.st.n);
+  launch_zero<T>(e, n3 * nb, P->stream);
+  launch_gather<T, double>(F.n, F.row_cell, s, n3, F.y, nb, P->stream);
+  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<double>(F, D.lu.tasks[h], nb, P->stream);
+  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward<double, T>(F, D.lu.tasks[h], e, n3, nb, P->stream);
 }
 
 // e = VCycle(s) on level m (e overwritten); tmp is a work array of the level.
-void vcycle(cc_problem* P, int m, const double* s, double* e, double* tmp) {
+template <class T>
+void vcycle(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, T* tmp, int nb) {
   const int M = (int)P->dev.size() - 1;
   if (m == M) {
-    bottom(P, s, e);
+    bottom<T>(P, W, s, e, nb);
     return;
   }
   DevLevel& D = P->dev[m];
-  const long long n3 = (long long)D.st.n * D.st.n * D.st.n;
+  const long long n3 = cube(D.st.n);
   const double om = P->prm.omega;
-  launch_zero(e, n3, P->stream);
-  double* cur = e;
-  double* oth = tmp;
+  launch_zero<T>(e, n3 * nb, P->stream);
+  T* cur = e;
+  T* oth = tmp;
   for (int it = 0; it < P->prm.nu1; ++it) {
-    launch_smo1(D.st, om, s, cur, oth, P->stream);
+    launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
     std::swap(cur, oth);
-    smo2(P, m, s, cur);
+    smo2<T>(P, W, m, s, cur, nb);
   }
   DevLevel& C = P->dev[m + 1];
-  launch_restrict(D.st, C.st, s, cur, C.s, P->stream);
-  vcycle(P, m + 1, C.s, C.e, C.et);
-  launch_prolong_add(D.st, C.st.n, C.e, cur, P->stream);
+  launch_restrict<T>(D.st, C.st, s, cur, W.s[m + 1], nb, P->stream);
+  vcycle<T>(P, W, m + 1, W.s[m + 1], W.e[m + 1], W.et[m + 1], nb);
+  launch_prolong_add<T>(D.st, C.st.n, W.e[m + 1], cur, nb, P->stream);
   for (int it = 0; it < P->prm.nu2; ++it) {
-    launch_smo1(D.st, om, s, cur, oth, P->stream);
+    launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
     std::swap(cur, oth);
-    smo2(P, m, s, cur);
+    smo2<T>(P, W, m, s, cur, nb);
   }
-  if (cur != e) HIPCHK(hipMemcpyAsync(e, cur, n3 * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+  if (cur != e) HIPCHK(hipMemcpyAsync(e, cur, n3 * nb * sizeof(T), hipMemcpyDeviceToDevice, P->stream));
 }
 
-void residual(cc_problem* P, int m, const double* r, const double* x, double* s) {
+// s = r - L x on level m for nb arrays (FP64)
+void residual(cc_problem* P, int m, const double* r, const double* x, double* s, int nb = 1) {
   DevLevel& D = P->dev[m];
-  launch_stencil_residual(D.st, r, x, s, P->stream);
-  launch_plg_residual(D.plg, r, x, s, 0, P->stream);
+  launch_stencil_residual(D.st, r, x, s, nb, P->stream);
+  launch_plg_residual(D.plg, r, x, s, 0, nb, cube(D.st.n), P->stream);
 }
 
-double read_norm(cc_problem* P) {
-  unsigned long long bits = 0;
-  HIPCHK(hipMemcpyAsync(&bits, P->d_norm, sizeof(bits), hipMemcpyDeviceToHost, P->stream));
+std::vector<double> read_norms(cc_problem* P, const unsigned long long* d, int nb) {
+  std::vector<unsigned long long> bits(nb);
+  HIPCHK(hipMemcpyAsync(bits.data(), d, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
-  double v;
-  std::memcpy(&v, &bits, sizeof(v));
+  std::vector<double> v(nb);
+  for (int b = 0; b < nb; ++b) std::memcpy(&v[b], &bits[b], sizeof(double));
   return v;
 }
+double read_norm(cc_problem* P) { return read_norms(P, P->d_norm, 1)[0]; }
 
-// one outer iteration after the initial residual: phi += VCycle(s0); s0 = r - L phi; |s0|
-void outer_step(cc_problem* P, const double* r, double* phi) {
+// One outer iteration after the residual s0 and its norms are current:
+// FP64: phi += VCycle(s0).  Mixed (defect correction): d = s0 / |s0| in FP32,
+// phi += |s0| VCycle32(d).  Then s0 = r - L phi and its norms.
+template <class T>
+void outer_step(cc_problem* P, const Work<T>& W, const double* r, double* phi, int nb) {
   DevLevel& D0 = P->dev[0];
-  long long n3 = (long long)D0.st.n * D0.st.n * D0.st.n;
-  vcycle(P, 0, P->s0, P->e0, D0.et);
-  launch_add_unknowns(D0.st, P->e0, phi, P->stream);
-  residual(P, 0, r, phi, P->s0);
-  launch_zero_u64(P->d_norm, P->stream);
-  launch_maxabs(P->s0, n3, P->d_norm, P->stream);
+  const long long n3 = cube(D0.st.n);
+  if constexpr (std::is_same<T, double>::value) {
+    vcycle<T>(P, W, 0, W.s0, W.e[0], W.et[0], nb);
+    launch_add_unknowns<T>(D0.st, W.e[0], nullptr, phi, nb, P->stream);
+  } else {
+    launch_scale_residual<T>(n3, W.s0, W.norm, W.s[0], nb, P->stream);
+    vcycle<T>(P, W, 0, W.s[0], W.e[0], W.et[0], nb);
+    launch_add_unknowns<T>(D0.st, W.e[0], W.norm, phi, nb, P->stream);
+  }
+  residual(P, 0, r, phi, W.s0, nb);
+  launch_zero_u64(W.norm, nb, P->stream);
+  launch_maxabs(W.s0, n3, nb, W.norm, P->stream);
+}
+
+struct SolveRec {
+  int iterations = 0;
+  double rel = 0.0;
+  std::vector<double> hist;
+};
+
+// The multigrid iteration of Sec. 5.3 on nb right-hand sides at once (r, phi:
+// nb * n^3, batch-major) until every relative residual is below tol or max_iter.
+template <class T>
+void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb, std::vector<SolveRec>& rec) {
+  DevLevel& D0 = P->dev[0];
+  const long long n3 = cube(D0.st.n);
+  launch_zero_u64(W.norm, nb, P->stream);
+  launch_maxabs(r, n3, nb, W.norm, P->stream);
+  std::vector<double> rn = read_norms(P, W.norm, nb);
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(rn[b])) fail(CC_EINVAL, "non-finite right-hand side");
+  launch_mask_unknowns(D0.st, phi, nb, P->stream);
+  residual(P, 0, r, phi, W.s0, nb);
+  launch_zero_u64(W.norm, nb, P->stream);
+  launch_maxabs(W.s0, n3, nb, W.norm, P->stream);
+  std::vector<double> sn = read_norms(P, W.norm, nb);
+  rec.assign(nb, SolveRec{});
+  auto update = [&](bool first) {
+    bool all = true;
+    for (int b = 0; b < nb; ++b) {
+      double rel = rn[b] > 0 ? sn[b] / rn[b] : 0.0;
+      rec[b].rel = rel;
+      rec[b].hist.push_back(rel);
+      if (!first) ++rec[b].iterations;
+      if (!(rel < P->prm.tol)) all = false;
+      if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
+    }
+    return all;
+  };
+  bool done = update(true);
+  const bool use_graph = P->prm.use_graph != 0;
+  if (use_graph && !done && (W.g_r != r || W.g_phi != phi || W.g_nb != nb || !W.gexec)) {
+    W.drop_graph();
+    HIPCHK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    outer_step<T>(P, W, r, phi, nb);
+    HIPCHK(hipStreamEndCapture(P->stream, &W.graph));
+    HIPCHK(hipGraphInstantiate(&W.gexec, W.graph, nullptr, nullptr, 0));
+    W.g_r = r;
+    W.g_phi = phi;
+    W.g_nb = nb;
+  }
+  int it = 0;
+  while (!done && it < P->prm.max_iter) {
+    if (use_graph)
+      HIPCHK(hipGraphLaunch(W.gexec, P->stream));
+    else
+      outer_step<T>(P, W, r, phi, nb);
+    sn = read_norms(P, W.norm, nb);
+    ++it;
+    done = update(false);
+  }
+  launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, n3, nb, P->stream);
+  HIPCHK(hipStreamSynchronize(P->stream));
+}
+
+void fill_info(const SolveRec& rc, double seconds, cc_solve_info* info) {
+  if (!info) return;
+  info->iterations = rc.iterations;
+  info->rel_residual = rc.rel;
+  info->history_len = (int)std::min<size_t>(rc.hist.size(), CC_HISTORY_MAX);
+  for (int i = 0; i < info->history_len; ++i) info->history[i] = rc.hist[i];
+  info->seconds = seconds;
 }
 
 FieldDesc to_desc(const cc_field* f) {
@@ -505,6 +688,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (!(prm->omega > 0 && prm->omega < 2)) fail(CC_EINVAL, "omega must lie in (0, 2)");
     if (prm->nu1 < 0 || prm->nu2 < 0 || prm->max_iter < 0 || prm->n_min < 8 || prm->leaf_size < 1)
       fail(CC_EINVAL, "bad multigrid parameters");
+    if (prm->precision != CC_FP64 && prm->precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
     for (int a = 0; a < 6; ++a)
       if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
     auto P = std::make_unique<cc_problem>();
@@ -762,7 +946,7 @@ int cc_apply(cc_problem* p, int level, const double* x, double* y) {
     if (!x || !y) fail(CC_EINVAL, "null array");
     DevLevel& D = p->dev[level];
     launch_stencil_apply(D.st, x, y, p->stream);
-    launch_plg_residual(D.plg, nullptr, x, y, 1, p->stream);
+    launch_plg_residual(D.plg, nullptr, x, y, 1, 1, cube(D.st.n), p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -774,8 +958,8 @@ int cc_residual(cc_problem* p, int level, const double* r, const double* x, doub
     if (!r || !x || !s) fail(CC_EINVAL, "null array");
     DevLevel& D = p->dev[level];
     residual(p, level, r, x, s);
-    launch_zero_u64(p->d_norm, p->stream);
-    launch_maxabs(s, (long long)D.st.n * D.st.n * D.st.n, p->d_norm, p->stream);
+    launch_zero_u64(p->d_norm, 1, p->stream);
+    launch_maxabs(s, cube(D.st.n), 1, p->d_norm, p->stream);
     double v = read_norm(p);
     if (maxabs) *maxabs = v;
   });
@@ -788,7 +972,7 @@ int cc_smo1(cc_problem* p, int level, const double* s, double* e) {
     if (!s || !e) fail(CC_EINVAL, "null array");
     DevLevel& D = p->dev[level];
     long long n3 = (long long)D.st.n * D.st.n * D.st.n;
-    launch_smo1(D.st, p->prm.omega, s, e, D.et, p->stream);
+    launch_smo1<double>(D.st, p->prm.omega, s, e, D.et, 1, p->stream);
     HIPCHK(hipMemcpyAsync(e, D.et, n3 * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
   });
@@ -800,7 +984,7 @@ int cc_smo2(cc_problem* p, int level, const double* s, double* e) {
     need_device(p);
     if (!s || !e) fail(CC_EINVAL, "null array");
     if (level == (int)p->lv.size() - 1) fail(CC_EINVAL, "the coarsest level has no LU-correction");
-    smo2(p, level, s, e);
+    smo2<double>(p, p->w64, level, s, e, 1);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -811,7 +995,7 @@ int cc_restrict(cc_problem* p, int level, const double* s, const double* e, doub
     need_device(p);
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!s || !e || !sc) fail(CC_EINVAL, "null array");
-    launch_restrict(p->dev[level].st, p->dev[level + 1].st, s, e, sc, p->stream);
+    launch_restrict<double>(p->dev[level].st, p->dev[level + 1].st, s, e, sc, 1, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -822,7 +1006,7 @@ int cc_prolong_add(cc_problem* p, int level, const double* ec, double* ef) {
     need_device(p);
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!ec || !ef) fail(CC_EINVAL, "null array");
-    launch_prolong_add(p->dev[level].st, p->dev[level + 1].st.n, ec, ef, p->stream);
+    launch_prolong_add<double>(p->dev[level].st, p->dev[level + 1].st.n, ec, ef, 1, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -831,7 +1015,7 @@ int cc_bottom_solve(cc_problem* p, const double* s, double* e) {
   return guard([&] {
     if (!p || !s || !e) fail(CC_EINVAL, "null argument");
     need_device(p);
-    bottom(p, s, e);
+    bottom<double>(p, p->w64, s, e, 1);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -841,7 +1025,7 @@ int cc_vcycle(cc_problem* p, int level, const double* s, double* e) {
     check_level(p, level);
     need_device(p);
     if (!s || !e) fail(CC_EINVAL, "null array");
-    vcycle(p, level, s, e, p->dev[level].et);
+    vcycle<double>(p, p->w64, level, s, e, p->dev[level].et, 1);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -852,54 +1036,15 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
     if (!p || !r || !phi) fail(CC_EINVAL, "null argument");
     need_device(p);
     double t0 = now_s();
-    DevLevel& D0 = p->dev[0];
-    long long n3 = (long long)D0.st.n * D0.st.n * D0.st.n;
-    launch_zero_u64(p->d_norm, p->stream);
-    launch_maxabs(r, n3, p->d_norm, p->stream);
-    double rn = read_norm(p);
-    if (!std::isfinite(rn)) fail(CC_EINVAL, "non-finite right-hand side");
-    launch_mask_unknowns(D0.st, phi, p->stream);
-    residual(p, 0, r, phi, p->s0);
-    launch_zero_u64(p->d_norm, p->stream);
-    launch_maxabs(p->s0, n3, p->d_norm, p->stream);
-    double rel = (rn > 0) ? read_norm(p) / rn : 0.0;
-    int it = 0;
-    std::vector<double> hist = {rel};
-    bool use_graph = p->prm.use_graph != 0;
-    if (use_graph && (p->g_r != r || p->g_phi != phi || !p->gexec)) {
-      if (p->gexec) {
-        (void)hipGraphExecDestroy(p->gexec);
-        (void)hipGraphDestroy(p->graph);
-        p->gexec = nullptr;
-        p->graph = nullptr;
-      }
-      HIPCHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-      outer_step(p, r, phi);
-      HIPCHK(hipStreamEndCapture(p->stream, &p->graph));
-      HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
-      p->g_r = r;
-      p->g_phi = phi;
+    std::vector<SolveRec> rec;
+    if (p->prm.precision == CC_MIXED) {
+      if (p->w32.nb < 1) alloc_work(p, p->w32, 1);
+      solve_loop<float>(p, p->w32, r, phi, 1, rec);
+    } else {
+      solve_loop<double>(p, p->w64, r, phi, 1, rec);
     }
-    while (rel >= p->prm.tol && it < p->prm.max_iter) {
-      if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
-      if (use_graph)
-        HIPCHK(hipGraphLaunch(p->gexec, p->stream));
-      else
-        outer_step(p, r, phi);
-      rel = read_norm(p) / rn;
-      ++it;
-      hist.push_back(rel);
-    }
-    launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
-    if (info) {
-      info->iterations = it;
-      info->rel_residual = rel;
-      info->history_len = (int)std::min<size_t>(hist.size(), CC_HISTORY_MAX);
-      for (int i = 0; i < info->history_len; ++i) info->history[i] = hist[i];
-      info->seconds = now_s() - t0;
-    }
-    conv = (rel < p->prm.tol) ? 1 : 0;
+    fill_info(rec[0], now_s() - t0, info);
+    conv = (rec[0].rel < p->prm.tol) ? 1 : 0;
   });
   if (rc == CC_OK && !conv) {
     set_last_error("max_iter reached before tol");
@@ -908,27 +1053,136 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
   return rc;
 }
 
-int cc_time_smoother(cc_problem* p, int reps, double* ms) {
+int cc_set_precision(cc_problem* p, int precision) {
+  return guard([&] {
+    if (!p) fail(CC_EINVAL, "null problem");
+    if (precision != CC_FP64 && precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
+    p->prm.precision = precision;
+  });
+}
+
+int cc_solve_batched(cc_problem* p, int nrhs, const double* r, double* phi, cc_solve_info* info) {
+  int conv = 1;
+  int rc = guard([&] {
+    if (!p || !r || !phi || nrhs < 1) fail(CC_EINVAL, "bad argument");
+    need_device(p);
+    const long long n3 = cube(p->dev[0].st.n);
+    const int cap = std::min(nrhs, CC_BATCH_MAX);
+    const bool mixed = p->prm.precision == CC_MIXED;
+    if (mixed ? p->wb32.nb < cap : p->wb64.nb < cap) {
+      if (mixed)
+        alloc_work(p, p->wb32, cap);
+      else
+        alloc_work(p, p->wb64, cap);
+    }
+    for (int b0 = 0; b0 < nrhs; b0 += CC_BATCH_MAX) {
+      const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
+      double t0 = now_s();
+      std::vector<SolveRec> rec;
+      if (mixed)
+        solve_loop<float>(p, p->wb32, r + b0 * n3, phi + b0 * n3, nb, rec);
+      else
+        solve_loop<double>(p, p->wb64, r + b0 * n3, phi + b0 * n3, nb, rec);
+      double dt = now_s() - t0;
+      for (int b = 0; b < nb; ++b) {
+        if (info) fill_info(rec[b], dt, info + b0 + b);
+        if (!(rec[b].rel < p->prm.tol)) conv = 0;
+      }
+    }
+  });
+  if (rc == CC_OK && !conv) {
+    set_last_error("max_iter reached before tol for some right-hand side");
+    return CC_ENOCONV;
+  }
+  return rc;
+}
+
+// Algorithmic bytes of one LU-correction sweep pair (forward + backward) of a
+// level with values of `vb` bytes: every stored factor entry once, the
+// right-hand side, intermediate and solution vectors, index lists and the
+// scatter to the grid.
+static double lu_sweep_bytes(const SupernodalLU& F, double vb) {
+  double b = 0.0;
+  for (const SnNode& nd : F.nodes) {
+    const double p = nd.p, q = nd.q;
+    b += vb * (p * p + 2.0 * p * q);          // M (both triangles), V, W
+    b += vb * (2.0 * p) + (vb * 2.0 + 4.0) * q;  // forward: y_F, z_F; y_U update, Uf
+    b += vb * (3.0 * p) + (vb + 4.0) * q + 4.0 * p + 8.0 * p;  // backward: z_F, x_F, x_U, U, var_cell, out
+  }
+  return b;
+}
+
+int cc_time_kernel(cc_problem* p, int which, int reps, double* ms, double* bytes) {
   return guard([&] {
     if (!p || !ms || reps <= 0) fail(CC_EINVAL, "bad argument");
     need_device(p);
     DevLevel& D = p->dev[0];
+    const long long n3 = cube(D.st.n);
+    if ((which == CC_TIME_SMO1_F32 || which == CC_TIME_LU_F32) && p->w32.nb < 1) alloc_work(p, p->w32, 1);
+    std::function<void()> launch;
+    double by = 0.0;
+    double* x0 = p->e0;
+    double* x1 = D.et;
+    switch (which) {
+      case CC_TIME_SMO1:
+        launch = [&] {
+          launch_smo1<double>(D.st, p->prm.omega, p->s0, x0, x1, 1, p->stream);
+          std::swap(x0, x1);
+        };
+        by = 25.0 * n3;
+        break;
+      case CC_TIME_SMO1_F32: {
+        float* a = p->w32.e[0];
+        float* b = p->w32.et[0];
+        const float* s = p->w32.s[0];
+        launch = [&p, &D, a, b, s]() mutable {
+          launch_smo1<float>(D.st, p->prm.omega, s, a, b, 1, p->stream);
+          std::swap(a, b);
+        };
+        by = 13.0 * n3;
+        break;
+      }
+      case CC_TIME_LU:
+      case CC_TIME_LU_F32: {
+        if ((int)p->dev.size() < 2) fail(CC_EINVAL, "no LU-correction on a one-level problem");
+        if (which == CC_TIME_LU) {
+          launch = [&] {
+            for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<double>(D.lu.d, D.lu.tasks[h], 1, p->stream);
+            for (int h = D.lu.height; h >= 0; --h)
+              launch_lu_backward<double, double>(D.lu.d, D.lu.tasks[h], D.et, n3, 1, p->stream);
+          };
+          by = lu_sweep_bytes(p->lu[0], 8.0);
+        } else {
+          const LuDev F = p->w32.lu[0];
+          float* out = p->w32.et[0];
+          launch = [&p, &D, F, out] {
+            for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<float>(F, D.lu.tasks[h], 1, p->stream);
+            for (int h = D.lu.height; h >= 0; --h)
+              launch_lu_backward<float, float>(F, D.lu.tasks[h], out, cube(D.st.n), 1, p->stream);
+          };
+          by = lu_sweep_bytes(p->lu[0], 4.0);
+        }
+        break;
+      }
+      case CC_TIME_COPY:
+        launch = [&] { launch_copy(n3, p->s0, p->e0, p->stream); };
+        by = 16.0 * n3;
+        break;
+      default:
+        fail(CC_EINVAL, "unknown kernel id");
+    }
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
-    double* x0 = p->e0;
-    double* x1 = D.et;
-    launch_smo1(D.st, p->prm.omega, p->s0, x0, x1, p->stream);
+    launch();
     HIPCHK(hipEventRecord(a, p->stream));
-    for (int i = 0; i < reps; ++i) {
-      launch_smo1(D.st, p->prm.omega, p->s0, x0, x1, p->stream);
-      std::swap(x0, x1);
-    }
+    for (int i = 0; i < reps; ++i) launch();
     HIPCHK(hipEventRecord(b, p->stream));
     HIPCHK(hipEventSynchronize(b));
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, a, b));
     *ms = t / reps;
+    if (bytes) *bytes = by;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
   });
@@ -939,8 +1193,10 @@ void cc_destroy(cc_problem* p) {
   if (p->device >= 0) {
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->w64.drop_graph();
+    p->w32.release();
+    p->wb64.release();
+    p->wb32.release();
     p->buf.release();
     if (p->own_stream) (void)hipStreamDestroy(p->stream);
   }

@@ -32,60 +32,65 @@ __device__ __forceinline__ double wave_max(double v) {
 // One axis of the assembled regular row (times 12 h^2): the 5-point
 // fourth-order stencil, with the ghost-substituted forms in the two cell layers
 // next to a Dirichlet (bc 0) or Neumann (bc 1) wall.  Adds the diagonal to diag.
-__device__ __forceinline__ double axis_op(const double* __restrict__ x, long c, long s, int t, int n,
-                                          int blo, int bhi, double& diag) {
+template <class T>
+__device__ __forceinline__ T axis_op(const T* __restrict__ x, long c, long s, int t, int n, int blo, int bhi,
+                                     T& diag) {
   if (t >= 2 && t <= n - 3) {
-    diag += -30.0;
-    return -x[c - 2 * s] + 16.0 * x[c - s] - 30.0 * x[c] + 16.0 * x[c + s] - x[c + 2 * s];
+    diag += T(-30.0);
+    return -x[c - 2 * s] + T(16.0) * x[c - s] - T(30.0) * x[c] + T(16.0) * x[c + s] - x[c + 2 * s];
   }
   if (t == n - 1) {
     if (bhi == 0) {
-      diag += -1087.0 / 12.0;
-      return (21.0 * x[c - 3 * s] - 139.0 * x[c - 2 * s] + 545.0 * x[c - s] - 1087.0 * x[c]) / 12.0;
+      diag += T(-1087.0 / 12.0);
+      return (T(21.0) * x[c - 3 * s] - T(139.0) * x[c - 2 * s] + T(545.0) * x[c - s] - T(1087.0) * x[c]) /
+             T(12.0);
     }
-    diag += -14.5;
-    return 0.1 * x[c - 3 * s] - 1.5 * x[c - 2 * s] + 15.9 * x[c - s] - 14.5 * x[c];
+    diag += T(-14.5);
+    return T(0.1) * x[c - 3 * s] - T(1.5) * x[c - 2 * s] + T(15.9) * x[c - s] - T(14.5) * x[c];
   }
   if (t == n - 2) {
     if (bhi == 0) {
-      diag += -403.0 / 12.0;
-      return (-15.0 * x[c - 2 * s] + 209.0 * x[c - s] - 403.0 * x[c] + 269.0 * x[c + s]) / 12.0;
+      diag += T(-403.0 / 12.0);
+      return (T(-15.0) * x[c - 2 * s] + T(209.0) * x[c - s] - T(403.0) * x[c] + T(269.0) * x[c + s]) / T(12.0);
     }
-    diag += -30.9;
-    return -1.1 * x[c - 2 * s] + 16.5 * x[c - s] - 30.9 * x[c] + 15.5 * x[c + s];
+    diag += T(-30.9);
+    return T(-1.1) * x[c - 2 * s] + T(16.5) * x[c - s] - T(30.9) * x[c] + T(15.5) * x[c + s];
   }
   if (t == 0) {
     if (blo == 0) {
-      diag += -1087.0 / 12.0;
-      return (21.0 * x[c + 3 * s] - 139.0 * x[c + 2 * s] + 545.0 * x[c + s] - 1087.0 * x[c]) / 12.0;
+      diag += T(-1087.0 / 12.0);
+      return (T(21.0) * x[c + 3 * s] - T(139.0) * x[c + 2 * s] + T(545.0) * x[c + s] - T(1087.0) * x[c]) /
+             T(12.0);
     }
-    diag += -14.5;
-    return 0.1 * x[c + 3 * s] - 1.5 * x[c + 2 * s] + 15.9 * x[c + s] - 14.5 * x[c];
+    diag += T(-14.5);
+    return T(0.1) * x[c + 3 * s] - T(1.5) * x[c + 2 * s] + T(15.9) * x[c + s] - T(14.5) * x[c];
   }
   // t == 1
   if (blo == 0) {
-    diag += -403.0 / 12.0;
-    return (-15.0 * x[c + 2 * s] + 209.0 * x[c + s] - 403.0 * x[c] + 269.0 * x[c - s]) / 12.0;
+    diag += T(-403.0 / 12.0);
+    return (T(-15.0) * x[c + 2 * s] + T(209.0) * x[c + s] - T(403.0) * x[c] + T(269.0) * x[c - s]) / T(12.0);
   }
-  diag += -30.9;
-  return -1.1 * x[c + 2 * s] + 16.5 * x[c + s] - 30.9 * x[c] + 15.5 * x[c - s];
+  diag += T(-30.9);
+  return T(-1.1) * x[c + 2 * s] + T(16.5) * x[c + s] - T(30.9) * x[c] + T(15.5) * x[c - s];
 }
 
 // (L x)_c * 12 h^2 for a phi_1 cell and its diagonal.
-__device__ __forceinline__ double regular_row(const StencilLevel& L, const double* __restrict__ x, int i,
-                                              int j, int k, long c, double& diag) {
+template <class T>
+__device__ __forceinline__ T regular_row(const StencilLevel& L, const T* __restrict__ x, int i, int j, int k,
+                                         long c, T& diag) {
   const int n = L.n;
   const long nn = (long)n * n;
-  diag = 0.0;
-  double a = axis_op(x, c, 1, i, n, L.bc[0], L.bc[1], diag);
-  a += axis_op(x, c, n, j, n, L.bc[2], L.bc[3], diag);
-  a += axis_op(x, c, nn, k, n, L.bc[4], L.bc[5], diag);
+  diag = T(0);
+  T a = axis_op<T>(x, c, 1, i, n, L.bc[0], L.bc[1], diag);
+  a += axis_op<T>(x, c, n, j, n, L.bc[2], L.bc[3], diag);
+  a += axis_op<T>(x, c, nn, k, n, L.bc[4], L.bc[5], diag);
   return a;
 }
 
 // 1D grid over 64 x 4 x 1 cell tiles, z fastest: concurrently resident blocks
 // work on a narrow range of (x, y) columns, so the +-2 z-neighbour planes are
-// re-read from cache (measured faster than x- or y-fastest orders).
+// re-read from cache (measured faster than x- or y-fastest orders).  The batch
+// index is blockIdx.y.
 __device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
   const int b = blockIdx.x;
   k = b % n;
@@ -94,19 +99,26 @@ __device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
   j = (r % ny) * 4 + threadIdx.y;
   i = (r / ny) * 64 + threadIdx.x;
 }
+__device__ __forceinline__ long long batch_off(int n) { return (long long)blockIdx.y * n * n * n; }
 
-__global__ void k_smo1(StencilLevel L, double omega, const double* __restrict__ s, const double* __restrict__ ein,
-                       double* __restrict__ eout) {
+template <class T>
+__global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T* __restrict__ ein,
+                       T* __restrict__ eout) {
   const int n = L.n;
   int i, j, k;
   tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
+  const long long o = batch_off(n);
+  s += o;
+  ein += o;
+  eout += o;
   long c = i + (long)n * (j + (long)n * k);
-  double v = ein[c];
+  T v = ein[c];
   if (L.type[c] == 1) {
-    double diag;
-    double a = regular_row(L, ein, i, j, k, c, diag);
-    v += omega * (s[c] - a * L.inv12h2) / (diag * L.inv12h2);
+    T diag;
+    const T inv = T(L.inv12h2);
+    T a = regular_row<T>(L, ein, i, j, k, c, diag);
+    v += omega * (s[c] - a * inv) / (diag * inv);
   }
   eout[c] = v;
 }
@@ -117,20 +129,39 @@ __global__ void k_stencil_residual(StencilLevel L, const double* __restrict__ r,
   int i, j, k;
   tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
+  const long long o = batch_off(n);
+  x += o;
+  s += o;
+  if (!apply) r += o;
   long c = i + (long)n * (j + (long)n * k);
   double v = 0.0;
   if (L.type[c] == 1) {
     double diag;
-    double a = regular_row(L, x, i, j, k, c, diag) * L.inv12h2;
+    double a = regular_row<double>(L, x, i, j, k, c, diag) * L.inv12h2;
     v = apply ? a : r[c] - a;
   }
   s[c] = v;
 }
 
+template <class T>
+__device__ __forceinline__ const T* plg_vals(const PlgRows& P);
+template <>
+__device__ __forceinline__ const double* plg_vals<double>(const PlgRows& P) {
+  return P.vals;
+}
+template <>
+__device__ __forceinline__ const float* plg_vals<float>(const PlgRows& P) {
+  return P.vals32;
+}
+
 __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const double* __restrict__ x,
-                               double* __restrict__ s, int apply) {
+                               double* __restrict__ s, int apply, long long stride) {
   int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= P.N2) return;
+  const long long o = (long long)blockIdx.y * stride;
+  x += o;
+  s += o;
+  if (!apply) r += o;
   double a = 0.0;
 #pragma unroll 5
   for (int t = 0; t < 35; ++t) a += P.vals[(long)t * P.N2 + row] * x[P.cols[(long)t * P.N2 + row]];
@@ -138,64 +169,103 @@ __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const do
   s[c] = apply ? a : r[c] - a;
 }
 
-__global__ void k_plg_b2(PlgRows P, const double* __restrict__ s, const double* __restrict__ e,
-                         double* __restrict__ y) {
+// b_2 = s_2 - L21 e_1 of every FV-PLG row, written in factorization order
+// (y[position * nb + batch]).
+template <class T>
+__global__ void k_plg_b2(PlgRows P, const T* __restrict__ s, const T* __restrict__ e, T* __restrict__ y,
+                         long long stride) {
   int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= P.N2) return;
+  const int b = blockIdx.y, nb = gridDim.y;
+  s += b * stride;
+  e += b * stride;
+  const T* vals = plg_vals<T>(P);
   uint64_t m = P.phi2[row];
-  double a = 0.0;
+  T a = T(0);
   for (int t = 0; t < 35; ++t)
-    if (!((m >> t) & 1ull)) a += P.vals[(long)t * P.N2 + row] * e[P.cols[(long)t * P.N2 + row]];
-  y[P.nd[row]] = s[P.cell[row]] - a;
+    if (!((m >> t) & 1ull)) a += vals[(long)t * P.N2 + row] * e[P.cols[(long)t * P.N2 + row]];
+  y[(long long)P.nd[row] * nb + b] = s[P.cell[row]] - a;
 }
 
 // coarse cell = 2^-3 sum over its 8 children of (s - L e) on phi_1 children
-__global__ void k_restrict(StencilLevel F, StencilLevel C, const double* __restrict__ s,
-                           const double* __restrict__ e, double* __restrict__ sc) {
+template <class T>
+__global__ void k_restrict(StencilLevel F, StencilLevel C, const T* __restrict__ s, const T* __restrict__ e,
+                           T* __restrict__ sc) {
   const int nc = C.n, nf = F.n;
   int I, J, K;
   tile_ijk(nc, I, J, K);
   if (I >= nc || J >= nc) return;
+  const long long of = batch_off(nf);
+  s += of;
+  e += of;
+  sc += batch_off(nc);
   long cc = I + (long)nc * (J + (long)nc * K);
-  double acc = 0.0;
+  T acc = T(0);
   if (C.type[cc] != 0) {
+    const T inv = T(F.inv12h2);
     for (int dz = 0; dz < 2; ++dz)
       for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx) {
           int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
           long c = i + (long)nf * (j + (long)nf * k);
           if (F.type[c] != 1) continue;
-          double diag;
-          acc += s[c] - regular_row(F, e, i, j, k, c, diag) * F.inv12h2;
+          T diag;
+          acc += s[c] - regular_row<T>(F, e, i, j, k, c, diag) * inv;
         }
   }
-  sc[cc] = 0.125 * acc;
+  sc[cc] = T(0.125) * acc;
 }
 
-__global__ void k_prolong_add(StencilLevel F, int nc, const double* __restrict__ ec, double* __restrict__ ef) {
+template <class T>
+__global__ void k_prolong_add(StencilLevel F, int nc, const T* __restrict__ ec, T* __restrict__ ef) {
   const int n = F.n;
   int i, j, k;
   tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
+  ef += batch_off(n);
+  ec += batch_off(nc);
   long c = i + (long)n * (j + (long)n * k);
   if (F.type[c] == 1) ef[c] += ec[(i >> 1) + (long)nc * ((j >> 1) + (long)nc * (k >> 1))];
 }
 
-__global__ void k_gather(int n, const int* __restrict__ var_cell, const double* __restrict__ src,
-                         double* __restrict__ y) {
+template <class TS, class TY>
+__global__ void k_gather(int n, const int* __restrict__ cell, const TS* __restrict__ src, long long stride,
+                         TY* __restrict__ y) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) y[v] = src[var_cell[v]];
+  const int b = blockIdx.y, nb = gridDim.y;
+  if (v < n) y[(long long)v * nb + b] = TY(src[b * stride + cell[v]]);
 }
 
-// Supernodal sweeps.  Rows of every node are stored row-major; the node's
-// equations are numbered in pivot order, so its right-hand side is contiguous.
-// A task is one wavefront handling 64/g rows of one node with g lanes per row:
-// (node, first row, log2 g).
+// ---------------------------------------------------------------- factorizations
+// Rows of every node are stored row-major; the node's equations are numbered
+// in pivot order, so its right-hand side is contiguous.
+
+template <class T>
+struct LuArr;
+template <>
+struct LuArr<double> {
+  __device__ static const double* M(const LuDev& F) { return F.M; }
+  __device__ static const double* V(const LuDev& F) { return F.V; }
+  __device__ static const double* W(const LuDev& F) { return F.W; }
+  __device__ static double* y(const LuDev& F) { return F.y; }
+  __device__ static double* z(const LuDev& F) { return F.z; }
+  __device__ static double* x(const LuDev& F) { return F.x; }
+};
+template <>
+struct LuArr<float> {
+  __device__ static const float* M(const LuDev& F) { return F.M32; }
+  __device__ static const float* V(const LuDev& F) { return F.V32; }
+  __device__ static const float* W(const LuDev& F) { return F.W32; }
+  __device__ static float* y(const LuDev& F) { return F.y32; }
+  __device__ static float* z(const LuDev& F) { return F.z32; }
+  __device__ static float* x(const LuDev& F) { return F.x32; }
+};
 
 // acc += sum_{j in [j0, j1), j = gl mod g} a[j] * b[j], four independent chains
-__device__ __forceinline__ double lane_dot(const double* __restrict__ a, const double* __restrict__ b, int j0,
-                                           int j1, int gl, int g) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+template <class T>
+__device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restrict__ b, int j0, int j1, int gl,
+                                      int g) {
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
   int j = j0 + gl;
   for (; j + 3 * g < j1; j += 4 * g) {
     s0 += a[j] * b[j];
@@ -207,101 +277,289 @@ __device__ __forceinline__ double lane_dot(const double* __restrict__ a, const d
   return (s0 + s1) + (s2 + s3);
 }
 
-// Forward sweep of one height: z_F = L11^-1 y_F on the node's rows, and
-// y_U -= (L21 L11^-1) y_F accumulated atomically into the later equations.
-__global__ void k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks) {
-  int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  int lane = threadIdx.x % kWave;
-  if (wave >= ntasks) return;
-  const LuTask t = tasks[wave];
-  const int lg = t.lg, g = 1 << lg;
-  const int sub = lane >> lg, gl = lane & (g - 1);
-  const int p = t.p, q = t.q, base = t.base;
-  const int i = t.row0 + sub;
-  const bool valid = i < p + q;
-  const double* yF = F.y + base;
-  double acc = 0.0;
-  if (valid) {
-    if (i < p)
-      acc = lane_dot(F.M + t.offM + (long)i * p, yF, 0, i, gl, g);
-    else
-      acc = lane_dot(F.V + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
-  }
-  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (valid && gl == 0) {
-    if (i < p)
-      F.z[base + i] = acc + yF[i];
-    else
-      atomicAdd(&F.y[F.Uf[t.offU + (i - p)]], -acc);
-  }
-}
-
-// Backward sweep of one height: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered
-// to the grid array `out` through var_cell.
-__global__ void k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, double* __restrict__ out) {
-  int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  int lane = threadIdx.x % kWave;
-  if (wave >= ntasks) return;
-  const LuTask t = tasks[wave];
-  const int lg = t.lg, g = 1 << lg;
-  const int sub = lane >> lg, gl = lane & (g - 1);
-  const int p = t.p, q = t.q, base = t.base;
-  const int i = t.row0 + sub;
-  const bool valid = i < p;
-  double acc = 0.0;
-  if (valid) {
-    acc = lane_dot(F.M + t.offM + (long)i * p, F.z + base, i, p, gl, g);
-    if (q > 0) {
-      const double* Wr = F.W + t.offVW + (long)i * q;
-      const int* U = F.U + t.offU;
-      double s0 = 0.0, s1 = 0.0;
-      int j = gl;
-      for (; j + g < q; j += 2 * g) {
-        s0 += Wr[j] * F.x[U[j]];
-        s1 += Wr[j + g] * F.x[U[j + g]];
-      }
-      for (; j < q; j += g) s0 += Wr[j] * F.x[U[j]];
-      acc -= s0 + s1;
+// Single right-hand side: a task takes 64/g rows of one node, g lanes per row.
+// Forward: z_F = L11^-1 y_F on the node's rows, and y_U -= (L21 L11^-1) y_F
+// accumulated atomically into the later equations.
+template <class T>
+__global__ void __launch_bounds__(256) k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks) {
+  const int lane = threadIdx.x % kWave;
+  T* y = LuArr<T>::y(F);
+  {
+    const int ti = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (ti >= ntasks) return;
+    const LuTask t = tasks[ti];
+    const int lg = t.lg, g = 1 << lg;
+    const int sub = lane >> lg, gl = lane & (g - 1);
+    const int p = t.p, q = t.q, base = t.base;
+    const int i = t.row0 + sub;
+    const bool valid = i < p + q;
+    const T* yF = y + base;
+    T acc = T(0);
+    if (valid) {
+      if (i < p)
+        acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, yF, 0, i, gl, g);
+      else
+        acc = lane_dot<T>(LuArr<T>::V(F) + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
+    }
+    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (valid && gl == 0) {
+      if (i < p)
+        LuArr<T>::z(F)[base + i] = acc + yF[i];
+      else
+        atomicAdd(&y[F.Uf[t.offU + (i - p)]], -acc);
     }
   }
-  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (valid && gl == 0) {
-    F.x[base + i] = acc;
-    out[F.var_cell[base + i]] = acc;
+}
+
+// Backward: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered to the grid array
+// `out` through var_cell.
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks,
+                                                     TO* __restrict__ out) {
+  const int lane = threadIdx.x % kWave;
+  T* x = LuArr<T>::x(F);
+  {
+    const int ti = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (ti >= ntasks) return;
+    const LuTask t = tasks[ti];
+    const int lg = t.lg, g = 1 << lg;
+    const int sub = lane >> lg, gl = lane & (g - 1);
+    const int p = t.p, q = t.q, base = t.base;
+    const int i = t.row0 + sub;
+    const bool valid = i < p;
+    T acc = T(0);
+    if (valid) {
+      acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, LuArr<T>::z(F) + base, i, p, gl, g);
+      if (q > 0) {
+        const T* Wr = LuArr<T>::W(F) + t.offVW + (long)i * q;
+        const int* U = F.U + t.offU;
+        T s0 = T(0), s1 = T(0);
+        int j = gl;
+        for (; j + g < q; j += 2 * g) {
+          s0 += Wr[j] * x[U[j]];
+          s1 += Wr[j + g] * x[U[j + g]];
+        }
+        for (; j < q; j += g) s0 += Wr[j] * x[U[j]];
+        acc -= s0 + s1;
+      }
+    }
+    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (valid && gl == 0) {
+      x[base + i] = acc;
+      out[F.var_cell[base + i]] = TO(acc);
+    }
   }
 }
 
-__global__ void k_zero(double* p, long long count) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (; i < count; i += stride) p[i] = 0.0;
+// Several right-hand sides (nb <= 64): a task takes up to kMrRows rows of one
+// node; lane b works on right-hand side b.  The rows' entries are read 64 at a
+// time, coalesced, and broadcast lane by lane, so every factor entry is read
+// once for all right-hand sides; vector values are loaded 16 at a time so that
+// their latencies overlap.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+constexpr int kMrBlock = 16;
+
+// acc[r] += sum over the chunk's jn entries of ch[r](lane jj) * vec(jj); vec(jj)
+// is v[jj * nb] for lanes < nb.  Entries jj >= jn have ch == 0.
+template <class T>
+__device__ __forceinline__ void mr_chunk(const T (&ch)[kMrRows], const T* __restrict__ v, int nb, int jn, bool act,
+                                         T (&acc)[kMrRows]) {
+  for (int jb = 0; jb < jn; jb += kMrBlock) {
+    T vv[kMrBlock];
+#pragma unroll
+    for (int u = 0; u < kMrBlock; ++u) vv[u] = (act && jb + u < jn) ? v[(long long)(jb + u) * nb] : T(0);
+#pragma unroll
+    for (int u = 0; u < kMrBlock; ++u)
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) acc[r] += lane_bcast(ch[r], jb + u) * vv[u];
+  }
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+template <class T>
+__global__ void __launch_bounds__(256) k_lu_forward_mr(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb) {
+  const int lane = threadIdx.x % kWave;
+  const bool act = lane < nb;
+  T* y = LuArr<T>::y(F);
+  {
+    const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    if (ti >= ntasks) return;
+    const LuTask t = tasks[ti];
+    const int p = t.p, q = t.q, base = t.base;
+    const T* M = LuArr<T>::M(F) + t.offM;
+    const T* V = LuArr<T>::V(F) + t.offVW;
+    const T* ptr[kMrRows];
+    int end[kMrRows];
+    T acc[kMrRows];
+    int jmax = 0;
+#pragma unroll
+    for (int r = 0; r < kMrRows; ++r) {
+      const int i = t.row0 + r;
+      acc[r] = T(0);
+      if (i < p) {
+        ptr[r] = M + (long)i * p;
+        end[r] = i;
+      } else if (i < p + q) {
+        ptr[r] = V + (long)(i - p) * p;
+        end[r] = p;
+      } else {
+        ptr[r] = M;
+        end[r] = 0;
+      }
+      jmax = max(jmax, end[r]);
+    }
+    for (int j0 = 0; j0 < jmax; j0 += kWave) {
+      T ch[kMrRows];
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) ch[r] = (j0 + lane < end[r]) ? ptr[r][j0 + lane] : T(0);
+      mr_chunk<T>(ch, y + (long long)(base + j0) * nb + lane, nb, min(kWave, jmax - j0), act, acc);
+    }
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) {
+        const int i = t.row0 + r;
+        if (i < p)
+          LuArr<T>::z(F)[(long long)(base + i) * nb + lane] = acc[r] + y[(long long)(base + i) * nb + lane];
+        else if (i < p + q)
+          atomicAdd(&y[(long long)F.Uf[t.offU + (i - p)] * nb + lane], -acc[r]);
+      }
+    }
+  }
+}
 
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_lu_backward_mr(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb,
+                                                        TO* __restrict__ out, long long ostride) {
+  const int lane = threadIdx.x % kWave;
+  const bool act = lane < nb;
+  const T* z = LuArr<T>::z(F);
+  T* x = LuArr<T>::x(F);
+  {
+    const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    if (ti >= ntasks) return;
+    const LuTask t = tasks[ti];
+    const int p = t.p, q = t.q, base = t.base;
+    const T* M = LuArr<T>::M(F) + t.offM;
+    const T* W = LuArr<T>::W(F) + t.offVW;
+    const int* U = F.U + t.offU;
+    T acc[kMrRows];
+#pragma unroll
+    for (int r = 0; r < kMrRows; ++r) acc[r] = T(0);
+    // U11^-1 z_F: row i uses columns [i, p)
+    for (int j0 = t.row0; j0 < p; j0 += kWave) {
+      T ch[kMrRows];
+      const int j = j0 + lane;
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) {
+        const int i = t.row0 + r;
+        ch[r] = (i < p && j >= i && j < p) ? M[(long)i * p + j] : T(0);
+      }
+      mr_chunk<T>(ch, z + (long long)(base + j0) * nb + lane, nb, min(kWave, p - j0), act, acc);
+    }
+    // - (U11^-1 U12) x_U
+    for (int j0 = 0; j0 < q; j0 += kWave) {
+      T ch[kMrRows];
+      const int j = j0 + lane;
+      const int uj = (j < q) ? U[j] : 0;
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) {
+        const int i = t.row0 + r;
+        ch[r] = (i < p && j < q) ? -W[(long)i * q + j] : T(0);
+      }
+      const int jn = min(kWave, q - j0);
+      for (int jb = 0; jb < jn; jb += kMrBlock) {
+        T vv[kMrBlock];
+#pragma unroll
+        for (int u = 0; u < kMrBlock; ++u) {
+          const int uu = lane_bcast(uj, jb + u);
+          vv[u] = (act && jb + u < jn) ? x[(long long)uu * nb + lane] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kMrBlock; ++u)
+#pragma unroll
+          for (int r = 0; r < kMrRows; ++r) acc[r] += lane_bcast(ch[r], jb + u) * vv[u];
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < kMrRows; ++r) {
+        const int i = t.row0 + r;
+        if (i < p) {
+          x[(long long)(base + i) * nb + lane] = acc[r];
+          out[lane * ostride + F.var_cell[base + i]] = TO(acc[r]);
+        }
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ void k_zero(T* p, long long count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = T(0);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+// per-batch max |v| as the bit pattern of a non-negative double (ordered like
+// unsigned integers), combined with atomicMax
 __global__ void k_maxabs(const double* __restrict__ v, long long count, unsigned long long* out) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long stride = (long long)gridDim.x * blockDim.x;
+  v += (long long)blockIdx.y * count;
   double m = 0.0;
   for (; i < count; i += stride) m = fmax(m, fabs(v[i]));
   m = wave_max(m);
-  if (threadIdx.x % kWave == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  if (threadIdx.x % kWave == 0) atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
 }
 
-__global__ void k_add_unknowns(StencilLevel L, const double* __restrict__ e, double* __restrict__ phi) {
+__device__ __forceinline__ double norm_value(const unsigned long long* norm, int b) {
+  return norm ? __longlong_as_double((long long)norm[b]) : 1.0;
+}
+
+template <class T>
+__global__ void k_add_unknowns(StencilLevel L, const T* __restrict__ e, const unsigned long long* __restrict__ norm,
+                               double* __restrict__ phi) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long n3 = (long long)L.n * L.n * L.n;
-  if (c < n3 && L.type[c] != 0) phi[c] += e[c];
+  if (c >= n3 || L.type[c] == 0) return;
+  const int b = blockIdx.y;
+  const double sc = norm_value(norm, b);
+  phi[b * n3 + c] += sc * (double)e[b * n3 + c];
+}
+
+template <class T>
+__global__ void k_scale_residual(long long n3, const double* __restrict__ s, const unsigned long long* __restrict__ norm,
+                                 T* __restrict__ d) {
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n3) return;
+  const int b = blockIdx.y;
+  const double nv = norm_value(norm, b);
+  const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
+  d[b * n3 + c] = T(s[b * n3 + c] * inv);
 }
 
 __global__ void k_mask_unknowns(StencilLevel L, double* __restrict__ a) {
   long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long n3 = (long long)L.n * L.n * L.n;
-  if (c < n3 && L.type[c] == 0) a[c] = 0.0;
+  if (c < n3 && L.type[c] == 0) a[blockIdx.y * n3 + c] = 0.0;
 }
 
-__global__ void k_copy_pairs(int count, const int2* __restrict__ pairs, double* __restrict__ a) {
+__global__ void k_copy_pairs(int count, const int2* __restrict__ pairs, double* __restrict__ a, long long stride) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  a += blockIdx.y * stride;
   if (t < count) a[pairs[t].x] = a[pairs[t].y];
 }
 
@@ -309,6 +567,13 @@ __global__ void k_set_values(int count, const int* __restrict__ cells, const dou
                              double* __restrict__ a) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) a[cells[t]] = vals[t];
+}
+
+// plain copy (used to calibrate memory-traffic counters against a known size)
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long count) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) dst[i] = src[i];
 }
 
 struct GaussQ {
@@ -339,78 +604,106 @@ __global__ void k_cell_average(int n, double h, double ox, double oy, double oz,
 }
 
 inline dim3 grid3(int n) { return dim3((n + 63) / 64, (n + 3) / 4, n); }
-inline dim3 grid_tiles(int n) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n); }
+inline dim3 grid_tiles(int n, int nb = 1) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n, nb); }
 const dim3 kBlock3(64, 4, 1);
 inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs); }
+inline long long cube(int n) { return (long long)n * n * n; }
 
 }  // namespace
 
-void launch_smo1(const StencilLevel& L, double omega, const double* s, const double* e_in, double* e_out,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_smo1, grid_tiles(L.n), kBlock3, 0, st, L, omega, s, e_in, e_out);
+template <class T>
+void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_smo1<T>, grid_tiles(L.n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
 }
-void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, r, x, s, 0);
+void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, int nb,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n, nb), kBlock3, 0, st, L, r, x, s, 0);
 }
 void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
 }
-void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only,
-                         hipStream_t st) {
+void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only, int nb,
+                         long long stride, hipStream_t st) {
   if (P.N2 == 0) return;
-  hipLaunchKernelGGL(k_plg_residual, dim3(blocks(P.N2, 256)), dim3(256), 0, st, P, r, x, s, apply_only);
+  hipLaunchKernelGGL(k_plg_residual, dim3(blocks(P.N2, 256), nb), dim3(256), 0, st, P, r, x, s, apply_only, stride);
 }
-void launch_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, const double* e, double* sc,
+template <class T>
+void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict, grid_tiles(C.n), kBlock3, 0, st, F, C, s, e, sc);
+  hipLaunchKernelGGL(k_restrict<T>, grid_tiles(C.n, nb), kBlock3, 0, st, F, C, s, e, sc);
 }
-void launch_prolong_add(const StencilLevel& F, int nc, const double* ec, double* ef, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong_add, grid_tiles(F.n), kBlock3, 0, st, F, nc, ec, ef);
+template <class T>
+void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_add<T>, grid_tiles(F.n, nb), kBlock3, 0, st, F, nc, ec, ef);
 }
-void launch_plg_b2(const PlgRows& P, const double* s, const double* e, double* y, hipStream_t st) {
+template <class T>
+void launch_plg_b2(const PlgRows& P, const T* s, const T* e, T* y, long long stride, int nb, hipStream_t st) {
   if (P.N2 == 0) return;
-  hipLaunchKernelGGL(k_plg_b2, dim3(blocks(P.N2, 256)), dim3(256), 0, st, P, s, e, y);
+  hipLaunchKernelGGL(k_plg_b2<T>, dim3(blocks(P.N2, 256), nb), dim3(256), 0, st, P, s, e, y, stride);
 }
-void launch_gather(int n, const int* var_cell, const double* src, double* y, hipStream_t st) {
+template <class TS, class TY>
+void launch_gather(int n, const int* row_cell, const TS* src, long long src_stride, TY* y, int nb, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gather, dim3(blocks(n, 256)), dim3(256), 0, st, n, var_cell, src, y);
+  hipLaunchKernelGGL((k_gather<TS, TY>), dim3(blocks(n, 256), nb), dim3(256), 0, st, n, row_cell, src, src_stride,
+                     y);
 }
-void launch_lu_forward(const LuDev& F, const LuTasks& T, hipStream_t st) {
-  if (T.nF > 0)
-    hipLaunchKernelGGL(k_lu_forward, dim3(blocks((long long)T.nF * kWave, 256)), dim3(256), 0, st, F, T.ftask, T.nF);
+inline dim3 wave_grid(int ntasks) { return dim3(blocks((long long)ntasks * kWave, 256)); }
+
+template <class T>
+void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st) {
+  if (nb == 1) {
+    if (S.nF > 0) hipLaunchKernelGGL(k_lu_forward<T>, wave_grid(S.nF), dim3(256), 0, st, F, S.ftask, S.nF);
+  } else if (S.nFm > 0) {
+    hipLaunchKernelGGL(k_lu_forward_mr<T>, wave_grid(S.nFm), dim3(256), 0, st, F, S.ftask_m, S.nFm, nb);
+  }
 }
-void launch_lu_backward(const LuDev& F, const LuTasks& T, double* out, hipStream_t st) {
-  if (T.nB == 0) return;
-  hipLaunchKernelGGL(k_lu_backward, dim3(blocks((long long)T.nB * kWave, 256)), dim3(256), 0, st, F, T.btask, T.nB,
-                     out);
+template <class T, class TO>
+void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st) {
+  if (nb == 1) {
+    if (S.nB > 0) hipLaunchKernelGGL((k_lu_backward<T, TO>), wave_grid(S.nB), dim3(256), 0, st, F, S.btask, S.nB, out);
+  } else if (S.nBm > 0) {
+    hipLaunchKernelGGL((k_lu_backward_mr<T, TO>), wave_grid(S.nBm), dim3(256), 0, st, F, S.btask_m, S.nBm, nb, out,
+                       out_stride);
+  }
 }
-void launch_zero(double* p, long long count, hipStream_t st) {
+template <class T>
+void launch_zero(T* p, long long count, hipStream_t st) {
   if (count == 0) return;
   int nb = (int)std::min<long long>(blocks(count, 256), 8192);
-  hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, st, p, count);
+  hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(256), 0, st, p, count);
 }
-void launch_zero_u64(unsigned long long* p, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, p);
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(blocks(count, 64)), dim3(64), 0, st, p, count);
 }
-void launch_maxabs(const double* v, long long count, unsigned long long* out, hipStream_t st) {
-  int nb = (int)std::min<long long>(blocks(count, 256), 2048);
-  hipLaunchKernelGGL(k_maxabs, dim3(nb), dim3(256), 0, st, v, count, out);
+void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, hipStream_t st) {
+  int g = (int)std::min<long long>(blocks(count, 256), 2048);
+  hipLaunchKernelGGL(k_maxabs, dim3(g, nb), dim3(256), 0, st, v, count, out);
 }
-void launch_add_unknowns(const StencilLevel& L, const double* e, double* phi, hipStream_t st) {
-  long long n3 = (long long)L.n * L.n * L.n;
-  hipLaunchKernelGGL(k_add_unknowns, dim3(blocks(n3, 256)), dim3(256), 0, st, L, e, phi);
+template <class T>
+void launch_add_unknowns(const StencilLevel& L, const T* e, const unsigned long long* norm, double* phi, int nb,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_add_unknowns<T>, dim3(blocks(cube(L.n), 256), nb), dim3(256), 0, st, L, e, norm, phi);
 }
-void launch_mask_unknowns(const StencilLevel& L, double* a, hipStream_t st) {
-  long long n3 = (long long)L.n * L.n * L.n;
-  hipLaunchKernelGGL(k_mask_unknowns, dim3(blocks(n3, 256)), dim3(256), 0, st, L, a);
+template <class T>
+void launch_scale_residual(long long n3, const double* s, const unsigned long long* norm, T* d, int nb,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_residual<T>, dim3(blocks(n3, 256), nb), dim3(256), 0, st, n3, s, norm, d);
 }
-void launch_copy_pairs(int count, const int2* pairs, double* a, hipStream_t st) {
+void launch_mask_unknowns(const StencilLevel& L, double* a, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_mask_unknowns, dim3(blocks(cube(L.n), 256), nb), dim3(256), 0, st, L, a);
+}
+void launch_copy_pairs(int count, const int2* pairs, double* a, long long stride, int nb, hipStream_t st) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_copy_pairs, dim3(blocks(count, 256)), dim3(256), 0, st, count, pairs, a);
+  hipLaunchKernelGGL(k_copy_pairs, dim3(blocks(count, 256), nb), dim3(256), 0, st, count, pairs, a, stride);
 }
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_values, dim3(blocks(count, 256)), dim3(256), 0, st, count, cells, vals, a);
+}
+void launch_copy(long long count, const double* src, double* dst, hipStream_t st) {
+  if (count == 0) return;
+  int g = (int)std::min<long long>(blocks(count, 256), 16384);
+  hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, st, src, dst, count);
 }
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q, double* out,
                          hipStream_t st) {
@@ -425,5 +718,27 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
   hipLaunchKernelGGL(k_cell_average, grid3(n), kBlock3, 0, st, n, h, origin[0], origin[1], origin[2], f, mode, G,
                      out);
 }
+
+#define CC_INST(T)                                                                                            \
+  template void launch_smo1<T>(const StencilLevel&, double, const T*, const T*, T*, int, hipStream_t);        \
+  template void launch_restrict<T>(const StencilLevel&, const StencilLevel&, const T*, const T*, T*, int,     \
+                                   hipStream_t);                                                              \
+  template void launch_prolong_add<T>(const StencilLevel&, int, const T*, T*, int, hipStream_t);              \
+  template void launch_plg_b2<T>(const PlgRows&, const T*, const T*, T*, long long, int, hipStream_t);        \
+  template void launch_zero<T>(T*, long long, hipStream_t);                                                   \
+  template void launch_lu_forward<T>(const LuDev&, const LuTasks&, int, hipStream_t);                        \
+  template void launch_add_unknowns<T>(const StencilLevel&, const T*, const unsigned long long*, double*, int, \
+                                       hipStream_t);                                                          \
+  template void launch_scale_residual<T>(long long, const double*, const unsigned long long*, T*, int,        \
+                                         hipStream_t);
+CC_INST(double)
+CC_INST(float)
+#undef CC_INST
+template void launch_lu_backward<double, double>(const LuDev&, const LuTasks&, double*, long long, int,
+                                                 hipStream_t);
+template void launch_lu_backward<double, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
+template void launch_lu_backward<float, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
+template void launch_gather<double, double>(int, const int*, const double*, long long, double*, int, hipStream_t);
+template void launch_gather<float, double>(int, const int*, const float*, long long, double*, int, hipStream_t);
 
 }  // namespace cc

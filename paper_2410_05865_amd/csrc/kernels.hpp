@@ -1,5 +1,8 @@
 // Device kernels of the solve path and their host launchers (all asynchronous on
 // the given stream).  Layout: cell arrays n^3, index i + n (j + n k), x fastest.
+// Batched launches process `nb` arrays at a stride of n^3 elements (leading
+// batch index); vectors of the factorizations hold `nb` values per variable
+// (variable-major, batch fastest).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -23,11 +26,13 @@ struct PlgRows {
   const int* cell;        // N2 target cells
   const int* cols;        // 35 * N2 stencil cells
   const double* vals;     // 35 * N2 coefficients
+  const float* vals32;    // the same rounded to FP32 (mixed precision; may be null)
   const uint64_t* phi2;   // N2 masks: bit j set if entry j is a phi_2 cell
   const int* nd;          // N2: position of row r in the level's factorization order
 };
 
-// Supernodal factors and the per-height task lists of one factorization.
+// Supernodal factors and work vectors of one factorization, in FP64 and (for
+// mixed precision) FP32 copies.
 struct LuDev {
   int n;                 // variables
   const int* var_cell;   // n: grid cell of each variable (ND order)
@@ -35,26 +40,26 @@ struct LuDev {
   const double* M;
   const double* V;
   const double* W;
+  const float* M32;
+  const float* V32;
+  const float* W32;
   const int* U;           // later variables of each node (backward)
   const int* Uf;          // their equation positions in pivot order (forward)
-  const int* nbase;
-  const int* np;
-  const int* nq;
-  const long long* offM;
-  const long long* offV;
-  const long long* offW;
-  const long long* offU;
-  const long long* offPiv;
-  double* y;             // work vectors (n)
+  double* y;              // work vectors, n * nb values (FP64)
   double* z;
   double* x;
+  float* y32;             // FP32 work vectors
+  float* z32;
+  float* x32;
 };
 
-// Task lists of one height.  A task is one wavefront: (node, first row,
-// log2 g, unused) taking 64/g rows with g lanes per row.  Forward rows are those
-// of [L11^-1 ; L21 L11^-1] (p + q rows); their L21 part is accumulated
-// atomically into the later equations.  Backward rows are those of
-// [U11^-1 | U11^-1 U12] (p rows).
+// Task lists of one height of a factorization's tree (the heights run as
+// successive launches).  A single-RHS task is one wavefront taking 64/g rows
+// of one node with g lanes per row (lg = log2 g); a multi-RHS task is one
+// wavefront taking up to kMrRows rows of one node, one lane per right-hand
+// side.  Forward rows are those of [L11^-1 ; L21 L11^-1] (p + q rows), whose
+// L21 part is accumulated atomically into the later equations; backward rows
+// are those of [U11^-1 | U11^-1 U12] (p rows).
 struct LuTask {
   long long offM;         // node's M block
   long long offVW;        // node's V block (forward) or W block (backward)
@@ -62,34 +67,62 @@ struct LuTask {
   int base, p, q;         // node's first variable, size, later variables
   int row0, lg, pad;      // first row of this task, log2 lanes per row
 };
+constexpr int kMrRows = 4;
 struct LuTasks {
-  int nF;                 // forward tasks
+  int nF, nB;             // single-RHS forward / backward tasks
   const LuTask* ftask;
-  int nB;                 // backward tasks
   const LuTask* btask;
+  int nFm, nBm;           // multi-RHS forward / backward tasks
+  const LuTask* ftask_m;
+  const LuTask* btask_m;
 };
 
-void launch_smo1(const StencilLevel& L, double omega, const double* s, const double* e_in, double* e_out,
-                 hipStream_t st);
-void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, hipStream_t st);
+// ---- stencil work (T = double or float), nb arrays at stride n^3
+template <class T>
+void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st);
+template <class T>
+void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
+                     hipStream_t st);
+template <class T>
+void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int nb, hipStream_t st);
+template <class T>
+void launch_plg_b2(const PlgRows& P, const T* s, const T* e, T* y, long long stride, int nb, hipStream_t st);
+template <class T>
+void launch_zero(T* p, long long count, hipStream_t st);
+
+// ---- FP64 outer residual and apply
+void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, int nb,
+                             hipStream_t st);
 void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hipStream_t st);
-void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only,
+void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only, int nb,
+                         long long stride, hipStream_t st);
+
+// ---- factorizations: T is the factor and work-vector type, TO the output array
+// type.  y (work vector) gathers src at the stored equation cells.
+template <class TS, class TY>
+void launch_gather(int n, const int* row_cell, const TS* src, long long src_stride, TY* y, int nb, hipStream_t st);
+template <class T>
+void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st);
+template <class T, class TO>
+void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st);
+
+// ---- norms, updates, fills (nb arrays; norms are nb u64 bit patterns of
+// non-negative doubles, combined by atomicMax)
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
+void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, hipStream_t st);
+// phi += scale_b * e on unknown cells; scale_b = norm[b] (or 1 if norm is null)
+template <class T>
+void launch_add_unknowns(const StencilLevel& L, const T* e, const unsigned long long* norm, double* phi, int nb,
                          hipStream_t st);
-void launch_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, const double* e,
-                     double* sc, hipStream_t st);
-void launch_prolong_add(const StencilLevel& F, int nc, const double* ec, double* ef, hipStream_t st);
-void launch_plg_b2(const PlgRows& P, const double* s, const double* e, double* y, hipStream_t st);
-void launch_gather(int n, const int* var_cell, const double* src, double* y, hipStream_t st);
-void launch_lu_forward(const LuDev& F, const LuTasks& T, hipStream_t st);  // GEMV tasks + reduction
-void launch_lu_backward(const LuDev& F, const LuTasks& T, double* out, hipStream_t st);
-void launch_zero(double* p, long long count, hipStream_t st);
-void launch_zero_u64(unsigned long long* p, hipStream_t st);
-void launch_maxabs(const double* v, long long count, unsigned long long* out, hipStream_t st);
-void launch_add_unknowns(const StencilLevel& L, const double* e, double* phi, hipStream_t st);
-void launch_copy_pairs(int count, const int2* pairs, double* a, hipStream_t st);
+// d = s / norm[b] (0 where norm[b] == 0), converted to T
+template <class T>
+void launch_scale_residual(long long n3, const double* s, const unsigned long long* norm, T* d, int nb,
+                           hipStream_t st);
+void launch_mask_unknowns(const StencilLevel& L, double* a, int nb, hipStream_t st);
+void launch_copy_pairs(int count, const int2* pairs, double* a, long long stride, int nb, hipStream_t st);
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q,
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
-void launch_mask_unknowns(const StencilLevel& L, double* a, hipStream_t st);
+void launch_copy(long long count, const double* src, double* dst, hipStream_t st);
 
 }  // namespace cc

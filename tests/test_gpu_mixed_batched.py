@@ -1,0 +1,161 @@
+"""GPU parity of the mixed-precision (FP32 V-cycles inside FP64 defect
+correction) and batched (several right-hand sides per launch) solves, through
+the C ABI, against the oracle."""
+import numpy as np
+import pytest
+
+from oracle.multigrid import Hierarchy, MGParams
+from paper_2410_05865_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_05865_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _ell32():
+    d = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    d.wall_bc = (0, 1, 0, 0, 1, 0)
+    d.n_min = 16
+    return d
+
+
+WORK = {
+    "sphere32": lambda: inputs.sphere_domain(n=32, radius=0.25, n_min=16),
+    "ellipsoid32_neumann": _ell32,
+}
+_CACHE = {}
+
+
+def _hier(name):
+    if name not in _CACHE:
+        dom = WORK[name]()
+        _CACHE[name] = (dom, Hierarchy(dom))
+    return _CACHE[name]
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _rhs(lv, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal(lv.N) * (1.0 + 10.0 * b) for b in range(nrhs)]
+
+
+def _direct(H, r):
+    import scipy.sparse.linalg as spla
+    return spla.splu(H.fine.L.tocsc()).solve(r)
+
+
+@pytest.mark.parametrize("name", sorted(WORK))
+def test_mixed_solve_meets_fp64_tolerance(name):
+    """Defect correction: FP64 residual and update around FP32 V-cycles.  The
+    result satisfies the FP64 stopping test on the oracle's operator, needs about
+    as many V-cycles as the FP64 solve, and refined to 1e-12 matches the direct
+    solve to 1e-10."""
+    L = _lib()
+    dom, H = _hier(name)
+    lv = H.fine
+    print(f"[mixed] {name}", flush=True)
+    r_or = _rhs(lv, 1, 11)[0]
+    xd = _direct(H, r_or)
+    for tol in (1e-10, 1e-12):
+        P = L.Problem(dom, precision=L.CC_MIXED, tol=tol)
+        r = _dev(lv.to_grid(r_or))
+        phi = _dev(np.zeros(lv.n ** 3))
+        info = P.solve(r, phi)
+        assert info["converged"], info
+        got = phi.cpu().numpy()[lv.unknowns]
+        res = np.max(np.abs(r_or - lv.L @ got)) / np.max(np.abs(r_or))
+        assert res < tol
+        err = _rel(got, xd)
+        _, hist = H.solve(r_or, MGParams(tol=tol))
+        print(f"  tol {tol:g}: {info['iterations']} mixed V-cycles (FP64 oracle {len(hist) - 1}), "
+              f"residual {res:.2e}, max rel error vs direct {err:.2e}", flush=True)
+        assert info["iterations"] <= len(hist) - 1 + 3
+        if tol == 1e-12:
+            assert err < 1e-10
+        P.close()
+
+
+@pytest.mark.parametrize("name", sorted(WORK))
+def test_batched_fp64_matches_oracle_iterates(name):
+    """nb right-hand sides in one group: every member receives the group's V-cycle
+    count k, so it equals the oracle's iterate after k V-cycles (tol 0, k cycles)."""
+    L = _lib()
+    dom, H = _hier(name)
+    lv = H.fine
+    print(f"[batched] {name}", flush=True)
+    rs = _rhs(lv, 3, 12)
+    P = L.Problem(dom)
+    r = torch.stack([_dev(lv.to_grid(x)) for x in rs])
+    phi = torch.zeros_like(r)
+    infos = P.solve_batched(r, phi)
+    k = infos[0]["iterations"]
+    assert all(i["converged"] and i["iterations"] == k for i in infos)
+    out = phi.cpu().numpy()
+    for b, rb in enumerate(rs):
+        x_or, hist = H.solve(rb, MGParams(tol=0.0, max_iter=k))
+        assert _rel(out[b][lv.unknowns], x_or) < 1e-11
+        for a, c in zip(infos[b]["history"], hist):
+            assert a == pytest.approx(c, rel=1e-5, abs=1e-14)
+        # the member's own single solve stops at or before the group's count
+        _, h1 = H.solve(rb, MGParams(tol=1e-10))
+        assert len(h1) - 1 <= k
+    P.close()
+
+
+def test_batched_groups_and_mixed():
+    """More right-hand sides than one group (groups of 64 and 2) in FP64, and a
+    mixed-precision batch; small sphere problem."""
+    L = _lib()
+    dom = inputs.sphere_domain(n=16, radius=0.25, n_min=8)
+    H = Hierarchy(dom)
+    lv = H.fine
+    rng = np.random.default_rng(13)
+    nrhs = L.BATCH_MAX + 2
+    R = rng.standard_normal((nrhs, lv.N))
+    r = torch.stack([_dev(lv.to_grid(x)) for x in R])
+    P = L.Problem(dom)
+    phi = torch.zeros_like(r)
+    infos = P.solve_batched(r, phi)
+    assert all(i["converged"] for i in infos)
+    out = phi.cpu().numpy()
+    for b in (0, 37, nrhs - 1):
+        x_or, _ = H.solve(R[b], MGParams(tol=0.0, max_iter=infos[b]["iterations"]))
+        assert _rel(out[b][lv.unknowns], x_or) < 1e-11
+    P.close()
+    Q = L.Problem(dom, precision=L.CC_MIXED, tol=1e-12)
+    phi = torch.zeros_like(r[:5])
+    infos = Q.solve_batched(r[:5].contiguous(), phi)
+    assert all(i["converged"] for i in infos)
+    out = phi.cpu().numpy()
+    for b in range(5):
+        xd = _direct(H, R[b])
+        assert _rel(out[b][lv.unknowns], xd) < 1e-10
+    Q.close()
+
+
+def test_timing_hooks_report_bytes():
+    L = _lib()
+    dom = inputs.sphere_domain(n=32, radius=0.25, n_min=16)
+    P = L.Problem(dom, precision=L.CC_MIXED)
+    n3 = 32 ** 3
+    for which, per_cell in ((L.CC_TIME_SMO1, 25), (L.CC_TIME_SMO1_F32, 13), (L.CC_TIME_COPY, 16)):
+        ms, by = P.time_kernel(which, 5)
+        assert ms > 0 and by == per_cell * n3
+    for which in (L.CC_TIME_LU, L.CC_TIME_LU_F32):
+        ms, by = P.time_kernel(which, 3)
+        assert ms > 0 and by >= (8 if which == L.CC_TIME_LU else 4) * P.level_info(0)["lu_entries"]
+    P.close()
