@@ -1,28 +1,62 @@
-"""Benchmark: time to 1e-10 relative residual of the FP64 multigrid solve at 256^3
-on the 8-ellipsoid workload, plus the smoother's HBM bandwidth against the
-MI355X roofline, and the CPU oracle timed on a bounded sample.
+"""Benchmark of the cut-cell multigrid solve on one MI355X.
 
-One step = one whole solve (outer residual, V-cycles with SMO-1, SMO-2
-LU-corrections, transfers and bottom solves) from a zero guess to
+Workload: the unit box minus 8 seeded ellipsoids (Dirichlet walls, Neumann
+obstacles), 256^3 cells, manufactured phi = exp(x + y/2) cos(3z).  One step is
+one whole solve (outer residual, V-cycles with SMO-1, SMO-2 LU-corrections,
+transfers and the bottom solve) from a zero guess to
 max|r - L phi| / max|r| < 1e-10, with r resident in HBM.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
+Reported: the plain FP64 solve time (`value`), the mixed-precision solve (FP32
+V-cycles inside FP64 defect correction) and a batched solve of many
+right-hand sides on the same geometry (time per right-hand side), the SMO-1
+smoother's achieved HBM bandwidth against the MI355X peak (`roofline`, timed
+with HIP events on the library's stream), and the CPU oracle timed on a
+bounded sample (`cpu_baseline`).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
+                    [--no-mixed] [--no-batch] [--no-cpu-baseline]
+    python bench.py --kernels-only          # only the timing hooks (for counter runs)
+    python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
+    python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-SMOOTHER_BYTES_PER_CELL = 25   # read e, s and the cell type, write e (FP64), over the n^3 grid
+KERNEL_SRC = os.path.join(ROOT, "paper_2410_05865_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_smo1_ellipsoid256_traffic.md")
 
 
-def _cpu_baseline(n_sample: int, gpu_cycles: int, n_target: int, N_target: int):
+def _src_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(n: int):
+    """HBM bytes per SMO-1 launch from the committed counter summary, or None if
+    it is missing, for another size, or taken from a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    h = re.search(r"kernels\.hip sha256\[:16\]: `([0-9a-f]+)`", text)
+    v = re.search(r"k_smo1 bytes per launch \(calibrated\): `([0-9.eE+]+)`", text)
+    m = re.search(r"grid: `(\d+)\^3`", text)
+    if not (h and v and m) or h.group(1) != _src_hash() or int(m.group(1)) != n:
+        return None
+    return float(v.group(1))
+
+
+def _cpu_baseline(n_sample: int, gpu_cycles: int, n_target: int, N_target: int, min_seconds: float = 10.0):
     """Oracle (plain numpy/scipy, FP64) on the same workload family at a small
     size: time per V-cycle, scaled by unknowns to the target size and by the
     V-cycle count the GPU needed there."""
@@ -37,10 +71,13 @@ def _cpu_baseline(n_sample: int, gpu_cycles: int, n_target: int, N_target: int):
     t_setup = time.perf_counter() - t0
     lv = H.fine
     r = lv.rhs(F.laplacian_desc(), F)
-    t0 = time.perf_counter()
-    x, hist = H.solve(r, MGParams(tol=1e-10))
-    t_solve = time.perf_counter() - t0
-    cycles = max(1, len(hist) - 1)
+    reps, t_solve, cycles = 0, 0.0, 0
+    while t_solve < min_seconds or reps == 0:      # repeat to a bounded ~10 s of CPU work
+        t0 = time.perf_counter()
+        x, hist = H.solve(r, MGParams(tol=1e-10))
+        t_solve += time.perf_counter() - t0
+        cycles += max(1, len(hist) - 1)
+        reps += 1
     per_cycle_per_dof = t_solve / cycles / lv.N
     try:
         cores = len(os.sched_getaffinity(0))
@@ -51,26 +88,55 @@ def _cpu_baseline(n_sample: int, gpu_cycles: int, n_target: int, N_target: int):
         "unit": "s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"oracle Multigrid to 1e-10 on the same 8-ellipsoid workload at {n_sample}^3 "
-                   f"({lv.N} unknowns, {cycles} V-cycles, {t_solve:.1f} s; setup {t_setup:.0f} s not counted), "
+        "sample": (f"oracle multigrid to 1e-10 on the same 8-ellipsoid workload at {n_sample}^3 "
+                   f"({lv.N} unknowns; {reps} solves, {cycles} V-cycles, {t_solve:.1f} s; setup {t_setup:.0f} s "
+                   f"not counted), "
                    f"scaled per unknown to {n_target}^3 and to the GPU's {gpu_cycles} V-cycles; numpy stencil "
                    f"work is single-threaded, BLAS/SuperLU may use the listed cores"),
     }
 
 
+def _timed(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch-base", type=int, default=4,
+                    help="assembled Gaussian right-hand sides the batch is mixed from")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=64)
     ap.add_argument("--smoother-reps", type=int, default=50)
+    ap.add_argument("--kernels-only", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
+    ap.add_argument("--summarize-trace", metavar="TRACE_DB")
     args = ap.parse_args()
+    if args.summarize_pmc or args.summarize_trace:
+        from paper_2410_05865_amd import profiling
+        if args.summarize_pmc:
+            print(profiling.traffic_summary(*args.summarize_pmc, n=args.n, src_hash=_src_hash()))
+        if args.summarize_trace:
+            print(profiling.kernel_stats_summary(args.summarize_trace, n=args.n))
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
 
     import torch
@@ -88,35 +154,82 @@ def main():
     t_setup = time.perf_counter() - t0
     li0 = P.level_info(0)
     n3 = args.n ** 3
+
     with torch.cuda.stream(stream):
+        if args.kernels_only:
+            for which in (_lib.CC_TIME_SMO1, _lib.CC_TIME_COPY, _lib.CC_TIME_LU):
+                P.time_kernel(which, 5)
+            torch.cuda.synchronize()
+            print(json.dumps({"kernels_only": True, "n": args.n}), flush=True)
+            return
         r = torch.zeros(n3, dtype=torch.float64, device=dev)
         x = torch.zeros(n3, dtype=torch.float64, device=dev)
         P.assemble_rhs(phi, phi, r, f_mode=_lib.CC_LAPLACIAN)
-        infos = []
-        for _ in range(args.warmup):
+
+        def solve_once():
             x.zero_()
-            P.solve(r, x)
+            return P.solve(r, x)
+
+        sec, info = _timed(solve_once, args.steps, args.warmup)
+        print(f"[bench] plain FP64: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
+        out_mixed = None
+        if not args.no_mixed:
+            P.set_precision(_lib.CC_MIXED)
+            sec_m, info_m = _timed(solve_once, args.steps, args.warmup)
+            P.set_precision(_lib.CC_FP64)
+            print(f"[bench] mixed: {sec_m * 1e3:.1f} ms, {info_m['iterations']} V-cycles", file=sys.stderr, flush=True)
+            out_mixed = {"s_per_solve": sec_m, "v_cycles": info_m["iterations"],
+                         "final_rel_residual": info_m["rel_residual"], "speedup_vs_plain": sec / sec_m}
+        out_batch = None
+        if not args.no_batch and args.batch > 0:
+            B = args.batch
+            base = torch.zeros(args.batch_base, n3, dtype=torch.float64, device=dev)
+            for k in range(args.batch_base):
+                P.assemble_rhs(inputs.gaussian_rhs(dom, seed=100 + k), None, base[k])
+            rng = np.random.default_rng(args.seed)
+            coef = torch.from_numpy(rng.uniform(-1.0, 1.0, size=(B, args.batch_base))).to(dev)
+            rb = (coef @ base).contiguous()
+            del base
+            xb = torch.zeros_like(rb)
+            res = {}
+            for prec, name in ((_lib.CC_FP64, "fp64"), (_lib.CC_MIXED, "mixed")):
+                if name == "mixed" and args.no_mixed:
+                    continue
+                P.set_precision(prec)
+
+                def solve_batch():
+                    xb.zero_()
+                    return P.solve_batched(rb, xb)
+
+                sb, infos = _timed(solve_batch, 1, 1)
+                res[name] = {"s_per_rhs": sb / B, "s_per_batch": sb,
+                             "v_cycles": max(i["iterations"] for i in infos),
+                             "max_final_rel_residual": max(i["rel_residual"] for i in infos),
+                             "speedup_per_rhs_vs_plain": sec / (sb / B)}
+                print(f"[bench] batched {name}: {sb * 1e3:.0f} ms for {B} rhs", file=sys.stderr, flush=True)
+            P.set_precision(_lib.CC_FP64)
+            out_batch = {"rhs": B, "rhs_recipe": f"{B} seeded mixtures of {args.batch_base} assembled right-hand "
+                                                  f"sides, each f = sum of 16 seeded Gaussians (sigma U[0.02, 0.1]), "
+                                                  f"g = 0", **res}
+            del rb, xb
+            torch.cuda.empty_cache()
+        ms_smo, by_smo = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
+        ms_smo32, by_smo32 = P.time_kernel(_lib.CC_TIME_SMO1_F32, args.smoother_reps)
+        ms_lu, by_lu = P.time_kernel(_lib.CC_TIME_LU, 10)
+        ms_copy, by_copy = P.time_kernel(_lib.CC_TIME_COPY, args.smoother_reps)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            x.zero_()
-            infos.append(P.solve(r, x))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms_smoother, _ = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
-        torch.cuda.synchronize()
-    ms = (t1 - t0) * 1000.0 / args.steps
-    cycles = infos[-1]["iterations"]
-    achieved = SMOOTHER_BYTES_PER_CELL * n3 / (ms_smoother * 1e-3) / 1e9
+
+    achieved = by_smo / (ms_smo * 1e-3) / 1e9
     N = li0["n_unknowns"]
+    cycles = info["iterations"]
     out = {
-        "metric": "time to 1e-10 rel. residual at 256^3 (plain FP64) + smoother HBM GB/s",
-        "value": ms / 1000.0,
+        "metric": "time to 1e-10 rel. residual at 256^3 (plain vs mixed/learned) + smoother HBM GB/s",
+        "value": sec,
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": sec * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -127,22 +240,33 @@ def main():
                         f"obstacles, manufactured phi = exp(x + y/2) cos(3z), {args.n}^3, plain FP64 V-cycles "
                         f"to 1e-10 max-norm relative residual",
             "n": args.n, "levels": P.num_levels, "unknowns": N, "phi2_rows": li0["n_phi2"],
+            "lu_entries_level0": li0["lu_entries"],
             "omega": P.params.omega, "nu1": P.params.nu1, "nu2": P.params.nu2,
         },
         "v_cycles": cycles,
-        "final_rel_residual": infos[-1]["rel_residual"],
-        "dof_per_s": N * cycles / (ms / 1000.0),
+        "final_rel_residual": info["rel_residual"],
+        "dof_per_s": N * cycles / sec,
         "setup_s": t_setup,
+        "mixed": out_mixed,
+        "batched": out_batch,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_smo1 (SMO-1 weighted Jacobi, level 0)",
+            "kernel": "k_smo1<double> (SMO-1 weighted Jacobi, level 0)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "ms_per_launch": ms_smoother,
-            "bytes_per_launch": SMOOTHER_BYTES_PER_CELL * n3,
+            "traffic": _traffic(args.n),
+            "ms_per_launch": ms_smo,
+            "bytes_per_launch": by_smo,
+        },
+        "roofline_other": {
+            "k_smo1<float>": {"achieved_GBs": by_smo32 / (ms_smo32 * 1e-3) / 1e9, "ms_per_launch": ms_smo32,
+                              "bytes_per_launch": by_smo32},
+            "lu_correction_level0_fp64": {"achieved_GBs": by_lu / (ms_lu * 1e-3) / 1e9, "ms_per_correction": ms_lu,
+                                          "bytes_per_correction": by_lu},
+            "copy": {"achieved_GBs": by_copy / (ms_copy * 1e-3) / 1e9, "ms_per_launch": ms_copy,
+                     "bytes_per_launch": by_copy},
         },
     }
     if not args.no_cpu_baseline:

@@ -1,0 +1,102 @@
+"""Memory-traffic summary from two rocprofv3 --pmc runs (FETCH_SIZE, then
+WRITE_SIZE) of `bench.py --kernels-only`.
+
+The counters are read per dispatch in KiB.  They are converted to bytes with
+factors taken from the plain copy kernel of the same run, whose true traffic is
+known (8 bytes read and 8 written per element): bytes = counter * factor.
+"""
+from __future__ import annotations
+
+import re
+import sqlite3
+from collections import defaultdict
+
+import numpy as np
+
+
+def _load(path: str, counter: str):
+    con = sqlite3.connect(path)
+    rows = con.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                       "from counters_collection order by dispatch_id").fetchall()
+    out = []
+    for did, name, grid, cname, val in rows:
+        if cname != counter:
+            continue
+        m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
+        key = (m.group(1) + (m.group(2) or "")) if m else name[:40]
+        out.append((did, key, int(grid), float(val)))
+    return out
+
+
+def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
+    fe = _load(fetch_db, "FETCH_SIZE")
+    wr = _load(write_db, "WRITE_SIZE")
+    n3 = n ** 3
+
+    def by_kernel(rows, prefix, largest=True):
+        g = defaultdict(list)
+        for _, k, grid, v in rows:
+            if k.startswith(prefix):
+                g[grid].append(v)
+        if not g:
+            raise ValueError(f"no dispatch of {prefix}")
+        grid = max(g) if largest else min(g)
+        return float(np.mean(g[grid])), len(g[grid]), grid
+
+    cf, ncf, _ = by_kernel(fe, "k_copy")
+    cw, ncw, _ = by_kernel(wr, "k_copy")
+    f_fac = 8.0 * n3 / (cf * 1024.0)
+    w_fac = 8.0 * n3 / (cw * 1024.0)
+    sf, nsf, sgrid = by_kernel(fe, "k_smo1<double>")
+    sw, nsw, _ = by_kernel(wr, "k_smo1<double>")
+    smo_bytes = sf * 1024.0 * f_fac + sw * 1024.0 * w_fac
+    alg = 25.0 * n3
+    # LU-correction sweeps: all k_lu_* dispatches, per correction (6 in the run)
+    lu_f = sum(v for _, k, _, v in fe if k.startswith("k_lu_"))
+    lu_w = sum(v for _, k, _, v in wr if k.startswith("k_lu_"))
+    n_lu = sum(1 for _, k, _, _ in fe if k.startswith("k_lu_forward"))
+    lines = [
+        f"# HBM traffic of k_smo1 (SMO-1, FP64, level 0) and the level-0 LU-correction sweeps",
+        "",
+        f"- grid: `{n}^3` (8-ellipsoid workload, seed 1)",
+        f"- kernels.hip sha256[:16]: `{src_hash}`",
+        f"- copy kernel (k_copy, {n3} doubles): FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per dispatch "
+        f"({ncf}/{ncw} dispatches); true traffic {8 * n3 / 1024:.1f} KiB each way",
+        f"- calibration factors: fetch x{f_fac:.4f}, write x{w_fac:.4f}",
+        f"- k_smo1<double>: FETCH_SIZE {sf:.1f} KiB, WRITE_SIZE {sw:.1f} KiB per dispatch ({nsf} dispatches, "
+        f"grid {sgrid} work-items)",
+        f"- k_smo1 bytes per launch (calibrated): `{smo_bytes:.6e}`",
+        f"- k_smo1 algorithmic bytes per launch (25 B/cell): {alg:.6e}; measured/algorithmic = {smo_bytes / alg:.3f}",
+        f"- LU-correction sweeps: {n_lu} forward launches in the run; FETCH {lu_f:.1f} KiB, WRITE {lu_w:.1f} KiB "
+        f"over all k_lu_* dispatches (calibrated {(lu_f * f_fac + lu_w * w_fac) * 1024:.6e} bytes)",
+    ]
+    return "\n".join(lines)
+
+
+def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
+    """Per-kernel totals from a rocprofv3 --kernel-trace database, plus the
+    average duration of the level-0 dispatches of k_smo1<double> (largest
+    grid), which the bench's event timing of the same kernel should match."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end, grid_x, grid_y, grid_z from kernels").fetchall()
+    tot = defaultdict(lambda: [0, 0.0])
+    smo = defaultdict(list)
+    for name, st, en, gx, gy, gz in rows:
+        m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
+        key = (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0][:40]
+        d = (en - st) / 1000.0
+        tot[key][0] += 1
+        tot[key][1] += d
+        if key == "k_smo1<double>":
+            smo[(gx, gy, gz)].append(d)
+    allt = sum(v[1] for v in tot.values())
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"| {k} | {c} | {t / 1000:.2f} | {t / c:.1f} | {100 * t / allt:.1f} |")
+    if smo:
+        g = max(smo, key=lambda k: k[0] * k[1] * k[2])
+        v = smo[g]
+        out.append("")
+        out.append(f"k_smo1<double> level-0 dispatches (grid {g[0]}x{g[1]}x{g[2]} work-items, {n}^3 cells): "
+                   f"{len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
+    return "\n".join(out)
