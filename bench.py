@@ -109,6 +109,43 @@ def _timed(fn, steps: int, warmup: int):
     return (time.perf_counter() - t0) / steps, out
 
 
+def _learned_leg(P, dom, args, stream):
+    """Train the learned guess on solver-generated pairs (64^3 problems of the
+    same family, network on their 32^3 level; a 3-level U-Net on a 64^3 grid
+    does not see far enough to learn the global solve), then solve a held-out
+    Gaussian right-hand side on the benchmark problem from a zero guess and from
+    the network's guess (inferred on its 32^3 level and interpolated)."""
+    import torch
+    from paper_2410_05865_amd import _lib, inputs, learned
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    net, info = learned.fit(n_fine=64, level=1, geometries=6, rhs_per_geometry=32,
+                            steps=args.learned_steps, seed=3, log=log)
+    level = next(m for m in range(P.num_levels) if P.n(m) == 32)
+    n3 = args.n ** 3
+    with torch.cuda.stream(stream):
+        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(inputs.gaussian_rhs(dom, seed=999), None, r)
+        phi = torch.zeros_like(r)
+
+        def zero_guess():
+            phi.zero_()
+            return P.solve(r, phi)
+
+        def learned_guess():
+            P.learned_guess(net, level, learned.PHI_SCALE, r, phi)
+            return P.solve(r, phi)
+
+        s0, i0 = _timed(zero_guess, args.steps, args.warmup)
+        s1, i1 = _timed(learned_guess, args.steps, args.warmup)
+    net.close()
+    log(f"[bench] learned guess: {i0['iterations']} -> {i1['iterations']} V-cycles, {s0 * 1e3:.1f} -> {s1 * 1e3:.1f} ms")
+    return {"train": info, "rhs": "f = sum of 16 seeded Gaussians (seed 999), g = 0",
+            "zero_guess": {"s_per_solve": s0, "v_cycles": i0["iterations"]},
+            "learned_guess": {"s_per_solve_incl_inference": s1, "v_cycles": i1["iterations"],
+                              "initial_rel_residual": i1["history"][0]},
+            "speedup_vs_zero_guess": s0 / s1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +158,8 @@ def main():
                     help="assembled Gaussian right-hand sides the batch is mixed from")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=64)
     ap.add_argument("--smoother-reps", type=int, default=50)
@@ -213,6 +252,9 @@ def main():
                                                   f"g = 0", **res}
             del rb, xb
             torch.cuda.empty_cache()
+        out_learned = None
+        if not args.no_learned:
+            out_learned = _learned_leg(P, dom, args, stream)
         ms_smo, by_smo = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
         ms_smo32, by_smo32 = P.time_kernel(_lib.CC_TIME_SMO1_F32, args.smoother_reps)
         ms_lu, by_lu = P.time_kernel(_lib.CC_TIME_LU, 10)
@@ -249,6 +291,7 @@ def main():
         "setup_s": t_setup,
         "mixed": out_mixed,
         "batched": out_batch,
+        "learned": out_learned,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_smo1<double> (SMO-1 weighted Jacobi, level 0)",

@@ -229,6 +229,51 @@ int cc_time_kernel(cc_problem* p, int which, int reps, double* ms_per_launch, do
 void cc_destroy(cc_problem* p);
 const char* cc_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Learned initial guess (an addition on top of the paper's method: the
+ * multigrid solve stays the judge, the network only supplies phi_0).
+ *
+ * A 3-level 3D U-Net with base width C (16 or 32): two input channels (the
+ * scaled right-hand side and a geometry channel), one output channel, 3x3x3
+ * convolutions with bias, 2x2x2 average pooling, nearest upsampling and skip
+ * connections (see the architecture in csrc/net.hip).  Weights are kept in FP32
+ * with a BF16 copy; activations are BF16; convolutions accumulate in FP32 on
+ * MFMA.  Tensors are channel-last:
+ *   x:      nb x n^3 x 2 FP32 (device), voxel i + n (j + n k)
+ *   y, t:   nb x n^3 FP32 (device)
+ *   mask:   nb x n^3 bytes (device), nonzero where the loss counts
+ * n must be a multiple of 16.  Work runs on `stream` (NULL: the default
+ * stream); every call synchronises it.  Parameters are one flat FP32 array in
+ * layer order, each layer W[27][Cout][Cin] (tap = (dz+1) 9 + (dy+1) 3 + (dx+1))
+ * then bias[Cout]; the first layer has 16 input slots (2 used) and the last 16
+ * outputs (1 used; the others are held at zero). */
+typedef struct cc_net cc_net;
+int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_net** out);
+long long cc_net_num_params(const cc_net* net);
+int cc_net_get_params(const cc_net* net, float* host);
+int cc_net_set_params(cc_net* net, const float* host);
+/* y = net(x) */
+int cc_net_forward(cc_net* net, int n, int nb, const float* x_dev, float* y_dev);
+/* loss = sum over mask of (net(x) - t)^2 / count(mask); gradients of the loss
+ * with respect to the parameters are left in the network (for cc_net_adam_step)
+ * and, if grad_host is not NULL, copied to it (cc_net_num_params floats). */
+int cc_net_loss_grad(cc_net* net, int n, int nb, const float* x_dev, const float* t_dev,
+                     const unsigned char* mask_dev, double* loss, float* grad_host);
+/* one Adam update with the gradients of the last cc_net_loss_grad */
+int cc_net_adam_step(cc_net* net, float lr, float beta1, float beta2, float eps);
+void cc_net_destroy(cc_net* net);
+
+/* Initial guess for cc_solve from the network, evaluated on level `level` of
+ * the problem (m cells per axis, a multiple of 16): the features are the mean of
+ * r over each level cell scaled by 1 / max|r| and the cell's volume fraction;
+ * the output y is turned into phi = y * max|r| / phi_scale at the level cells
+ * and interpolated trilinearly to the level-0 unknowns (other cells get 0).
+ * phi_scale is the factor the targets were scaled by in training (targets =
+ * phi_scale * phi / max|r|).  r_dev, phi_dev: level-0 arrays (n^3, device).
+ * Synchronises the problem's stream; the network runs on its own stream. */
+int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r_dev,
+                     double* phi_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,8 @@ EXPORTED = [
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision",
+    "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
+    "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
 
 
@@ -104,6 +106,17 @@ def load() -> C.CDLL:
     lib.cc_selfcheck_lu.argtypes = [vp, C.c_int, P(C.c_double)]
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_set_precision.argtypes = [vp, C.c_int]
+    lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
+    lib.cc_net_num_params.argtypes = [vp]
+    lib.cc_net_num_params.restype = C.c_longlong
+    lib.cc_net_get_params.argtypes = [vp, vp]
+    lib.cc_net_set_params.argtypes = [vp, vp]
+    lib.cc_net_forward.argtypes = [vp, C.c_int, C.c_int, vp, vp]
+    lib.cc_net_loss_grad.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, P(C.c_double), vp]
+    lib.cc_net_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+    lib.cc_learned_guess.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp]
+    lib.cc_net_destroy.argtypes = [vp]
+    lib.cc_net_destroy.restype = None
     lib.cc_solve_batched.argtypes = [vp, C.c_int, vp, vp, P(CcSolveInfo)]
     lib.cc_time_kernel.argtypes = [vp, C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
     lib.cc_destroy.argtypes = [vp]
@@ -322,9 +335,79 @@ class Problem:
         n3 = self.n(level) ** 3
         _check(load().cc_vcycle(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
+    def learned_guess(self, net: "Net", level: int, phi_scale: float, r, phi):
+        """phi <- the network's guess (see cc_learned_guess)."""
+        n3 = self.n() ** 3
+        _check(load().cc_learned_guess(self._h, net._h, level, phi_scale, _ptr(r, n3), _ptr(phi, n3)))
+
     def time_kernel(self, which: int, reps: int = 20):
         """(ms per launch, algorithmic bytes per launch) of a timing hook."""
         v = C.c_double()
         b = C.c_double()
         _check(load().cc_time_kernel(self._h, which, reps, C.byref(v), C.byref(b)))
         return v.value, b.value
+
+
+def _dptr(t, dtype, numel):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
+    if t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The learned-guess U-Net of the library (cc_net_*)."""
+
+    def __init__(self, base_channels: int = 16, seed: int = 0, stream=None):
+        h = C.c_void_p()
+        _check(load().cc_net_create(base_channels, seed, C.c_void_p(stream) if stream is not None else None,
+                                    C.byref(h)))
+        self._h = h
+        self.C = base_channels
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().cc_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(load().cc_net_num_params(self._h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _check(load().cc_net_get_params(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.num_params:
+            raise ValueError("wrong parameter count")
+        _check(load().cc_net_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def forward(self, x, y, n: int, nb: int):
+        """x: float32 (nb, n^3, 2) device tensor; y: float32 (nb, n^3)."""
+        import torch
+        v = nb * n ** 3
+        _check(load().cc_net_forward(self._h, n, nb, _dptr(x, torch.float32, 2 * v), _dptr(y, torch.float32, v)))
+
+    def loss_grad(self, x, t, mask, n: int, nb: int, want_grad: bool = False):
+        import torch
+        v = nb * n ** 3
+        loss = C.c_double()
+        g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        _check(load().cc_net_loss_grad(self._h, n, nb, _dptr(x, torch.float32, 2 * v), _dptr(t, torch.float32, v),
+                                       _dptr(mask, torch.uint8, v), C.byref(loss),
+                                       g.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(load().cc_net_adam_step(self._h, lr, beta1, beta2, eps))

@@ -178,6 +178,10 @@ struct cc_problem {
   cc::Work<float> w32;          // mixed precision, one right-hand side
   cc::Work<double> wb64;        // batched
   cc::Work<float> wb32;
+  std::vector<float*> volfrac;  // learned guess: per-level volume fractions (uploaded on demand)
+  float* net_x = nullptr;
+  float* net_y = nullptr;
+  long long net_cells = 0;
 };
 
 namespace cc {
@@ -1051,6 +1055,41 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
     return CC_ENOCONV;
   }
   return rc;
+}
+
+int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r, double* phi) {
+  return guard([&] {
+    if (!p || !net || !r || !phi) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    check_level(p, level);
+    if (!(phi_scale > 0)) fail(CC_EINVAL, "phi_scale must be positive");
+    const LevelHost& Lm = *p->lv[level];
+    const int m = Lm.n, n0 = p->lv[0]->n;
+    if (m % 16 != 0) fail(CC_EINVAL, "the network level needs a multiple of 16 cells per axis");
+    const long long m3 = cube(m);
+    if ((int)p->volfrac.size() <= level) p->volfrac.resize(level + 1, nullptr);
+    if (!p->volfrac[level]) {
+      std::vector<float> vf(m3);
+      const double h3 = Lm.h * Lm.h * Lm.h;
+      for (long long c = 0; c < m3; ++c) vf[c] = (float)(Lm.vol[c] / h3);
+      p->volfrac[level] = p->buf.upload(vf);
+    }
+    if (p->net_cells < m3) {
+      p->net_x = p->buf.alloc<float>(2 * m3);
+      p->net_y = p->buf.alloc<float>(m3);
+      p->net_cells = m3;
+    }
+    launch_zero_u64(p->d_norm, 1, p->stream);
+    launch_maxabs(r, cube(n0), 1, p->d_norm, p->stream);
+    const double rn = read_norm(p);
+    const double inv = rn > 0 ? 1.0 / rn : 0.0;
+    launch_net_features(n0, m, r, inv, p->volfrac[level], p->net_x, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    int rc = cc_net_forward(net, m, 1, p->net_x, p->net_y);
+    if (rc != CC_OK) fail(rc, cc_last_error());
+    launch_prolong_trilinear(p->dev[0].st, m, p->net_y, rn / phi_scale, phi, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
 }
 
 int cc_set_precision(cc_problem* p, int precision) {

@@ -569,6 +569,56 @@ __global__ void k_set_values(int count, const int* __restrict__ cells, const dou
   if (t < count) a[cells[t]] = vals[t];
 }
 
+// Learned-guess features on a coarse level of m^3 cells: x[V][0] = mean of r
+// over the V's (n0/m)^3 fine cells times inv_norm, x[V][1] = volume fraction.
+__global__ void k_net_features(int n0, int m, const double* __restrict__ r, double inv_norm,
+                               const float* __restrict__ volfrac, float* __restrict__ x) {
+  long long V = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long m3 = (long long)m * m * m;
+  if (V >= m3) return;
+  const int f = n0 / m;
+  const int I = (int)(V % m), J = (int)((V / m) % m), K = (int)(V / ((long long)m * m));
+  double s = 0.0;
+  for (int dz = 0; dz < f; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx)
+        s += r[(I * f + dx) + (long long)n0 * ((J * f + dy) + (long long)n0 * (K * f + dz))];
+  x[2 * V] = (float)(s / ((double)f * f * f) * inv_norm);
+  x[2 * V + 1] = volfrac[V];
+}
+
+// phi (level 0, unknown cells) = scale * trilinear interpolation of the
+// cell-centred coarse field y (m^3) at the fine cell centres (clamped at the
+// outer cells); 0 on cells without an unknown.
+__global__ void k_prolong_trilinear(StencilLevel L0, int m, const float* __restrict__ y, double scale,
+                                    double* __restrict__ phi) {
+  const int n = L0.n;
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n3 = (long long)n * n * n;
+  if (c >= n3) return;
+  if (L0.type[c] == 0) {
+    phi[c] = 0.0;
+    return;
+  }
+  const int ii[3] = {(int)(c % n), (int)((c / n) % n), (int)(c / ((long long)n * n))};
+  int lo[3], hi[3];
+  double w[3];
+  for (int a = 0; a < 3; ++a) {
+    double X = (ii[a] + 0.5) * m / (double)n - 0.5;
+    X = fmin(fmax(X, 0.0), (double)(m - 1));
+    lo[a] = (int)floor(X);
+    hi[a] = min(lo[a] + 1, m - 1);
+    w[a] = X - lo[a];
+  }
+  double v = 0.0;
+  for (int d = 0; d < 8; ++d) {
+    const int ix = (d & 1) ? hi[0] : lo[0], iy = (d & 2) ? hi[1] : lo[1], iz = (d & 4) ? hi[2] : lo[2];
+    const double wt = ((d & 1) ? w[0] : 1.0 - w[0]) * ((d & 2) ? w[1] : 1.0 - w[1]) * ((d & 4) ? w[2] : 1.0 - w[2]);
+    v += wt * (double)y[ix + (long long)m * (iy + (long long)m * iz)];
+  }
+  phi[c] = scale * v;
+}
+
 // plain copy (used to calibrate memory-traffic counters against a known size)
 __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long count) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -699,6 +749,15 @@ void launch_copy_pairs(int count, const int2* pairs, double* a, long long stride
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_values, dim3(blocks(count, 256)), dim3(256), 0, st, count, cells, vals, a);
+}
+void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
+                         hipStream_t st) {
+  const long long m3 = (long long)m * m * m;
+  hipLaunchKernelGGL(k_net_features, dim3(blocks(m3, 256)), dim3(256), 0, st, n0, m, r, inv_norm, volfrac, x);
+}
+void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong_trilinear, dim3(blocks(cube(L0.n), 256)), dim3(256), 0, st, L0, m, y, scale, phi);
 }
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st) {
   if (count == 0) return;

@@ -124,5 +124,11 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st);
+// learned guess: coarse features (block mean of r scaled, volume fraction) and
+// trilinear prolongation of the network output to the level-0 unknowns
+void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
+                         hipStream_t st);
+void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
+                              hipStream_t st);
 
 }  // namespace cc

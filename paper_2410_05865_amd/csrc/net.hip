@@ -1,0 +1,669 @@
+// Learned initial guess: a small 3D U-Net (BF16 activations and weights, FP32
+// accumulation on MFMA) that maps (scaled right-hand side, geometry) on a grid
+// to a scaled solution.  The multigrid solve stays the judge: the network only
+// supplies phi_0.  Not part of the paper's method; an addition on top of it.
+//
+// Architecture (C = base channels, grid n divisible by 16):
+//   e1 = relu(conv(x, 16 -> C))             n      (x: 2 input channels padded to 16)
+//   e2 = relu(conv(pool(e1), C -> 2C))      n/2
+//   b  = relu(conv(pool(e2), 2C -> 2C))     n/4
+//   d2 = relu(conv([up(b), e2], 4C -> 2C))  n/2
+//   d1 = relu(conv([up(d2), e1], 3C -> C))  n
+//   y  = conv(d1, C -> 16)[channel 0]       n      (output channels 1..15 held at 0)
+// conv: 3x3x3, zero padding, bias; pool: 2x2x2 average; up: nearest.
+//
+// Activations are channel-last ([batch][voxel][channel], voxel i + n (j + n k)).
+// A conv is an implicit GEMM (voxels x taps*Cin x Cout) on
+// v_mfma_f32_16x16x16_bf16: a wavefront computes 16 voxels x Cout.  Backward:
+// data gradients are the forward conv of the output gradient with the
+// transposed, flipped kernel; weight gradients are a GEMM over voxels staged
+// through LDS, one workgroup per (tap, voxel range), accumulated with FP32
+// atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace cc {
+namespace {
+
+#define NETCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t _e = (expr);                                                                    \
+    if (_e != hipSuccess) fail(CC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// element (b, v, c) of a channel slice: p[(b * n3 + v) * cs + co + c]
+struct View {
+  uint16_t* p;
+  int cs, co;
+};
+
+// ---------------------------------------------------------------- conv forward
+// grid: nb * n^3 / 64 blocks of 256 threads (4 waves x 16 voxels).
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_fwd(int n, View in, int cin, const uint16_t* __restrict__ wt,
+                                                  const float* __restrict__ bias, int relu, View out,
+                                                  float* __restrict__ out32) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long n3 = (long long)n * n * n;
+  const long long vg0 = ((long long)blockIdx.x * 4 + wave) * 16;  // first voxel (global over the batch)
+  const int r = lane & 15, kg = lane >> 4;
+  const long long vg = vg0 + r;
+  const long long b = vg / n3;
+  const int v = (int)(vg - b * n3);
+  const int i = v % n, j = (v / n) % n, k = v / (n * n);
+  const int cout = NT * 16;
+  v4f acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 27; ++tap) {
+    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const int ii = i + dx, jj = j + dy, kk = k + dz;
+    const bool inside = ii >= 0 && ii < n && jj >= 0 && jj < n && kk >= 0 && kk < n;
+    const long long vn = b * n3 + ii + (long long)n * (jj + (long long)n * kk);
+    const uint16_t* arow = in.p + vn * in.cs + in.co + 4 * kg;
+    const uint16_t* wrow = wt + ((long long)tap * cout + r) * cin + 4 * kg;
+    for (int ci0 = 0; ci0 < cin; ci0 += 16) {
+      v4s a = v4s{0, 0, 0, 0};
+      if (inside) a = *reinterpret_cast<const v4s*>(arow + ci0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const v4s bw = *reinterpret_cast<const v4s*>(wrow + (long long)t * 16 * cin + ci0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds D[4 kg + q][r]: voxel vg0 + 4 kg + q, channel t * 16 + r
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = t * 16 + r;
+    const float bs = bias ? bias[c] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long vo = vg0 + 4 * kg + q;
+      float val = acc[t][q] + bs;
+      if (relu) val = fmaxf(val, 0.f);
+      out.p[vo * out.cs + out.co + c] = f2bf(val);
+      if (out32 && c == 0) out32[vo] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- weight gradient
+// dW[tap][co][ci] += sum over voxels of g[v][co] * in[v + off(tap)][ci].
+// grid (27, splits); 256 threads; voxels of the split staged 64 at a time in LDS.
+constexpr int kWgChunk = 64;
+__global__ void __launch_bounds__(256) k_conv_wgrad(int n, long long nvox, View in, int cin, View g, int cout,
+                                                    float* __restrict__ dw, long long per_split) {
+  extern __shared__ uint16_t lds[];
+  uint16_t* lg = lds;                        // [64][cout]
+  uint16_t* li = lds + kWgChunk * cout;      // [64][cin]
+  const int tap = blockIdx.x;
+  const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+  const long long n3 = (long long)n * n * n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int tm = cout / 16, tn = cin / 16, ntile = tm * tn;
+  // up to 8 tiles per wave (cout, cin <= 128 -> <= 64 tiles)
+  v4f acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  const long long v_begin = (long long)blockIdx.y * per_split;
+  const long long v_end = v_begin + per_split < nvox ? v_begin + per_split : nvox;
+  for (long long c0 = v_begin; c0 < v_end; c0 += kWgChunk) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kWgChunk * cout; e += 256) {
+      const int vv = e / cout, c = e % cout;
+      const long long vg = c0 + vv;
+      lg[e] = (vg < v_end) ? g.p[vg * g.cs + g.co + c] : (uint16_t)0;
+    }
+    for (int e = threadIdx.x; e < kWgChunk * cin; e += 256) {
+      const int vv = e / cin, c = e % cin;
+      const long long vg = c0 + vv;
+      uint16_t val = 0;
+      if (vg < v_end) {
+        const long long b = vg / n3;
+        const int v = (int)(vg - b * n3);
+        const int ii = v % n + dx, jj = (v / n) % n + dy, kk = v / (n * n) + dz;
+        if (ii >= 0 && ii < n && jj >= 0 && jj < n && kk >= 0 && kk < n)
+          val = in.p[(b * n3 + ii + (long long)n * (jj + (long long)n * kk)) * in.cs + in.co + c];
+      }
+      li[e] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int tile = wave + 4 * t;
+      if (tile >= ntile) break;
+      const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
+#pragma unroll
+      for (int ks = 0; ks < kWgChunk; ks += 16) {
+        v4s a, bw;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int vv = ks + 4 * kg + q;
+          a[q] = (short)lg[vv * cout + m0 + r];
+          bw[q] = (short)li[vv * cin + n0 + r];
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile >= ntile) break;
+    const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      atomicAdd(&dw[((long long)tap * cout + m0 + 4 * kg + q) * cin + n0 + r], acc[t][q]);
+  }
+}
+
+__global__ void k_bias_grad(long long nvox, View g, int cout, float* __restrict__ db) {
+  const int c = threadIdx.x % cout;
+  const int lanes_per_c = blockDim.x / cout;
+  float s = 0.f;
+  for (long long v = (long long)blockIdx.x * lanes_per_c + threadIdx.x / cout; v < nvox;
+       v += (long long)gridDim.x * lanes_per_c)
+    s += bf2f(g.p[v * g.cs + g.co + c]);
+  atomicAdd(&db[c], s);
+}
+
+// flipped transpose: wf[26 - tap][ci][co] = wt[tap][co][ci]
+__global__ void k_flip(const uint16_t* __restrict__ wt, int cout, int cin, uint16_t* __restrict__ wf) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 27LL * cout * cin) return;
+  const int ci = (int)(e % cin), co = (int)((e / cin) % cout), tap = (int)(e / ((long long)cin * cout));
+  wf[((long long)(26 - tap) * cin + ci) * cout + co] = wt[e];
+}
+
+// ---------------------------------------------------------------- pointwise
+__global__ void k_pool(int n, int nb, View in, View out, int C) {
+  // out at n/2
+  const int m = n / 2;
+  const long long m3 = (long long)m * m * m, n3 = (long long)n * n * n;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * m3 * C) return;
+  const int c = (int)(e % C);
+  const long long vg = e / C, b = vg / m3;
+  const int v = (int)(vg - b * m3);
+  const int I = v % m, J = (v / m) % m, K = v / (m * m);
+  float s = 0.f;
+  for (int d = 0; d < 8; ++d) {
+    const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
+    s += bf2f(in.p[(b * n3 + i + (long long)n * (j + (long long)n * k)) * in.cs + in.co + c]);
+  }
+  out.p[vg * out.cs + out.co + c] = f2bf(0.125f * s);
+}
+// gin (at n) += gout(parent) / 8
+__global__ void k_pool_bwd_add(int n, int nb, View gout, View gin, int C) {
+  const int m = n / 2;
+  const long long m3 = (long long)m * m * m, n3 = (long long)n * n * n;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * n3 * C) return;
+  const int c = (int)(e % C);
+  const long long vg = e / C, b = vg / n3;
+  const int v = (int)(vg - b * n3);
+  const int i = v % n, j = (v / n) % n, k = v / (n * n);
+  const long long p = b * m3 + (i / 2) + (long long)m * ((j / 2) + (long long)m * (k / 2));
+  uint16_t* dst = &gin.p[vg * gin.cs + gin.co + c];
+  *dst = f2bf(bf2f(*dst) + 0.125f * bf2f(gout.p[p * gout.cs + gout.co + c]));
+}
+// out (at n) = in(parent at n/2)
+__global__ void k_up(int n, int nb, View in, View out, int C) {
+  const int m = n / 2;
+  const long long m3 = (long long)m * m * m, n3 = (long long)n * n * n;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * n3 * C) return;
+  const int c = (int)(e % C);
+  const long long vg = e / C, b = vg / n3;
+  const int v = (int)(vg - b * n3);
+  const int i = v % n, j = (v / n) % n, k = v / (n * n);
+  const long long p = b * m3 + (i / 2) + (long long)m * ((j / 2) + (long long)m * (k / 2));
+  out.p[vg * out.cs + out.co + c] = in.p[p * in.cs + in.co + c];
+}
+// gin (at n/2) = sum over the 8 children of gout (at n)
+__global__ void k_up_bwd(int n, int nb, View gout, View gin, int C) {
+  const int m = n / 2;
+  const long long m3 = (long long)m * m * m, n3 = (long long)n * n * n;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * m3 * C) return;
+  const int c = (int)(e % C);
+  const long long vg = e / C, b = vg / m3;
+  const int v = (int)(vg - b * m3);
+  const int I = v % m, J = (v / m) % m, K = v / (m * m);
+  float s = 0.f;
+  for (int d = 0; d < 8; ++d) {
+    const int i = 2 * I + (d & 1), j = 2 * J + ((d >> 1) & 1), k = 2 * K + (d >> 2);
+    s += bf2f(gout.p[(b * n3 + i + (long long)n * (j + (long long)n * k)) * gout.cs + gout.co + c]);
+  }
+  gin.p[vg * gin.cs + gin.co + c] = f2bf(s);
+}
+__global__ void k_relu_bwd(long long nvox, int C, View g, View y) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nvox * C) return;
+  const int c = (int)(e % C);
+  const long long v = e / C;
+  if (!(bf2f(y.p[v * y.cs + y.co + c]) > 0.f)) g.p[v * g.cs + g.co + c] = 0;
+}
+// x (fp32 [voxel][2]) -> bf16 [voxel][16], channels 2..15 zero
+__global__ void k_pack(long long nvox, const float* __restrict__ x, uint16_t* __restrict__ out) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nvox * 16) return;
+  const int c = (int)(e % 16);
+  const long long v = e / 16;
+  out[e] = c < 2 ? f2bf(x[v * 2 + c]) : (uint16_t)0;
+}
+// masked mean-square loss on channel 0: per-block partial sums of (y - t)^2 and
+// of the mask; gradient 2 (y - t) / count into g (bf16 [voxel][16], other
+// channels 0).  count comes from a first pass (k_count).
+__global__ void k_count(long long nvox, const uint8_t* __restrict__ mask, float* __restrict__ acc) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float s = (v < nvox && mask[v]) ? 1.f : 0.f;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(acc, s);
+}
+__global__ void k_loss(long long nvox, const float* __restrict__ y, const float* __restrict__ t,
+                       const uint8_t* __restrict__ mask, const float* __restrict__ count, float* __restrict__ acc,
+                       uint16_t* __restrict__ g) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float s = 0.f;
+  if (v < nvox) {
+    const float cnt = fmaxf(*count, 1.f);
+    float d = mask[v] ? (y[v] - t[v]) : 0.f;
+    s = d * d;
+    if (g) {
+      g[v * 16] = f2bf(2.f * d / cnt);
+      for (int c = 1; c < 16; ++c) g[v * 16 + c] = 0;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(acc, s);
+}
+__global__ void k_adam(long long np, float* __restrict__ w, const float* __restrict__ gr, float* __restrict__ m,
+                       float* __restrict__ v2, float lr, float b1, float b2, float eps, float c1, float c2,
+                       const uint8_t* __restrict__ frozen) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np || frozen[e]) return;
+  const float g = gr[e];
+  m[e] = b1 * m[e] + (1.f - b1) * g;
+  v2[e] = b2 * v2[e] + (1.f - b2) * g * g;
+  w[e] -= lr * (m[e] / c1) / (sqrtf(v2[e] / c2) + eps);
+}
+__global__ void k_to_bf16(long long np, const float* __restrict__ w, uint16_t* __restrict__ o) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < np) o[e] = f2bf(w[e]);
+}
+__global__ void k_fill0(long long count, float* __restrict__ p) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = 0.f;
+}
+__global__ void k_fill0_u16(long long count, uint16_t* __restrict__ p) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = 0;
+}
+
+inline int nblk(long long count, int bs = 256) { return (int)((count + bs - 1) / bs); }
+
+// ---------------------------------------------------------------- host side
+struct Layer {
+  int cin, cout;
+  long long offW, offB;  // offsets into the flat FP32 parameter array
+};
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) fail(CC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+}  // namespace cc
+
+using namespace cc;
+
+struct cc_net {
+  int C = 16;
+  hipStream_t stream = nullptr;
+  std::vector<Layer> layers;
+  long long np = 0;
+  DevMem pmem;                // parameters and optimizer state
+  float* w = nullptr;         // FP32 master weights
+  float* g = nullptr;         // gradients
+  float* m = nullptr;
+  float* v = nullptr;
+  uint8_t* frozen = nullptr;  // padded output channels stay 0
+  uint16_t* wb = nullptr;     // BF16 copy
+  uint16_t* wf = nullptr;     // flipped transpose scratch (largest layer)
+  long long step = 0;
+  // activations for (n, nb)
+  int an = 0, anb = 0;
+  DevMem amem;
+  uint16_t *X0 = nullptr, *CAT1 = nullptr, *P1 = nullptr, *CAT2 = nullptr, *P2 = nullptr, *BT = nullptr,
+           *D2 = nullptr, *D1 = nullptr, *Y = nullptr;
+  uint16_t *GY = nullptr, *GD1 = nullptr, *GCAT1 = nullptr, *GD2 = nullptr, *GCAT2 = nullptr, *GBT = nullptr,
+           *GP2 = nullptr, *GP1 = nullptr;
+  float* Y32 = nullptr;
+  float* red = nullptr;       // [0] loss sum, [1] mask count
+};
+
+namespace cc {
+namespace {
+
+void launch_conv(cc_net* N, int n, int nb, View in, int cin, const uint16_t* wt, const float* bias, int cout,
+                 int relu, View out, float* out32) {
+  const long long nvox = (long long)nb * n * n * n;
+  dim3 grid((unsigned)(nvox / 64)), block(256);
+  switch (cout / 16) {
+    case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 3: hipLaunchKernelGGL(k_conv_fwd<3>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 6: hipLaunchKernelGGL(k_conv_fwd<6>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 8: hipLaunchKernelGGL(k_conv_fwd<8>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    default: fail(CC_EINVAL, "unsupported channel count");
+  }
+}
+
+// gradients of one conv layer: dW, db from (in, g); gin = conv(g, flipped W) if gin.p
+void conv_backward(cc_net* N, const Layer& L, int n, int nb, View in, View g, View gin) {
+  const long long nvox = (long long)nb * n * n * n;
+  const int splits = (int)std::min<long long>(256, std::max<long long>(1, nvox / 4096));
+  const long long per = ((nvox + splits - 1) / splits + kWgChunk - 1) / kWgChunk * kWgChunk;
+  const size_t lds = (size_t)kWgChunk * (L.cout + L.cin) * sizeof(uint16_t);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(27, splits), dim3(256), lds, N->stream, n, nvox, in, L.cin, g, L.cout,
+                     N->g + L.offW, per);
+  hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, N->stream, nvox, g, L.cout, N->g + L.offB);
+  if (gin.p) {
+    const long long nw = 27LL * L.cout * L.cin;
+    hipLaunchKernelGGL(k_flip, dim3(nblk(nw)), dim3(256), 0, N->stream, N->wb + L.offW, L.cout, L.cin, N->wf);
+    launch_conv(N, n, nb, g, L.cout, N->wf, nullptr, L.cin, 0, gin, nullptr);
+  }
+}
+
+void ensure_acts(cc_net* N, int n, int nb) {
+  if (N->an == n && N->anb == nb) return;
+  N->amem.release();
+  const int C = N->C;
+  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  DevMem& A = N->amem;
+  N->X0 = A.alloc<uint16_t>(v1 * 16);
+  N->CAT1 = A.alloc<uint16_t>(v1 * 3 * C);
+  N->P1 = A.alloc<uint16_t>(v2 * C);
+  N->CAT2 = A.alloc<uint16_t>(v2 * 4 * C);
+  N->P2 = A.alloc<uint16_t>(v4 * 2 * C);
+  N->BT = A.alloc<uint16_t>(v4 * 2 * C);
+  N->D2 = A.alloc<uint16_t>(v2 * 2 * C);
+  N->D1 = A.alloc<uint16_t>(v1 * C);
+  N->Y = A.alloc<uint16_t>(v1 * 16);
+  N->GY = A.alloc<uint16_t>(v1 * 16);
+  N->GD1 = A.alloc<uint16_t>(v1 * C);
+  N->GCAT1 = A.alloc<uint16_t>(v1 * 3 * C);
+  N->GD2 = A.alloc<uint16_t>(v2 * 2 * C);
+  N->GCAT2 = A.alloc<uint16_t>(v2 * 4 * C);
+  N->GBT = A.alloc<uint16_t>(v4 * 2 * C);
+  N->GP2 = A.alloc<uint16_t>(v4 * 2 * C);
+  N->GP1 = A.alloc<uint16_t>(v2 * C);
+  N->Y32 = A.alloc<float>(v1);
+  N->red = A.alloc<float>(2);
+  N->an = n;
+  N->anb = nb;
+}
+
+void forward(cc_net* N, int n, int nb, const float* x) {
+  const int C = N->C;
+  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  hipStream_t st = N->stream;
+  const std::vector<Layer>& L = N->layers;
+  hipLaunchKernelGGL(k_pack, dim3(nblk(v1 * 16)), dim3(256), 0, st, v1, x, N->X0);
+  const View x0{N->X0, 16, 0}, e1{N->CAT1, 3 * C, 2 * C}, u1{N->CAT1, 3 * C, 0}, cat1{N->CAT1, 3 * C, 0};
+  const View p1{N->P1, C, 0}, e2{N->CAT2, 4 * C, 2 * C}, u2{N->CAT2, 4 * C, 0}, cat2{N->CAT2, 4 * C, 0};
+  const View p2{N->P2, 2 * C, 0}, bt{N->BT, 2 * C, 0}, d2{N->D2, 2 * C, 0}, d1{N->D1, C, 0}, y{N->Y, 16, 0};
+  launch_conv(N, n, nb, x0, 16, N->wb + L[0].offW, N->w + L[0].offB, C, 1, e1, nullptr);
+  hipLaunchKernelGGL(k_pool, dim3(nblk(v2 * C)), dim3(256), 0, st, n, nb, e1, p1, C);
+  launch_conv(N, n / 2, nb, p1, C, N->wb + L[1].offW, N->w + L[1].offB, 2 * C, 1, e2, nullptr);
+  hipLaunchKernelGGL(k_pool, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, n / 2, nb, e2, p2, 2 * C);
+  launch_conv(N, n / 4, nb, p2, 2 * C, N->wb + L[2].offW, N->w + L[2].offB, 2 * C, 1, bt, nullptr);
+  hipLaunchKernelGGL(k_up, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n / 2, nb, bt, u2, 2 * C);
+  launch_conv(N, n / 2, nb, cat2, 4 * C, N->wb + L[3].offW, N->w + L[3].offB, 2 * C, 1, d2, nullptr);
+  hipLaunchKernelGGL(k_up, dim3(nblk(v1 * 2 * C)), dim3(256), 0, st, n, nb, d2, u1, 2 * C);
+  launch_conv(N, n, nb, cat1, 3 * C, N->wb + L[4].offW, N->w + L[4].offB, C, 1, d1, nullptr);
+  launch_conv(N, n, nb, d1, C, N->wb + L[5].offW, N->w + L[5].offB, 16, 0, y, N->Y32);
+}
+
+void backward(cc_net* N, int n, int nb) {
+  const int C = N->C;
+  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  hipStream_t st = N->stream;
+  const std::vector<Layer>& L = N->layers;
+  const View x0{N->X0, 16, 0}, e1{N->CAT1, 3 * C, 2 * C}, cat1{N->CAT1, 3 * C, 0};
+  const View p1{N->P1, C, 0}, e2{N->CAT2, 4 * C, 2 * C}, cat2{N->CAT2, 4 * C, 0};
+  const View p2{N->P2, 2 * C, 0}, bt{N->BT, 2 * C, 0}, d2{N->D2, 2 * C, 0}, d1{N->D1, C, 0};
+  const View gy{N->GY, 16, 0}, gd1{N->GD1, C, 0}, gcat1{N->GCAT1, 3 * C, 0}, gu1{N->GCAT1, 3 * C, 0},
+      ge1{N->GCAT1, 3 * C, 2 * C};
+  const View gd2{N->GD2, 2 * C, 0}, gcat2{N->GCAT2, 4 * C, 0}, gu2{N->GCAT2, 4 * C, 0}, ge2{N->GCAT2, 4 * C, 2 * C};
+  const View gbt{N->GBT, 2 * C, 0}, gp2{N->GP2, 2 * C, 0}, gp1{N->GP1, C, 0};
+  const View none{nullptr, 0, 0};
+  conv_backward(N, L[5], n, nb, d1, gy, gd1);
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v1 * C)), dim3(256), 0, st, v1, C, gd1, d1);
+  conv_backward(N, L[4], n, nb, cat1, gd1, gcat1);
+  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n, nb, gu1, gd2, 2 * C);
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, v2, 2 * C, gd2, d2);
+  conv_backward(N, L[3], n / 2, nb, cat2, gd2, gcat2);
+  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, n / 2, nb, gu2, gbt, 2 * C);
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, v4, 2 * C, gbt, bt);
+  conv_backward(N, L[2], n / 4, nb, p2, gbt, gp2);
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n / 2, nb, gp2, ge2, 2 * C);
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, v2, 2 * C, ge2, e2);
+  conv_backward(N, L[1], n / 2, nb, p1, ge2, gp1);
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblk(v1 * C)), dim3(256), 0, st, n, nb, gp1, ge1, C);
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v1 * C)), dim3(256), 0, st, v1, C, ge1, e1);
+  conv_backward(N, L[0], n, nb, x0, ge1, none);
+}
+
+void check_shape(int n, int nb) {
+  if (n < 16 || n % 16 != 0) fail(CC_EINVAL, "grid size must be a positive multiple of 16");
+  if (nb < 1) fail(CC_EINVAL, "batch must be positive");
+}
+
+template <class F>
+int net_guard(F&& f) {
+  try {
+    f();
+    return CC_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return CC_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CC_EINVAL;
+  }
+}
+
+}  // namespace
+}  // namespace cc
+
+extern "C" {
+
+int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_net** out) {
+  return net_guard([&] {
+    if (!out) fail(CC_EINVAL, "null output");
+    *out = nullptr;
+    if (base_channels != 16 && base_channels != 32) fail(CC_EINVAL, "base_channels must be 16 or 32");
+    auto N = std::make_unique<cc_net>();
+    N->C = base_channels;
+    N->stream = (hipStream_t)stream;
+    const int C = base_channels;
+    const int io[6][2] = {{16, C}, {C, 2 * C}, {2 * C, 2 * C}, {4 * C, 2 * C}, {3 * C, C}, {C, 16}};
+    long long off = 0;
+    for (auto& p : io) {
+      Layer L{p[0], p[1], off, off + 27LL * p[0] * p[1]};
+      off = L.offB + p[1];
+      N->layers.push_back(L);
+    }
+    N->np = off;
+    // He-normal weights over the real fan-in; padded input (first layer,
+    // channels 2..15) and output (last layer, channels 1..15) weights are 0 and
+    // the latter frozen
+    std::vector<float> w(off, 0.f);
+    std::vector<uint8_t> frozen(off, 0);
+    std::mt19937_64 rng(seed);
+    for (size_t li = 0; li < N->layers.size(); ++li) {
+      const Layer& L = N->layers[li];
+      const int real_in = li == 0 ? 2 : L.cin;
+      std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (27.f * real_in)));
+      for (int tap = 0; tap < 27; ++tap)
+        for (int co = 0; co < L.cout; ++co)
+          for (int ci = 0; ci < L.cin; ++ci) {
+            long long e = L.offW + ((long long)tap * L.cout + co) * L.cin + ci;
+            bool pad = (li == 0 && ci >= 2) || (li == 5 && co >= 1);
+            w[e] = pad ? 0.f : nd(rng);
+            if (li == 5 && co >= 1) frozen[e] = 1;
+          }
+      for (int co = 0; co < L.cout; ++co)
+        if (li == 5 && co >= 1) frozen[L.offB + co] = 1;
+    }
+    DevMem& P = N->pmem;
+    N->w = P.alloc<float>(off);
+    N->g = P.alloc<float>(off);
+    N->m = P.alloc<float>(off);
+    N->v = P.alloc<float>(off);
+    N->frozen = P.alloc<uint8_t>(off);
+    N->wb = P.alloc<uint16_t>(off);
+    long long wmax = 0;
+    for (const Layer& L : N->layers) wmax = std::max(wmax, 27LL * L.cin * L.cout);
+    N->wf = P.alloc<uint16_t>(wmax);
+    NETCHK(hipMemcpy(N->w, w.data(), off * sizeof(float), hipMemcpyHostToDevice));
+    NETCHK(hipMemcpy(N->frozen, frozen.data(), off, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_fill0, dim3(nblk(off)), dim3(256), 0, N->stream, off, N->g);
+    hipLaunchKernelGGL(k_fill0, dim3(nblk(off)), dim3(256), 0, N->stream, off, N->m);
+    hipLaunchKernelGGL(k_fill0, dim3(nblk(off)), dim3(256), 0, N->stream, off, N->v);
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(off)), dim3(256), 0, N->stream, off, N->w, N->wb);
+    NETCHK(hipStreamSynchronize(N->stream));
+    *out = N.release();
+  });
+}
+
+long long cc_net_num_params(const cc_net* N) { return N ? N->np : 0; }
+
+int cc_net_get_params(const cc_net* N, float* host) {
+  return net_guard([&] {
+    if (!N || !host) fail(CC_EINVAL, "null argument");
+    NETCHK(hipMemcpyAsync(host, N->w, N->np * sizeof(float), hipMemcpyDeviceToHost, N->stream));
+    NETCHK(hipStreamSynchronize(N->stream));
+  });
+}
+
+int cc_net_set_params(cc_net* N, const float* host) {
+  return net_guard([&] {
+    if (!N || !host) fail(CC_EINVAL, "null argument");
+    NETCHK(hipMemcpyAsync(N->w, host, N->np * sizeof(float), hipMemcpyHostToDevice, N->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(N->np)), dim3(256), 0, N->stream, N->np, N->w, N->wb);
+    NETCHK(hipStreamSynchronize(N->stream));
+  });
+}
+
+int cc_net_forward(cc_net* N, int n, int nb, const float* x, float* y) {
+  return net_guard([&] {
+    if (!N || !x || !y) fail(CC_EINVAL, "null argument");
+    check_shape(n, nb);
+    ensure_acts(N, n, nb);
+    forward(N, n, nb, x);
+    const long long v1 = (long long)nb * n * n * n;
+    NETCHK(hipMemcpyAsync(y, N->Y32, v1 * sizeof(float), hipMemcpyDeviceToDevice, N->stream));
+    NETCHK(hipStreamSynchronize(N->stream));
+  });
+}
+
+int cc_net_loss_grad(cc_net* N, int n, int nb, const float* x, const float* target, const unsigned char* mask,
+                     double* loss, float* grad_host) {
+  return net_guard([&] {
+    if (!N || !x || !target || !mask) fail(CC_EINVAL, "null argument");
+    check_shape(n, nb);
+    ensure_acts(N, n, nb);
+    const long long v1 = (long long)nb * n * n * n;
+    hipStream_t st = N->stream;
+    forward(N, n, nb, x);
+    hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, st, 2LL, N->red);
+    hipLaunchKernelGGL(k_count, dim3(nblk(v1)), dim3(256), 0, st, v1, mask, N->red + 1);
+    hipLaunchKernelGGL(k_loss, dim3(nblk(v1)), dim3(256), 0, st, v1, N->Y32, target, mask, N->red + 1, N->red,
+                       N->GY);
+    // gradient buffers that are accumulated into must start at zero
+    const int C = N->C;
+    hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(v1 * 3 * C)), dim3(256), 0, st, v1 * 3 * C, N->GCAT1);
+    hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(v1 / 8 * 4 * C)), dim3(256), 0, st, v1 / 8 * 4 * C, N->GCAT2);
+    hipLaunchKernelGGL(k_fill0, dim3(nblk(N->np)), dim3(256), 0, st, N->np, N->g);
+    backward(N, n, nb);
+    float red[2];
+    NETCHK(hipMemcpyAsync(red, N->red, sizeof(red), hipMemcpyDeviceToHost, st));
+    NETCHK(hipStreamSynchronize(st));
+    if (loss) *loss = red[1] > 0 ? (double)red[0] / red[1] : 0.0;
+    if (grad_host) {
+      NETCHK(hipMemcpyAsync(grad_host, N->g, N->np * sizeof(float), hipMemcpyDeviceToHost, st));
+      NETCHK(hipStreamSynchronize(st));
+    }
+  });
+}
+
+int cc_net_adam_step(cc_net* N, float lr, float beta1, float beta2, float eps) {
+  return net_guard([&] {
+    if (!N) fail(CC_EINVAL, "null argument");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+      fail(CC_EINVAL, "bad optimizer parameters");
+    N->step += 1;
+    const float c1 = 1.f - std::pow(beta1, (float)N->step), c2 = 1.f - std::pow(beta2, (float)N->step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(N->np)), dim3(256), 0, N->stream, N->np, N->w, N->g, N->m, N->v, lr, beta1,
+                       beta2, eps, c1, c2, N->frozen);
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(N->np)), dim3(256), 0, N->stream, N->np, N->w, N->wb);
+    NETCHK(hipStreamSynchronize(N->stream));
+  });
+}
+
+void cc_net_destroy(cc_net* N) {
+  if (!N) return;
+  if (N->stream) (void)hipStreamSynchronize(N->stream);
+  N->amem.release();
+  N->pmem.release();
+  delete N;
+}
+
+}  // extern "C"

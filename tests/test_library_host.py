@@ -29,7 +29,7 @@ def _lib():
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*(cc_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|long long|const char\s*\*)\s*(cc_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_symbols_exported():
