@@ -74,6 +74,9 @@ typedef struct cc_params {
   int leaf_size;      /* nested-dissection leaf size, default 64 */
   int device;         /* HIP device ordinal; -1 builds a host-only handle */
   int use_graph;      /* capture the V-cycle in a hipGraph (default 1) */
+  int krylov;         /* 0 (default): the plain multigrid iteration; k > 0: restarted
+                         GMRES(k) preconditioned by one V-cycle per iteration (FP64;
+                         for geometries where the plain iteration does not contract) */
 } cc_params;
 
 /* Analytic fields (problem data).  data layout by kind:

@@ -155,6 +155,18 @@ struct Work {
   }
 };
 
+// Restarted GMRES workspace: k+1 Arnoldi vectors, k preconditioned vectors,
+// one work vector (all level-0 grids), small device buffers.
+struct Krylov {
+  int k = 0;
+  DevBuf own;
+  double* V = nullptr;
+  double* Z = nullptr;
+  double* w = nullptr;
+  double* d = nullptr;
+  unsigned long long* amax = nullptr;
+};
+
 }  // namespace
 
 }  // namespace cc
@@ -182,6 +194,7 @@ struct cc_problem {
   float* net_x = nullptr;
   float* net_y = nullptr;
   long long net_cells = 0;
+  cc::Krylov kr;                // GMRES acceleration (cc_params.krylov > 0)
 };
 
 namespace cc {
@@ -573,6 +586,140 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
   HIPCHK(hipStreamSynchronize(P->stream));
 }
 
+// Restarted flexible GMRES(k), right-preconditioned by one FP64 V-cycle per
+// iteration (cc_params.krylov = k > 0): an acceleration of the multigrid
+// iteration for geometries where the plain iteration does not contract.  The
+// outer residual, the max-norm test and the iteration count (V-cycles) are
+// those of the plain iteration.
+void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
+  Work<double>& W = P->w64;
+  DevLevel& D0 = P->dev[0];
+  const long long n3 = cube(D0.st.n);
+  const int k = P->prm.krylov;
+  Krylov& K = P->kr;
+  if (K.k != k) {
+    K.own.release();
+    K.k = k;
+    K.V = K.own.alloc<double>((size_t)(k + 1) * n3);
+    K.Z = K.own.alloc<double>((size_t)k * n3);
+    K.w = K.own.alloc<double>((size_t)n3);
+    K.d = K.own.alloc<double>((size_t)k + 2);
+    K.amax = K.own.alloc<unsigned long long>(1);
+  }
+  hipStream_t st = P->stream;
+  auto dots = [&](const double* w, const double* V, int nv) {
+    launch_dots(n3, w, V, n3, nv, K.d, st);
+    std::vector<double> h(nv);
+    HIPCHK(hipMemcpyAsync(h.data(), K.d, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return h;
+  };
+  auto put = [&](const std::vector<double>& c) {
+    HIPCHK(hipMemcpyAsync(K.d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  auto maxabs = [&](const double* v) {
+    launch_zero_u64(P->d_norm, 1, st);
+    launch_maxabs(v, n3, 1, P->d_norm, st);
+    return read_norm(P);
+  };
+  const double rn = maxabs(r);
+  if (!std::isfinite(rn)) fail(CC_EINVAL, "non-finite right-hand side");
+  launch_mask_unknowns(D0.st, phi, 1, st);
+  const double nunk = (double)P->lv[0]->unknowns.size();
+  rec = SolveRec{};
+  int cycles = 0;
+  for (;;) {
+    residual(P, 0, r, phi, W.s0, 1);
+    const double rel = rn > 0 ? maxabs(W.s0) / rn : 0.0;
+    rec.hist.push_back(rel);
+    rec.rel = rel;
+    if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
+    if (rel < P->prm.tol || cycles >= P->prm.max_iter) break;
+    const double beta = std::sqrt(dots(W.s0, W.s0, 1)[0]);
+    put({1.0 / beta});
+    launch_combo(n3, W.s0, n3, 1, K.d, K.V, 0, nullptr, st);
+    std::vector<std::vector<double>> Hb(k + 1, std::vector<double>(k, 0.0));  // unrotated
+    std::vector<std::vector<double>> R(k + 1, std::vector<double>(k, 0.0));   // rotated
+    std::vector<double> cs(k), sn(k), g(k + 1, 0.0);
+    g[0] = beta;
+    int j = 0;
+    bool converged = false;
+    auto solve_y = [&](int m) {
+      std::vector<double> y(m, 0.0);
+      for (int i = m - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < m; ++l) t -= R[i][l] * y[l];
+        y[i] = t / R[i][i];
+      }
+      return y;
+    };
+    while (j < k && cycles < P->prm.max_iter) {
+      double* vj = K.V + (long long)j * n3;
+      double* zj = K.Z + (long long)j * n3;
+      vcycle<double>(P, W, 0, vj, zj, W.et[0], 1);
+      ++cycles;
+      launch_stencil_apply(D0.st, zj, K.w, st);
+      launch_plg_residual(D0.plg, nullptr, zj, K.w, 1, 1, n3, st);
+      std::vector<double> h = dots(K.w, K.V, j + 1);  // classical Gram-Schmidt, twice
+      put(h);
+      launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
+      std::vector<double> h2 = dots(K.w, K.V, j + 1);
+      put(h2);
+      launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      const double hn = std::sqrt(dots(K.w, K.w, 1)[0]);
+      for (int i = 0; i <= j; ++i) Hb[i][j] = R[i][j] = h[i];
+      Hb[j + 1][j] = R[j + 1][j] = hn;
+      if (hn > 0) {
+        put({1.0 / hn});
+        launch_combo(n3, K.w, n3, 1, K.d, K.V + (long long)(j + 1) * n3, 0, nullptr, st);
+      }
+      for (int i = 0; i < j; ++i) {
+        const double a = R[i][j], b = R[i + 1][j];
+        R[i][j] = cs[i] * a + sn[i] * b;
+        R[i + 1][j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = R[j][j], b = R[j + 1][j], den = std::hypot(a, b);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? b / den : 0.0;
+      R[j][j] = den;
+      R[j + 1][j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++j;
+      const double est = std::fabs(g[j]);
+      // |res|_inf >= |res|_2 / sqrt(N): the max-norm test can pass only if
+      if (est <= P->prm.tol * rn * std::sqrt(nunk) || hn == 0.0) {
+        // residual vector V_{j+1} (beta e1 - Hb y), its max-norm
+        std::vector<double> y = solve_y(j), c(j + 1, 0.0);
+        c[0] = beta;
+        for (int i = 0; i <= j; ++i)
+          for (int l = 0; l < j; ++l) c[i] -= Hb[i][l] * y[l];
+        put(c);
+        launch_zero_u64(K.amax, 1, st);
+        launch_combo(n3, K.V, n3, j + 1, K.d, nullptr, 0, K.amax, st);
+        unsigned long long bits = 0;
+        HIPCHK(hipMemcpyAsync(&bits, K.amax, sizeof(bits), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        double res;
+        std::memcpy(&res, &bits, sizeof(res));
+        if (res < P->prm.tol * rn || hn == 0.0) {
+          converged = true;
+          break;
+        }
+      }
+    }
+    std::vector<double> y = solve_y(j);
+    put(y);
+    launch_combo(n3, K.Z, n3, j, K.d, phi, 1, nullptr, st);
+    (void)converged;
+  }
+  rec.iterations = cycles;
+  launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, n3, 1, st);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 void fill_info(const SolveRec& rc, double seconds, cc_solve_info* info) {
   if (!info) return;
   info->iterations = rc.iterations;
@@ -679,6 +826,7 @@ void cc_default_params(cc_params* p) {
   p->leaf_size = 64;
   p->device = 0;
   p->use_graph = 1;
+  p->krylov = 0;
 }
 
 int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out) {
@@ -693,6 +841,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (prm->nu1 < 0 || prm->nu2 < 0 || prm->max_iter < 0 || prm->n_min < 8 || prm->leaf_size < 1)
       fail(CC_EINVAL, "bad multigrid parameters");
     if (prm->precision != CC_FP64 && prm->precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
+    if (prm->krylov < 0 || prm->krylov > 64) fail(CC_EINVAL, "krylov must lie in [0, 64]");
     for (int a = 0; a < 6; ++a)
       if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
     auto P = std::make_unique<cc_problem>();
@@ -1041,7 +1190,11 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
     need_device(p);
     double t0 = now_s();
     std::vector<SolveRec> rec;
-    if (p->prm.precision == CC_MIXED) {
+    if (p->prm.krylov > 0) {
+      if (p->prm.precision == CC_MIXED) fail(CC_EINVAL, "Krylov acceleration runs in FP64 (precision CC_FP64)");
+      rec.resize(1);
+      gmres_loop(p, r, phi, rec[0]);
+    } else if (p->prm.precision == CC_MIXED) {
       if (p->w32.nb < 1) alloc_work(p, p->w32, 1);
       solve_loop<float>(p, p->w32, r, phi, 1, rec);
     } else {
@@ -1108,11 +1261,22 @@ int cc_solve_batched(cc_problem* p, int nrhs, const double* r, double* phi, cc_s
     const long long n3 = cube(p->dev[0].st.n);
     const int cap = std::min(nrhs, CC_BATCH_MAX);
     const bool mixed = p->prm.precision == CC_MIXED;
-    if (mixed ? p->wb32.nb < cap : p->wb64.nb < cap) {
+    if (p->prm.krylov <= 0 && (mixed ? p->wb32.nb < cap : p->wb64.nb < cap)) {
       if (mixed)
         alloc_work(p, p->wb32, cap);
       else
         alloc_work(p, p->wb64, cap);
+    }
+    if (p->prm.krylov > 0) {  // Krylov acceleration: one right-hand side at a time
+      if (mixed) fail(CC_EINVAL, "Krylov acceleration runs in FP64 (precision CC_FP64)");
+      for (int b = 0; b < nrhs; ++b) {
+        double t0 = now_s();
+        SolveRec rc;
+        gmres_loop(p, r + b * n3, phi + b * n3, rc);
+        if (info) fill_info(rc, now_s() - t0, info + b);
+        if (!(rc.rel < p->prm.tol)) conv = 0;
+      }
+      return;
     }
     for (int b0 = 0; b0 < nrhs; b0 += CC_BATCH_MAX) {
       const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
@@ -1233,6 +1397,7 @@ void cc_destroy(cc_problem* p) {
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     p->w64.drop_graph();
+    p->kr.own.release();
     p->w32.release();
     p->wb64.release();
     p->wb32.release();

@@ -619,6 +619,38 @@ __global__ void k_prolong_trilinear(StencilLevel L0, int m, const float* __restr
   phi[c] = scale * v;
 }
 
+// Krylov vectors (n3 doubles each, stride apart): out[i] += (w, V_i) for
+// i = blockIdx.y (per-block partial sums, atomically combined)
+__global__ void k_dots(long long n3, const double* __restrict__ w, const double* __restrict__ V, long long stride,
+                       double* __restrict__ out) {
+  const double* v = V + blockIdx.y * stride;
+  double s = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3; c += (long long)gridDim.x * blockDim.x)
+    s += w[c] * v[c];
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out + blockIdx.y, s);
+}
+
+// out = mode 0: sum_i coef[i] V_i;  1: out + sum;  2: out - sum;  3: scale: coef[0] * V_0
+// and, if amax is not null, atomicMax of max |out| (bit pattern)
+__global__ void k_combo(long long n3, const double* __restrict__ V, long long stride, int nv,
+                        const double* __restrict__ coef, double* __restrict__ out, int mode,
+                        unsigned long long* __restrict__ amax) {
+  double m = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3;
+       c += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += coef[i] * V[i * stride + c];
+    double o = mode == 0 || mode == 3 ? s : (mode == 1 ? out[c] + s : out[c] - s);
+    if (out) out[c] = o;
+    m = fmax(m, fabs(o));
+  }
+  if (amax) {
+    m = wave_max(m);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(amax, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 // plain copy (used to calibrate memory-traffic counters against a known size)
 __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long count) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -758,6 +790,17 @@ void launch_net_features(int n0, int m, const double* r, double inv_norm, const 
 void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_prolong_trilinear, dim3(blocks(cube(L0.n), 256)), dim3(256), 0, st, L0, m, y, scale, phi);
+}
+void launch_dots(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, out, (long long)nv);
+  const int g = (int)std::min<long long>(blocks(n3, 256), 1024);
+  hipLaunchKernelGGL(k_dots, dim3(g, nv), dim3(256), 0, st, n3, w, V, stride, out);
+}
+void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
+                  unsigned long long* amax, hipStream_t st) {
+  const int g = (int)std::min<long long>(blocks(n3, 256), 4096);
+  hipLaunchKernelGGL(k_combo, dim3(g), dim3(256), 0, st, n3, V, stride, nv, coef, out, mode, amax);
 }
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st) {
   if (count == 0) return;

@@ -124,6 +124,13 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st);
+// Krylov helpers over n3-element FP64 vectors stored `stride` apart:
+// out[i] = (w, V_i), i < nv (out zeroed first);  out = / += / -= sum_i coef_i V_i
+// (mode 0 / 1 / 2; coef on the device) with optional max |out| into *amax
+void launch_dots(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
+                 hipStream_t st);
+void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
+                  unsigned long long* amax, hipStream_t st);
 // learned guess: coarse features (block mean of r scaled, volume fraction) and
 // trilinear prolongation of the network output to the level-0 unknowns
 void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
