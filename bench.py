@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=64)
@@ -219,6 +221,26 @@ def main():
             print(f"[bench] mixed: {sec_m * 1e3:.1f} ms, {info_m['iterations']} V-cycles", file=sys.stderr, flush=True)
             out_mixed = {"s_per_solve": sec_m, "v_cycles": info_m["iterations"],
                          "final_rel_residual": info_m["rel_residual"], "speedup_vs_plain": sec / sec_m}
+        out_krylov = None
+        if not args.no_krylov:
+            P.set_krylov(args.krylov)
+            sec_k, info_k = _timed(solve_once, args.steps, args.warmup)
+            P.set_krylov(0)
+            print(f"[bench] GMRES({args.krylov}): {sec_k * 1e3:.1f} ms, {info_k['iterations']} V-cycles", file=sys.stderr,
+                  flush=True)
+            out_krylov = {"restart": args.krylov, "s_per_solve": sec_k, "v_cycles": info_k["iterations"],
+                          "final_rel_residual": info_k["rel_residual"], "speedup_vs_plain": sec / sec_k}
+            if not args.no_mixed:
+                P.set_krylov(args.krylov)
+                P.set_precision(_lib.CC_MIXED)
+                sec_km, info_km = _timed(solve_once, args.steps, args.warmup)
+                P.set_precision(_lib.CC_FP64)
+                P.set_krylov(0)
+                print(f"[bench] GMRES({args.krylov}) + FP32 V-cycle: {sec_km * 1e3:.1f} ms, "
+                      f"{info_km['iterations']} V-cycles", file=sys.stderr, flush=True)
+                out_krylov["mixed_preconditioner"] = {
+                    "s_per_solve": sec_km, "v_cycles": info_km["iterations"],
+                    "final_rel_residual": info_km["rel_residual"], "speedup_vs_plain": sec / sec_km}
         out_batch = None
         if not args.no_batch and args.batch > 0:
             B = args.batch
@@ -290,6 +312,7 @@ def main():
         "dof_per_s": N * cycles / sec,
         "setup_s": t_setup,
         "mixed": out_mixed,
+        "krylov": out_krylov,
         "batched": out_batch,
         "learned": out_learned,
         "roofline": {

@@ -75,8 +75,9 @@ typedef struct cc_params {
   int device;         /* HIP device ordinal; -1 builds a host-only handle */
   int use_graph;      /* capture the V-cycle in a hipGraph (default 1) */
   int krylov;         /* 0 (default): the plain multigrid iteration; k > 0: restarted
-                         GMRES(k) preconditioned by one V-cycle per iteration (FP64;
-                         for geometries where the plain iteration does not contract) */
+                         flexible GMRES(k) in FP64 preconditioned by one V-cycle per
+                         iteration (an FP32 V-cycle with CC_MIXED); converges also
+                         where the plain iteration does not contract */
 } cc_params;
 
 /* Analytic fields (problem data).  data layout by kind:
@@ -159,7 +160,12 @@ int cc_solve(cc_problem* p, const double* r_dev, double* phi_dev, cc_solve_info*
  * CC_MIXED); the build-time value is cc_params.precision. */
 int cc_set_precision(cc_problem* p, int precision);
 
-/* Several right-hand sides on one geometry: r_dev and phi_dev hold nrhs arrays of
+/* Switch between the plain multigrid iteration (0) and GMRES(k) preconditioned
+ * by the V-cycle (k in 1..64) for later solves; build-time value cc_params.krylov. */
+int cc_set_krylov(cc_problem* p, int krylov);
+
+/* Several right-hand sides on one geometry (with krylov > 0 they are solved one
+ * after the other): r_dev and phi_dev hold nrhs arrays of
  * n^3 at a stride of n^3 (batch-major).  Groups of up to CC_BATCH_MAX
  * right-hand sides run together: every kernel of the V-cycle processes the whole
  * group in one launch, and the LU-correction reads each factor entry once for

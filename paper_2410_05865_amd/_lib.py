@@ -30,7 +30,7 @@ EXPORTED = [
     "cc_default_params", "cc_build", "cc_num_levels", "cc_get_level_info", "cc_assemble_rhs", "cc_solve",
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
-    "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision",
+    "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -106,6 +106,7 @@ def load() -> C.CDLL:
     lib.cc_selfcheck_lu.argtypes = [vp, C.c_int, P(C.c_double)]
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_set_precision.argtypes = [vp, C.c_int]
+    lib.cc_set_krylov.argtypes = [vp, C.c_int]
     lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
     lib.cc_net_num_params.restype = C.c_longlong
@@ -275,6 +276,10 @@ class Problem:
     def set_precision(self, precision: int):
         _check(load().cc_set_precision(self._h, precision))
         self.params.precision = precision
+
+    def set_krylov(self, k: int):
+        _check(load().cc_set_krylov(self._h, k))
+        self.params.krylov = k
 
     def solve(self, r, phi) -> dict:
         n3 = self.n() ** 3

@@ -586,16 +586,19 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
   HIPCHK(hipStreamSynchronize(P->stream));
 }
 
-// Restarted flexible GMRES(k), right-preconditioned by one FP64 V-cycle per
-// iteration (cc_params.krylov = k > 0): an acceleration of the multigrid
-// iteration for geometries where the plain iteration does not contract.  The
-// outer residual, the max-norm test and the iteration count (V-cycles) are
-// those of the plain iteration.
+// Restarted flexible GMRES(k), right-preconditioned by one V-cycle per
+// iteration (cc_params.krylov = k > 0; FP64, or the FP32 V-cycle on the
+// max-norm-scaled vector in mixed precision): an acceleration of the multigrid
+// iteration, also for geometries where the plain iteration does not contract.
+// The Krylov vectors, the outer residual, the max-norm test and the iteration
+// count (V-cycles) are FP64 as in the plain iteration.
 void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
   Work<double>& W = P->w64;
   DevLevel& D0 = P->dev[0];
   const long long n3 = cube(D0.st.n);
   const int k = P->prm.krylov;
+  const bool mixed = P->prm.precision == CC_MIXED;
+  if (mixed && P->w32.nb < 1) alloc_work(P, P->w32, 1);
   Krylov& K = P->kr;
   if (K.k != k) {
     K.own.release();
@@ -657,18 +660,35 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     while (j < k && cycles < P->prm.max_iter) {
       double* vj = K.V + (long long)j * n3;
       double* zj = K.Z + (long long)j * n3;
-      vcycle<double>(P, W, 0, vj, zj, W.et[0], 1);
+      if (mixed) {
+        // z = max|v| * VCycle32(v / max|v|): the FP32 V-cycle as preconditioner
+        Work<float>& W32 = P->w32;
+        launch_zero_u64(P->d_norm, 1, st);
+        launch_maxabs(vj, n3, 1, P->d_norm, st);
+        launch_scale_residual<float>(n3, vj, P->d_norm, W32.s[0], 1, st);
+        vcycle<float>(P, W32, 0, W32.s[0], W32.e[0], W32.et[0], 1);
+        launch_zero<double>(zj, n3, st);
+        launch_add_unknowns<float>(D0.st, W32.e[0], P->d_norm, zj, 1, st);
+      } else {
+        vcycle<double>(P, W, 0, vj, zj, W.et[0], 1);
+      }
       ++cycles;
       launch_stencil_apply(D0.st, zj, K.w, st);
       launch_plg_residual(D0.plg, nullptr, zj, K.w, 1, 1, n3, st);
-      std::vector<double> h = dots(K.w, K.V, j + 1);  // classical Gram-Schmidt, twice
+      // classical Gram-Schmidt; a second pass only when the norm drops by more
+      // than 1/sqrt(2) (Daniel-Gragg-Kaufman-Stewart criterion)
+      const double wn0 = std::sqrt(dots(K.w, K.w, 1)[0]);
+      std::vector<double> h = dots(K.w, K.V, j + 1);
       put(h);
       launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
-      std::vector<double> h2 = dots(K.w, K.V, j + 1);
-      put(h2);
-      launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
-      for (int i = 0; i <= j; ++i) h[i] += h2[i];
-      const double hn = std::sqrt(dots(K.w, K.w, 1)[0]);
+      double hn = std::sqrt(dots(K.w, K.w, 1)[0]);
+      if (hn < 0.7071 * wn0) {
+        std::vector<double> h2 = dots(K.w, K.V, j + 1);
+        put(h2);
+        launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
+        for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        hn = std::sqrt(dots(K.w, K.w, 1)[0]);
+      }
       for (int i = 0; i <= j; ++i) Hb[i][j] = R[i][j] = h[i];
       Hb[j + 1][j] = R[j + 1][j] = hn;
       if (hn > 0) {
@@ -1191,7 +1211,6 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
     double t0 = now_s();
     std::vector<SolveRec> rec;
     if (p->prm.krylov > 0) {
-      if (p->prm.precision == CC_MIXED) fail(CC_EINVAL, "Krylov acceleration runs in FP64 (precision CC_FP64)");
       rec.resize(1);
       gmres_loop(p, r, phi, rec[0]);
     } else if (p->prm.precision == CC_MIXED) {
@@ -1253,6 +1272,14 @@ int cc_set_precision(cc_problem* p, int precision) {
   });
 }
 
+int cc_set_krylov(cc_problem* p, int krylov) {
+  return guard([&] {
+    if (!p) fail(CC_EINVAL, "null problem");
+    if (krylov < 0 || krylov > 64) fail(CC_EINVAL, "krylov must lie in [0, 64]");
+    p->prm.krylov = krylov;
+  });
+}
+
 int cc_solve_batched(cc_problem* p, int nrhs, const double* r, double* phi, cc_solve_info* info) {
   int conv = 1;
   int rc = guard([&] {
@@ -1268,7 +1295,6 @@ int cc_solve_batched(cc_problem* p, int nrhs, const double* r, double* phi, cc_s
         alloc_work(p, p->wb64, cap);
     }
     if (p->prm.krylov > 0) {  // Krylov acceleration: one right-hand side at a time
-      if (mixed) fail(CC_EINVAL, "Krylov acceleration runs in FP64 (precision CC_FP64)");
       for (int b = 0; b < nrhs; ++b) {
         double t0 = now_s();
         SolveRec rc;

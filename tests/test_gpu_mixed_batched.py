@@ -186,6 +186,16 @@ def test_krylov_acceleration():
     assert _rel(got, xd) < 1e-9
     print(f"[krylov] ellipsoid32: plain {i_plain['iterations']} V-cycles, GMRES {i_k['iterations']}", flush=True)
     Q.close()
+    # FP32 V-cycle as the preconditioner (flexible GMRES, FP64 vectors)
+    Q = L.Problem(dom, krylov=20, precision=L.CC_MIXED)
+    phi = _dev(np.zeros(lv.n ** 3))
+    i_km = Q.solve(r, phi)
+    assert i_km["converged"] and i_km["iterations"] <= i_k["iterations"] + 2
+    got = phi.cpu().numpy()[lv.unknowns]
+    assert np.max(np.abs(r_or - lv.L @ got)) < 1e-10 * np.max(np.abs(r_or))
+    assert _rel(got, xd) < 1e-9
+    print(f"[krylov] ellipsoid32 mixed-precision preconditioner: {i_km['iterations']} V-cycles", flush=True)
+    Q.close()
     from paper_2410_05865_amd import inputs as inp
     dom = inp.ellipsoid_domain(n=64, seed=4)
     for kr in (0, 20):
