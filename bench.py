@@ -109,6 +109,54 @@ def _timed(fn, steps: int, warmup: int):
     return (time.perf_counter() - t0) / steps, out
 
 
+def _multi_leg(args):
+    """16 geometries of the ellipsoid family (8 at 64^3, 8 at 128^3, seeds
+    2000..2015), each with a Gaussian right-hand side, solved with GMRES(20)
+    one after the other and all at once (cc_solve_multi: one stream and host
+    thread per problem)."""
+    import torch
+    from paper_2410_05865_amd import _lib, inputs
+    t0 = time.perf_counter()
+    probs, rs, phis, dofs = [], [], [], 0
+    for i in range(16):
+        n = 64 if i < 8 else 128
+        dom = inputs.ellipsoid_domain(n=n, seed=2000 + i)
+        P = _lib.Problem(dom, krylov=args.krylov)
+        r = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(inputs.gaussian_rhs(dom, seed=3000 + i), None, r)
+        probs.append(P)
+        rs.append(r)
+        phis.append(torch.zeros_like(r))
+        dofs += P.level_info(0)["n_unknowns"]
+    t_setup = time.perf_counter() - t0
+
+    def seq():
+        out = []
+        for P, r, x in zip(probs, rs, phis):
+            x.zero_()
+            out.append(P.solve(r, x))
+        return out
+
+
+    def conc():
+        for x in phis:
+            x.zero_()
+        torch.cuda.synchronize()
+        return _lib.solve_multi(probs, rs, phis)
+
+    s_seq, i_seq = _timed(seq, 1, 1)
+    s_con, i_con = _timed(conc, 1, 1)
+    for P in probs:
+        P.close()
+    print(f"[bench] 16 geometries: sequential {s_seq * 1e3:.0f} ms, concurrent {s_con * 1e3:.0f} ms", file=sys.stderr,
+          flush=True)
+    return {"problems": "8 x 64^3 + 8 x 128^3 ellipsoid geometries (seeds 2000-2015), Gaussian right-hand sides, "
+                        f"GMRES({args.krylov}) with the V-cycle",
+            "unknowns": dofs, "setup_s": t_setup, "sequential_s": s_seq, "concurrent_s": s_con,
+            "speedup": s_seq / s_con, "all_converged": all(i["converged"] for i in i_con),
+            "v_cycles": [i["iterations"] for i in i_con]}
+
+
 def _learned_leg(P, dom, args, stream):
     """Train the learned guess on solver-generated pairs (64^3 problems of the
     same family, network on their 32^3 level; a 3-level U-Net on a 64^3 grid
@@ -160,6 +208,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -274,6 +323,9 @@ def main():
                                                   f"g = 0", **res}
             del rb, xb
             torch.cuda.empty_cache()
+        out_multi = None
+        if not args.no_multi:
+            out_multi = _multi_leg(args)
         out_learned = None
         if not args.no_learned:
             out_learned = _learned_leg(P, dom, args, stream)
@@ -315,6 +367,7 @@ def main():
         "krylov": out_krylov,
         "batched": out_batch,
         "learned": out_learned,
+        "multi_geometry": out_multi,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_smo1<double> (SMO-1 weighted Jacobi, level 0)",

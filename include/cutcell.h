@@ -156,6 +156,14 @@ int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field
  * factors are made at cc_build; FP32 work arrays at the first mixed solve. */
 int cc_solve(cc_problem* p, const double* r_dev, double* phi_dev, cc_solve_info* info);
 
+/* Several problems (geometries, sizes) at once: problem i solves L phi_i = r_i as
+ * cc_solve does, each on its own host thread and its own stream (every handle
+ * must have been built with a distinct stream, e.g. NULL: a library stream), so
+ * the problems' kernels run concurrently.  info, if not NULL, has nprob entries.
+ * Returns CC_OK, else the status of a failing problem (message names it). */
+int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r_dev,
+                   double* const* phi_dev, cc_solve_info* info);
+
 /* Switch the precision of later cc_solve / cc_solve_batched calls (CC_FP64 or
  * CC_MIXED); the build-time value is cc_params.precision. */
 int cc_set_precision(cc_problem* p, int precision);

@@ -30,7 +30,7 @@ EXPORTED = [
     "cc_default_params", "cc_build", "cc_num_levels", "cc_get_level_info", "cc_assemble_rhs", "cc_solve",
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
-    "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov",
+    "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -107,6 +107,7 @@ def load() -> C.CDLL:
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
+    lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
     lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
     lib.cc_net_num_params.restype = C.c_longlong
@@ -175,6 +176,23 @@ def _ptr(t, numel=None):
     return C.c_void_p(t.data_ptr())
 
 
+def solve_multi(problems, rs, phis) -> list:
+    """Solve several problems concurrently (cc_solve_multi); rs[i], phis[i] are
+    the n_i^3 float64 device tensors of problem i."""
+    import torch
+    torch.cuda.current_stream().synchronize()
+    k = len(problems)
+    hs = (C.c_void_p * k)(*[p._h.value for p in problems])
+    rp = (C.c_void_p * k)(*[_ptr(r, p.n() ** 3).value for p, r in zip(problems, rs)])
+    pp = (C.c_void_p * k)(*[_ptr(x, p.n() ** 3).value for p, x in zip(problems, phis)])
+    infos = (CcSolveInfo * k)()
+    rc = load().cc_solve_multi(k, hs, rp, pp, infos)
+    if rc not in (CC_OK, CC_ENOCONV):
+        _check(rc)
+    return [dict(Problem._info(infos[i], CC_OK), converged=infos[i].rel_residual < problems[i].params.tol)
+            for i in range(k)]
+
+
 class Problem:
     """A built cut-cell problem (geometry, rows, factorizations, device data)."""
 
@@ -203,9 +221,18 @@ class Problem:
         st = C.c_void_p(stream) if stream is not None else None
         _check(lib.cc_build(C.byref(dom), C.byref(prm), st, C.byref(h)))
         self._h = h
+        self._stream = stream
         self.params = prm
         self.domain = domain
         self.device = device
+
+    def _order(self):
+        """The library works on its own stream unless it was given torch's:
+        wait for torch's pending work on the tensors passed in."""
+        import torch
+        cur = torch.cuda.current_stream()
+        if self._stream is None or cur.cuda_stream != self._stream:
+            cur.synchronize()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -263,6 +290,7 @@ class Problem:
 
     # -------------------------------------------------------------- device
     def assemble_rhs(self, f: dict, g: Optional[dict], r, f_mode: int = CC_VALUE):
+        self._order()
         fs, fk = _field(f)
         gs, gk = _field(g)
         _check(load().cc_assemble_rhs(self._h, C.byref(fs), f_mode, C.byref(gs), _ptr(r, self.n() ** 3)))
@@ -282,6 +310,7 @@ class Problem:
         self.params.krylov = k
 
     def solve(self, r, phi) -> dict:
+        self._order()
         n3 = self.n() ** 3
         info = CcSolveInfo()
         rc = load().cc_solve(self._h, _ptr(r, n3), _ptr(phi, n3), C.byref(info))
@@ -291,6 +320,7 @@ class Problem:
 
     def solve_batched(self, r, phi) -> list:
         """r, phi: (nrhs, n^3) contiguous float64 device tensors (batch-major)."""
+        self._order()
         n3 = self.n() ** 3
         if r.dim() != 2 or r.shape[1] != n3 or phi.shape != r.shape:
             raise ValueError("expected (nrhs, n^3) tensors of equal shape")
@@ -307,41 +337,50 @@ class Problem:
         return out
 
     def apply(self, level, x, y):
+        self._order()
         n3 = self.n(level) ** 3
         _check(load().cc_apply(self._h, level, _ptr(x, n3), _ptr(y, n3)))
 
     def residual(self, level, r, x, s) -> float:
+        self._order()
         n3 = self.n(level) ** 3
         m = C.c_double()
         _check(load().cc_residual(self._h, level, _ptr(r, n3), _ptr(x, n3), _ptr(s, n3), C.byref(m)))
         return m.value
 
     def smo1(self, level, s, e):
+        self._order()
         n3 = self.n(level) ** 3
         _check(load().cc_smo1(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
     def smo2(self, level, s, e):
+        self._order()
         n3 = self.n(level) ** 3
         _check(load().cc_smo2(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
     def restrict(self, level, s, e, sc):
+        self._order()
         n3 = self.n(level) ** 3
         _check(load().cc_restrict(self._h, level, _ptr(s, n3), _ptr(e, n3), _ptr(sc, self.n(level + 1) ** 3)))
 
     def prolong_add(self, level, ec, ef):
+        self._order()
         _check(load().cc_prolong_add(self._h, level, _ptr(ec, self.n(level + 1) ** 3), _ptr(ef, self.n(level) ** 3)))
 
     def bottom_solve(self, s, e):
+        self._order()
         M = self.num_levels - 1
         n3 = self.n(M) ** 3
         _check(load().cc_bottom_solve(self._h, _ptr(s, n3), _ptr(e, n3)))
 
     def vcycle(self, level, s, e):
+        self._order()
         n3 = self.n(level) ** 3
         _check(load().cc_vcycle(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
     def learned_guess(self, net: "Net", level: int, phi_scale: float, r, phi):
         """phi <- the network's guess (see cc_learned_guess)."""
+        self._order()
         n3 = self.n() ** 3
         _check(load().cc_learned_guess(self._h, net._h, level, phi_scale, _ptr(r, n3), _ptr(phi, n3)))
 
@@ -401,11 +440,13 @@ class Net:
     def forward(self, x, y, n: int, nb: int):
         """x: float32 (nb, n^3, 2) device tensor; y: float32 (nb, n^3)."""
         import torch
+        torch.cuda.current_stream().synchronize()
         v = nb * n ** 3
         _check(load().cc_net_forward(self._h, n, nb, _dptr(x, torch.float32, 2 * v), _dptr(y, torch.float32, v)))
 
     def loss_grad(self, x, t, mask, n: int, nb: int, want_grad: bool = False):
         import torch
+        torch.cuda.current_stream().synchronize()
         v = nb * n ** 3
         loss = C.c_double()
         g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None

@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -1270,6 +1271,42 @@ int cc_set_precision(cc_problem* p, int precision) {
     if (precision != CC_FP64 && precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
     p->prm.precision = precision;
   });
+}
+
+int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r, double* const* phi,
+                   cc_solve_info* info) {
+  if (nprob < 1 || !probs || !r || !phi) {
+    set_last_error("bad argument");
+    return CC_EINVAL;
+  }
+  for (int i = 0; i < nprob; ++i) {
+    if (!probs[i] || !r[i] || !phi[i] || probs[i]->device < 0) {
+      set_last_error("null or host-only problem in the list");
+      return CC_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i] || probs[j]->stream == probs[i]->stream) {
+        set_last_error("every problem needs its own handle and stream");
+        return CC_EINVAL;
+      }
+  }
+  std::vector<int> rc(nprob, CC_OK);
+  std::vector<std::string> msg(nprob);
+  std::vector<std::thread> th;
+  for (int i = 0; i < nprob; ++i)
+    th.emplace_back([&, i] {
+      (void)hipSetDevice(probs[i]->device);
+      rc[i] = cc_solve(probs[i], r[i], phi[i], info ? info + i : nullptr);
+      if (rc[i] != CC_OK) msg[i] = cc_last_error();
+    });
+  for (auto& t : th) t.join();
+  int worst = CC_OK;
+  for (int i = 0; i < nprob; ++i)
+    if (rc[i] != CC_OK && (worst == CC_OK || worst == CC_ENOCONV)) {
+      worst = rc[i];
+      set_last_error("problem " + std::to_string(i) + ": " + msg[i]);
+    }
+  return worst;
 }
 
 int cc_set_krylov(cc_problem* p, int krylov) {

@@ -214,3 +214,27 @@ def test_krylov_acceleration():
             res = P.residual(0, r, phi, s)
             assert res < 1e-10 * float(r.abs().max())
         P.close()
+
+
+def test_solve_multi_matches_single_solves():
+    """Several geometries of different size solved concurrently (one stream and
+    host thread each) give the single solves' iterations and solutions."""
+    L = _lib()
+    doms = [inputs.sphere_domain(n=16, radius=0.25, n_min=8), WORK["sphere32"](), _ell32()]
+    probs, rs, singles = [], [], []
+    for i, d in enumerate(doms):
+        P = L.Problem(d)
+        n3 = d.n ** 3
+        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(inputs.gaussian_rhs(d, seed=50 + i), None, r)
+        x = torch.zeros_like(r)
+        singles.append((P.solve(r, x), x.clone()))
+        probs.append(P)
+        rs.append(r)
+    phis = [torch.zeros_like(r) for r in rs]
+    infos = L.solve_multi(probs, rs, phis)
+    for (i1, x1), i2, x2 in zip(singles, infos, phis):
+        assert i2["converged"] and i2["iterations"] == i1["iterations"]
+        assert float((x2 - x1).abs().max() / x1.abs().max()) < 1e-11
+    for P in probs:
+        P.close()
