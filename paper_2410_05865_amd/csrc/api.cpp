@@ -480,6 +480,8 @@ void vcycle(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, T* tmp, in
   DevLevel& C = P->dev[m + 1];
   launch_restrict<T>(D.st, C.st, s, cur, W.s[m + 1], nb, P->stream);
   vcycle<T>(P, W, m + 1, W.s[m + 1], W.e[m + 1], W.et[m + 1], nb);
+  // merged coarse cells take their host's value before the prolongation
+  launch_copy_pairs<T>(C.n_absorbed, C.absorbed, W.e[m + 1], cube(C.st.n), nb, P->stream);
   launch_prolong_add<T>(D.st, C.st.n, W.e[m + 1], cur, nb, P->stream);
   for (int it = 0; it < P->prm.nu2; ++it) {
     launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
@@ -583,7 +585,7 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
     ++it;
     done = update(false);
   }
-  launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, n3, nb, P->stream);
+  launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, phi, n3, nb, P->stream);
   HIPCHK(hipStreamSynchronize(P->stream));
 }
 
@@ -737,7 +739,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     (void)converged;
   }
   rec.iterations = cycles;
-  launch_copy_pairs(D0.n_absorbed, D0.absorbed, phi, n3, 1, st);
+  launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, phi, n3, 1, st);
   HIPCHK(hipStreamSynchronize(st));
 }
 

@@ -557,7 +557,8 @@ __global__ void k_mask_unknowns(StencilLevel L, double* __restrict__ a) {
   if (c < n3 && L.type[c] == 0) a[blockIdx.y * n3 + c] = 0.0;
 }
 
-__global__ void k_copy_pairs(int count, const int2* __restrict__ pairs, double* __restrict__ a, long long stride) {
+template <class T>
+__global__ void k_copy_pairs(int count, const int2* __restrict__ pairs, T* __restrict__ a, long long stride) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   a += blockIdx.y * stride;
   if (t < count) a[pairs[t].x] = a[pairs[t].y];
@@ -774,10 +775,13 @@ void launch_scale_residual(long long n3, const double* s, const unsigned long lo
 void launch_mask_unknowns(const StencilLevel& L, double* a, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_mask_unknowns, dim3(blocks(cube(L.n), 256), nb), dim3(256), 0, st, L, a);
 }
-void launch_copy_pairs(int count, const int2* pairs, double* a, long long stride, int nb, hipStream_t st) {
+template <class T>
+void launch_copy_pairs(int count, const int2* pairs, T* a, long long stride, int nb, hipStream_t st) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_copy_pairs, dim3(blocks(count, 256), nb), dim3(256), 0, st, count, pairs, a, stride);
+  hipLaunchKernelGGL(k_copy_pairs<T>, dim3(blocks(count, 256), nb), dim3(256), 0, st, count, pairs, a, stride);
 }
+template void launch_copy_pairs<double>(int, const int2*, double*, long long, int, hipStream_t);
+template void launch_copy_pairs<float>(int, const int2*, float*, long long, int, hipStream_t);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_values, dim3(blocks(count, 256)), dim3(256), 0, st, count, cells, vals, a);

@@ -119,7 +119,9 @@ template <class T>
 void launch_scale_residual(long long n3, const double* s, const unsigned long long* norm, T* d, int nb,
                            hipStream_t st);
 void launch_mask_unknowns(const StencilLevel& L, double* a, int nb, hipStream_t st);
-void launch_copy_pairs(int count, const int2* pairs, double* a, long long stride, int nb, hipStream_t st);
+// a[pair.x] = a[pair.y] for every pair (merged cell <- its host), nb arrays
+template <class T>
+void launch_copy_pairs(int count, const int2* pairs, T* a, long long stride, int nb, hipStream_t st);
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q,
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
