@@ -117,6 +117,8 @@ typedef struct cc_level_info {
   int lu_nodes;           /* supernodes */
   int lu_depth;           /* levels of the supernode tree */
   double setup_seconds;
+  int lu_subtree_cut;     /* device sweeps: heights below this run as one launch of subtrees */
+  int lu_subtrees;        /* number of those subtrees (0: one launch per height throughout) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */

@@ -102,9 +102,23 @@ struct DevBuf {
 
 struct DevLU {
   LuDev d{};
-  std::vector<LuTasks> tasks;  // per height
+  std::vector<LuTasks> tasks;  // per height, all nodes
+  LuSub sub;                   // the heights below sub.hcut grouped in subtrees
+  bool sub_on = false;         // sweeps use the subtrees (chosen by timing at build)
   int height = 0;
 };
+
+// One LU solve with a level's factorization: forward then backward sweeps,
+// through the subtree launch for the low heights if chosen, one launch per
+// height above; the backward sweep writes the solution to `out`.
+template <class T, class TO>
+void lu_sweeps(hipStream_t st, const DevLU& L, const LuDev& F, TO* out, long long ostride, int nb) {
+  const int h0 = L.sub_on ? L.sub.hcut : 0;
+  if (L.sub_on) launch_lu_forward_sub<T>(F, L.sub, nb, st);
+  for (int h = h0; h <= L.height; ++h) launch_lu_forward<T>(F, L.tasks[h], nb, st);
+  for (int h = L.height; h >= h0; --h) launch_lu_backward<T, TO>(F, L.tasks[h], out, ostride, nb, st);
+  if (L.sub_on) launch_lu_backward_sub<T, TO>(F, L.sub, out, ostride, nb, st);
+}
 
 struct DevLevel {
   StencilLevel st{};
@@ -300,6 +314,116 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
     while ((1 << l) < g) ++l;
     return l;
   };
+  // Subtrees: the nodes below height hcut, grouped under the highest ancestor
+  // below hcut, run in one launch (one workgroup per subtree).  hcut is the
+  // highest cut that leaves at least kMinSub subtrees and at most kMaxRounds
+  // sequential task rounds in any subtree.
+  constexpr int kMinSub = 256, kMaxRounds = 24, kWaves = 8;
+  auto single_tasks = [&](const SnNode& nd, bool fwd) {
+    const int g = fwd ? lanes_for(nd.p) : lanes_for(0.5 * nd.p + nd.q);
+    const int rows = fwd ? nd.p + nd.q : nd.p;
+    return (rows + 64 / g - 1) / (64 / g);
+  };
+  int hcut = 0;
+  std::vector<int> root_of(ns, -1);
+  for (int hc = F.max_height; hc >= 2; --hc) {
+    std::vector<int> rt(ns, -1);
+    int nroots = 0;
+    for (int s = ns - 1; s >= 0; --s) {  // parents come after children: walk from the top
+      const SnNode& nd = F.nodes[s];
+      if (nd.height >= hc) continue;
+      const int par = nd.parent;
+      if (par < 0 || F.nodes[par].height >= hc) {
+        rt[s] = s;
+        ++nroots;
+      } else {
+        rt[s] = rt[par];
+      }
+    }
+    if (nroots < kMinSub) continue;
+    std::map<int, std::vector<int>> per;  // root -> tasks per height
+    for (int s = 0; s < ns; ++s)
+      if (rt[s] >= 0) {
+        auto& v = per[rt[s]];
+        v.resize(hc, 0);
+        v[F.nodes[s].height] += single_tasks(F.nodes[s], true);
+      }
+    int worst = 0;
+    for (auto& kv : per) {
+      int rounds = 0;
+      for (int c : kv.second) rounds += (c + kWaves - 1) / kWaves;
+      worst = std::max(worst, rounds);
+    }
+    if (worst <= kMaxRounds) {
+      hcut = hc;
+      root_of = rt;
+      break;
+    }
+  }
+  LuSub& SB = D.sub;
+  SB.hcut = hcut;
+  SB.nsub = 0;
+  if (hcut >= 2) {
+    std::vector<int> roots;
+    for (int s = 0; s < ns; ++s)
+      if (root_of[s] == s) roots.push_back(s);
+    std::map<int, int> rindex;
+    for (size_t i = 0; i < roots.size(); ++i) rindex[roots[i]] = (int)i;
+    // members of each subtree by height
+    std::vector<std::vector<std::vector<int>>> mem(roots.size(), std::vector<std::vector<int>>(hcut));
+    for (int s = 0; s < ns; ++s)
+      if (root_of[s] >= 0) mem[rindex[root_of[s]]][F.nodes[s].height].push_back(s);
+    auto build = [&](bool multi, LuSubList& L) {
+      std::vector<LuTask> ft, bt;
+      std::vector<int2> fl, bl;
+      std::vector<int> fp(1, 0), bp(1, 0);
+      for (size_t i = 0; i < roots.size(); ++i) {
+        for (int h = 0; h < hcut; ++h) {
+          if (mem[i][h].empty()) continue;
+          const int b0 = (int)ft.size();
+          for (int s : mem[i][h]) {
+            const SnNode& nd = F.nodes[s];
+            if (multi) {
+              for (int r = 0; r < nd.p + nd.q; r += kMrRows)
+                ft.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, 0, 0});
+            } else {
+              const int g = lanes_for(nd.p), lg = log2i(g);
+              for (int r = 0; r < nd.p + nd.q; r += 64 / g)
+                ft.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, lg, 0});
+            }
+          }
+          fl.push_back(make_int2(b0, (int)ft.size()));
+        }
+        fp.push_back((int)fl.size());
+        for (int h = hcut - 1; h >= 0; --h) {
+          if (mem[i][h].empty()) continue;
+          const int b0 = (int)bt.size();
+          for (int s : mem[i][h]) {
+            const SnNode& nd = F.nodes[s];
+            if (multi) {
+              for (int r = 0; r < nd.p; r += kMrRows)
+                bt.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, 0, 0});
+            } else {
+              const int g = lanes_for(0.5 * nd.p + nd.q), lg = log2i(g);
+              for (int r = 0; r < nd.p; r += 64 / g)
+                bt.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, lg, 0});
+            }
+          }
+          bl.push_back(make_int2(b0, (int)bt.size()));
+        }
+        bp.push_back((int)bl.size());
+      }
+      L.ftask = B.upload(ft);
+      L.flev = B.upload(fl);
+      L.fptr = B.upload(fp);
+      L.btask = B.upload(bt);
+      L.blev = B.upload(bl);
+      L.bptr = B.upload(bp);
+    };
+    build(false, SB.single);
+    build(true, SB.multi);
+    SB.nsub = (int)roots.size();
+  }
   D.tasks.assign(F.max_height + 1, LuTasks{});
   for (int h = 0; h <= F.max_height; ++h) {
     std::vector<LuTask> ft, bt, fm, bm;
@@ -423,6 +547,30 @@ void upload(cc_problem* P) {
   }
   W.s0 = P->s0;
   W.norm = P->d_norm;
+  // Sweep schedule per factorization: time one LU solve with and without the
+  // subtree launch on this device (the work vectors' contents do not matter)
+  // and keep the faster.
+  hipEvent_t ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  for (int m = 0; m <= M; ++m) {
+    DevLU& L = P->dev[m].lu;
+    if (L.sub.nsub == 0) continue;
+    const long long n3m = cube(P->dev[m].st.n);
+    float t[2] = {0.f, 0.f};
+    for (int on = 0; on < 2; ++on) {
+      L.sub_on = on != 0;
+      lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+      HIPCHK(hipEventRecord(ev0, P->stream));
+      for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+      HIPCHK(hipEventRecord(ev1, P->stream));
+      HIPCHK(hipEventSynchronize(ev1));
+      HIPCHK(hipEventElapsedTime(&t[on], ev0, ev1));
+    }
+    L.sub_on = t[1] < 0.97f * t[0];
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
 }
 
 // ---------------------------------------------------------------- solve steps
@@ -441,8 +589,7 @@ void smo2(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, int nb) {
   const LuDev& F = W.lu[m];
   const long long n3 = cube(D.st.n);
   launch_plg_b2<T>(D.plg, s, e, vec_y<T>(F), n3, nb, P->stream);
-  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<T>(F, D.lu.tasks[h], nb, P->stream);
-  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward<T, T>(F, D.lu.tasks[h], e, n3, nb, P->stream);
+  lu_sweeps<T, T>(P->stream, D.lu, F, e, n3, nb);
 }
 
 // e = L^(M)^-1 s on the coarsest level, in FP64 whatever T is
@@ -454,8 +601,7 @@ void bottom(cc_problem* P, const Work<T>& W, const T* s, T* e, int nb) {
   const long long n3 = cube(D.st.n);
   launch_zero<T>(e, n3 * nb, P->stream);
   launch_gather<T, double>(F.n, F.row_cell, s, n3, F.y, nb, P->stream);
-  for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<double>(F, D.lu.tasks[h], nb, P->stream);
-  for (int h = D.lu.height; h >= 0; --h) launch_lu_backward<double, T>(F, D.lu.tasks[h], e, n3, nb, P->stream);
+  lu_sweeps<double, T>(P->stream, D.lu, F, e, n3, nb);
 }
 
 // e = VCycle(s) on level m (e overwritten); tmp is a work array of the level.
@@ -938,6 +1084,10 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_nodes = (int)p->lu[level].nodes.size();
     info->lu_depth = p->lu[level].max_height + 1;
     info->setup_seconds = p->setup_s[level];
+    const bool dev = p->device >= 0 && (int)p->dev.size() > level;
+    const bool on = dev && p->dev[level].lu.sub_on;
+    info->lu_subtree_cut = on ? p->dev[level].lu.sub.hcut : 0;
+    info->lu_subtrees = on ? p->dev[level].lu.sub.nsub : 0;
   });
 }
 
@@ -1415,18 +1565,14 @@ int cc_time_kernel(cc_problem* p, int which, int reps, double* ms, double* bytes
         if ((int)p->dev.size() < 2) fail(CC_EINVAL, "no LU-correction on a one-level problem");
         if (which == CC_TIME_LU) {
           launch = [&] {
-            for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<double>(D.lu.d, D.lu.tasks[h], 1, p->stream);
-            for (int h = D.lu.height; h >= 0; --h)
-              launch_lu_backward<double, double>(D.lu.d, D.lu.tasks[h], D.et, n3, 1, p->stream);
+            lu_sweeps<double, double>(p->stream, D.lu, D.lu.d, D.et, n3, 1);
           };
           by = lu_sweep_bytes(p->lu[0], 8.0);
         } else {
           const LuDev F = p->w32.lu[0];
           float* out = p->w32.et[0];
           launch = [&p, &D, F, out] {
-            for (int h = 0; h <= D.lu.height; ++h) launch_lu_forward<float>(F, D.lu.tasks[h], 1, p->stream);
-            for (int h = D.lu.height; h >= 0; --h)
-              launch_lu_backward<float, float>(F, D.lu.tasks[h], out, cube(D.st.n), 1, p->stream);
+            lu_sweeps<float, float>(p->stream, D.lu, F, out, cube(D.st.n), 1);
           };
           by = lu_sweep_bytes(p->lu[0], 4.0);
         }

@@ -281,73 +281,60 @@ __device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restri
 // Forward: z_F = L11^-1 y_F on the node's rows, and y_U -= (L21 L11^-1) y_F
 // accumulated atomically into the later equations.
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks) {
-  const int lane = threadIdx.x % kWave;
+__device__ __forceinline__ void fwd_task(const LuDev& F, const LuTask& t, int lane) {
   T* y = LuArr<T>::y(F);
-  {
-    const int ti = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (ti >= ntasks) return;
-    const LuTask t = tasks[ti];
-    const int lg = t.lg, g = 1 << lg;
-    const int sub = lane >> lg, gl = lane & (g - 1);
-    const int p = t.p, q = t.q, base = t.base;
-    const int i = t.row0 + sub;
-    const bool valid = i < p + q;
-    const T* yF = y + base;
-    T acc = T(0);
-    if (valid) {
-      if (i < p)
-        acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, yF, 0, i, gl, g);
-      else
-        acc = lane_dot<T>(LuArr<T>::V(F) + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
-    }
-    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-    if (valid && gl == 0) {
-      if (i < p)
-        LuArr<T>::z(F)[base + i] = acc + yF[i];
-      else
-        atomicAdd(&y[F.Uf[t.offU + (i - p)]], -acc);
-    }
+  const int lg = t.lg, g = 1 << lg;
+  const int sub = lane >> lg, gl = lane & (g - 1);
+  const int p = t.p, q = t.q, base = t.base;
+  const int i = t.row0 + sub;
+  const bool valid = i < p + q;
+  const T* yF = y + base;
+  T acc = T(0);
+  if (valid) {
+    if (i < p)
+      acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, yF, 0, i, gl, g);
+    else
+      acc = lane_dot<T>(LuArr<T>::V(F) + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
+  }
+  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && gl == 0) {
+    if (i < p)
+      LuArr<T>::z(F)[base + i] = acc + yF[i];
+    else
+      atomicAdd(&y[F.Uf[t.offU + (i - p)]], -acc);
   }
 }
 
 // Backward: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered to the grid array
 // `out` through var_cell.
 template <class T, class TO>
-__global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks,
-                                                     TO* __restrict__ out) {
-  const int lane = threadIdx.x % kWave;
+__device__ __forceinline__ void bwd_task(const LuDev& F, const LuTask& t, int lane, TO* __restrict__ out) {
   T* x = LuArr<T>::x(F);
-  {
-    const int ti = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    if (ti >= ntasks) return;
-    const LuTask t = tasks[ti];
-    const int lg = t.lg, g = 1 << lg;
-    const int sub = lane >> lg, gl = lane & (g - 1);
-    const int p = t.p, q = t.q, base = t.base;
-    const int i = t.row0 + sub;
-    const bool valid = i < p;
-    T acc = T(0);
-    if (valid) {
-      acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, LuArr<T>::z(F) + base, i, p, gl, g);
-      if (q > 0) {
-        const T* Wr = LuArr<T>::W(F) + t.offVW + (long)i * q;
-        const int* U = F.U + t.offU;
-        T s0 = T(0), s1 = T(0);
-        int j = gl;
-        for (; j + g < q; j += 2 * g) {
-          s0 += Wr[j] * x[U[j]];
-          s1 += Wr[j + g] * x[U[j + g]];
-        }
-        for (; j < q; j += g) s0 += Wr[j] * x[U[j]];
-        acc -= s0 + s1;
+  const int lg = t.lg, g = 1 << lg;
+  const int sub = lane >> lg, gl = lane & (g - 1);
+  const int p = t.p, q = t.q, base = t.base;
+  const int i = t.row0 + sub;
+  const bool valid = i < p;
+  T acc = T(0);
+  if (valid) {
+    acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, LuArr<T>::z(F) + base, i, p, gl, g);
+    if (q > 0) {
+      const T* Wr = LuArr<T>::W(F) + t.offVW + (long)i * q;
+      const int* U = F.U + t.offU;
+      T s0 = T(0), s1 = T(0);
+      int j = gl;
+      for (; j + g < q; j += 2 * g) {
+        s0 += Wr[j] * x[U[j]];
+        s1 += Wr[j + g] * x[U[j + g]];
       }
+      for (; j < q; j += g) s0 += Wr[j] * x[U[j]];
+      acc -= s0 + s1;
     }
-    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-    if (valid && gl == 0) {
-      x[base + i] = acc;
-      out[F.var_cell[base + i]] = TO(acc);
-    }
+  }
+  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && gl == 0) {
+    x[base + i] = acc;
+    out[F.var_cell[base + i]] = TO(acc);
   }
 }
 
@@ -385,119 +372,175 @@ __device__ __forceinline__ void mr_chunk(const T (&ch)[kMrRows], const T* __rest
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_lu_forward_mr(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb) {
-  const int lane = threadIdx.x % kWave;
+__device__ __forceinline__ void fwd_task_mr(const LuDev& F, const LuTask& t, int lane, int nb) {
   const bool act = lane < nb;
   T* y = LuArr<T>::y(F);
-  {
-    const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    if (ti >= ntasks) return;
-    const LuTask t = tasks[ti];
-    const int p = t.p, q = t.q, base = t.base;
-    const T* M = LuArr<T>::M(F) + t.offM;
-    const T* V = LuArr<T>::V(F) + t.offVW;
-    const T* ptr[kMrRows];
-    int end[kMrRows];
-    T acc[kMrRows];
-    int jmax = 0;
+  const int p = t.p, q = t.q, base = t.base;
+  const T* M = LuArr<T>::M(F) + t.offM;
+  const T* V = LuArr<T>::V(F) + t.offVW;
+  const T* ptr[kMrRows];
+  int end[kMrRows];
+  T acc[kMrRows];
+  int jmax = 0;
+#pragma unroll
+  for (int r = 0; r < kMrRows; ++r) {
+    const int i = t.row0 + r;
+    acc[r] = T(0);
+    if (i < p) {
+      ptr[r] = M + (long)i * p;
+      end[r] = i;
+    } else if (i < p + q) {
+      ptr[r] = V + (long)(i - p) * p;
+      end[r] = p;
+    } else {
+      ptr[r] = M;
+      end[r] = 0;
+    }
+    jmax = max(jmax, end[r]);
+  }
+  for (int j0 = 0; j0 < jmax; j0 += kWave) {
+    T ch[kMrRows];
+#pragma unroll
+    for (int r = 0; r < kMrRows; ++r) ch[r] = (j0 + lane < end[r]) ? ptr[r][j0 + lane] : T(0);
+    mr_chunk<T>(ch, y + (long long)(base + j0) * nb + lane, nb, min(kWave, jmax - j0), act, acc);
+  }
+  if (act) {
 #pragma unroll
     for (int r = 0; r < kMrRows; ++r) {
       const int i = t.row0 + r;
-      acc[r] = T(0);
-      if (i < p) {
-        ptr[r] = M + (long)i * p;
-        end[r] = i;
-      } else if (i < p + q) {
-        ptr[r] = V + (long)(i - p) * p;
-        end[r] = p;
-      } else {
-        ptr[r] = M;
-        end[r] = 0;
-      }
-      jmax = max(jmax, end[r]);
-    }
-    for (int j0 = 0; j0 < jmax; j0 += kWave) {
-      T ch[kMrRows];
-#pragma unroll
-      for (int r = 0; r < kMrRows; ++r) ch[r] = (j0 + lane < end[r]) ? ptr[r][j0 + lane] : T(0);
-      mr_chunk<T>(ch, y + (long long)(base + j0) * nb + lane, nb, min(kWave, jmax - j0), act, acc);
-    }
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < kMrRows; ++r) {
-        const int i = t.row0 + r;
-        if (i < p)
-          LuArr<T>::z(F)[(long long)(base + i) * nb + lane] = acc[r] + y[(long long)(base + i) * nb + lane];
-        else if (i < p + q)
-          atomicAdd(&y[(long long)F.Uf[t.offU + (i - p)] * nb + lane], -acc[r]);
-      }
+      if (i < p)
+        LuArr<T>::z(F)[(long long)(base + i) * nb + lane] = acc[r] + y[(long long)(base + i) * nb + lane];
+      else if (i < p + q)
+        atomicAdd(&y[(long long)F.Uf[t.offU + (i - p)] * nb + lane], -acc[r]);
     }
   }
 }
 
 template <class T, class TO>
-__global__ void __launch_bounds__(256) k_lu_backward_mr(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb,
-                                                        TO* __restrict__ out, long long ostride) {
-  const int lane = threadIdx.x % kWave;
+__device__ __forceinline__ void bwd_task_mr(const LuDev& F, const LuTask& t, int lane, int nb, TO* __restrict__ out,
+                                            long long ostride) {
   const bool act = lane < nb;
   const T* z = LuArr<T>::z(F);
   T* x = LuArr<T>::x(F);
-  {
-    const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-    if (ti >= ntasks) return;
-    const LuTask t = tasks[ti];
-    const int p = t.p, q = t.q, base = t.base;
-    const T* M = LuArr<T>::M(F) + t.offM;
-    const T* W = LuArr<T>::W(F) + t.offVW;
-    const int* U = F.U + t.offU;
-    T acc[kMrRows];
+  const int p = t.p, q = t.q, base = t.base;
+  const T* M = LuArr<T>::M(F) + t.offM;
+  const T* W = LuArr<T>::W(F) + t.offVW;
+  const int* U = F.U + t.offU;
+  T acc[kMrRows];
 #pragma unroll
-    for (int r = 0; r < kMrRows; ++r) acc[r] = T(0);
-    // U11^-1 z_F: row i uses columns [i, p)
-    for (int j0 = t.row0; j0 < p; j0 += kWave) {
-      T ch[kMrRows];
-      const int j = j0 + lane;
+  for (int r = 0; r < kMrRows; ++r) acc[r] = T(0);
+  // U11^-1 z_F: row i uses columns [i, p)
+  for (int j0 = t.row0; j0 < p; j0 += kWave) {
+    T ch[kMrRows];
+    const int j = j0 + lane;
 #pragma unroll
-      for (int r = 0; r < kMrRows; ++r) {
-        const int i = t.row0 + r;
-        ch[r] = (i < p && j >= i && j < p) ? M[(long)i * p + j] : T(0);
-      }
-      mr_chunk<T>(ch, z + (long long)(base + j0) * nb + lane, nb, min(kWave, p - j0), act, acc);
+    for (int r = 0; r < kMrRows; ++r) {
+      const int i = t.row0 + r;
+      ch[r] = (i < p && j >= i && j < p) ? M[(long)i * p + j] : T(0);
     }
-    // - (U11^-1 U12) x_U
-    for (int j0 = 0; j0 < q; j0 += kWave) {
-      T ch[kMrRows];
-      const int j = j0 + lane;
-      const int uj = (j < q) ? U[j] : 0;
+    mr_chunk<T>(ch, z + (long long)(base + j0) * nb + lane, nb, min(kWave, p - j0), act, acc);
+  }
+  // - (U11^-1 U12) x_U
+  for (int j0 = 0; j0 < q; j0 += kWave) {
+    T ch[kMrRows];
+    const int j = j0 + lane;
+    const int uj = (j < q) ? U[j] : 0;
 #pragma unroll
-      for (int r = 0; r < kMrRows; ++r) {
-        const int i = t.row0 + r;
-        ch[r] = (i < p && j < q) ? -W[(long)i * q + j] : T(0);
-      }
-      const int jn = min(kWave, q - j0);
-      for (int jb = 0; jb < jn; jb += kMrBlock) {
-        T vv[kMrBlock];
-#pragma unroll
-        for (int u = 0; u < kMrBlock; ++u) {
-          const int uu = lane_bcast(uj, jb + u);
-          vv[u] = (act && jb + u < jn) ? x[(long long)uu * nb + lane] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kMrBlock; ++u)
-#pragma unroll
-          for (int r = 0; r < kMrRows; ++r) acc[r] += lane_bcast(ch[r], jb + u) * vv[u];
-      }
+    for (int r = 0; r < kMrRows; ++r) {
+      const int i = t.row0 + r;
+      ch[r] = (i < p && j < q) ? -W[(long)i * q + j] : T(0);
     }
-    if (act) {
+    const int jn = min(kWave, q - j0);
+    for (int jb = 0; jb < jn; jb += kMrBlock) {
+      T vv[kMrBlock];
 #pragma unroll
-      for (int r = 0; r < kMrRows; ++r) {
-        const int i = t.row0 + r;
-        if (i < p) {
-          x[(long long)(base + i) * nb + lane] = acc[r];
-          out[lane * ostride + F.var_cell[base + i]] = TO(acc[r]);
-        }
+      for (int u = 0; u < kMrBlock; ++u) {
+        const int uu = lane_bcast(uj, jb + u);
+        vv[u] = (act && jb + u < jn) ? x[(long long)uu * nb + lane] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kMrBlock; ++u)
+#pragma unroll
+        for (int r = 0; r < kMrRows; ++r) acc[r] += lane_bcast(ch[r], jb + u) * vv[u];
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < kMrRows; ++r) {
+      const int i = t.row0 + r;
+      if (i < p) {
+        x[(long long)(base + i) * nb + lane] = acc[r];
+        out[lane * ostride + F.var_cell[base + i]] = TO(acc[r]);
       }
     }
+  }
+}
+
+// One height of the tree per launch: one task per wavefront.
+template <class T>
+__global__ void __launch_bounds__(256) k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb) {
+  const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (ti >= ntasks) return;
+  const LuTask t = tasks[ti];
+  if (nb == 1)
+    fwd_task<T>(F, t, threadIdx.x % kWave);
+  else
+    fwd_task_mr<T>(F, t, threadIdx.x % kWave, nb);
+}
+template <class T, class TO>
+__global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb,
+                                                     TO* __restrict__ out, long long ostride) {
+  const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (ti >= ntasks) return;
+  const LuTask t = tasks[ti];
+  if (nb == 1)
+    bwd_task<T, TO>(F, t, threadIdx.x % kWave, out);
+  else
+    bwd_task_mr<T, TO>(F, t, threadIdx.x % kWave, nb, out, ostride);
+}
+
+// The lower heights of the tree in one launch: workgroup s takes subtree s
+// through all its heights (levels lptr[s] .. lptr[s+1] of the list, each a
+// range of tasks), its kSubWaves wavefronts sharing each height's tasks, with a
+// workgroup barrier between heights (a subtree's values are written and read
+// only by its workgroup; contributions to ancestors above the cut are device
+// atomics read by later launches); nothing waits on another workgroup.
+constexpr int kSubWaves = 8;  // wavefronts per subtree workgroup
+
+template <class T>
+__global__ void __launch_bounds__(512) k_lu_forward_sub(LuDev F, const LuTask* __restrict__ tasks,
+                                                        const int2* __restrict__ lev, const int* __restrict__ lptr,
+                                                        int nb) {
+  const int s = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  for (int l = lptr[s]; l < lptr[s + 1]; ++l) {
+    const int2 rg = lev[l];
+    for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
+      const LuTask t = tasks[ti];
+      if (nb == 1)
+        fwd_task<T>(F, t, lane);
+      else
+        fwd_task_mr<T>(F, t, lane, nb);
+    }
+    __syncthreads();  // this height's stores and atomics visible to the workgroup
+  }
+}
+template <class T, class TO>
+__global__ void __launch_bounds__(512) k_lu_backward_sub(LuDev F, const LuTask* __restrict__ tasks,
+                                                         const int2* __restrict__ lev, const int* __restrict__ lptr,
+                                                         int nb, TO* __restrict__ out, long long ostride) {
+  const int s = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  for (int l = lptr[s]; l < lptr[s + 1]; ++l) {
+    const int2 rg = lev[l];
+    for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
+      const LuTask t = tasks[ti];
+      if (nb == 1)
+        bwd_task<T, TO>(F, t, lane, out);
+      else
+        bwd_task_mr<T, TO>(F, t, lane, nb, out, ostride);
+    }
+    __syncthreads();  // this height's stores and atomics visible to the workgroup
   }
 }
 
@@ -734,20 +777,29 @@ inline dim3 wave_grid(int ntasks) { return dim3(blocks((long long)ntasks * kWave
 
 template <class T>
 void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st) {
-  if (nb == 1) {
-    if (S.nF > 0) hipLaunchKernelGGL(k_lu_forward<T>, wave_grid(S.nF), dim3(256), 0, st, F, S.ftask, S.nF);
-  } else if (S.nFm > 0) {
-    hipLaunchKernelGGL(k_lu_forward_mr<T>, wave_grid(S.nFm), dim3(256), 0, st, F, S.ftask_m, S.nFm, nb);
-  }
+  const int n = nb == 1 ? S.nF : S.nFm;
+  if (n > 0)
+    hipLaunchKernelGGL(k_lu_forward<T>, wave_grid(n), dim3(256), 0, st, F, nb == 1 ? S.ftask : S.ftask_m, n, nb);
 }
 template <class T, class TO>
 void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st) {
-  if (nb == 1) {
-    if (S.nB > 0) hipLaunchKernelGGL((k_lu_backward<T, TO>), wave_grid(S.nB), dim3(256), 0, st, F, S.btask, S.nB, out);
-  } else if (S.nBm > 0) {
-    hipLaunchKernelGGL((k_lu_backward_mr<T, TO>), wave_grid(S.nBm), dim3(256), 0, st, F, S.btask_m, S.nBm, nb, out,
-                       out_stride);
-  }
+  const int n = nb == 1 ? S.nB : S.nBm;
+  if (n > 0)
+    hipLaunchKernelGGL((k_lu_backward<T, TO>), wave_grid(n), dim3(256), 0, st, F, nb == 1 ? S.btask : S.btask_m, n,
+                       nb, out, out_stride);
+}
+template <class T>
+void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t st) {
+  if (S.nsub == 0) return;
+  const LuSubList& L = nb == 1 ? S.single : S.multi;
+  hipLaunchKernelGGL(k_lu_forward_sub<T>, dim3(S.nsub), dim3(64 * kSubWaves), 0, st, F, L.ftask, L.flev, L.fptr, nb);
+}
+template <class T, class TO>
+void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long out_stride, int nb, hipStream_t st) {
+  if (S.nsub == 0) return;
+  const LuSubList& L = nb == 1 ? S.single : S.multi;
+  hipLaunchKernelGGL((k_lu_backward_sub<T, TO>), dim3(S.nsub), dim3(64 * kSubWaves), 0, st, F, L.btask, L.blev, L.bptr,
+                     nb, out, out_stride);
 }
 template <class T>
 void launch_zero(T* p, long long count, hipStream_t st) {
@@ -833,6 +885,7 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
   template void launch_plg_b2<T>(const PlgRows&, const T*, const T*, T*, long long, int, hipStream_t);        \
   template void launch_zero<T>(T*, long long, hipStream_t);                                                   \
   template void launch_lu_forward<T>(const LuDev&, const LuTasks&, int, hipStream_t);                        \
+  template void launch_lu_forward_sub<T>(const LuDev&, const LuSub&, int, hipStream_t);                      \
   template void launch_add_unknowns<T>(const StencilLevel&, const T*, const unsigned long long*, double*, int, \
                                        hipStream_t);                                                          \
   template void launch_scale_residual<T>(long long, const double*, const unsigned long long*, T*, int,        \
@@ -844,6 +897,9 @@ template void launch_lu_backward<double, double>(const LuDev&, const LuTasks&, d
                                                  hipStream_t);
 template void launch_lu_backward<double, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
 template void launch_lu_backward<float, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
+template void launch_lu_backward_sub<double, double>(const LuDev&, const LuSub&, double*, long long, int, hipStream_t);
+template void launch_lu_backward_sub<double, float>(const LuDev&, const LuSub&, float*, long long, int, hipStream_t);
+template void launch_lu_backward_sub<float, float>(const LuDev&, const LuSub&, float*, long long, int, hipStream_t);
 template void launch_gather<double, double>(int, const int*, const double*, long long, double*, int, hipStream_t);
 template void launch_gather<float, double>(int, const int*, const float*, long long, double*, int, hipStream_t);
 

@@ -77,6 +77,23 @@ struct LuTasks {
   const LuTask* btask_m;
 };
 
+// The lower heights of the tree as subtrees, one workgroup each: for subtree s,
+// levels lptr[s] .. lptr[s+1] of lev, each a task range [x, y) of one height
+// (forward: heights ascending; backward: descending).
+struct LuSubList {
+  const LuTask* ftask;
+  const int2* flev;
+  const int* fptr;
+  const LuTask* btask;
+  const int2* blev;
+  const int* bptr;
+};
+struct LuSub {
+  int nsub = 0;           // subtrees (0: no subtree launch)
+  int hcut = 0;           // heights below hcut belong to the subtrees
+  LuSubList single{}, multi{};
+};
+
 // ---- stencil work (T = double or float), nb arrays at stride n^3
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st);
@@ -105,6 +122,10 @@ template <class T>
 void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st);
 template <class T, class TO>
 void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st);
+template <class T>
+void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t st);
+template <class T, class TO>
+void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long out_stride, int nb, hipStream_t st);
 
 // ---- norms, updates, fills (nb arrays; norms are nb u64 bit patterns of
 // non-negative doubles, combined by atomicMax)
