@@ -142,3 +142,14 @@ def test_errors_are_status_codes():
     rc = lib.cc_solve(P._h, C.c_void_p(16), C.c_void_p(16), C.byref(info))
     assert rc == L.CC_EDEVICE and b"host-only" in lib.cc_last_error()
     P.close()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every entry point raises."""
+    from paper_2410_05865_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libcutcell.so"))
+    monkeypatch.setattr(_lib, "_LIB", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+    with pytest.raises(ImportError):
+        _lib.Problem(inputs.sphere_domain(n=16, radius=0.25, n_min=8), device=-1)
