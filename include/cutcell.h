@@ -119,6 +119,7 @@ typedef struct cc_level_info {
   double setup_seconds;
   int lu_subtree_cut;     /* device sweeps: heights below this run as one launch of subtrees */
   int lu_subtrees;        /* number of those subtrees (0: one launch per height throughout) */
+  int lu_entries_per_lane;/* device sweeps: factor entries per lane of a row (chosen at build) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */

@@ -64,7 +64,7 @@ class CcLevelInfo(C.Structure):
     _fields_ = [("n", C.c_int), ("n_unknowns", C.c_longlong), ("n_phi2", C.c_longlong), ("n_cut", C.c_longlong),
                 ("n_merged", C.c_longlong), ("lu_vars", C.c_longlong), ("lu_entries", C.c_longlong),
                 ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double),
-                ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int)]
+                ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int)]
 
 
 class CutCellError(RuntimeError):

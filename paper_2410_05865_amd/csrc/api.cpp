@@ -105,6 +105,7 @@ struct DevLU {
   std::vector<LuTasks> tasks;  // per height, all nodes
   LuSub sub;                   // the heights below sub.hcut grouped in subtrees
   bool sub_on = false;         // sweeps use the subtrees (chosen by timing at build)
+  double epl = 8.0;            // factor entries per lane of the task lists (chosen by timing)
   int height = 0;
 };
 
@@ -303,10 +304,17 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
   d.z = B.alloc<double>(F.n);
   d.x = B.alloc<double>(F.n);
   D.height = F.max_height;
-  // g lanes per row: the largest power of two with about 8 entries per lane
-  auto lanes_for = [](double len) {
+}
+
+// Task lists of a factorization for a given number of factor entries per
+// lane (epl): per-height lists of all nodes and the subtree grouping of the
+// low heights.  Arrays go to B.
+void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
+  const int ns = (int)F.nodes.size();
+  // g lanes per row: the largest power of two leaving more than epl entries per lane
+  auto lanes_for = [epl](double len) {
     int g = 1;
-    while (g < 64 && 16.0 * g <= len) g <<= 1;
+    while (g < 64 && 2.0 * epl * g <= len) g <<= 1;
     return g;
   };
   auto log2i = [](int g) {
@@ -547,27 +555,47 @@ void upload(cc_problem* P) {
   }
   W.s0 = P->s0;
   W.norm = P->d_norm;
-  // Sweep schedule per factorization: time one LU solve with and without the
-  // subtree launch on this device (the work vectors' contents do not matter)
-  // and keep the faster.
+  // Sweep schedule per factorization (the autotuner): for 2, 4 and 8 factor
+  // entries per lane, each with and without the subtree launch, time one LU
+  // solve on this device (the work vectors' contents do not matter) and keep
+  // the fastest; the task lists of the other candidates are freed.
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   for (int m = 0; m <= M; ++m) {
     DevLU& L = P->dev[m].lu;
-    if (L.sub.nsub == 0) continue;
     const long long n3m = cube(P->dev[m].st.n);
-    float t[2] = {0.f, 0.f};
-    for (int on = 0; on < 2; ++on) {
-      L.sub_on = on != 0;
-      lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
-      HIPCHK(hipEventRecord(ev0, P->stream));
-      for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
-      HIPCHK(hipEventRecord(ev1, P->stream));
-      HIPCHK(hipEventSynchronize(ev1));
-      HIPCHK(hipEventElapsedTime(&t[on], ev0, ev1));
+    float best = 1e30f;
+    DevLU keep = L;
+    DevBuf keep_buf;
+    for (double epl : {2.0, 4.0, 8.0}) {
+      DevBuf cand;
+      make_schedule(P->lu[m], L, epl, cand);
+      for (int on = 0; on < (L.sub.nsub > 0 ? 2 : 1); ++on) {
+        L.sub_on = on != 0;
+        lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+        HIPCHK(hipEventRecord(ev0, P->stream));
+        for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+        HIPCHK(hipEventRecord(ev1, P->stream));
+        HIPCHK(hipEventSynchronize(ev1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, ev0, ev1));
+        if (t < best) {
+          best = t;
+          keep = L;
+          keep.epl = epl;
+        }
+      }
+      if (keep.epl == epl) {
+        keep_buf.release();
+        keep_buf = std::move(cand);
+      } else {
+        cand.release();
+      }
     }
-    L.sub_on = t[1] < 0.97f * t[0];
+    L = keep;
+    for (void* q : keep_buf.ptrs) B.ptrs.push_back(q);
+    keep_buf.ptrs.clear();
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
@@ -1088,6 +1116,7 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     const bool on = dev && p->dev[level].lu.sub_on;
     info->lu_subtree_cut = on ? p->dev[level].lu.sub.hcut : 0;
     info->lu_subtrees = on ? p->dev[level].lu.sub.nsub : 0;
+    info->lu_entries_per_lane = dev ? (int)p->dev[level].lu.epl : 0;
   });
 }
 
