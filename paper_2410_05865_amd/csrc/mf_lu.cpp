@@ -28,6 +28,35 @@ struct Builder {
   std::vector<TNode> t;
   std::vector<int> mark;   // scratch: side of each vertex during a split
 
+  // Connected components of verts (in the graph restricted to verts), largest
+  // first; mark[] is left zero.
+  std::vector<std::vector<int>> components(const std::vector<int>& verts) {
+    for (int v : verts) mark[v] = 1;
+    std::vector<std::vector<int>> comps;
+    std::vector<int> stack;
+    for (int v0 : verts) {
+      if (mark[v0] != 1) continue;
+      comps.emplace_back();
+      std::vector<int>& c = comps.back();
+      mark[v0] = 2;
+      stack.push_back(v0);
+      while (!stack.empty()) {
+        int v = stack.back();
+        stack.pop_back();
+        c.push_back(v);
+        for (int w : (*adj)[v])
+          if (mark[w] == 1) {
+            mark[w] = 2;
+            stack.push_back(w);
+          }
+      }
+    }
+    for (int v : verts) mark[v] = 0;
+    std::stable_sort(comps.begin(), comps.end(),
+                     [](const std::vector<int>& a, const std::vector<int>& b) { return a.size() > b.size(); });
+    return comps;
+  }
+
   int build(std::vector<int>& verts) {
     int id = (int)t.size();
     t.emplace_back();
@@ -35,6 +64,23 @@ struct Builder {
       std::sort(verts.begin(), verts.end());
       t[id].F = verts;
       return id;
+    }
+    // Disconnected vertex sets need no separator: split the components into
+    // two groups of similar size under an empty node.
+    {
+      std::vector<std::vector<int>> comps = components(verts);
+      if (comps.size() > 1) {
+        std::vector<int> L, R;
+        for (auto& c : comps) {
+          std::vector<int>& dst = L.size() <= R.size() ? L : R;
+          dst.insert(dst.end(), c.begin(), c.end());
+        }
+        int l = build(L);
+        t[id].left = l;
+        int r = build(R);
+        t[id].right = r;
+        return id;
+      }
     }
     // Candidate cuts: a few planes per axis (quantiles of the coordinates);
     // for each, the vertex separator is the smaller of the two one-sided sets
