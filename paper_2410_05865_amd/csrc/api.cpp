@@ -200,6 +200,7 @@ struct cc_problem {
   std::vector<cc::DevLevel> dev;
   cc::DevBuf buf;
   unsigned long long* d_norm = nullptr;
+  double* d_partial = nullptr;  // reduction scratch (kReductionScratch doubles)
   double* s0 = nullptr;
   double* e0 = nullptr;
   cc::Work<double> w64;         // FP64, one right-hand side (arrays of dev[])
@@ -541,6 +542,7 @@ void upload(cc_problem* P) {
     D.absorbed = B.upload(ab);
   }
   P->d_norm = B.alloc<unsigned long long>(1);
+  P->d_partial = B.alloc<double>(kReductionScratch);
   size_t n3 = (size_t)P->lv[0]->n * P->lv[0]->n * P->lv[0]->n;
   P->s0 = B.alloc<double>(n3);
   P->e0 = B.alloc<double>(n3);
@@ -555,7 +557,7 @@ void upload(cc_problem* P) {
   }
   W.s0 = P->s0;
   W.norm = P->d_norm;
-  // Sweep schedule per factorization (the autotuner): for 2, 4 and 8 factor
+  // Sweep schedule per factorization (the autotuner): for 2 to 32 factor
   // entries per lane, each with and without the subtree launch, time one LU
   // solve on this device (the work vectors' contents do not matter) and keep
   // the fastest; the task lists of the other candidates are freed.
@@ -568,7 +570,7 @@ void upload(cc_problem* P) {
     float best = 1e30f;
     DevLU keep = L;
     DevBuf keep_buf;
-    for (double epl : {2.0, 4.0, 8.0}) {
+    for (double epl : {2.0, 4.0, 8.0, 16.0, 32.0}) {
       DevBuf cand;
       make_schedule(P->lu[m], L, epl, cand);
       for (int on = 0; on < (L.sub.nsub > 0 ? 2 : 1); ++on) {
@@ -643,11 +645,14 @@ void vcycle(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, T* tmp, in
   DevLevel& D = P->dev[m];
   const long long n3 = cube(D.st.n);
   const double om = P->prm.omega;
-  launch_zero<T>(e, n3 * nb, P->stream);
   T* cur = e;
   T* oth = tmp;
+  if (P->prm.nu1 == 0) launch_zero<T>(e, n3 * nb, P->stream);
   for (int it = 0; it < P->prm.nu1; ++it) {
-    launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
+    if (it == 0)  // from e = 0 the sweep is e = omega D^-1 s (no stencil reads)
+      launch_smo1_first<T>(D.st, om, s, oth, nb, P->stream);
+    else
+      launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
     std::swap(cur, oth);
     smo2<T>(P, W, m, s, cur, nb);
   }
@@ -699,7 +704,7 @@ void outer_step(cc_problem* P, const Work<T>& W, const double* r, double* phi, i
   }
   residual(P, 0, r, phi, W.s0, nb);
   launch_zero_u64(W.norm, nb, P->stream);
-  launch_maxabs(W.s0, n3, nb, W.norm, P->stream);
+  launch_maxabs(W.s0, n3, nb, W.norm, P->d_partial, P->stream);
 }
 
 struct SolveRec {
@@ -715,14 +720,14 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
   DevLevel& D0 = P->dev[0];
   const long long n3 = cube(D0.st.n);
   launch_zero_u64(W.norm, nb, P->stream);
-  launch_maxabs(r, n3, nb, W.norm, P->stream);
+  launch_maxabs(r, n3, nb, W.norm, P->d_partial, P->stream);
   std::vector<double> rn = read_norms(P, W.norm, nb);
   for (int b = 0; b < nb; ++b)
     if (!std::isfinite(rn[b])) fail(CC_EINVAL, "non-finite right-hand side");
   launch_mask_unknowns(D0.st, phi, nb, P->stream);
   residual(P, 0, r, phi, W.s0, nb);
   launch_zero_u64(W.norm, nb, P->stream);
-  launch_maxabs(W.s0, n3, nb, W.norm, P->stream);
+  launch_maxabs(W.s0, n3, nb, W.norm, P->d_partial, P->stream);
   std::vector<double> sn = read_norms(P, W.norm, nb);
   rec.assign(nb, SolveRec{});
   auto update = [&](bool first) {
@@ -787,12 +792,12 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     K.amax = K.own.alloc<unsigned long long>(1);
   }
   hipStream_t st = P->stream;
-  auto dots = [&](const double* w, const double* V, int nv) {
-    launch_dots(n3, w, V, n3, nv, K.d, st);
-    std::vector<double> h(nv);
-    HIPCHK(hipMemcpyAsync(h.data(), K.d, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+  auto norm2 = [&](const double* w) {  // (w, w)
+    launch_dots_norm(n3, w, w, n3, 0, K.d, P->d_partial, st);
+    double q = 0.0;
+    HIPCHK(hipMemcpyAsync(&q, K.d, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    return h;
+    return q;
   };
   auto put = [&](const std::vector<double>& c) {
     HIPCHK(hipMemcpyAsync(K.d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -800,7 +805,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
   };
   auto maxabs = [&](const double* v) {
     launch_zero_u64(P->d_norm, 1, st);
-    launch_maxabs(v, n3, 1, P->d_norm, st);
+    launch_maxabs(v, n3, 1, P->d_norm, P->d_partial, st);
     return read_norm(P);
   };
   const double rn = maxabs(r);
@@ -816,9 +821,9 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     rec.rel = rel;
     if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
     if (rel < P->prm.tol || cycles >= P->prm.max_iter) break;
-    const double beta = std::sqrt(dots(W.s0, W.s0, 1)[0]);
+    const double beta = std::sqrt(norm2(W.s0));
     put({1.0 / beta});
-    launch_combo(n3, W.s0, n3, 1, K.d, K.V, 0, nullptr, st);
+    launch_combo(n3, W.s0, n3, 1, K.d, K.V, 0, nullptr, nullptr, P->d_partial, st);
     std::vector<std::vector<double>> Hb(k + 1, std::vector<double>(k, 0.0));  // unrotated
     std::vector<std::vector<double>> R(k + 1, std::vector<double>(k, 0.0));   // rotated
     std::vector<double> cs(k), sn(k), g(k + 1, 0.0);
@@ -841,7 +846,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
         // z = max|v| * VCycle32(v / max|v|): the FP32 V-cycle as preconditioner
         Work<float>& W32 = P->w32;
         launch_zero_u64(P->d_norm, 1, st);
-        launch_maxabs(vj, n3, 1, P->d_norm, st);
+        launch_maxabs(vj, n3, 1, P->d_norm, P->d_partial, st);
         launch_scale_residual<float>(n3, vj, P->d_norm, W32.s[0], 1, st);
         vcycle<float>(P, W32, 0, W32.s[0], W32.e[0], W32.et[0], 1);
         launch_zero<double>(zj, n3, st);
@@ -852,25 +857,38 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
       ++cycles;
       launch_stencil_apply(D0.st, zj, K.w, st);
       launch_plg_residual(D0.plg, nullptr, zj, K.w, 1, 1, n3, st);
-      // classical Gram-Schmidt; a second pass only when the norm drops by more
+      // classical Gram-Schmidt (projections and |w| in one pass, the update and
+      // the new |w| in another); a second pass only when the norm drops by more
       // than 1/sqrt(2) (Daniel-Gragg-Kaufman-Stewart criterion)
-      const double wn0 = std::sqrt(dots(K.w, K.w, 1)[0]);
-      std::vector<double> h = dots(K.w, K.V, j + 1);
-      put(h);
-      launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
-      double hn = std::sqrt(dots(K.w, K.w, 1)[0]);
+      auto project = [&](std::vector<double>& h) {  // returns |w|^2 before
+        launch_dots_norm(n3, K.w, K.V, n3, j + 1, K.d, P->d_partial, st);
+        std::vector<double> hw(j + 2);
+        HIPCHK(hipMemcpyAsync(hw.data(), K.d, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        h.assign(hw.begin(), hw.begin() + j + 1);
+        return hw[j + 1];
+      };
+      auto subtract = [&](const std::vector<double>& h) {  // w -= V h; returns |w|^2 after
+        put(h);
+        launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, K.d + k + 1, P->d_partial, st);
+        double q = 0.0;
+        HIPCHK(hipMemcpyAsync(&q, K.d + k + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return q;
+      };
+      std::vector<double> h, h2;
+      const double wn0 = std::sqrt(project(h));
+      double hn = std::sqrt(subtract(h));
       if (hn < 0.7071 * wn0) {
-        std::vector<double> h2 = dots(K.w, K.V, j + 1);
-        put(h2);
-        launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, st);
+        project(h2);
+        hn = std::sqrt(subtract(h2));
         for (int i = 0; i <= j; ++i) h[i] += h2[i];
-        hn = std::sqrt(dots(K.w, K.w, 1)[0]);
       }
       for (int i = 0; i <= j; ++i) Hb[i][j] = R[i][j] = h[i];
       Hb[j + 1][j] = R[j + 1][j] = hn;
       if (hn > 0) {
         put({1.0 / hn});
-        launch_combo(n3, K.w, n3, 1, K.d, K.V + (long long)(j + 1) * n3, 0, nullptr, st);
+        launch_combo(n3, K.w, n3, 1, K.d, K.V + (long long)(j + 1) * n3, 0, nullptr, nullptr, P->d_partial, st);
       }
       for (int i = 0; i < j; ++i) {
         const double a = R[i][j], b = R[i + 1][j];
@@ -895,7 +913,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
           for (int l = 0; l < j; ++l) c[i] -= Hb[i][l] * y[l];
         put(c);
         launch_zero_u64(K.amax, 1, st);
-        launch_combo(n3, K.V, n3, j + 1, K.d, nullptr, 0, K.amax, st);
+        launch_combo(n3, K.V, n3, j + 1, K.d, nullptr, 0, K.amax, nullptr, P->d_partial, st);
         unsigned long long bits = 0;
         HIPCHK(hipMemcpyAsync(&bits, K.amax, sizeof(bits), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -909,7 +927,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     }
     std::vector<double> y = solve_y(j);
     put(y);
-    launch_combo(n3, K.Z, n3, j, K.d, phi, 1, nullptr, st);
+    launch_combo(n3, K.Z, n3, j, K.d, phi, 1, nullptr, nullptr, P->d_partial, st);
     (void)converged;
   }
   rec.iterations = cycles;
@@ -1314,7 +1332,7 @@ int cc_residual(cc_problem* p, int level, const double* r, const double* x, doub
     DevLevel& D = p->dev[level];
     residual(p, level, r, x, s);
     launch_zero_u64(p->d_norm, 1, p->stream);
-    launch_maxabs(s, cube(D.st.n), 1, p->d_norm, p->stream);
+    launch_maxabs(s, cube(D.st.n), 1, p->d_norm, p->d_partial, p->stream);
     double v = read_norm(p);
     if (maxabs) *maxabs = v;
   });
@@ -1434,7 +1452,7 @@ int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, co
       p->net_cells = m3;
     }
     launch_zero_u64(p->d_norm, 1, p->stream);
-    launch_maxabs(r, cube(n0), 1, p->d_norm, p->stream);
+    launch_maxabs(r, cube(n0), 1, p->d_norm, p->d_partial, p->stream);
     const double rn = read_norm(p);
     const double inv = rn > 0 ? 1.0 / rn : 0.0;
     launch_net_features(n0, m, r, inv, p->volfrac[level], p->net_x, p->stream);

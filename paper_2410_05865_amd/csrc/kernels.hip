@@ -29,6 +29,33 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Workgroup reductions (blockDim.x a multiple of 64, at most 1024); the
+// result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[16];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) t += part[i];
+  return t;
+}
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double part[16];
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) part[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) t = fmax(t, part[i]);
+  return t;
+}
+
 // One axis of the assembled regular row (times 12 h^2): the 5-point
 // fourth-order stencil, with the ghost-substituted forms in the two cell layers
 // next to a Dirichlet (bc 0) or Neumann (bc 1) wall.  Adds the diagonal to diag.
@@ -137,6 +164,41 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
     const T inv = T(L.inv12h2);
     T a = regular_row<T>(L, ein, i, j, k, c, diag);
     v += omega * (ld_stream(s + c) - a * inv) / (diag * inv);
+  }
+  st_stream(v, eout + c);
+}
+
+// Diagonal of the assembled regular row (times 12 h^2), summed over the axes in
+// the order regular_row uses.
+template <class T>
+__device__ __forceinline__ T axis_diag(int t, int n, int blo, int bhi) {
+  if (t >= 2 && t <= n - 3) return T(-30.0);
+  if (t == n - 1) return bhi == 0 ? T(-1087.0 / 12.0) : T(-14.5);
+  if (t == n - 2) return bhi == 0 ? T(-403.0 / 12.0) : T(-30.9);
+  if (t == 0) return blo == 0 ? T(-1087.0 / 12.0) : T(-14.5);
+  return blo == 0 ? T(-403.0 / 12.0) : T(-30.9);
+}
+
+// The first SMO-1 sweep of a V-cycle level, from e = 0: e' = omega s / D on
+// phi_1 cells, 0 elsewhere (the same arithmetic as k_smo1 with e = 0).
+template <class T>
+__global__ void k_smo1_first(StencilLevel L, T omega, const T* __restrict__ s, T* __restrict__ eout) {
+  const int n = L.n;
+  int i, j, k;
+  tile_ijk(n, i, j, k);
+  if (i >= n || j >= n) return;
+  const long long o = batch_off(n);
+  s += o;
+  eout += o;
+  long c = i + (long)n * (j + (long)n * k);
+  T v = T(0);
+  if (L.type[c] == 1) {
+    T diag = T(0);
+    diag += axis_diag<T>(i, n, L.bc[0], L.bc[1]);
+    diag += axis_diag<T>(j, n, L.bc[2], L.bc[3]);
+    diag += axis_diag<T>(k, n, L.bc[4], L.bc[5]);
+    const T inv = T(L.inv12h2);
+    v += omega * (ld_stream(s + c) - T(0) * inv) / (diag * inv);
   }
   st_stream(v, eout + c);
 }
@@ -574,16 +636,36 @@ __global__ void k_zero_u64(unsigned long long* p, int count) {
   if (i < count) p[i] = 0ull;
 }
 
-// per-batch max |v| as the bit pattern of a non-negative double (ordered like
-// unsigned integers), combined with atomicMax
-__global__ void k_maxabs(const double* __restrict__ v, long long count, unsigned long long* out) {
+// per-batch max |v|: per-block maxima into partial[b * gridDim.x + block], then
+// k_max_finish writes the bit pattern of the non-negative double to out[b]
+__global__ void k_maxabs(const double* __restrict__ v, long long count, double* __restrict__ partial) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long stride = (long long)gridDim.x * blockDim.x;
   v += (long long)blockIdx.y * count;
   double m = 0.0;
   for (; i < count; i += stride) m = fmax(m, fabs(v[i]));
-  m = wave_max(m);
-  if (threadIdx.x % kWave == 0) atomicMax(out + blockIdx.y, (unsigned long long)__double_as_longlong(m));
+  m = block_max(m);
+  if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = m;
+}
+__global__ void k_max_finish(const double* __restrict__ partial, int g, unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < g; i += blockDim.x) m = fmax(m, partial[(long long)blockIdx.x * g + i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) out[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
+}
+// *out = sum of partial[i * nv + j] over i < g
+__global__ void k_sum_finish_one(const double* __restrict__ partial, int g, int nv, int j, double* __restrict__ out) {
+  double t = 0.0;
+  for (int i = threadIdx.x; i < g; i += blockDim.x) t += partial[(long long)i * nv + j];
+  t = block_sum(t);
+  if (threadIdx.x == 0) *out = t;
+}
+// out[j] = sum of partial[i * nv + j] over i < g (one block per j)
+__global__ void k_sum_finish(const double* __restrict__ partial, int g, int nv, double* __restrict__ out) {
+  double t = 0.0;
+  for (int i = threadIdx.x; i < g; i += blockDim.x) t += partial[(long long)i * nv + blockIdx.x];
+  t = block_sum(t);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 __device__ __forceinline__ double norm_value(const unsigned long long* norm, int b) {
@@ -681,24 +763,34 @@ __global__ void k_prolong_trilinear(StencilLevel L0, int m, const float* __restr
   phi[c] = scale * v;
 }
 
-// Krylov vectors (n3 doubles each, stride apart): out[i] += (w, V_i) for
-// i = blockIdx.y (per-block partial sums, atomically combined)
-__global__ void k_dots(long long n3, const double* __restrict__ w, const double* __restrict__ V, long long stride,
-                       double* __restrict__ out) {
-  const double* v = V + blockIdx.y * stride;
-  double s = 0.0;
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3; c += (long long)gridDim.x * blockDim.x)
-    s += w[c] * v[c];
-  s = wave_sum(s);
-  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out + blockIdx.y, s);
+// per-block partial sums of (w, V_i), i < NV, and (w, w) into
+// partial[block * (NV + 1) + i]: w is read once for all the vectors
+template <int NV>
+__global__ void k_dots_multi(long long n3, const double* __restrict__ w, const double* __restrict__ V,
+                             long long stride, double* __restrict__ partial) {
+  double acc[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3;
+       c += (long long)gridDim.x * blockDim.x) {
+    const double wc = w[c];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += wc * V[i * stride + c];
+    acc[NV] += wc * wc;
+  }
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) {
+    const double t = block_sum(acc[i]);
+    if (threadIdx.x == 0) partial[(long long)blockIdx.x * (NV + 1) + i] = t;
+  }
 }
 
 // out = mode 0: sum_i coef[i] V_i;  1: out + sum;  2: out - sum;  3: scale: coef[0] * V_0
 // and, if amax is not null, atomicMax of max |out| (bit pattern)
 __global__ void k_combo(long long n3, const double* __restrict__ V, long long stride, int nv,
                         const double* __restrict__ coef, double* __restrict__ out, int mode,
-                        unsigned long long* __restrict__ amax) {
-  double m = 0.0;
+                        double* __restrict__ pmax, double* __restrict__ psq) {
+  double m = 0.0, q = 0.0;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3;
        c += (long long)gridDim.x * blockDim.x) {
     double s = 0.0;
@@ -706,10 +798,15 @@ __global__ void k_combo(long long n3, const double* __restrict__ V, long long st
     double o = mode == 0 || mode == 3 ? s : (mode == 1 ? out[c] + s : out[c] - s);
     if (out) out[c] = o;
     m = fmax(m, fabs(o));
+    q += o * o;
   }
-  if (amax) {
-    m = wave_max(m);
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(amax, (unsigned long long)__double_as_longlong(m));
+  if (pmax) {
+    m = block_max(m);
+    if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+  }
+  if (psq) {
+    q = block_sum(q);
+    if (threadIdx.x == 0) psq[blockIdx.x] = q;
   }
 }
 
@@ -752,12 +849,17 @@ inline dim3 grid_tiles(int n, int nb = 1) { return dim3(((n + 63) / 64) * ((n + 
 const dim3 kBlock3(64, 4, 1);
 inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs); }
 inline long long cube(int n) { return (long long)n * n * n; }
+constexpr int kRedBlocks = 2048;   // blocks of the reductions (partial sums per block)
 
 }  // namespace
 
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_smo1<T>, grid_tiles(L.n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
+}
+template <class T>
+void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_smo1_first<T>, grid_tiles(L.n, nb), kBlock3, 0, st, L, T(omega), s, e_out);
 }
 void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, int nb,
                              hipStream_t st) {
@@ -828,9 +930,11 @@ void launch_zero(T* p, long long count, hipStream_t st) {
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(blocks(count, 64)), dim3(64), 0, st, p, count);
 }
-void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, hipStream_t st) {
-  int g = (int)std::min<long long>(blocks(count, 256), 2048);
-  hipLaunchKernelGGL(k_maxabs, dim3(g, nb), dim3(256), 0, st, v, count, out);
+void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, double* partial,
+                   hipStream_t st) {
+  const int g = (int)std::min<long long>(blocks(count, 256), kRedBlocks);
+  hipLaunchKernelGGL(k_maxabs, dim3(g, nb), dim3(256), 0, st, v, count, partial);
+  hipLaunchKernelGGL(k_max_finish, dim3(nb), dim3(256), 0, st, partial, g, out);
 }
 template <class T>
 void launch_add_unknowns(const StencilLevel& L, const T* e, const unsigned long long* norm, double* phi, int nb,
@@ -865,16 +969,41 @@ void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, dou
                               hipStream_t st) {
   hipLaunchKernelGGL(k_prolong_trilinear, dim3(blocks(cube(L0.n), 256)), dim3(256), 0, st, L0, m, y, scale, phi);
 }
-void launch_dots(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, out, (long long)nv);
-  const int g = (int)std::min<long long>(blocks(n3, 256), 1024);
-  hipLaunchKernelGGL(k_dots, dim3(g, nv), dim3(256), 0, st, n3, w, V, stride, out);
-}
 void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
-                  unsigned long long* amax, hipStream_t st) {
-  const int g = (int)std::min<long long>(blocks(n3, 256), 4096);
-  hipLaunchKernelGGL(k_combo, dim3(g), dim3(256), 0, st, n3, V, stride, nv, coef, out, mode, amax);
+                  unsigned long long* amax, double* sumsq, double* partial, hipStream_t st) {
+  const int g = (int)std::min<long long>(blocks(n3, 256), kRedBlocks);
+  double* pmax = amax ? partial : nullptr;
+  double* psq = sumsq ? partial + kRedBlocks : nullptr;
+  hipLaunchKernelGGL(k_combo, dim3(g), dim3(256), 0, st, n3, V, stride, nv, coef, out, mode, pmax, psq);
+  if (amax) hipLaunchKernelGGL(k_max_finish, dim3(1), dim3(256), 0, st, pmax, g, amax);
+  if (sumsq) hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(256), 0, st, psq, g, 1, sumsq);
+}
+void launch_dots_norm(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
+                      double* partial, hipStream_t st) {
+  const int g = (int)std::min<long long>(blocks(n3, 256), kRedBlocks);
+  if (nv == 0) {
+    hipLaunchKernelGGL(k_dots_multi<0>, dim3(g), dim3(256), 0, st, n3, w, V, stride, partial);
+    hipLaunchKernelGGL(k_sum_finish_one, dim3(1), dim3(256), 0, st, partial, g, 1, 0, out);
+    return;
+  }
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    const int k = std::min(8, nv - i0);
+    const double* Vi = V + (long long)i0 * stride;
+    switch (k) {
+#define CC_DOTS_CASE(K)                                                                   \
+  case K:                                                                                 \
+    hipLaunchKernelGGL(k_dots_multi<K>, dim3(g), dim3(256), 0, st, n3, w, Vi, stride, partial); \
+    break;
+      CC_DOTS_CASE(0) CC_DOTS_CASE(1) CC_DOTS_CASE(2) CC_DOTS_CASE(3) CC_DOTS_CASE(4) CC_DOTS_CASE(5)
+      CC_DOTS_CASE(6) CC_DOTS_CASE(7) CC_DOTS_CASE(8)
+#undef CC_DOTS_CASE
+    }
+    // out[i0 .. i0 + k - 1] are the projections; the chunk's norm slot is
+    // written only by the last chunk, at out[nv]
+    const int last = i0 + k >= nv;
+    hipLaunchKernelGGL(k_sum_finish, dim3(k), dim3(256), 0, st, partial, g, k + 1, out + i0);
+    if (last) hipLaunchKernelGGL(k_sum_finish_one, dim3(1), dim3(256), 0, st, partial, g, k + 1, k, out + nv);
+  }
 }
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st) {
   if (count == 0) return;
@@ -897,6 +1026,7 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
 
 #define CC_INST(T)                                                                                            \
   template void launch_smo1<T>(const StencilLevel&, double, const T*, const T*, T*, int, hipStream_t);        \
+  template void launch_smo1_first<T>(const StencilLevel&, double, const T*, T*, int, hipStream_t);           \
   template void launch_restrict<T>(const StencilLevel&, const StencilLevel&, const T*, const T*, T*, int,     \
                                    hipStream_t);                                                              \
   template void launch_prolong_add<T>(const StencilLevel&, int, const T*, T*, int, hipStream_t);              \

@@ -97,6 +97,9 @@ struct LuSub {
 // ---- stencil work (T = double or float), nb arrays at stride n^3
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st);
+// first sweep of a level from e = 0: e_out = omega D^-1 s on phi_1 cells, 0 elsewhere
+template <class T>
+void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st);
 template <class T>
 void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
                      hipStream_t st);
@@ -130,7 +133,11 @@ void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long o
 // ---- norms, updates, fills (nb arrays; norms are nb u64 bit patterns of
 // non-negative doubles, combined by atomicMax)
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st);
-void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, hipStream_t st);
+// out[b] = bit pattern of max |v_b| (non-negative doubles order like unsigned
+// integers); partial: kReductionScratch doubles of scratch
+constexpr int kReductionScratch = 2048 * 64;
+void launch_maxabs(const double* v, long long count, int nb, unsigned long long* out, double* partial,
+                   hipStream_t st);
 // phi += scale_b * e on unknown cells; scale_b = norm[b] (or 1 if norm is null)
 template <class T>
 void launch_add_unknowns(const StencilLevel& L, const T* e, const unsigned long long* norm, double* phi, int nb,
@@ -147,13 +154,15 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st);
-// Krylov helpers over n3-element FP64 vectors stored `stride` apart:
-// out[i] = (w, V_i), i < nv (out zeroed first);  out = / += / -= sum_i coef_i V_i
-// (mode 0 / 1 / 2; coef on the device) with optional max |out| into *amax
-void launch_dots(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
-                 hipStream_t st);
+// Krylov helpers over n3-element FP64 vectors stored `stride` apart (partial:
+// reduction scratch as for launch_maxabs):
+// out = / += / -= sum_i coef_i V_i (mode 0 / 1 / 2; coef on the device), with
+// optional max |out| into *amax (bit pattern) and sum of out^2 into *sumsq;
+// out[i] = (w, V_i) for i < nv and out[nv] = (w, w), w read once per 8 vectors
 void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
-                  unsigned long long* amax, hipStream_t st);
+                  unsigned long long* amax, double* sumsq, double* partial, hipStream_t st);
+void launch_dots_norm(long long n3, const double* w, const double* V, long long stride, int nv, double* out,
+                      double* partial, hipStream_t st);
 // learned guess: coarse features (block mean of r scaled, volume fraction) and
 // trilinear prolongation of the network output to the level-0 unknowns
 void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
