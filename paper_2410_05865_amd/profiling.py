@@ -67,8 +67,9 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
         f"grid {sgrid} work-items)",
         f"- k_smo1 bytes per launch (calibrated): `{smo_bytes:.6e}`",
         f"- k_smo1 algorithmic bytes per launch (25 B/cell): {alg:.6e}; measured/algorithmic = {smo_bytes / alg:.3f}",
-        f"- LU-correction sweeps: {n_lu} forward launches in the run; FETCH {lu_f:.1f} KiB, WRITE {lu_w:.1f} KiB "
-        f"over all k_lu_* dispatches (calibrated {(lu_f * f_fac + lu_w * w_fac) * 1024:.6e} bytes)",
+        f"- LU sweeps: {n_lu} forward launches in the run (the build-time schedule trials included); FETCH "
+        f"{lu_f:.1f} KiB, WRITE {lu_w:.1f} KiB over all k_lu_* dispatches (calibrated "
+        f"{(lu_f * f_fac + lu_w * w_fac) * 1024:.6e} bytes)",
     ]
     return "\n".join(lines)
 
