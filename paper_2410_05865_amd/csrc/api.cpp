@@ -294,7 +294,12 @@ void upload_lu(cc_problem* P, const SupernodalLU& F, const std::vector<int>& var
   d.M = B.upload(F.Mbuf);
   d.V = B.upload(F.Vbuf);
   d.W = B.upload(F.Wbuf);
-  d.U = B.upload(F.Ubuf);
+  // one trailing entry so that a node's list start is a valid index even when
+  // it has no later variables (the sweeps load it unconditionally)
+  std::vector<int> Upad(F.Ubuf);
+  Upad.push_back(0);
+  Uf.push_back(0);
+  d.U = B.upload(Upad);
   d.Uf = B.upload(Uf);
   if (fp32) {
     d.M32 = B.upload(std::vector<float>(F.Mbuf.begin(), F.Mbuf.end()));
@@ -433,6 +438,10 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     build(true, SB.multi);
     SB.nsub = (int)roots.size();
   }
+  // entries per lane loaded per round: rows hold between epl and 2 epl entries
+  // per lane (fewer when short, more only at 64 lanes per row)
+  const int kc = epl <= 2.0 ? 4 : (epl <= 4.0 ? 8 : 16);
+  SB.kc = kc;
   D.tasks.assign(F.max_height + 1, LuTasks{});
   for (int h = 0; h <= F.max_height; ++h) {
     std::vector<LuTask> ft, bt, fm, bm;
@@ -452,6 +461,7 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
         bm.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, 0, 0});
     }
     LuTasks& T = D.tasks[h];
+    T.kc = kc;
     T.nF = (int)ft.size();
     T.nB = (int)bt.size();
     T.ftask = B.upload(ft);

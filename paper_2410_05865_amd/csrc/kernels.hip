@@ -234,6 +234,30 @@ __device__ __forceinline__ const float* plg_vals<float>(const PlgRows& P) {
   return P.vals32;
 }
 
+// sum over the row's 35 entries of vals * x[cols] (entries whose bit is set in
+// `skip` left out).  All 35 indices are loaded first, then every coefficient and
+// gathered value, so a row costs two memory round trips.
+template <class T, class TX>
+__device__ __forceinline__ T plg_dot(const PlgRows& P, const T* __restrict__ vals, const TX* __restrict__ x, int row,
+                                     uint64_t skip) {
+  const long N2 = P.N2;
+  int col[35];
+#pragma unroll
+  for (int t = 0; t < 35; ++t) col[t] = P.cols[t * N2 + row];
+  T a0 = T(0), a1 = T(0);
+#pragma unroll
+  for (int t = 0; t < 35; ++t) {
+    const T v = vals[t * N2 + row] * T(x[col[t]]);
+    if (!((skip >> t) & 1ull)) {
+      if (t & 1)
+        a1 += v;
+      else
+        a0 += v;
+    }
+  }
+  return a0 + a1;
+}
+
 __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const double* __restrict__ x,
                                double* __restrict__ s, int apply, long long stride) {
   int row = blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,9 +266,7 @@ __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const do
   x += o;
   s += o;
   if (!apply) r += o;
-  double a = 0.0;
-#pragma unroll 5
-  for (int t = 0; t < 35; ++t) a += P.vals[(long)t * P.N2 + row] * x[P.cols[(long)t * P.N2 + row]];
+  const double a = plg_dot<double, double>(P, P.vals, x, row, 0ull);
   int c = P.cell[row];
   s[c] = apply ? a : r[c] - a;
 }
@@ -259,11 +281,7 @@ __global__ void k_plg_b2(PlgRows P, const T* __restrict__ s, const T* __restrict
   const int b = blockIdx.y, nb = gridDim.y;
   s += b * stride;
   e += b * stride;
-  const T* vals = plg_vals<T>(P);
-  uint64_t m = P.phi2[row];
-  T a = T(0);
-  for (int t = 0; t < 35; ++t)
-    if (!((m >> t) & 1ull)) a += vals[(long)t * P.N2 + row] * e[P.cols[(long)t * P.N2 + row]];
+  const T a = plg_dot<T, T>(P, plg_vals<T>(P), e, row, P.phi2[row]);
   y[(long long)P.nd[row] * nb + b] = s[P.cell[row]] - a;
 }
 
@@ -341,26 +359,38 @@ struct LuArr<float> {
   __device__ static float* x(const LuDev& F) { return F.x32; }
 };
 
-// acc += sum_{j in [j0, j1), j = gl mod g} a[j] * b[j], four independent chains
-template <class T>
+// acc += sum_{j in [j0, j1), j = gl mod g} a[j] * b[j].  Entries are loaded K
+// per lane per round, every load of a round issued before the first product,
+// so a row of at most K g entries costs one memory round trip.  Indices past
+// the row are clamped to its last entry (an in-bounds load) and their products
+// dropped.
+template <int K, class T>
 __device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restrict__ b, int j0, int j1, int gl,
                                       int g) {
-  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-  int j = j0 + gl;
-  for (; j + 3 * g < j1; j += 4 * g) {
-    s0 += a[j] * b[j];
-    s1 += a[j + g] * b[j + g];
-    s2 += a[j + 2 * g] * b[j + 2 * g];
-    s3 += a[j + 3 * g] * b[j + 3 * g];
+  T s0 = T(0), s1 = T(0);
+  for (int jb = j0 + gl; jb < j1; jb += K * g) {
+    T va[K], vb[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int j = min(jb + u * g, j1 - 1);
+      va[u] = a[j];
+      vb[u] = b[j];
+    }
+#pragma unroll
+    for (int u = 0; u < K; u += 2) {
+      if (jb + u * g < j1) s0 += va[u] * vb[u];
+      if (jb + (u + 1) * g < j1) s1 += va[u + 1] * vb[u + 1];
+    }
   }
-  for (; j < j1; j += g) s0 += a[j] * b[j];
-  return (s0 + s1) + (s2 + s3);
+  return s0 + s1;
 }
 
 // Single right-hand side: a task takes 64/g rows of one node, g lanes per row.
 // Forward: z_F = L11^-1 y_F on the node's rows, and y_U -= (L21 L11^-1) y_F
-// accumulated atomically into the later equations.
-template <class T>
+// accumulated atomically into the later equations.  The row's destination
+// (y_F[i], or the later equation's position) is loaded with the first round,
+// unconditionally at a clamped index (U and Uf end with one padding entry).
+template <int K, class T>
 __device__ __forceinline__ void fwd_task(const LuDev& F, const LuTask& t, int lane) {
   T* y = LuArr<T>::y(F);
   const int lg = t.lg, g = 1 << lg;
@@ -368,26 +398,27 @@ __device__ __forceinline__ void fwd_task(const LuDev& F, const LuTask& t, int la
   const int p = t.p, q = t.q, base = t.base;
   const int i = t.row0 + sub;
   const bool valid = i < p + q;
+  const int ii = min(i, p + q - 1);
   const T* yF = y + base;
-  T acc = T(0);
-  if (valid) {
-    if (i < p)
-      acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, yF, 0, i, gl, g);
-    else
-      acc = lane_dot<T>(LuArr<T>::V(F) + t.offVW + (long)(i - p) * p, yF, 0, p, gl, g);
-  }
+  const T yi = yF[min(ii, p - 1)];
+  const int dst = F.Uf[t.offU + max(ii - p, 0)];
+  const T* row = ii < p ? LuArr<T>::M(F) + t.offM + (long)ii * p : LuArr<T>::V(F) + t.offVW + (long)(ii - p) * p;
+  const int jend = !valid ? 0 : (ii < p ? ii : p);
+  T acc = lane_dot<K, T>(row, yF, 0, jend, gl, g);
   for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (valid && gl == 0) {
     if (i < p)
-      LuArr<T>::z(F)[base + i] = acc + yF[i];
+      LuArr<T>::z(F)[base + i] = acc + yi;
     else
-      atomicAdd(&y[F.Uf[t.offU + (i - p)]], -acc);
+      atomicAdd(&y[dst], -acc);
   }
 }
 
 // Backward: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered to the grid array
-// `out` through var_cell.
-template <class T, class TO>
+// `out` through var_cell.  Round one loads the U11 part with the first K
+// indices of U per lane, round two their coefficients and the gathered x_U, so
+// a short row waits on two memory round trips.
+template <int K, class T, class TO>
 __device__ __forceinline__ void bwd_task(const LuDev& F, const LuTask& t, int lane, TO* __restrict__ out) {
   T* x = LuArr<T>::x(F);
   const int lg = t.lg, g = 1 << lg;
@@ -395,26 +426,40 @@ __device__ __forceinline__ void bwd_task(const LuDev& F, const LuTask& t, int la
   const int p = t.p, q = t.q, base = t.base;
   const int i = t.row0 + sub;
   const bool valid = i < p;
-  T acc = T(0);
-  if (valid) {
-    acc = lane_dot<T>(LuArr<T>::M(F) + t.offM + (long)i * p, LuArr<T>::z(F) + base, i, p, gl, g);
-    if (q > 0) {
-      const T* Wr = LuArr<T>::W(F) + t.offVW + (long)i * q;
-      const int* U = F.U + t.offU;
-      T s0 = T(0), s1 = T(0);
-      int j = gl;
-      for (; j + g < q; j += 2 * g) {
-        s0 += Wr[j] * x[U[j]];
-        s1 += Wr[j + g] * x[U[j + g]];
-      }
-      for (; j < q; j += g) s0 += Wr[j] * x[U[j]];
-      acc -= s0 + s1;
+  const int ii = min(i, p - 1);
+  const T* Wr = LuArr<T>::W(F) + t.offVW + (long)ii * q;
+  const int* U = F.U + t.offU;
+  const int cell = F.var_cell[base + ii];
+  int uu[K];
+  if (q > 0) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) uu[u] = U[min(gl + u * g, q - 1)];
+  }
+  T acc = lane_dot<K, T>(LuArr<T>::M(F) + t.offM + (long)ii * p, LuArr<T>::z(F) + base, valid ? ii : p, p, gl, g);
+  T s0 = T(0), s1 = T(0);
+  const int qv = valid ? q : 0;
+  for (int jb = gl; jb < qv; jb += K * g) {
+    if (jb != gl) {
+#pragma unroll
+      for (int u = 0; u < K; ++u) uu[u] = U[min(jb + u * g, q - 1)];
+    }
+    T w[K], vx[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      w[u] = Wr[min(jb + u * g, q - 1)];
+      vx[u] = x[uu[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < K; u += 2) {
+      if (jb + u * g < q) s0 += w[u] * vx[u];
+      if (jb + (u + 1) * g < q) s1 += w[u + 1] * vx[u + 1];
     }
   }
+  acc -= s0 + s1;
   for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (valid && gl == 0) {
     x[base + i] = acc;
-    out[F.var_cell[base + i]] = TO(acc);
+    out[cell] = TO(acc);
   }
 }
 
@@ -557,24 +602,24 @@ __device__ __forceinline__ void bwd_task_mr(const LuDev& F, const LuTask& t, int
 }
 
 // One height of the tree per launch: one task per wavefront.
-template <class T>
+template <int K, class T>
 __global__ void __launch_bounds__(256) k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb) {
   const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   if (ti >= ntasks) return;
   const LuTask t = tasks[ti];
   if (nb == 1)
-    fwd_task<T>(F, t, threadIdx.x % kWave);
+    fwd_task<K, T>(F, t, threadIdx.x % kWave);
   else
     fwd_task_mr<T>(F, t, threadIdx.x % kWave, nb);
 }
-template <class T, class TO>
+template <int K, class T, class TO>
 __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb,
                                                      TO* __restrict__ out, long long ostride) {
   const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   if (ti >= ntasks) return;
   const LuTask t = tasks[ti];
   if (nb == 1)
-    bwd_task<T, TO>(F, t, threadIdx.x % kWave, out);
+    bwd_task<K, T, TO>(F, t, threadIdx.x % kWave, out);
   else
     bwd_task_mr<T, TO>(F, t, threadIdx.x % kWave, nb, out, ostride);
 }
@@ -587,7 +632,7 @@ __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __re
 // atomics read by later launches); nothing waits on another workgroup.
 constexpr int kSubWaves = 8;  // wavefronts per subtree workgroup
 
-template <class T>
+template <int K, class T>
 __global__ void __launch_bounds__(512) k_lu_forward_sub(LuDev F, const LuTask* __restrict__ tasks,
                                                         const int2* __restrict__ lev, const int* __restrict__ lptr,
                                                         int nb) {
@@ -598,14 +643,14 @@ __global__ void __launch_bounds__(512) k_lu_forward_sub(LuDev F, const LuTask* _
     for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
       const LuTask t = tasks[ti];
       if (nb == 1)
-        fwd_task<T>(F, t, lane);
+        fwd_task<K, T>(F, t, lane);
       else
         fwd_task_mr<T>(F, t, lane, nb);
     }
     __syncthreads();  // this height's stores and atomics visible to the workgroup
   }
 }
-template <class T, class TO>
+template <int K, class T, class TO>
 __global__ void __launch_bounds__(512) k_lu_backward_sub(LuDev F, const LuTask* __restrict__ tasks,
                                                          const int2* __restrict__ lev, const int* __restrict__ lptr,
                                                          int nb, TO* __restrict__ out, long long ostride) {
@@ -616,7 +661,7 @@ __global__ void __launch_bounds__(512) k_lu_backward_sub(LuDev F, const LuTask* 
     for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
       const LuTask t = tasks[ti];
       if (nb == 1)
-        bwd_task<T, TO>(F, t, lane, out);
+        bwd_task<K, T, TO>(F, t, lane, out);
       else
         bwd_task_mr<T, TO>(F, t, lane, nb, out, ostride);
     }
@@ -898,28 +943,57 @@ inline dim3 wave_grid(int ntasks) { return dim3(blocks((long long)ntasks * kWave
 template <class T>
 void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st) {
   const int n = nb == 1 ? S.nF : S.nFm;
-  if (n > 0)
-    hipLaunchKernelGGL(k_lu_forward<T>, wave_grid(n), dim3(256), 0, st, F, nb == 1 ? S.ftask : S.ftask_m, n, nb);
+  if (n == 0) return;
+  const LuTask* tk = nb == 1 ? S.ftask : S.ftask_m;
+  const int kc = nb == 1 ? S.kc : 4;
+  if (kc <= 4)
+    hipLaunchKernelGGL((k_lu_forward<4, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
+  else if (kc <= 8)
+    hipLaunchKernelGGL((k_lu_forward<8, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
+  else
+    hipLaunchKernelGGL((k_lu_forward<16, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
 }
 template <class T, class TO>
 void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st) {
   const int n = nb == 1 ? S.nB : S.nBm;
-  if (n > 0)
-    hipLaunchKernelGGL((k_lu_backward<T, TO>), wave_grid(n), dim3(256), 0, st, F, nb == 1 ? S.btask : S.btask_m, n,
-                       nb, out, out_stride);
+  if (n == 0) return;
+  const LuTask* tk = nb == 1 ? S.btask : S.btask_m;
+  const int kc = nb == 1 ? S.kc : 4;
+  if (kc <= 4)
+    hipLaunchKernelGGL((k_lu_backward<4, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
+  else if (kc <= 8)
+    hipLaunchKernelGGL((k_lu_backward<8, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
+  else
+    hipLaunchKernelGGL((k_lu_backward<16, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
 }
 template <class T>
 void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t st) {
   if (S.nsub == 0) return;
   const LuSubList& L = nb == 1 ? S.single : S.multi;
-  hipLaunchKernelGGL(k_lu_forward_sub<T>, dim3(S.nsub), dim3(64 * kSubWaves), 0, st, F, L.ftask, L.flev, L.fptr, nb);
+  const int kc = nb == 1 ? S.kc : 4;
+  const dim3 grid(S.nsub), block(64 * kSubWaves);
+  if (kc <= 4)
+    hipLaunchKernelGGL((k_lu_forward_sub<4, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
+  else if (kc <= 8)
+    hipLaunchKernelGGL((k_lu_forward_sub<8, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
+  else
+    hipLaunchKernelGGL((k_lu_forward_sub<16, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
 }
 template <class T, class TO>
 void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long out_stride, int nb, hipStream_t st) {
   if (S.nsub == 0) return;
   const LuSubList& L = nb == 1 ? S.single : S.multi;
-  hipLaunchKernelGGL((k_lu_backward_sub<T, TO>), dim3(S.nsub), dim3(64 * kSubWaves), 0, st, F, L.btask, L.blev, L.bptr,
-                     nb, out, out_stride);
+  const int kc = nb == 1 ? S.kc : 4;
+  const dim3 grid(S.nsub), block(64 * kSubWaves);
+  if (kc <= 4)
+    hipLaunchKernelGGL((k_lu_backward_sub<4, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
+                       out_stride);
+  else if (kc <= 8)
+    hipLaunchKernelGGL((k_lu_backward_sub<8, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
+                       out_stride);
+  else
+    hipLaunchKernelGGL((k_lu_backward_sub<16, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
+                       out_stride);
 }
 template <class T>
 void launch_zero(T* p, long long count, hipStream_t st) {

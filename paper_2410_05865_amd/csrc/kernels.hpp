@@ -68,8 +68,12 @@ struct LuTask {
   int row0, lg, pad;      // first row of this task, log2 lanes per row
 };
 constexpr int kMrRows = 4;
+// Single-RHS tasks load a row's entries kc per lane at a time (kc in {4, 8,
+// 16}, all loads of a round in flight together), so a task whose rows hold at
+// most kc entries per lane waits on one memory round trip.
 struct LuTasks {
   int nF, nB;             // single-RHS forward / backward tasks
+  int kc = 8;             // entries per lane per load round
   const LuTask* ftask;
   const LuTask* btask;
   int nFm, nBm;           // multi-RHS forward / backward tasks
@@ -91,6 +95,7 @@ struct LuSubList {
 struct LuSub {
   int nsub = 0;           // subtrees (0: no subtree launch)
   int hcut = 0;           // heights below hcut belong to the subtrees
+  int kc = 8;             // entries per lane per load round (single RHS)
   LuSubList single{}, multi{};
 };
 
