@@ -363,6 +363,11 @@ def main():
         "final_rel_residual": info["rel_residual"],
         "dof_per_s": N * cycles / sec,
         "setup_s": t_setup,
+        "lu_schedule": [
+            {"level": m, "n": li["n"], "entries_per_lane": li["lu_entries_per_lane"],
+             "subtrees": li["lu_subtrees"], "subtree_cut": li["lu_subtree_cut"], "waves_cap": li["lu_waves_cap"],
+             "trial_ms": [round(v, 4) for v in li["lu_tune_ms"]]}
+            for m, li in ((m, P.level_info(m)) for m in range(P.num_levels))],
         "mixed": out_mixed,
         "krylov": out_krylov,
         "batched": out_batch,

@@ -120,6 +120,11 @@ typedef struct cc_level_info {
   int lu_subtree_cut;     /* device sweeps: heights below this run as one launch of subtrees */
   int lu_subtrees;        /* number of those subtrees (0: one launch per height throughout) */
   int lu_entries_per_lane;/* device sweeps: factor entries per lane of a row (chosen at build) */
+  double lu_tune_ms[10];  /* the build-time trials: ms of one FP64 LU solve with 2^(k+1) entries
+                             per lane at [2k] (one launch per height) and [2k+1] (subtree launch
+                             for the low heights); 0 where not tried; the fastest over the
+                             wavefront caps */
+  int lu_waves_cap;       /* device sweeps: wavefronts per height launch at most (chosen at build) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */

@@ -64,7 +64,8 @@ class CcLevelInfo(C.Structure):
     _fields_ = [("n", C.c_int), ("n_unknowns", C.c_longlong), ("n_phi2", C.c_longlong), ("n_cut", C.c_longlong),
                 ("n_merged", C.c_longlong), ("lu_vars", C.c_longlong), ("lu_entries", C.c_longlong),
                 ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double),
-                ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int)]
+                ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int),
+                ("lu_tune_ms", C.c_double * 10), ("lu_waves_cap", C.c_int)]
 
 
 class CutCellError(RuntimeError):
@@ -254,7 +255,11 @@ class Problem:
     def level_info(self, level: int) -> dict:
         info = CcLevelInfo()
         _check(load().cc_get_level_info(self._h, level, C.byref(info)))
-        return {f: getattr(info, f) for f, _ in CcLevelInfo._fields_}
+        out = {}
+        for f, _ in CcLevelInfo._fields_:
+            v = getattr(info, f)
+            out[f] = list(v) if isinstance(v, C.Array) else v
+        return out
 
     def n(self, level: int = 0) -> int:
         return self.level_info(level)["n"]

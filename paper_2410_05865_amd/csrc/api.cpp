@@ -107,6 +107,8 @@ struct DevLU {
   bool sub_on = false;         // sweeps use the subtrees (chosen by timing at build)
   double epl = 8.0;            // factor entries per lane of the task lists (chosen by timing)
   int height = 0;
+  float tune_ms[10] = {};      // build-time trials: ms per solve, [2k + subtree on] for 2^(k+1) entries
+  int wcap = 1 << 30;          // single RHS: wavefronts per height launch at most (chosen by timing)
 };
 
 // One LU solve with a level's factorization: forward then backward sweeps,
@@ -439,8 +441,9 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     SB.nsub = (int)roots.size();
   }
   // entries per lane loaded per round: rows hold between epl and 2 epl entries
-  // per lane (fewer when short, more only at 64 lanes per row)
-  const int kc = epl <= 2.0 ? 4 : (epl <= 4.0 ? 8 : 16);
+  // per lane (fewer when short, more only at 64 lanes per row); at most 8 to
+  // bound the registers of the two pipeline stages
+  const int kc = epl <= 2.0 ? 4 : 8;
   SB.kc = kc;
   D.tasks.assign(F.max_height + 1, LuTasks{});
   for (int h = 0; h <= F.max_height; ++h) {
@@ -568,9 +571,10 @@ void upload(cc_problem* P) {
   W.s0 = P->s0;
   W.norm = P->d_norm;
   // Sweep schedule per factorization (the autotuner): for 2 to 32 factor
-  // entries per lane, each with and without the subtree launch, time one LU
-  // solve on this device (the work vectors' contents do not matter) and keep
-  // the fastest; the task lists of the other candidates are freed.
+  // entries per lane, each with and without the subtree launch and with at
+  // most 2048, 4096, 8192 or any number of wavefronts per height launch, time
+  // one LU solve on this device (the work vectors' contents do not matter) and
+  // keep the fastest; the task lists of the other candidates are freed.
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
@@ -583,21 +587,30 @@ void upload(cc_problem* P) {
     for (double epl : {2.0, 4.0, 8.0, 16.0, 32.0}) {
       DevBuf cand;
       make_schedule(P->lu[m], L, epl, cand);
-      for (int on = 0; on < (L.sub.nsub > 0 ? 2 : 1); ++on) {
-        L.sub_on = on != 0;
-        lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
-        HIPCHK(hipEventRecord(ev0, P->stream));
-        for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
-        HIPCHK(hipEventRecord(ev1, P->stream));
-        HIPCHK(hipEventSynchronize(ev1));
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, ev0, ev1));
-        if (t < best) {
-          best = t;
-          keep = L;
-          keep.epl = epl;
+      for (int on = 0; on < (L.sub.nsub > 0 ? 2 : 1); ++on)
+        for (int wcap : {1 << 30, 8192, 4096, 2048}) {
+          L.sub_on = on != 0;
+          for (LuTasks& T : L.tasks) T.wcap = wcap;
+          lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+          HIPCHK(hipEventRecord(ev0, P->stream));
+          for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
+          HIPCHK(hipEventRecord(ev1, P->stream));
+          HIPCHK(hipEventSynchronize(ev1));
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, ev0, ev1));
+          {
+            int k = 0;
+            while (k < 4 && (2 << k) < (int)epl) ++k;
+            float& slot = L.tune_ms[2 * k + on];
+            slot = slot > 0.f ? std::min(slot, t / 5.0f) : t / 5.0f;
+          }
+          if (t < best) {
+            best = t;
+            keep = L;
+            keep.epl = epl;
+            keep.wcap = wcap;
+          }
         }
-      }
       if (keep.epl == epl) {
         keep_buf.release();
         keep_buf = std::move(cand);
@@ -605,6 +618,7 @@ void upload(cc_problem* P) {
         cand.release();
       }
     }
+    std::copy(L.tune_ms, L.tune_ms + 10, keep.tune_ms);
     L = keep;
     for (void* q : keep_buf.ptrs) B.ptrs.push_back(q);
     keep_buf.ptrs.clear();
@@ -1145,6 +1159,8 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_subtree_cut = on ? p->dev[level].lu.sub.hcut : 0;
     info->lu_subtrees = on ? p->dev[level].lu.sub.nsub : 0;
     info->lu_entries_per_lane = dev ? (int)p->dev[level].lu.epl : 0;
+    info->lu_waves_cap = dev ? p->dev[level].lu.wcap : 0;
+    for (int k = 0; k < 10; ++k) info->lu_tune_ms[k] = dev ? p->dev[level].lu.tune_ms[k] : 0.0;
   });
 }
 

@@ -386,80 +386,196 @@ __device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restri
 }
 
 // Single right-hand side: a task takes 64/g rows of one node, g lanes per row.
+// A wavefront runs a strided sequence of tasks in pairs: the descriptors and
+// first load rounds of both tasks are issued before any of their products are
+// formed, so their memory latencies overlap.
+// Indices are clamped in bounds (U and Uf end with one padding entry, every
+// node has p >= 1) and products past a row's end are dropped.
+struct TaskLanes {
+  int g, gl, i;
+  __device__ TaskLanes(const LuTask& t, int lane) {
+    g = 1 << t.lg;
+    gl = lane & (g - 1);
+    i = t.row0 + (lane >> t.lg);
+  }
+};
+
 // Forward: z_F = L11^-1 y_F on the node's rows, and y_U -= (L21 L11^-1) y_F
-// accumulated atomically into the later equations.  The row's destination
-// (y_F[i], or the later equation's position) is loaded with the first round,
-// unconditionally at a clamped index (U and Uf end with one padding entry).
+// accumulated atomically into the later equations.
 template <int K, class T>
-__device__ __forceinline__ void fwd_task(const LuDev& F, const LuTask& t, int lane) {
-  T* y = LuArr<T>::y(F);
-  const int lg = t.lg, g = 1 << lg;
-  const int sub = lane >> lg, gl = lane & (g - 1);
-  const int p = t.p, q = t.q, base = t.base;
-  const int i = t.row0 + sub;
-  const bool valid = i < p + q;
-  const int ii = min(i, p + q - 1);
-  const T* yF = y + base;
-  const T yi = yF[min(ii, p - 1)];
-  const int dst = F.Uf[t.offU + max(ii - p, 0)];
-  const T* row = ii < p ? LuArr<T>::M(F) + t.offM + (long)ii * p : LuArr<T>::V(F) + t.offVW + (long)(ii - p) * p;
-  const int jend = !valid ? 0 : (ii < p ? ii : p);
-  T acc = lane_dot<K, T>(row, yF, 0, jend, gl, g);
-  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (valid && gl == 0) {
-    if (i < p)
-      LuArr<T>::z(F)[base + i] = acc + yi;
+struct FwdRound {
+  T va[K], vb[K];
+  T yi;
+  int dst;
+};
+template <class T>
+__device__ __forceinline__ const T* fwd_row(const LuDev& F, const LuTask& t, int ii) {
+  return ii < t.p ? LuArr<T>::M(F) + t.offM + (long)ii * t.p : LuArr<T>::V(F) + t.offVW + (long)(ii - t.p) * t.p;
+}
+template <int K, class T>
+__device__ __forceinline__ void fwd_issue(const LuDev& F, const LuTask& t, int lane, FwdRound<K, T>& r) {
+  const TaskLanes L(t, lane);
+  const int p = t.p, q = t.q;
+  const int ii = min(L.i, p + q - 1);
+  const T* yF = LuArr<T>::y(F) + t.base;
+  r.yi = yF[min(ii, p - 1)];
+  r.dst = F.Uf[t.offU + max(ii - p, 0)];
+  const T* row = fwd_row<T>(F, t, ii);
+  const int jend = L.i < p + q ? (ii < p ? ii : p) : 0;
+  const int jmax = max(jend - 1, 0);
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int j = min(L.gl + u * L.g, jmax);
+    r.va[u] = row[j];
+    r.vb[u] = yF[j];
+  }
+}
+template <int K, class T>
+__device__ __forceinline__ void fwd_finish(const LuDev& F, const LuTask& t, int lane, const FwdRound<K, T>& r) {
+  const TaskLanes L(t, lane);
+  const int p = t.p, q = t.q;
+  const bool valid = L.i < p + q;
+  const int ii = min(L.i, p + q - 1);
+  const int jend = valid ? (ii < p ? ii : p) : 0;
+  T s0 = T(0), s1 = T(0);
+#pragma unroll
+  for (int u = 0; u < K; u += 2) {
+    if (L.gl + u * L.g < jend) s0 += r.va[u] * r.vb[u];
+    if (L.gl + (u + 1) * L.g < jend) s1 += r.va[u + 1] * r.vb[u + 1];
+  }
+  T acc = s0 + s1;
+  if (L.gl + K * L.g < jend)
+    acc += lane_dot<K, T>(fwd_row<T>(F, t, ii), LuArr<T>::y(F) + t.base, K * L.g, jend, L.gl, L.g);
+  for (int o = L.g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && L.gl == 0) {
+    if (L.i < p)
+      LuArr<T>::z(F)[t.base + L.i] = acc + r.yi;
     else
-      atomicAdd(&y[dst], -acc);
+      atomicAdd(&LuArr<T>::y(F)[r.dst], -acc);
+  }
+}
+// tasks t0, t0 + stride, ... below t1, two at a time: both descriptors, then
+// both tasks' first load rounds, are issued before the first product (a lone
+// last task is issued alone)
+template <int K, class T>
+__device__ __forceinline__ void fwd_tasks(const LuDev& F, const LuTask* __restrict__ tasks, int t0, int t1,
+                                          int stride, int lane) {
+  for (int ti = t0; ti < t1; ti += 2 * stride) {
+    const bool two = ti + stride < t1;
+    const LuTask ta = tasks[ti];
+    LuTask tb = ta;
+    if (two) tb = tasks[ti + stride];
+    FwdRound<K, T> ra, rb;
+    fwd_issue<K, T>(F, ta, lane, ra);
+    if (two) fwd_issue<K, T>(F, tb, lane, rb);
+    __builtin_amdgcn_sched_barrier(0);  // every load of the pair ahead of the products
+    fwd_finish<K, T>(F, ta, lane, ra);
+    if (two) fwd_finish<K, T>(F, tb, lane, rb);
   }
 }
 
 // Backward: x_F = U11^-1 z_F - (U11^-1 U12) x_U, scattered to the grid array
-// `out` through var_cell.  Round one loads the U11 part with the first K
-// indices of U per lane, round two their coefficients and the gathered x_U, so
-// a short row waits on two memory round trips.
+// `out` through var_cell.  The issue stage loads the first K indices of U per
+// lane with the first round of the U11 part; the finish stage loads their
+// coefficients with the gathered x_U.
+template <int K, class T>
+struct BwdRound {
+  T va[K], vb[K];
+  int uu[K];
+  int cell;
+};
+template <int K, class T>
+__device__ __forceinline__ void bwd_issue(const LuDev& F, const LuTask& t, int lane, BwdRound<K, T>& r) {
+  const TaskLanes L(t, lane);
+  const int p = t.p, q = t.q;
+  const int ii = min(L.i, p - 1);
+  r.cell = F.var_cell[t.base + ii];
+  const int* U = F.U + t.offU;
+  const int qmax = max(q - 1, 0);
+#pragma unroll
+  for (int u = 0; u < K; ++u) r.uu[u] = U[min(L.gl + u * L.g, qmax)];
+  const T* Mr = LuArr<T>::M(F) + t.offM + (long)ii * p;
+  const T* z = LuArr<T>::z(F) + t.base;
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int j = min(ii + L.gl + u * L.g, p - 1);
+    r.va[u] = Mr[j];
+    r.vb[u] = z[j];
+  }
+}
 template <int K, class T, class TO>
-__device__ __forceinline__ void bwd_task(const LuDev& F, const LuTask& t, int lane, TO* __restrict__ out) {
+__device__ __forceinline__ void bwd_finish(const LuDev& F, const LuTask& t, int lane, const BwdRound<K, T>& r,
+                                           TO* __restrict__ out) {
+  const TaskLanes L(t, lane);
+  const int p = t.p, q = t.q;
+  const bool valid = L.i < p;
+  const int ii = min(L.i, p - 1);
+  const int jlo = valid ? ii : p;
   T* x = LuArr<T>::x(F);
-  const int lg = t.lg, g = 1 << lg;
-  const int sub = lane >> lg, gl = lane & (g - 1);
-  const int p = t.p, q = t.q, base = t.base;
-  const int i = t.row0 + sub;
-  const bool valid = i < p;
-  const int ii = min(i, p - 1);
   const T* Wr = LuArr<T>::W(F) + t.offVW + (long)ii * q;
   const int* U = F.U + t.offU;
-  const int cell = F.var_cell[base + ii];
-  int uu[K];
-  if (q > 0) {
+  // coefficients and gathered values of the first round of U12
+  T w[K], vx[K];
+  const int qmax = max(q - 1, 0);
 #pragma unroll
-    for (int u = 0; u < K; ++u) uu[u] = U[min(gl + u * g, q - 1)];
+  for (int u = 0; u < K; ++u) {
+    w[u] = Wr[min(L.gl + u * L.g, qmax)];
+    vx[u] = x[r.uu[u]];
   }
-  T acc = lane_dot<K, T>(LuArr<T>::M(F) + t.offM + (long)ii * p, LuArr<T>::z(F) + base, valid ? ii : p, p, gl, g);
   T s0 = T(0), s1 = T(0);
-  const int qv = valid ? q : 0;
-  for (int jb = gl; jb < qv; jb += K * g) {
-    if (jb != gl) {
 #pragma unroll
-      for (int u = 0; u < K; ++u) uu[u] = U[min(jb + u * g, q - 1)];
-    }
-    T w[K], vx[K];
+  for (int u = 0; u < K; u += 2) {
+    if (jlo + L.gl + u * L.g < p) s0 += r.va[u] * r.vb[u];
+    if (jlo + L.gl + (u + 1) * L.g < p) s1 += r.va[u + 1] * r.vb[u + 1];
+  }
+  T acc = s0 + s1;
+  if (jlo + L.gl + K * L.g < p)
+    acc += lane_dot<K, T>(LuArr<T>::M(F) + t.offM + (long)ii * p, LuArr<T>::z(F) + t.base, jlo + K * L.g, p, L.gl,
+                          L.g);
+  const int qv = valid ? q : 0;
+  s0 = T(0);
+  s1 = T(0);
+#pragma unroll
+  for (int u = 0; u < K; u += 2) {
+    if (L.gl + u * L.g < qv) s0 += w[u] * vx[u];
+    if (L.gl + (u + 1) * L.g < qv) s1 += w[u + 1] * vx[u + 1];
+  }
+  for (int jb = L.gl + K * L.g; jb < qv; jb += K * L.g) {
+    int uu[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) uu[u] = U[min(jb + u * L.g, q - 1)];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-      w[u] = Wr[min(jb + u * g, q - 1)];
+      w[u] = Wr[min(jb + u * L.g, q - 1)];
       vx[u] = x[uu[u]];
     }
 #pragma unroll
     for (int u = 0; u < K; u += 2) {
-      if (jb + u * g < q) s0 += w[u] * vx[u];
-      if (jb + (u + 1) * g < q) s1 += w[u + 1] * vx[u + 1];
+      if (jb + u * L.g < q) s0 += w[u] * vx[u];
+      if (jb + (u + 1) * L.g < q) s1 += w[u + 1] * vx[u + 1];
     }
   }
   acc -= s0 + s1;
-  for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (valid && gl == 0) {
-    x[base + i] = acc;
-    out[cell] = TO(acc);
+  for (int o = L.g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (valid && L.gl == 0) {
+    x[t.base + L.i] = acc;
+    out[r.cell] = TO(acc);
+  }
+}
+template <int K, class T, class TO>
+__device__ __forceinline__ void bwd_tasks(const LuDev& F, const LuTask* __restrict__ tasks, int t0, int t1,
+                                          int stride, int lane, TO* __restrict__ out) {
+  for (int ti = t0; ti < t1; ti += 2 * stride) {
+    const bool two = ti + stride < t1;
+    const LuTask ta = tasks[ti];
+    LuTask tb = ta;
+    if (two) tb = tasks[ti + stride];
+    BwdRound<K, T> ra, rb;
+    bwd_issue<K, T>(F, ta, lane, ra);
+    if (two) bwd_issue<K, T>(F, tb, lane, rb);
+    __builtin_amdgcn_sched_barrier(0);  // every load of the pair ahead of the products
+    bwd_finish<K, T, TO>(F, ta, lane, ra, out);
+    if (two) bwd_finish<K, T, TO>(F, tb, lane, rb, out);
   }
 }
 
@@ -601,27 +717,31 @@ __device__ __forceinline__ void bwd_task_mr(const LuDev& F, const LuTask& t, int
   }
 }
 
-// One height of the tree per launch: one task per wavefront.
+// One height of the tree per launch.  Single right-hand side: each wavefront
+// takes the tasks w, w + W, ... (W wavefronts in the grid) through the
+// pipeline; several right-hand sides: one task per wavefront.
 template <int K, class T>
 __global__ void __launch_bounds__(256) k_lu_forward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb) {
-  const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  if (ti >= ntasks) return;
-  const LuTask t = tasks[ti];
-  if (nb == 1)
-    fwd_task<K, T>(F, t, threadIdx.x % kWave);
-  else
+  const int w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nw = gridDim.x * (blockDim.x / kWave);
+  if (nb == 1) {
+    fwd_tasks<K, T>(F, tasks, w, ntasks, nw, threadIdx.x % kWave);
+  } else if (w < ntasks) {
+    const LuTask t = tasks[w];
     fwd_task_mr<T>(F, t, threadIdx.x % kWave, nb);
+  }
 }
 template <int K, class T, class TO>
 __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __restrict__ tasks, int ntasks, int nb,
                                                      TO* __restrict__ out, long long ostride) {
-  const int ti = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  if (ti >= ntasks) return;
-  const LuTask t = tasks[ti];
-  if (nb == 1)
-    bwd_task<K, T, TO>(F, t, threadIdx.x % kWave, out);
-  else
+  const int w = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nw = gridDim.x * (blockDim.x / kWave);
+  if (nb == 1) {
+    bwd_tasks<K, T, TO>(F, tasks, w, ntasks, nw, threadIdx.x % kWave, out);
+  } else if (w < ntasks) {
+    const LuTask t = tasks[w];
     bwd_task_mr<T, TO>(F, t, threadIdx.x % kWave, nb, out, ostride);
+  }
 }
 
 // The lower heights of the tree in one launch: workgroup s takes subtree s
@@ -640,12 +760,13 @@ __global__ void __launch_bounds__(512) k_lu_forward_sub(LuDev F, const LuTask* _
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   for (int l = lptr[s]; l < lptr[s + 1]; ++l) {
     const int2 rg = lev[l];
-    for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
-      const LuTask t = tasks[ti];
-      if (nb == 1)
-        fwd_task<K, T>(F, t, lane);
-      else
+    if (nb == 1) {
+      fwd_tasks<K, T>(F, tasks, rg.x + wave, rg.y, kSubWaves, lane);
+    } else {
+      for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
+        const LuTask t = tasks[ti];
         fwd_task_mr<T>(F, t, lane, nb);
+      }
     }
     __syncthreads();  // this height's stores and atomics visible to the workgroup
   }
@@ -658,12 +779,13 @@ __global__ void __launch_bounds__(512) k_lu_backward_sub(LuDev F, const LuTask* 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
   for (int l = lptr[s]; l < lptr[s + 1]; ++l) {
     const int2 rg = lev[l];
-    for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
-      const LuTask t = tasks[ti];
-      if (nb == 1)
-        bwd_task<K, T, TO>(F, t, lane, out);
-      else
+    if (nb == 1) {
+      bwd_tasks<K, T, TO>(F, tasks, rg.x + wave, rg.y, kSubWaves, lane, out);
+    } else {
+      for (int ti = rg.x + wave; ti < rg.y; ti += kSubWaves) {
+        const LuTask t = tasks[ti];
         bwd_task_mr<T, TO>(F, t, lane, nb, out, ostride);
+      }
     }
     __syncthreads();  // this height's stores and atomics visible to the workgroup
   }
@@ -939,6 +1061,15 @@ void launch_gather(int n, const int* row_cell, const TS* src, long long src_stri
                      y);
 }
 inline dim3 wave_grid(int ntasks) { return dim3(blocks((long long)ntasks * kWave, 256)); }
+// single right-hand side: at most wcap wavefronts, each looping over tasks
+inline dim3 lu_grid(const LuTasks& S, int nb) {
+  const int n = nb == 1 ? S.nF : S.nFm;
+  return wave_grid(nb == 1 ? std::min(n, std::max(S.wcap, 4)) : n);
+}
+inline dim3 lu_grid_b(const LuTasks& S, int nb) {
+  const int n = nb == 1 ? S.nB : S.nBm;
+  return wave_grid(nb == 1 ? std::min(n, std::max(S.wcap, 4)) : n);
+}
 
 template <class T>
 void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st) {
@@ -947,11 +1078,9 @@ void launch_lu_forward(const LuDev& F, const LuTasks& S, int nb, hipStream_t st)
   const LuTask* tk = nb == 1 ? S.ftask : S.ftask_m;
   const int kc = nb == 1 ? S.kc : 4;
   if (kc <= 4)
-    hipLaunchKernelGGL((k_lu_forward<4, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
-  else if (kc <= 8)
-    hipLaunchKernelGGL((k_lu_forward<8, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
+    hipLaunchKernelGGL((k_lu_forward<4, T>), lu_grid(S, nb), dim3(256), 0, st, F, tk, n, nb);
   else
-    hipLaunchKernelGGL((k_lu_forward<16, T>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb);
+    hipLaunchKernelGGL((k_lu_forward<8, T>), lu_grid(S, nb), dim3(256), 0, st, F, tk, n, nb);
 }
 template <class T, class TO>
 void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out_stride, int nb, hipStream_t st) {
@@ -960,11 +1089,11 @@ void launch_lu_backward(const LuDev& F, const LuTasks& S, TO* out, long long out
   const LuTask* tk = nb == 1 ? S.btask : S.btask_m;
   const int kc = nb == 1 ? S.kc : 4;
   if (kc <= 4)
-    hipLaunchKernelGGL((k_lu_backward<4, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
-  else if (kc <= 8)
-    hipLaunchKernelGGL((k_lu_backward<8, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
+    hipLaunchKernelGGL((k_lu_backward<4, T, TO>), lu_grid_b(S, nb), dim3(256), 0, st, F, tk, n, nb, out,
+                       out_stride);
   else
-    hipLaunchKernelGGL((k_lu_backward<16, T, TO>), wave_grid(n), dim3(256), 0, st, F, tk, n, nb, out, out_stride);
+    hipLaunchKernelGGL((k_lu_backward<8, T, TO>), lu_grid_b(S, nb), dim3(256), 0, st, F, tk, n, nb, out,
+                       out_stride);
 }
 template <class T>
 void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t st) {
@@ -974,10 +1103,8 @@ void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t s
   const dim3 grid(S.nsub), block(64 * kSubWaves);
   if (kc <= 4)
     hipLaunchKernelGGL((k_lu_forward_sub<4, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
-  else if (kc <= 8)
-    hipLaunchKernelGGL((k_lu_forward_sub<8, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
   else
-    hipLaunchKernelGGL((k_lu_forward_sub<16, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
+    hipLaunchKernelGGL((k_lu_forward_sub<8, T>), grid, block, 0, st, F, L.ftask, L.flev, L.fptr, nb);
 }
 template <class T, class TO>
 void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long out_stride, int nb, hipStream_t st) {
@@ -988,11 +1115,8 @@ void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long o
   if (kc <= 4)
     hipLaunchKernelGGL((k_lu_backward_sub<4, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
                        out_stride);
-  else if (kc <= 8)
-    hipLaunchKernelGGL((k_lu_backward_sub<8, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
-                       out_stride);
   else
-    hipLaunchKernelGGL((k_lu_backward_sub<16, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
+    hipLaunchKernelGGL((k_lu_backward_sub<8, T, TO>), grid, block, 0, st, F, L.btask, L.blev, L.bptr, nb, out,
                        out_stride);
 }
 template <class T>

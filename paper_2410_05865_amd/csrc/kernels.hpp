@@ -68,12 +68,13 @@ struct LuTask {
   int row0, lg, pad;      // first row of this task, log2 lanes per row
 };
 constexpr int kMrRows = 4;
-// Single-RHS tasks load a row's entries kc per lane at a time (kc in {4, 8,
-// 16}, all loads of a round in flight together), so a task whose rows hold at
-// most kc entries per lane waits on one memory round trip.
+// Single-RHS tasks load a row's entries kc per lane at a time (kc 4 or 8, all
+// loads of a round in flight together), so a task whose rows hold at most kc
+// entries per lane waits on one memory round trip.
 struct LuTasks {
   int nF, nB;             // single-RHS forward / backward tasks
   int kc = 8;             // entries per lane per load round
+  int wcap = 1 << 30;     // single RHS: at most this many wavefronts per launch
   const LuTask* ftask;
   const LuTask* btask;
   int nFm, nBm;           // multi-RHS forward / backward tasks
