@@ -180,6 +180,17 @@ int cc_set_precision(cc_problem* p, int precision);
  * by the V-cycle (k in 1..64) for later solves; build-time value cc_params.krylov. */
 int cc_set_krylov(cc_problem* p, int krylov);
 
+/* Replace the build-time choice of the device sweep schedule of `level`'s
+ * factorization (the LU-correction of Sec. 5.3 on levels m < M, the bottom
+ * solve on level M): entries_per_lane in {2, 4, 8, 16, 32} sets the lanes per
+ * row of a task, subtree = 1 runs the low heights as one launch of subtrees
+ * (only where cc_level_info.lu_subtrees > 0), waves_cap caps the wavefronts of
+ * a height launch (0: no cap; else at least 4).  Waits for the problem's
+ * stream, rebuilds the task lists (device allocation) and drops captured
+ * iterations.  The solution does not depend on the schedule beyond rounding.
+ * Errors: CC_EINVAL for a bad level or value. */
+int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtree, int waves_cap);
+
 /* Several right-hand sides on one geometry (with krylov > 0 they are solved one
  * after the other): r_dev and phi_dev hold nrhs arrays of
  * n^3 at a stride of n^3 (batch-major).  Groups of up to CC_BATCH_MAX

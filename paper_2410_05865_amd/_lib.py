@@ -31,6 +31,7 @@ EXPORTED = [
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
+    "cc_set_lu_schedule",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -109,6 +110,7 @@ def load() -> C.CDLL:
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
+    lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
     lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
@@ -314,6 +316,10 @@ class Problem:
     def set_krylov(self, k: int):
         _check(load().cc_set_krylov(self._h, k))
         self.params.krylov = k
+
+    def set_lu_schedule(self, level: int, entries_per_lane: int, subtree: int = 0, waves_cap: int = 0):
+        """Override the build-time sweep schedule of one level's factorization."""
+        _check(load().cc_set_lu_schedule(self._h, level, entries_per_lane, subtree, waves_cap))
 
     def solve(self, r, phi) -> dict:
         self._order()

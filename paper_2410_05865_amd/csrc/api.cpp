@@ -127,6 +127,7 @@ struct DevLevel {
   StencilLevel st{};
   PlgRows plg{};
   DevLU lu;
+  DevBuf sched;  // device task lists of lu's current schedule
   double* s = nullptr;
   double* e = nullptr;
   double* et = nullptr;
@@ -620,8 +621,7 @@ void upload(cc_problem* P) {
     }
     std::copy(L.tune_ms, L.tune_ms + 10, keep.tune_ms);
     L = keep;
-    for (void* q : keep_buf.ptrs) B.ptrs.push_back(q);
-    keep_buf.ptrs.clear();
+    P->dev[m].sched = std::move(keep_buf);
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
@@ -1542,6 +1542,41 @@ int cc_set_krylov(cc_problem* p, int krylov) {
   });
 }
 
+int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtree, int waves_cap) {
+  return guard([&] {
+    if (!p) fail(CC_EINVAL, "null problem");
+    need_device(p);
+    if (level < 0 || level >= (int)p->dev.size()) fail(CC_EINVAL, "bad level");
+    if (entries_per_lane != 2 && entries_per_lane != 4 && entries_per_lane != 8 && entries_per_lane != 16 &&
+        entries_per_lane != 32)
+      fail(CC_EINVAL, "entries_per_lane must be 2, 4, 8, 16 or 32");
+    if (subtree != 0 && subtree != 1) fail(CC_EINVAL, "subtree must be 0 or 1");
+    if (waves_cap != 0 && waves_cap < 4) fail(CC_EINVAL, "waves_cap must be 0 or at least 4");
+    HIPCHK(hipSetDevice(p->device));
+    HIPCHK(hipStreamSynchronize(p->stream));  // no launch in flight reads the old task lists
+    DevLevel& D = p->dev[level];
+    DevBuf nb;
+    DevLU L = D.lu;
+    make_schedule(p->lu[level], L, (double)entries_per_lane, nb);
+    if (subtree && L.sub.nsub == 0) {
+      nb.release();
+      fail(CC_EINVAL, "this factorization has no subtree launch (cc_level_info.lu_subtrees is 0)");
+    }
+    L.sub_on = subtree != 0;
+    L.epl = entries_per_lane;
+    L.wcap = waves_cap == 0 ? (1 << 30) : waves_cap;
+    for (LuTasks& T : L.tasks) T.wcap = L.wcap;
+    D.sched.release();
+    D.sched = std::move(nb);
+    D.lu = L;
+    // captured iterations hold the old task lists
+    p->w64.drop_graph();
+    p->w32.drop_graph();
+    p->wb64.drop_graph();
+    p->wb32.drop_graph();
+  });
+}
+
 int cc_solve_batched(cc_problem* p, int nrhs, const double* r, double* phi, cc_solve_info* info) {
   int conv = 1;
   int rc = guard([&] {
@@ -1681,6 +1716,7 @@ void cc_destroy(cc_problem* p) {
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     p->w64.drop_graph();
+    for (DevLevel& d : p->dev) d.sched.release();
     p->kr.own.release();
     p->w32.release();
     p->wb64.release();
