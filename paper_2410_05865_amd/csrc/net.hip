@@ -114,11 +114,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd(int n, View in, int cin, const
 }
 
 // ---------------------------------------------------------------- weight gradient
-// dW[tap][co][ci] += sum over voxels of g[v][co] * in[v + off(tap)][ci].
+// part[split][tap][co][ci] = sum over the split's voxels of g[v][co] *
+// in[v + off(tap)][ci]; k_sum_parts adds the splits in a fixed order (no
+// atomics, so gradients and training are reproducible).
 // grid (27, splits); 256 threads; voxels of the split staged 64 at a time in LDS.
 constexpr int kWgChunk = 64;
 __global__ void __launch_bounds__(256) k_conv_wgrad(int n, long long nvox, View in, int cin, View g, int cout,
-                                                    float* __restrict__ dw, long long per_split) {
+                                                    float* __restrict__ part, long long per_split) {
   extern __shared__ uint16_t lds[];
   uint16_t* lg = lds;                        // [64][cout]
   uint16_t* li = lds + kWgChunk * cout;      // [64][cin]
@@ -178,20 +180,38 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(int n, long long nvox, View 
     const int tile = wave + 4 * t;
     if (tile >= ntile) break;
     const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
+    float* out = part + (long long)blockIdx.y * 27 * cout * cin;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      atomicAdd(&dw[((long long)tap * cout + m0 + 4 * kg + q) * cin + n0 + r], acc[t][q]);
+    for (int q = 0; q < 4; ++q) out[((long long)tap * cout + m0 + 4 * kg + q) * cin + n0 + r] = acc[t][q];
   }
 }
 
-__global__ void k_bias_grad(long long nvox, View g, int cout, float* __restrict__ db) {
+// per-block bias-gradient partials part[block][c] (cout divides 256); the
+// block's threads of one channel are added in thread order
+__global__ void __launch_bounds__(256) k_bias_grad(long long nvox, View g, int cout, float* __restrict__ part) {
+  __shared__ float sh[256];
   const int c = threadIdx.x % cout;
   const int lanes_per_c = blockDim.x / cout;
   float s = 0.f;
   for (long long v = (long long)blockIdx.x * lanes_per_c + threadIdx.x / cout; v < nvox;
        v += (long long)gridDim.x * lanes_per_c)
     s += bf2f(g.p[v * g.cs + g.co + c]);
-  atomicAdd(&db[c], s);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x < cout) {
+    float t = 0.f;
+    for (int k = 0; k < lanes_per_c; ++k) t += sh[threadIdx.x + k * cout];
+    part[(long long)blockIdx.x * cout + threadIdx.x] = t;
+  }
+}
+
+// out[e] = sum over s < nparts of part[s * count + e], s ascending
+__global__ void k_sum_parts(long long count, int nparts, const float* __restrict__ part, float* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  float t = 0.f;
+  for (int q = 0; q < nparts; ++q) t += part[(long long)q * count + e];
+  out[e] = t;
 }
 
 // flipped transpose: wf[26 - tap][ci][co] = wt[tap][co][ci]
@@ -282,15 +302,24 @@ __global__ void k_pack(long long nvox, const float* __restrict__ x, uint16_t* __
 // masked mean-square loss on channel 0: per-block partial sums of (y - t)^2 and
 // of the mask; gradient 2 (y - t) / count into g (bf16 [voxel][16], other
 // channels 0).  count comes from a first pass (k_count).
-__global__ void k_count(long long nvox, const uint8_t* __restrict__ mask, float* __restrict__ acc) {
-  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  float s = (v < nvox && mask[v]) ? 1.f : 0.f;
+// sum of a 256-thread block in a fixed order, valid in thread 0
+__device__ __forceinline__ float block_sum256(float s) {
+  __shared__ float w[4];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(acc, s);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  return (w[0] + w[1]) + (w[2] + w[3]);
 }
-__global__ void k_loss(long long nvox, const float* __restrict__ y, const float* __restrict__ t,
-                       const uint8_t* __restrict__ mask, const float* __restrict__ count, float* __restrict__ acc,
-                       uint16_t* __restrict__ g) {
+__global__ void __launch_bounds__(256) k_count(long long nvox, const uint8_t* __restrict__ mask,
+                                               float* __restrict__ part) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const float s = block_sum256((v < nvox && mask[v]) ? 1.f : 0.f);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ void __launch_bounds__(256) k_loss(long long nvox, const float* __restrict__ y,
+                                              const float* __restrict__ t, const uint8_t* __restrict__ mask,
+                                              const float* __restrict__ count, float* __restrict__ part,
+                                              uint16_t* __restrict__ g) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   float s = 0.f;
   if (v < nvox) {
@@ -302,8 +331,8 @@ __global__ void k_loss(long long nvox, const float* __restrict__ y, const float*
       for (int c = 1; c < 16; ++c) g[v * 16 + c] = 0;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(acc, s);
+  s = block_sum256(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 __global__ void k_adam(long long np, float* __restrict__ w, const float* __restrict__ gr, float* __restrict__ m,
                        float* __restrict__ v2, float lr, float b1, float b2, float eps, float c1, float c2,
@@ -381,6 +410,7 @@ struct cc_net {
            *GP2 = nullptr, *GP1 = nullptr;
   float* Y32 = nullptr;
   float* red = nullptr;       // [0] loss sum, [1] mask count
+  float* part = nullptr;      // per-split / per-block gradient and loss partials
 };
 
 namespace cc {
@@ -402,14 +432,21 @@ void launch_conv(cc_net* N, int n, int nb, View in, int cin, const uint16_t* wt,
 }
 
 // gradients of one conv layer: dW, db from (in, g); gin = conv(g, flipped W) if gin.p
+constexpr int kBiasBlocks = 256;
+inline int wgrad_splits(long long nvox) { return (int)std::min<long long>(256, std::max<long long>(1, nvox / 4096)); }
+
 void conv_backward(cc_net* N, const Layer& L, int n, int nb, View in, View g, View gin) {
   const long long nvox = (long long)nb * n * n * n;
-  const int splits = (int)std::min<long long>(256, std::max<long long>(1, nvox / 4096));
+  const int splits = wgrad_splits(nvox);
   const long long per = ((nvox + splits - 1) / splits + kWgChunk - 1) / kWgChunk * kWgChunk;
   const size_t lds = (size_t)kWgChunk * (L.cout + L.cin) * sizeof(uint16_t);
+  const long long nw = 27LL * L.cout * L.cin;
   hipLaunchKernelGGL(k_conv_wgrad, dim3(27, splits), dim3(256), lds, N->stream, n, nvox, in, L.cin, g, L.cout,
-                     N->g + L.offW, per);
-  hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, N->stream, nvox, g, L.cout, N->g + L.offB);
+                     N->part, per);
+  hipLaunchKernelGGL(k_sum_parts, dim3(nblk(nw)), dim3(256), 0, N->stream, nw, splits, N->part, N->g + L.offW);
+  hipLaunchKernelGGL(k_bias_grad, dim3(kBiasBlocks), dim3(256), 0, N->stream, nvox, g, L.cout, N->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, N->stream, (long long)L.cout, kBiasBlocks, N->part,
+                     N->g + L.offB);
   if (gin.p) {
     const long long nw = 27LL * L.cout * L.cin;
     hipLaunchKernelGGL(k_flip, dim3(nblk(nw)), dim3(256), 0, N->stream, N->wb + L.offW, L.cout, L.cin, N->wf);
@@ -442,6 +479,19 @@ void ensure_acts(cc_net* N, int n, int nb) {
   N->GP1 = A.alloc<uint16_t>(v2 * C);
   N->Y32 = A.alloc<float>(v1);
   N->red = A.alloc<float>(2);
+  // partials: the largest of splits x 27 cout cin over the layers (at their
+  // resolutions), the bias partials, and two per-block loss arrays
+  {
+    static const int level_of[6] = {0, 1, 2, 1, 0, 0};
+    long long need = 2LL * nblk(v1);
+    for (size_t li = 0; li < N->layers.size(); ++li) {
+      const Layer& L = N->layers[li];
+      const long long nv = v1 >> (3 * level_of[li]);
+      need = std::max(need, (long long)wgrad_splits(nv) * 27 * L.cout * L.cin);
+      need = std::max(need, (long long)kBiasBlocks * L.cout);
+    }
+    N->part = A.alloc<float>((size_t)need);
+  }
   N->an = n;
   N->anb = nb;
 }
@@ -623,10 +673,12 @@ int cc_net_loss_grad(cc_net* N, int n, int nb, const float* x, const float* targ
     const long long v1 = (long long)nb * n * n * n;
     hipStream_t st = N->stream;
     forward(N, n, nb, x);
-    hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, st, 2LL, N->red);
-    hipLaunchKernelGGL(k_count, dim3(nblk(v1)), dim3(256), 0, st, v1, mask, N->red + 1);
-    hipLaunchKernelGGL(k_loss, dim3(nblk(v1)), dim3(256), 0, st, v1, N->Y32, target, mask, N->red + 1, N->red,
+    const int nbk = nblk(v1);
+    hipLaunchKernelGGL(k_count, dim3(nbk), dim3(256), 0, st, v1, mask, N->part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, 1LL, nbk, N->part, N->red + 1);
+    hipLaunchKernelGGL(k_loss, dim3(nbk), dim3(256), 0, st, v1, N->Y32, target, mask, N->red + 1, N->part + nbk,
                        N->GY);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, 1LL, nbk, N->part + nbk, N->red);
     // gradient buffers that are accumulated into must start at zero
     const int C = N->C;
     hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(v1 * 3 * C)), dim3(256), 0, st, v1 * 3 * C, N->GCAT1);

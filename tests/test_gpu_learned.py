@@ -84,6 +84,25 @@ def test_training_reduces_loss():
     net.close()
 
 
+def test_training_is_reproducible():
+    """Gradients are reduced in a fixed order (no atomics), so two runs from the
+    same seed on the same data give bit-identical parameters and losses."""
+    L = _lib()
+    n, nb = 16, 4
+    _, _, _, xd, td, md = _inputs(n, nb, 8)
+    runs = []
+    for _ in range(2):
+        net = L.Net(16, seed=6)
+        losses = []
+        for _ in range(30):
+            losses.append(net.loss_grad(xd, td, md, n, nb))
+            net.adam_step(3e-3)
+        runs.append((np.array(losses), net.get_params()))
+        net.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+
+
 def test_learned_guess_in_solve():
     """Train on solver-generated pairs (64^3 problems, network on the 32^3
     level), then solve held-out problems from the network's guess.  The guessed
