@@ -235,40 +235,48 @@ __device__ __forceinline__ const float* plg_vals<float>(const PlgRows& P) {
 }
 
 // sum over the row's 35 entries of vals * x[cols] (entries whose bit is set in
-// `skip` left out).  All 35 indices are loaded first, then every coefficient and
-// gathered value, so a row costs two memory round trips.
+// `skip` left out), kPlgLanes adjacent lanes per row: lane `sub` takes entries
+// sub, sub + kPlgLanes, ...; its indices are loaded first, then its
+// coefficients and gathered values, and the lanes' sums are added by
+// shuffles (valid in every lane of the row's group).  Rows of one wavefront
+// are consecutive, so each entry slot t is read coalesced across them.
+constexpr int kPlgLanes = 4;
 template <class T, class TX>
 __device__ __forceinline__ T plg_dot(const PlgRows& P, const T* __restrict__ vals, const TX* __restrict__ x, int row,
-                                     uint64_t skip) {
+                                     int sub, uint64_t skip) {
+  constexpr int U = (35 + kPlgLanes - 1) / kPlgLanes;
   const long N2 = P.N2;
-  int col[35];
+  int col[U];
 #pragma unroll
-  for (int t = 0; t < 35; ++t) col[t] = P.cols[t * N2 + row];
-  T a0 = T(0), a1 = T(0);
+  for (int u = 0; u < U; ++u) col[u] = P.cols[min(sub + u * kPlgLanes, 34) * N2 + row];
+  T a = T(0);
 #pragma unroll
-  for (int t = 0; t < 35; ++t) {
-    const T v = vals[t * N2 + row] * T(x[col[t]]);
-    if (!((skip >> t) & 1ull)) {
-      if (t & 1)
-        a1 += v;
-      else
-        a0 += v;
-    }
+  for (int u = 0; u < U; ++u) {
+    const int t = sub + u * kPlgLanes;
+    const T v = vals[min(t, 34) * N2 + row] * T(x[col[u]]);
+    if (t < 35 && !((skip >> t) & 1ull)) a += v;
   }
-  return a0 + a1;
+#pragma unroll
+  for (int o = kPlgLanes / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
+  return a;
 }
 
+// one row per kPlgLanes threads; rows past N2 take the last row's loads (the
+// whole lane group alike) and store nothing
 __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const double* __restrict__ x,
                                double* __restrict__ s, int apply, long long stride) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= P.N2) return;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row0 = (int)(tid / kPlgLanes), sub = (int)(tid % kPlgLanes);
+  const int row = min(row0, P.N2 - 1);
   const long long o = (long long)blockIdx.y * stride;
   x += o;
   s += o;
   if (!apply) r += o;
-  const double a = plg_dot<double, double>(P, P.vals, x, row, 0ull);
-  int c = P.cell[row];
-  s[c] = apply ? a : r[c] - a;
+  const double a = plg_dot<double, double>(P, P.vals, x, row, sub, 0ull);
+  if (row0 < P.N2 && sub == 0) {
+    int c = P.cell[row];
+    s[c] = apply ? a : r[c] - a;
+  }
 }
 
 // b_2 = s_2 - L21 e_1 of every FV-PLG row, written in factorization order
@@ -276,13 +284,14 @@ __global__ void k_plg_residual(PlgRows P, const double* __restrict__ r, const do
 template <class T>
 __global__ void k_plg_b2(PlgRows P, const T* __restrict__ s, const T* __restrict__ e, T* __restrict__ y,
                          long long stride) {
-  int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= P.N2) return;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row0 = (int)(tid / kPlgLanes), sub = (int)(tid % kPlgLanes);
+  const int row = min(row0, P.N2 - 1);
   const int b = blockIdx.y, nb = gridDim.y;
   s += b * stride;
   e += b * stride;
-  const T a = plg_dot<T, T>(P, plg_vals<T>(P), e, row, P.phi2[row]);
-  y[(long long)P.nd[row] * nb + b] = s[P.cell[row]] - a;
+  const T a = plg_dot<T, T>(P, plg_vals<T>(P), e, row, sub, P.phi2[row]);
+  if (row0 < P.N2 && sub == 0) y[(long long)P.nd[row] * nb + b] = s[P.cell[row]] - a;
 }
 
 // coarse cell = 2^-3 sum over its 8 children of (s - L e) on phi_1 children
@@ -1038,7 +1047,8 @@ void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hip
 void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only, int nb,
                          long long stride, hipStream_t st) {
   if (P.N2 == 0) return;
-  hipLaunchKernelGGL(k_plg_residual, dim3(blocks(P.N2, 256), nb), dim3(256), 0, st, P, r, x, s, apply_only, stride);
+  hipLaunchKernelGGL(k_plg_residual, dim3(blocks((long long)P.N2 * kPlgLanes, 256), nb), dim3(256), 0, st, P, r, x,
+                     s, apply_only, stride);
 }
 template <class T>
 void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
@@ -1052,7 +1062,8 @@ void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int n
 template <class T>
 void launch_plg_b2(const PlgRows& P, const T* s, const T* e, T* y, long long stride, int nb, hipStream_t st) {
   if (P.N2 == 0) return;
-  hipLaunchKernelGGL(k_plg_b2<T>, dim3(blocks(P.N2, 256), nb), dim3(256), 0, st, P, s, e, y, stride);
+  hipLaunchKernelGGL(k_plg_b2<T>, dim3(blocks((long long)P.N2 * kPlgLanes, 256), nb), dim3(256), 0, st, P, s, e, y,
+                     stride);
 }
 template <class TS, class TY>
 void launch_gather(int n, const int* row_cell, const TS* src, long long src_stride, TY* y, int nb, hipStream_t st) {
