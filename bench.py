@@ -18,6 +18,7 @@ bounded sample (`cpu_baseline`).
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
+    python bench.py --summarize-counters PMC_DB         # per-kernel counter averages from rocprofv3 --pmc output
 """
 from __future__ import annotations
 
@@ -217,7 +218,12 @@ def main():
     ap.add_argument("--kernels-only", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DB")
+    ap.add_argument("--summarize-counters", metavar="PMC_DB")
     args = ap.parse_args()
+    if args.summarize_counters:
+        from paper_2410_05865_amd import profiling
+        print(profiling.counters_summary(args.summarize_counters))
+        return
     if args.summarize_pmc or args.summarize_trace:
         from paper_2410_05865_amd import profiling
         if args.summarize_pmc:

@@ -101,3 +101,26 @@ def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
         out.append(f"k_smo1<double> level-0 dispatches (grid {g[0]}x{g[1]}x{g[2]} work-items, {n}^3 cells): "
                    f"{len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
     return "\n".join(out)
+
+
+def counters_summary(db: str, kernels=("k_smo1<double>", "k_copy")) -> str:
+    """Per-dispatch averages of every counter of a rocprofv3 --pmc database for
+    the named kernels (largest grid of each: the level-0 launches)."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
+    acc = defaultdict(lambda: defaultdict(list))
+    for name, grid, cname, val in rows:
+        m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
+        key = (m.group(1) + (m.group(2) or "")) if m else name[:40]
+        acc[(key, int(grid))][cname].append(float(val))
+    out = []
+    for k in kernels:
+        grids = [g for (kk, g) in acc if kk == k]
+        if not grids:
+            continue
+        g = max(grids)
+        d = acc[(k, g)]
+        n = max(len(v) for v in d.values())
+        out.append(f"- {k} (grid {g} work-items, {n} dispatches): "
+                   + ", ".join(f"{c} {np.mean(v):.4g}" for c, v in sorted(d.items())))
+    return "\n".join(out)
