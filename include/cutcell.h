@@ -124,7 +124,8 @@ typedef struct cc_level_info {
                              per lane at [2k] (one launch per height) and [2k+1] (subtree launch
                              for the low heights); 0 where not tried; the fastest over the
                              wavefront caps */
-  int lu_waves_cap;       /* device sweeps: wavefronts per height launch at most (chosen at build) */
+  int lu_waves_cap;       /* device sweeps: wavefronts per height launch at most (chosen at build;
+                             0: no cap) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */

@@ -1159,7 +1159,7 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_subtree_cut = on ? p->dev[level].lu.sub.hcut : 0;
     info->lu_subtrees = on ? p->dev[level].lu.sub.nsub : 0;
     info->lu_entries_per_lane = dev ? (int)p->dev[level].lu.epl : 0;
-    info->lu_waves_cap = dev ? p->dev[level].lu.wcap : 0;
+    info->lu_waves_cap = dev && p->dev[level].lu.wcap < (1 << 30) ? p->dev[level].lu.wcap : 0;
     for (int k = 0; k < 10; ++k) info->lu_tune_ms[k] = dev ? p->dev[level].lu.tune_ms[k] : 0.0;
   });
 }

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <stdexcept>
 #include <vector>
 
 #include "kernels.hpp"
@@ -962,16 +963,35 @@ __global__ void k_dots_multi(long long n3, const double* __restrict__ w, const d
 }
 
 // out = mode 0: sum_i coef[i] V_i;  1: out + sum;  2: out - sum;  3: scale: coef[0] * V_0
-// and, if amax is not null, atomicMax of max |out| (bit pattern)
-__global__ void k_combo(long long n3, const double* __restrict__ V, long long stride, int nv,
-                        const double* __restrict__ coef, double* __restrict__ out, int mode,
-                        double* __restrict__ pmax, double* __restrict__ psq) {
+// and, if pmax / psq are given, per-block max |out| and sum out^2.  The nv <=
+// kComboMax coefficients are staged in LDS; the vectors are read 8 at a time
+// with all 8 loads (and out's) in flight.
+constexpr int kComboMax = 128;
+__global__ void __launch_bounds__(256) k_combo(long long n3, const double* __restrict__ V, long long stride,
+                                               int nv, const double* __restrict__ coef, double* __restrict__ out,
+                                               int mode, double* __restrict__ pmax, double* __restrict__ psq) {
+  __shared__ double cs[kComboMax];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) cs[i] = coef[i];
+  __syncthreads();
   double m = 0.0, q = 0.0;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n3;
        c += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < nv; ++i) s += coef[i] * V[i * stride + c];
-    double o = mode == 0 || mode == 3 ? s : (mode == 1 ? out[c] + s : out[c] - s);
+    const double prev = (mode == 1 || mode == 2) ? out[c] : 0.0;
+    double s0 = 0.0, s1 = 0.0;
+    int i = 0;
+    for (; i + 8 <= nv; i += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(i + u) * stride + c];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        s0 += cs[i + u] * v[u];
+        s1 += cs[i + u + 1] * v[u + 1];
+      }
+    }
+    for (; i < nv; ++i) s0 += cs[i] * V[i * stride + c];
+    const double sum = s0 + s1;
+    const double o = mode == 1 ? prev + sum : (mode == 2 ? prev - sum : sum);
     if (out) out[c] = o;
     m = fmax(m, fabs(o));
     q += o * o;
@@ -1180,6 +1200,7 @@ void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, dou
 }
 void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
                   unsigned long long* amax, double* sumsq, double* partial, hipStream_t st) {
+  if (nv < 1 || nv > kComboMax) throw std::invalid_argument("launch_combo: vector count out of range");
   const int g = (int)std::min<long long>(blocks(n3, 256), kRedBlocks);
   double* pmax = amax ? partial : nullptr;
   double* psq = sumsq ? partial + kRedBlocks : nullptr;
