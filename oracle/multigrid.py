@@ -7,12 +7,19 @@
   Restrict  coarse <- 2^-3 sum of the 8 children, phi_2 residuals set to 0;
   Prolong   piecewise constant, added to phi_1 unknowns only;
   VCycle / Multigrid as in the two algorithms of Sec. 5.3, with the
-  bottom level solved by a precomputed LU of the whole L^(M).
+  bottom level solved by a precomputed LU of the whole L^(M);
+  FMG       the full-multigrid algorithm of Sec. 5 (right-hand side
+            restricted level by level, coarsest level solved, then per level
+            upward: interpolate and apply a fixed number of V-cycles).
 
 Readings: each "smoother and LU-correction" application is one SMO-1
 followed by one SMO-2, on every level m < M; the stopping test uses the
 max norm; every level is re-discretised on the same domain; levels are
-n, n/2, ... down to the first size below 2 * n_min.
+n, n/2, ... down to the first size below 2 * n_min.  FMG readings: its
+Restrict acts on a right-hand side, so phi_2 children count (see
+fmg_restrict); its Prolong is trilinear (fmg_prolong), since the error bound
+of the FMG theorem needs an interpolation accurate to h^p, which the V-cycle's
+piecewise-constant prolongation (O(h)) is not.
 """
 from __future__ import annotations
 
@@ -131,6 +138,75 @@ class Hierarchy:
             e = op.smo1(e, s, prm.omega)
             e = op.smo2(e, s)
         return e
+
+    # ------------------------------------------------------------- FMG
+    def fmg_restrict(self, m: int, s_fine: np.ndarray) -> np.ndarray:
+        """Right-hand side transfer of the FMG algorithm (Sec. 5, algorithm
+        FMG): 2^-3 times the sum of s over the 8 children; children that carry
+        no unknown (exterior, or absorbed into a host) count 0, and phi_2
+        children count like phi_1 ones (the V-cycle's restriction drops phi_2
+        children because their residual is zero after SMO-2; a right-hand side
+        has no such zero)."""
+        fl, cl = self.levels[m], self.levels[m + 1]
+        g = np.zeros(fl.n ** 3)
+        g[fl.unknowns] = s_fine
+        nf, nc = fl.n, cl.n
+        C = 0.125 * g.reshape(nc, 2, nc, 2, nc, 2).sum(axis=(1, 3, 5))
+        return C.reshape(-1)[cl.unknowns]
+
+    def fmg_prolong(self, m: int, x_coarse: np.ndarray) -> np.ndarray:
+        """Interpolation of the FMG algorithm: trilinear in the coarse cell
+        centres, over the 8 coarse cells around each fine centre that lie in
+        the box and carry an unknown, with their weights renormalised (a fine
+        cell whose 8 coarse cells carry none gets 0).  Exact for linear
+        functions where all 8 cells are present, for constants wherever one
+        is."""
+        fl, cl = self.levels[m], self.levels[m + 1]
+        nf, nc = fl.n, cl.n
+        has = np.zeros(nc ** 3, dtype=bool)
+        has[cl.unknowns] = True
+        val = np.zeros(nc ** 3)
+        val[cl.unknowns] = x_coarse
+        out = np.zeros(fl.N)
+        for q, p in enumerate(fl.unknowns):
+            idx = (p % nf, (p // nf) % nf, p // (nf * nf))
+            # fine centre (i + 1/2) h in coarse index units: i/2 - 1/4
+            axes = []
+            for i in idx:
+                lo = i // 2 - 1 if i % 2 == 0 else i // 2
+                t = 0.75 if i % 2 == 0 else 0.25
+                axes.append(((lo, 1.0 - t), (lo + 1, t)))
+            num = den = 0.0
+            for kz, wz in axes[2]:
+                for jy, wy in axes[1]:
+                    for ix, wx in axes[0]:
+                        if not (0 <= ix < nc and 0 <= jy < nc and 0 <= kz < nc):
+                            continue
+                        c = ix + nc * (jy + nc * kz)
+                        if not has[c]:
+                            continue
+                        w = wx * wy * wz
+                        num += w * val[c]
+                        den += w
+            out[q] = num / den if den > 0 else 0.0
+        return out
+
+    def fmg(self, r: np.ndarray, cycles: int, prm: MGParams = MGParams()) -> np.ndarray:
+        """Full multigrid (Sec. 5, algorithm FMG), written as its recursion
+        unrolled: the right-hand side is restricted to every level, the
+        coarsest level is solved directly, and from the coarsest level up each
+        level's solution is the interpolated coarser one improved by `cycles`
+        V-cycles (residual on that level, V-cycle correction, update)."""
+        M = len(self.levels) - 1
+        rhs = [r]
+        for m in range(M):
+            rhs.append(self.fmg_restrict(m, rhs[m]))
+        x = self.ops[M].lu_all.solve(rhs[M])
+        for m in range(M - 1, -1, -1):
+            x = self.fmg_prolong(m, x)
+            for _ in range(cycles):
+                x = x + self.vcycle(m, rhs[m] - self.ops[m].L @ x, prm)
+        return x
 
     def solve(self, r: np.ndarray, prm: MGParams = MGParams(), guess=None):
         """Multigrid driver; returns (phi, history of max-norm relative residuals)."""
