@@ -225,6 +225,22 @@ int cc_restrict(cc_problem* p, int level, const double* s_dev, const double* e_d
                 double* sc_dev);
 int cc_prolong_add(cc_problem* p, int level, const double* ec_dev, double* ef_dev);
 int cc_bottom_solve(cc_problem* p, const double* s_dev, double* e_dev);
+
+/* Full multigrid (Sec. 5, algorithm FMG), FP64 whatever cc_params.precision:
+ * phi_dev (n^3 doubles on the device, overwritten) receives an approximation
+ * of L phi = r_dev built from the coarsest level up with `cycles` V-cycles per
+ * level (1..64); pass it to cc_solve as the initial guess to continue to the
+ * tolerance.  The right-hand side is restricted by 2^-3 times the sum over the
+ * children that carry an unknown; the coarser solution is interpolated
+ * trilinearly in the cell centres over the coarse cells that carry an unknown
+ * (weights renormalised).  Cells merged into a host hold the host's value,
+ * cells without an unknown 0.  The first call allocates the coarse levels'
+ * arrays.  Synchronizes the problem's stream.  Errors: CC_EINVAL. */
+int cc_fmg(cc_problem* p, const double* r_dev, double* phi_dev, int cycles);
+/* The two FMG transfers between level and level + 1 (parity hooks):
+ * sc = restriction of the right-hand side s; xf = interpolation of xc. */
+int cc_fmg_restrict(cc_problem* p, int level, const double* s_dev, double* sc_dev);
+int cc_fmg_prolong(cc_problem* p, int level, const double* xc_dev, double* xf_dev);
 int cc_vcycle(cc_problem* p, int level, const double* s_dev, double* e_dev);
 
 /* Host copies of a level's integer decisions and rows (Sec. 2.2-2.4), for

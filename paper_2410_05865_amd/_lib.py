@@ -31,7 +31,7 @@ EXPORTED = [
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
-    "cc_set_lu_schedule",
+    "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -111,6 +111,9 @@ def load() -> C.CDLL:
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
     lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.cc_fmg.argtypes = [vp, vp, vp, C.c_int]
+    lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
+    lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
     lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
@@ -378,6 +381,20 @@ class Problem:
     def prolong_add(self, level, ec, ef):
         self._order()
         _check(load().cc_prolong_add(self._h, level, _ptr(ec, self.n(level + 1) ** 3), _ptr(ef, self.n(level) ** 3)))
+
+    def fmg(self, r, phi, cycles: int = 2):
+        """Full multigrid approximation of L phi = r into phi (FP64)."""
+        self._order()
+        n3 = self.n() ** 3
+        _check(load().cc_fmg(self._h, _ptr(r, n3), _ptr(phi, n3), cycles))
+
+    def fmg_restrict(self, level, s, sc):
+        self._order()
+        _check(load().cc_fmg_restrict(self._h, level, _ptr(s, self.n(level) ** 3), _ptr(sc, self.n(level + 1) ** 3)))
+
+    def fmg_prolong(self, level, xc, xf):
+        self._order()
+        _check(load().cc_fmg_prolong(self._h, level, _ptr(xc, self.n(level + 1) ** 3), _ptr(xf, self.n(level) ** 3)))
 
     def bottom_solve(self, s, e):
         self._order()

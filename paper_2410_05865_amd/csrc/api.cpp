@@ -215,6 +215,8 @@ struct cc_problem {
   float* net_y = nullptr;
   long long net_cells = 0;
   cc::Krylov kr;                // GMRES acceleration (cc_params.krylov > 0)
+  std::vector<double*> fmg_rhs;  // full multigrid: right-hand side and solution of levels 1..M
+  std::vector<double*> fmg_x;    // (allocated on the first cc_fmg)
 };
 
 namespace cc {
@@ -699,6 +701,45 @@ void residual(cc_problem* P, int m, const double* r, const double* x, double* s,
   DevLevel& D = P->dev[m];
   launch_stencil_residual(D.st, r, x, s, nb, P->stream);
   launch_plg_residual(D.plg, r, x, s, 0, nb, cube(D.st.n), P->stream);
+}
+
+// Full multigrid (Sec. 5, algorithm FMG) in FP64, its recursion unrolled: the
+// right-hand side is restricted to every level, the coarsest level solved by
+// its LU, and from the coarsest level up each level's solution is the
+// interpolated coarser one improved by `cycles` V-cycles (level residual,
+// V-cycle correction, update).  phi receives the level-0 result; merged cells
+// take their host's value.
+void fmg(cc_problem* P, const double* r, double* phi, int cycles) {
+  const int M = (int)P->dev.size() - 1;
+  if ((int)P->fmg_rhs.size() != M + 1) {
+    P->fmg_rhs.assign(M + 1, nullptr);
+    P->fmg_x.assign(M + 1, nullptr);
+    for (int m = 1; m <= M; ++m) {
+      P->fmg_rhs[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n));
+      P->fmg_x[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n));
+    }
+  }
+  std::vector<const double*> rhs(M + 1);
+  std::vector<double*> x(M + 1);
+  rhs[0] = r;
+  x[0] = phi;
+  for (int m = 1; m <= M; ++m) {
+    rhs[m] = P->fmg_rhs[m];
+    x[m] = P->fmg_x[m];
+  }
+  for (int m = 0; m < M; ++m) launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], P->stream);
+  const Work<double>& W = P->w64;
+  bottom<double>(P, W, rhs[M], x[M], 1);
+  for (int m = M - 1; m >= 0; --m) {
+    DevLevel& D = P->dev[m];
+    launch_fmg_prolong(D.st, P->dev[m + 1].st, x[m + 1], x[m], P->stream);
+    for (int c = 0; c < cycles; ++c) {
+      residual(P, m, rhs[m], x[m], W.s[m]);
+      vcycle<double>(P, W, m, W.s[m], W.e[m], D.et, 1);
+      launch_add_unknowns<double>(D.st, W.e[m], nullptr, x[m], 1, P->stream);
+    }
+  }
+  launch_copy_pairs<double>(P->dev[0].n_absorbed, P->dev[0].absorbed, phi, cube(P->dev[0].st.n), 1, P->stream);
 }
 
 std::vector<double> read_norms(cc_problem* P, const unsigned long long* d, int nb) {
@@ -1406,6 +1447,38 @@ int cc_prolong_add(cc_problem* p, int level, const double* ec, double* ef) {
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!ec || !ef) fail(CC_EINVAL, "null array");
     launch_prolong_add<double>(p->dev[level].st, p->dev[level + 1].st.n, ec, ef, 1, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_fmg(cc_problem* p, const double* r, double* phi, int cycles) {
+  return guard([&] {
+    if (!p || !r || !phi) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    if (cycles < 1 || cycles > 64) fail(CC_EINVAL, "cycles must lie in [1, 64]");
+    fmg(p, r, phi, cycles);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_fmg_restrict(cc_problem* p, int level, const double* s, double* sc) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
+    if (!s || !sc) fail(CC_EINVAL, "null array");
+    launch_fmg_restrict(p->dev[level].st, p->dev[level + 1].st, s, sc, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_fmg_prolong(cc_problem* p, int level, const double* xc, double* xf) {
+  return guard([&] {
+    check_level(p, level);
+    need_device(p);
+    if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
+    if (!xc || !xf) fail(CC_EINVAL, "null array");
+    launch_fmg_prolong(p->dev[level].st, p->dev[level + 1].st, xc, xf, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }

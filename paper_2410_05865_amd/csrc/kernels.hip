@@ -336,6 +336,73 @@ __global__ void k_prolong_add(StencilLevel F, int nc, const T* __restrict__ ec, 
   if (F.type[c] == 1) ef[c] += ec[(i >> 1) + (long)nc * ((j >> 1) + (long)nc * (k >> 1))];
 }
 
+// Full multigrid transfers (Sec. 5, algorithm FMG).  Right-hand side:
+// sc = 2^-3 sum of s over the 8 children that carry an unknown (type != 0);
+// coarse cells without an unknown get 0.
+__global__ void k_fmg_restrict(StencilLevel F, StencilLevel C, const double* __restrict__ s,
+                               double* __restrict__ sc) {
+  const int nc = C.n, nf = F.n;
+  int I, J, K;
+  tile_ijk(nc, I, J, K);
+  if (I >= nc || J >= nc) return;
+  const long cc = I + (long)nc * (J + (long)nc * K);
+  double acc = 0.0;
+  if (C.type[cc] != 0) {
+    double v[8];
+    uint8_t t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const long c = (2 * I + (q & 1)) + (long)nf * ((2 * J + ((q >> 1) & 1)) + (long)nf * (2 * K + (q >> 2)));
+      v[q] = s[c];
+      t[q] = F.type[c];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += t[q] != 0 ? v[q] : 0.0;
+    acc *= 0.125;
+  }
+  sc[cc] = acc;
+}
+
+// Interpolation: trilinear in the coarse cell centres over the 8 coarse cells
+// around each fine centre that lie in the box and carry an unknown, weights
+// renormalised (0 if none); fine cells without an unknown get 0.
+__global__ void k_fmg_prolong(StencilLevel F, StencilLevel C, const double* __restrict__ xc,
+                              double* __restrict__ xf) {
+  const int n = F.n, nc = C.n;
+  int i, j, k;
+  tile_ijk(n, i, j, k);
+  if (i >= n || j >= n) return;
+  const long c = i + (long)n * (j + (long)n * k);
+  double v = 0.0;
+  if (F.type[c] != 0) {
+    // fine centre (i + 1/2) h in coarse index units is i/2 - 1/4
+    const int lo[3] = {(i & 1) ? i / 2 : i / 2 - 1, (j & 1) ? j / 2 : j / 2 - 1, (k & 1) ? k / 2 : k / 2 - 1};
+    const double t[3] = {(i & 1) ? 0.25 : 0.75, (j & 1) ? 0.25 : 0.75, (k & 1) ? 0.25 : 0.75};
+    double num = 0.0, den = 0.0;
+    for (int dz = 0; dz < 2; ++dz) {
+      const int kz = lo[2] + dz;
+      if (kz < 0 || kz >= nc) continue;
+      const double wz = dz ? t[2] : 1.0 - t[2];
+      for (int dy = 0; dy < 2; ++dy) {
+        const int jy = lo[1] + dy;
+        if (jy < 0 || jy >= nc) continue;
+        const double wy = dy ? t[1] : 1.0 - t[1];
+        for (int dx = 0; dx < 2; ++dx) {
+          const int ix = lo[0] + dx;
+          if (ix < 0 || ix >= nc) continue;
+          const long q = ix + (long)nc * (jy + (long)nc * kz);
+          if (C.type[q] == 0) continue;
+          const double w = (dx ? t[0] : 1.0 - t[0]) * wy * wz;
+          num += w * xc[q];
+          den += w;
+        }
+      }
+    }
+    v = den > 0.0 ? num / den : 0.0;
+  }
+  xf[c] = v;
+}
+
 template <class TS, class TY>
 __global__ void k_gather(int n, const int* __restrict__ cell, const TS* __restrict__ src, long long stride,
                          TY* __restrict__ y) {
@@ -1074,6 +1141,12 @@ template <class T>
 void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
                      hipStream_t st) {
   hipLaunchKernelGGL(k_restrict<T>, grid_tiles(C.n, nb), kBlock3, 0, st, F, C, s, e, sc);
+}
+void launch_fmg_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_fmg_restrict, grid_tiles(C.n, 1), kBlock3, 0, st, F, C, s, sc);
+}
+void launch_fmg_prolong(const StencilLevel& F, const StencilLevel& C, const double* xc, double* xf, hipStream_t st) {
+  hipLaunchKernelGGL(k_fmg_prolong, grid_tiles(F.n, 1), kBlock3, 0, st, F, C, xc, xf);
 }
 template <class T>
 void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int nb, hipStream_t st) {
