@@ -191,16 +191,21 @@ class Hierarchy:
             out[q] = num / den if den > 0 else 0.0
         return out
 
-    def fmg(self, r: np.ndarray, cycles: int, prm: MGParams = MGParams()) -> np.ndarray:
+    def fmg(self, r: np.ndarray, cycles: int, prm: MGParams = MGParams(), coarse_rhs=None) -> np.ndarray:
         """Full multigrid (Sec. 5, algorithm FMG), written as its recursion
-        unrolled: the right-hand side is restricted to every level, the
-        coarsest level is solved directly, and from the coarsest level up each
-        level's solution is the interpolated coarser one improved by `cycles`
-        V-cycles (residual on that level, V-cycle correction, update)."""
+        unrolled: each coarser level's right-hand side is coarse_rhs[m - 1]
+        (the same problem discretised on that level) or, if None, the
+        restriction of the finer one; the coarsest level is solved directly,
+        and from the coarsest level up each level's solution is the
+        interpolated coarser one improved by `cycles` V-cycles (residual on
+        that level, V-cycle correction, update).  The theorem behind FMG
+        assumes every level solves a discretisation of the same problem; a
+        restricted right-hand side is one only when the boundary data vanish,
+        since its boundary terms carry the fine level's h."""
         M = len(self.levels) - 1
         rhs = [r]
         for m in range(M):
-            rhs.append(self.fmg_restrict(m, rhs[m]))
+            rhs.append(self.fmg_restrict(m, rhs[m]) if coarse_rhs is None else coarse_rhs[m])
         x = self.ops[M].lu_all.solve(rhs[M])
         for m in range(M - 1, -1, -1):
             x = self.fmg_prolong(m, x)
