@@ -14,7 +14,7 @@ with HIP events on the library's stream), and the CPU oracle timed on a
 bounded sample (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
-                    [--no-mixed] [--no-batch] [--no-cpu-baseline]
+                    [--no-mixed] [--no-batch] [--no-fmg] [--no-cpu-baseline]
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
@@ -209,6 +209,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-fmg", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
@@ -296,6 +297,45 @@ def main():
                 out_krylov["mixed_preconditioner"] = {
                     "s_per_solve": sec_km, "v_cycles": info_km["iterations"],
                     "final_rel_residual": info_km["rel_residual"], "speedup_vs_plain": sec / sec_km}
+        out_fmg = None
+        if not args.no_fmg:
+            # full multigrid first (FP64, c V-cycles per level), then the solve from its result
+            # each coarser level's right-hand side: the same problem assembled there
+            # (input data like r, not timed)
+            coarse = []
+            for m in range(1, P.num_levels):
+                rm = torch.zeros(P.n(m) ** 3, dtype=torch.float64, device=dev)
+                P.assemble_rhs(phi, phi, rm, f_mode=_lib.CC_LAPLACIAN, level=m)
+                coarse.append(rm)
+            legs = {}
+            for cyc in (1, 2, 3):
+                def fmg_solve(c=cyc):
+                    x.zero_()
+                    P.fmg(r, x, c, coarse_rhs=coarse)
+                    return P.solve(r, x)
+                sec_f, info_f = _timed(fmg_solve, args.steps, args.warmup)
+                print(f"[bench] FMG({cyc}) + plain FP64: {sec_f * 1e3:.1f} ms, {info_f['iterations']} V-cycles after "
+                      f"FMG", file=sys.stderr, flush=True)
+                legs[str(cyc)] = {"s_per_solve": sec_f, "v_cycles_after_fmg": info_f["iterations"],
+                                  "final_rel_residual": info_f["rel_residual"], "speedup_vs_plain": sec / sec_f}
+            best = min(legs, key=lambda k: legs[k]["s_per_solve"])
+            out_fmg = {"cycles_per_level": legs, "best_cycles": int(best)}
+            if not args.no_krylov and not args.no_mixed:
+                P.set_krylov(args.krylov)
+                P.set_precision(_lib.CC_MIXED)
+
+                def fmg_gmres():
+                    x.zero_()
+                    P.fmg(r, x, int(best), coarse_rhs=coarse)
+                    return P.solve(r, x)
+                sec_fg, info_fg = _timed(fmg_gmres, args.steps, args.warmup)
+                P.set_precision(_lib.CC_FP64)
+                P.set_krylov(0)
+                print(f"[bench] FMG({best}) + GMRES({args.krylov}) with the FP32 V-cycle: {sec_fg * 1e3:.1f} ms, "
+                      f"{info_fg['iterations']} V-cycles after FMG", file=sys.stderr, flush=True)
+                out_fmg["then_gmres_fp32_vcycle"] = {"s_per_solve": sec_fg, "v_cycles_after_fmg": info_fg["iterations"],
+                                                     "final_rel_residual": info_fg["rel_residual"],
+                                                     "speedup_vs_plain": sec / sec_fg}
         out_batch = None
         if not args.no_batch and args.batch > 0:
             B = args.batch
@@ -376,6 +416,7 @@ def main():
             for m, li in ((m, P.level_info(m)) for m in range(P.num_levels))],
         "mixed": out_mixed,
         "krylov": out_krylov,
+        "fmg": out_fmg,
         "batched": out_batch,
         "learned": out_learned,
         "multi_geometry": out_multi,

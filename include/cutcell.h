@@ -150,6 +150,10 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info);
  * outward normal derivative of g).  r_dev: device, n^3. */
 int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g,
                     double* r_dev);
+/* The same on level `level` (its cells, rows and boundary sites; r_dev has n_m^3
+ * doubles): the right-hand sides of the coarse levels for cc_fmg. */
+int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mode, const cc_field* g,
+                          double* r_dev);
 
 /* Multigrid (Sec. 5.3): phi <- phi + VCycle(r - L phi) until the max-norm relative
  * residual < tol or max_iter.  phi_dev is the initial guess on entry and the
@@ -230,13 +234,18 @@ int cc_bottom_solve(cc_problem* p, const double* s_dev, double* e_dev);
  * phi_dev (n^3 doubles on the device, overwritten) receives an approximation
  * of L phi = r_dev built from the coarsest level up with `cycles` V-cycles per
  * level (1..64); pass it to cc_solve as the initial guess to continue to the
- * tolerance.  The right-hand side is restricted by 2^-3 times the sum over the
- * children that carry an unknown; the coarser solution is interpolated
- * trilinearly in the cell centres over the coarse cells that carry an unknown
- * (weights renormalised).  Cells merged into a host hold the host's value,
- * cells without an unknown 0.  The first call allocates the coarse levels'
- * arrays.  Synchronizes the problem's stream.  Errors: CC_EINVAL. */
-int cc_fmg(cc_problem* p, const double* r_dev, double* phi_dev, int cycles);
+ * tolerance.  coarse_rhs (host array of M device pointers, level m's at
+ * [m - 1], n_m^3 doubles each) gives each coarser level's right-hand side,
+ * normally the same problem assembled there (cc_assemble_rhs_level); if NULL
+ * they are restricted from r_dev by 2^-3 times the sum over the children that
+ * carry an unknown, which is consistent only when the boundary data vanish
+ * (the boundary terms of r scale with the fine h).  The coarser solution is
+ * interpolated trilinearly in the cell centres over the coarse cells that
+ * carry an unknown (weights renormalised).  Cells merged into a host hold the
+ * host's value, cells without an unknown 0.  The first call allocates the
+ * coarse levels' arrays.  Synchronizes the problem's stream.
+ * Errors: CC_EINVAL. */
+int cc_fmg(cc_problem* p, const double* r_dev, const double* const* coarse_rhs, double* phi_dev, int cycles);
 /* The two FMG transfers between level and level + 1 (parity hooks):
  * sc = restriction of the right-hand side s; xf = interpolation of xc. */
 int cc_fmg_restrict(cc_problem* p, int level, const double* s_dev, double* sc_dev);

@@ -31,7 +31,7 @@ EXPORTED = [
     "cc_apply", "cc_residual", "cc_smo1", "cc_smo2", "cc_restrict", "cc_prolong_add", "cc_bottom_solve",
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
-    "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong",
+    "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -97,6 +97,7 @@ def load() -> C.CDLL:
     lib.cc_num_levels.argtypes = [vp]
     lib.cc_get_level_info.argtypes = [vp, C.c_int, P(CcLevelInfo)]
     lib.cc_assemble_rhs.argtypes = [vp, P(CcField), C.c_int, P(CcField), vp]
+    lib.cc_assemble_rhs_level.argtypes = [vp, C.c_int, P(CcField), C.c_int, P(CcField), vp]
     lib.cc_solve.argtypes = [vp, vp, vp, P(CcSolveInfo)]
     lib.cc_apply.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_residual.argtypes = [vp, C.c_int, vp, vp, vp, P(C.c_double)]
@@ -111,7 +112,7 @@ def load() -> C.CDLL:
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
     lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
-    lib.cc_fmg.argtypes = [vp, vp, vp, C.c_int]
+    lib.cc_fmg.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
@@ -300,11 +301,12 @@ class Problem:
         return v.value
 
     # -------------------------------------------------------------- device
-    def assemble_rhs(self, f: dict, g: Optional[dict], r, f_mode: int = CC_VALUE):
+    def assemble_rhs(self, f: dict, g: Optional[dict], r, f_mode: int = CC_VALUE, level: int = 0):
         self._order()
         fs, fk = _field(f)
         gs, gk = _field(g)
-        _check(load().cc_assemble_rhs(self._h, C.byref(fs), f_mode, C.byref(gs), _ptr(r, self.n() ** 3)))
+        _check(load().cc_assemble_rhs_level(self._h, level, C.byref(fs), f_mode, C.byref(gs),
+                                            _ptr(r, self.n(level) ** 3)))
 
     @staticmethod
     def _info(info: CcSolveInfo, rc: int) -> dict:
@@ -382,11 +384,18 @@ class Problem:
         self._order()
         _check(load().cc_prolong_add(self._h, level, _ptr(ec, self.n(level + 1) ** 3), _ptr(ef, self.n(level) ** 3)))
 
-    def fmg(self, r, phi, cycles: int = 2):
-        """Full multigrid approximation of L phi = r into phi (FP64)."""
+    def fmg(self, r, phi, cycles: int = 2, coarse_rhs=None):
+        """Full multigrid approximation of L phi = r into phi (FP64).
+        coarse_rhs: the right-hand sides of levels 1..M (assemble_rhs with
+        level=m), or None to restrict r."""
         self._order()
         n3 = self.n() ** 3
-        _check(load().cc_fmg(self._h, _ptr(r, n3), _ptr(phi, n3), cycles))
+        arr = None
+        if coarse_rhs is not None:
+            if len(coarse_rhs) != self.num_levels - 1:
+                raise ValueError("one right-hand side per coarser level expected")
+            arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, self.n(m + 1) ** 3) for m, t in enumerate(coarse_rhs)])
+        _check(load().cc_fmg(self._h, _ptr(r, n3), arr, _ptr(phi, n3), cycles))
 
     def fmg_restrict(self, level, s, sc):
         self._order()

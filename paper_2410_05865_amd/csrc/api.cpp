@@ -703,13 +703,14 @@ void residual(cc_problem* P, int m, const double* r, const double* x, double* s,
   launch_plg_residual(D.plg, r, x, s, 0, nb, cube(D.st.n), P->stream);
 }
 
-// Full multigrid (Sec. 5, algorithm FMG) in FP64, its recursion unrolled: the
-// right-hand side is restricted to every level, the coarsest level solved by
-// its LU, and from the coarsest level up each level's solution is the
-// interpolated coarser one improved by `cycles` V-cycles (level residual,
-// V-cycle correction, update).  phi receives the level-0 result; merged cells
-// take their host's value.
-void fmg(cc_problem* P, const double* r, double* phi, int cycles) {
+// Full multigrid (Sec. 5, algorithm FMG) in FP64, its recursion unrolled: each
+// level's right-hand side is coarse_rhs[m - 1] (the same problem assembled on
+// that level) or, with coarse_rhs null, the restriction of the finer one; the
+// coarsest level is solved by its LU, and from the coarsest level up each
+// level's solution is the interpolated coarser one improved by `cycles`
+// V-cycles (level residual, V-cycle correction, update).  phi receives the
+// level-0 result; merged cells take their host's value.
+void fmg(cc_problem* P, const double* r, const double* const* coarse_rhs, double* phi, int cycles) {
   const int M = (int)P->dev.size() - 1;
   if ((int)P->fmg_rhs.size() != M + 1) {
     P->fmg_rhs.assign(M + 1, nullptr);
@@ -724,10 +725,12 @@ void fmg(cc_problem* P, const double* r, double* phi, int cycles) {
   rhs[0] = r;
   x[0] = phi;
   for (int m = 1; m <= M; ++m) {
-    rhs[m] = P->fmg_rhs[m];
+    rhs[m] = coarse_rhs ? coarse_rhs[m - 1] : P->fmg_rhs[m];
     x[m] = P->fmg_x[m];
   }
-  for (int m = 0; m < M; ++m) launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], P->stream);
+  if (!coarse_rhs)
+    for (int m = 0; m < M; ++m)
+      launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], P->stream);
   const Work<double>& W = P->w64;
   bottom<double>(P, W, rhs[M], x[M], 1);
   for (int m = M - 1; m >= 0; --m) {
@@ -1252,13 +1255,15 @@ int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* 
   });
 }
 
-int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g, double* r_dev) {
+int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mode, const cc_field* g,
+                          double* r_dev) {
   return guard([&] {
     if (!p || !r_dev) fail(CC_EINVAL, "null argument");
+    check_level(p, level);
     need_device(p);
     if (f_mode != CC_VALUE && f_mode != CC_LAPLACIAN) fail(CC_EINVAL, "bad f_mode");
     FieldDesc fd = to_desc(f), gd = to_desc(g);
-    const LevelHost& L = *p->lv[0];
+    const LevelHost& L = *p->lv[level];
     const int n = L.n;
     const double h = L.h;
     const size_t n3 = (size_t)n * n * n;
@@ -1379,6 +1384,10 @@ int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field
   });
 }
 
+int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field* g, double* r_dev) {
+  return cc_assemble_rhs_level(p, 0, f, f_mode, g, r_dev);
+}
+
 int cc_apply(cc_problem* p, int level, const double* x, double* y) {
   return guard([&] {
     check_level(p, level);
@@ -1451,12 +1460,15 @@ int cc_prolong_add(cc_problem* p, int level, const double* ec, double* ef) {
   });
 }
 
-int cc_fmg(cc_problem* p, const double* r, double* phi, int cycles) {
+int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, double* phi, int cycles) {
   return guard([&] {
     if (!p || !r || !phi) fail(CC_EINVAL, "null argument");
     need_device(p);
     if (cycles < 1 || cycles > 64) fail(CC_EINVAL, "cycles must lie in [1, 64]");
-    fmg(p, r, phi, cycles);
+    if (coarse_rhs)
+      for (size_t m = 1; m < p->dev.size(); ++m)
+        if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
+    fmg(p, r, coarse_rhs, phi, cycles);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }

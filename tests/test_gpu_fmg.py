@@ -101,3 +101,39 @@ def test_fmg_matches_oracle_and_shortens_the_solve(name):
     assert i1["iterations"] < i0["iterations"]
     assert float((phi1 - phi0).abs().max() / phi0.abs().max()) < 1e-9
     print(f"[fmg] {name}: V-cycles from zero {i0['iterations']}, after FMG(2) {i1['iterations']}", flush=True)
+
+
+@pytest.mark.parametrize("name", sorted(WORK))
+def test_rhs_on_every_level_and_fmg_with_level_rhs(name):
+    """cc_assemble_rhs_level against the oracle's right-hand side of every
+    level; FMG from those right-hand sides against the oracle's, and the solve
+    continued from it."""
+    L = _lib()
+    H, P, F = _pair(name)
+    rs, ors = [], []
+    for m, lvm in enumerate(H.levels):
+        r_or = lvm.rhs(F.laplacian_desc(), F)
+        r = _dev(np.zeros(lvm.n ** 3))
+        P.assemble_rhs(F.desc, F.desc, r, f_mode=L.CC_LAPLACIAN, level=m)
+        err = _rel(r.cpu().numpy()[lvm.unknowns], r_or)
+        print(f"[fmg] {name} level {m} right-hand side: max rel difference {err:.2e}", flush=True)
+        assert err < 1e-12
+        rs.append(r)
+        ors.append(r_or)
+    lv = H.fine
+    for cycles in (1, 2):
+        phi = _dev(np.zeros(lv.n ** 3))
+        P.fmg(rs[0], phi, cycles, coarse_rhs=rs[1:])
+        ref = H.fmg(ors[0], cycles, coarse_rhs=ors[1:])
+        err = _rel(phi.cpu().numpy()[lv.unknowns], ref)
+        print(f"[fmg] {name} per-level FMG({cycles}): max rel difference to the oracle {err:.2e}", flush=True)
+        assert err < 1e-11
+    phi0 = _dev(np.zeros(lv.n ** 3))
+    i0 = P.solve(rs[0], phi0)
+    phi1 = _dev(np.zeros(lv.n ** 3))
+    P.fmg(rs[0], phi1, 2, coarse_rhs=rs[1:])
+    i1 = P.solve(rs[0], phi1)
+    assert i0["converged"] and i1["converged"] and i1["iterations"] < i0["iterations"]
+    assert float((phi1 - phi0).abs().max() / phi0.abs().max()) < 1e-9
+    print(f"[fmg] {name}: V-cycles from zero {i0['iterations']}, after per-level FMG(2) {i1['iterations']}",
+          flush=True)
