@@ -246,6 +246,12 @@ int cc_bottom_solve(cc_problem* p, const double* s_dev, double* e_dev);
  * coarse levels' arrays.  Synchronizes the problem's stream.
  * Errors: CC_EINVAL. */
 int cc_fmg(cc_problem* p, const double* r_dev, const double* const* coarse_rhs, double* phi_dev, int cycles);
+/* cc_fmg for nrhs right-hand sides at a stride of n^3 (groups of up to
+ * CC_BATCH_MAX share each level's V-cycles, as in cc_solve_batched);
+ * coarse_rhs[m - 1] then holds nrhs arrays of n_m^3 doubles.  Start
+ * cc_solve_batched from phi_dev.  Errors: CC_EINVAL. */
+int cc_fmg_batched(cc_problem* p, int nrhs, const double* r_dev, const double* const* coarse_rhs, double* phi_dev,
+                   int cycles);
 /* The two FMG transfers between level and level + 1 (parity hooks):
  * sc = restriction of the right-hand side s; xf = interpolation of xc. */
 int cc_fmg_restrict(cc_problem* p, int level, const double* s_dev, double* sc_dev);

@@ -32,6 +32,7 @@ EXPORTED = [
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
+    "cc_fmg_batched",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -113,6 +114,7 @@ def load() -> C.CDLL:
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
     lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.cc_fmg.argtypes = [vp, vp, vp, vp, C.c_int]
+    lib.cc_fmg_batched.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int]
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
@@ -396,6 +398,20 @@ class Problem:
                 raise ValueError("one right-hand side per coarser level expected")
             arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, self.n(m + 1) ** 3) for m, t in enumerate(coarse_rhs)])
         _check(load().cc_fmg(self._h, _ptr(r, n3), arr, _ptr(phi, n3), cycles))
+
+    def fmg_batched(self, r, phi, cycles: int = 2, coarse_rhs=None):
+        """FMG for r of shape (nrhs, n^3) into phi of the same shape; coarse_rhs:
+        per coarser level a (nrhs, n_m^3) tensor, or None to restrict r."""
+        self._order()
+        nrhs = r.shape[0]
+        n3 = self.n() ** 3
+        arr = None
+        if coarse_rhs is not None:
+            if len(coarse_rhs) != self.num_levels - 1:
+                raise ValueError("one right-hand side array per coarser level expected")
+            arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, nrhs * self.n(m + 1) ** 3)
+                                                  for m, t in enumerate(coarse_rhs)])
+        _check(load().cc_fmg_batched(self._h, nrhs, _ptr(r, nrhs * n3), arr, _ptr(phi, nrhs * n3), cycles))
 
     def fmg_restrict(self, level, s, sc):
         self._order()

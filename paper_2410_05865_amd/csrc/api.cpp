@@ -98,6 +98,16 @@ struct DevBuf {
     for (void* p : ptrs) (void)hipFree(p);
     ptrs.clear();
   }
+  // free one allocation of this buffer (no-op for null)
+  void free(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < ptrs.size(); ++i)
+      if (ptrs[i] == p) {
+        (void)hipFree(p);
+        ptrs.erase(ptrs.begin() + (long)i);
+        return;
+      }
+  }
 };
 
 struct DevLU {
@@ -216,7 +226,8 @@ struct cc_problem {
   long long net_cells = 0;
   cc::Krylov kr;                // GMRES acceleration (cc_params.krylov > 0)
   std::vector<double*> fmg_rhs;  // full multigrid: right-hand side and solution of levels 1..M
-  std::vector<double*> fmg_x;    // (allocated on the first cc_fmg)
+  std::vector<double*> fmg_x;    // (allocated on the first cc_fmg, for fmg_nb arrays)
+  int fmg_nb = 0;
 };
 
 namespace cc {
@@ -709,40 +720,47 @@ void residual(cc_problem* P, int m, const double* r, const double* x, double* s,
 // coarsest level is solved by its LU, and from the coarsest level up each
 // level's solution is the interpolated coarser one improved by `cycles`
 // V-cycles (level residual, V-cycle correction, update).  phi receives the
-// level-0 result; merged cells take their host's value.
-void fmg(cc_problem* P, const double* r, const double* const* coarse_rhs, double* phi, int cycles) {
+// level-0 result; merged cells take their host's value.  nb right-hand sides
+// at a stride of n_m^3 (W sized for nb); the coarse right-hand sides of the
+// group start coarse_off arrays into coarse_rhs[m - 1].
+void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* const* coarse_rhs, long long coarse_off,
+         double* phi, int cycles, int nb) {
   const int M = (int)P->dev.size() - 1;
-  if ((int)P->fmg_rhs.size() != M + 1) {
+  if ((int)P->fmg_rhs.size() != M + 1 || P->fmg_nb < nb) {
+    for (int m = 1; m < (int)P->fmg_rhs.size(); ++m) {
+      P->buf.free(P->fmg_rhs[m]);
+      P->buf.free(P->fmg_x[m]);
+    }
     P->fmg_rhs.assign(M + 1, nullptr);
     P->fmg_x.assign(M + 1, nullptr);
     for (int m = 1; m <= M; ++m) {
-      P->fmg_rhs[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n));
-      P->fmg_x[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n));
+      P->fmg_rhs[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
+      P->fmg_x[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
     }
+    P->fmg_nb = nb;
   }
   std::vector<const double*> rhs(M + 1);
   std::vector<double*> x(M + 1);
   rhs[0] = r;
   x[0] = phi;
   for (int m = 1; m <= M; ++m) {
-    rhs[m] = coarse_rhs ? coarse_rhs[m - 1] : P->fmg_rhs[m];
+    rhs[m] = coarse_rhs ? coarse_rhs[m - 1] + coarse_off * cube(P->dev[m].st.n) : P->fmg_rhs[m];
     x[m] = P->fmg_x[m];
   }
   if (!coarse_rhs)
     for (int m = 0; m < M; ++m)
-      launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], P->stream);
-  const Work<double>& W = P->w64;
-  bottom<double>(P, W, rhs[M], x[M], 1);
+      launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], nb, P->stream);
+  bottom<double>(P, W, rhs[M], x[M], nb);
   for (int m = M - 1; m >= 0; --m) {
     DevLevel& D = P->dev[m];
-    launch_fmg_prolong(D.st, P->dev[m + 1].st, x[m + 1], x[m], P->stream);
+    launch_fmg_prolong(D.st, P->dev[m + 1].st, x[m + 1], x[m], nb, P->stream);
     for (int c = 0; c < cycles; ++c) {
-      residual(P, m, rhs[m], x[m], W.s[m]);
-      vcycle<double>(P, W, m, W.s[m], W.e[m], D.et, 1);
-      launch_add_unknowns<double>(D.st, W.e[m], nullptr, x[m], 1, P->stream);
+      residual(P, m, rhs[m], x[m], W.s[m], nb);
+      vcycle<double>(P, W, m, W.s[m], W.e[m], W.et[m], nb);
+      launch_add_unknowns<double>(D.st, W.e[m], nullptr, x[m], nb, P->stream);
     }
   }
-  launch_copy_pairs<double>(P->dev[0].n_absorbed, P->dev[0].absorbed, phi, cube(P->dev[0].st.n), 1, P->stream);
+  launch_copy_pairs<double>(P->dev[0].n_absorbed, P->dev[0].absorbed, phi, cube(P->dev[0].st.n), nb, P->stream);
 }
 
 std::vector<double> read_norms(cc_problem* P, const unsigned long long* d, int nb) {
@@ -1468,7 +1486,27 @@ int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, doub
     if (coarse_rhs)
       for (size_t m = 1; m < p->dev.size(); ++m)
         if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
-    fmg(p, r, coarse_rhs, phi, cycles);
+    fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1);
+    HIPCHK(hipStreamSynchronize(p->stream));
+  });
+}
+
+int cc_fmg_batched(cc_problem* p, int nrhs, const double* r, const double* const* coarse_rhs, double* phi,
+                   int cycles) {
+  return guard([&] {
+    if (!p || !r || !phi || nrhs < 1) fail(CC_EINVAL, "bad argument");
+    need_device(p);
+    if (cycles < 1 || cycles > 64) fail(CC_EINVAL, "cycles must lie in [1, 64]");
+    if (coarse_rhs)
+      for (size_t m = 1; m < p->dev.size(); ++m)
+        if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
+    const int cap = std::min(nrhs, CC_BATCH_MAX);
+    if (p->wb64.nb < cap) alloc_work(p, p->wb64, cap);
+    const long long n3 = cube(p->dev[0].st.n);
+    for (int b0 = 0; b0 < nrhs; b0 += CC_BATCH_MAX) {
+      const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
+      fmg(p, p->wb64, r + b0 * n3, coarse_rhs, b0, phi + b0 * n3, cycles, nb);
+    }
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -1479,7 +1517,7 @@ int cc_fmg_restrict(cc_problem* p, int level, const double* s, double* sc) {
     need_device(p);
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!s || !sc) fail(CC_EINVAL, "null array");
-    launch_fmg_restrict(p->dev[level].st, p->dev[level + 1].st, s, sc, p->stream);
+    launch_fmg_restrict(p->dev[level].st, p->dev[level + 1].st, s, sc, 1, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }
@@ -1490,7 +1528,7 @@ int cc_fmg_prolong(cc_problem* p, int level, const double* xc, double* xf) {
     need_device(p);
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!xc || !xf) fail(CC_EINVAL, "null array");
-    launch_fmg_prolong(p->dev[level].st, p->dev[level + 1].st, xc, xf, p->stream);
+    launch_fmg_prolong(p->dev[level].st, p->dev[level + 1].st, xc, xf, 1, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
   });
 }

@@ -346,6 +346,8 @@ __global__ void k_fmg_restrict(StencilLevel F, StencilLevel C, const double* __r
   tile_ijk(nc, I, J, K);
   if (I >= nc || J >= nc) return;
   const long cc = I + (long)nc * (J + (long)nc * K);
+  s += batch_off(nf);
+  sc += batch_off(nc);
   double acc = 0.0;
   if (C.type[cc] != 0) {
     double v[8];
@@ -373,6 +375,8 @@ __global__ void k_fmg_prolong(StencilLevel F, StencilLevel C, const double* __re
   tile_ijk(n, i, j, k);
   if (i >= n || j >= n) return;
   const long c = i + (long)n * (j + (long)n * k);
+  xc += batch_off(nc);
+  xf += batch_off(n);
   double v = 0.0;
   if (F.type[c] != 0) {
     // fine centre (i + 1/2) h in coarse index units is i/2 - 1/4
@@ -1142,11 +1146,13 @@ void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, c
                      hipStream_t st) {
   hipLaunchKernelGGL(k_restrict<T>, grid_tiles(C.n, nb), kBlock3, 0, st, F, C, s, e, sc);
 }
-void launch_fmg_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_fmg_restrict, grid_tiles(C.n, 1), kBlock3, 0, st, F, C, s, sc);
+void launch_fmg_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, double* sc, int nb,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_fmg_restrict, grid_tiles(C.n, nb), kBlock3, 0, st, F, C, s, sc);
 }
-void launch_fmg_prolong(const StencilLevel& F, const StencilLevel& C, const double* xc, double* xf, hipStream_t st) {
-  hipLaunchKernelGGL(k_fmg_prolong, grid_tiles(F.n, 1), kBlock3, 0, st, F, C, xc, xf);
+void launch_fmg_prolong(const StencilLevel& F, const StencilLevel& C, const double* xc, double* xf, int nb,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_fmg_prolong, grid_tiles(F.n, nb), kBlock3, 0, st, F, C, xc, xf);
 }
 template <class T>
 void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int nb, hipStream_t st) {

@@ -111,10 +111,12 @@ void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, c
                      hipStream_t st);
 template <class T>
 void launch_prolong_add(const StencilLevel& F, int nc, const T* ec, T* ef, int nb, hipStream_t st);
-// full multigrid transfers (FP64, one array): right-hand side restriction
+// full multigrid transfers (FP64, nb arrays): right-hand side restriction
 // (children with an unknown averaged) and renormalised trilinear interpolation
-void launch_fmg_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, double* sc, hipStream_t st);
-void launch_fmg_prolong(const StencilLevel& F, const StencilLevel& C, const double* xc, double* xf, hipStream_t st);
+void launch_fmg_restrict(const StencilLevel& F, const StencilLevel& C, const double* s, double* sc, int nb,
+                         hipStream_t st);
+void launch_fmg_prolong(const StencilLevel& F, const StencilLevel& C, const double* xc, double* xf, int nb,
+                        hipStream_t st);
 template <class T>
 void launch_plg_b2(const PlgRows& P, const T* s, const T* e, T* y, long long stride, int nb, hipStream_t st);
 template <class T>
