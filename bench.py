@@ -14,7 +14,7 @@ with HIP events on the library's stream), and the CPU oracle timed on a
 bounded sample (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
-                    [--no-mixed] [--no-batch] [--no-fmg] [--no-cpu-baseline]
+                    [--no-mixed] [--no-batch] [--no-fmg] [--no-table4] [--no-cpu-baseline]
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
@@ -108,6 +108,53 @@ def _timed(fn, steps: int, warmup: int):
         out = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, out
+
+
+def _table4_leg(args, sec_plain_value=None):
+    """The paper's Table 4 solving-time workload (unit cube minus the sphere of
+    radius 0.3, its 'Multigrid solution' 146.46 s at h = 1/256 on one CPU
+    thread, tolerance unstated): time to 1e-10 from the zero guess with the
+    paper's omega = 0.5 and with omega = 0.8, and FMG(2) then V-cycles."""
+    import torch
+    from paper_2410_05865_amd import _lib, inputs as inp
+    dev = torch.device("cuda:0")
+    dom, phi = inp.sphere03_workload(args.n)
+    n3 = args.n ** 3
+    out = {"workload": f"unit cube minus the sphere r = 0.3 at the centre, {args.n}^3, Dirichlet walls and sphere, "
+                       f"phi = exp(x + y/2) cos(3z)", "paper_multigrid_solution_s": 146.46 if args.n == 256 else None,
+           "paper_conditions": "AMD Ryzen 9 7950X, one thread, omega 0.5, nu 3/3, tolerance not stated"}
+    for omega in (0.5, 0.8):
+        P = _lib.Problem(dom, omega=omega)
+        r = torch.zeros(n3, dtype=torch.float64, device=dev)
+        P.assemble_rhs(phi, phi, r, f_mode=_lib.CC_LAPLACIAN)
+        x = torch.zeros_like(r)
+
+        def solve():
+            x.zero_()
+            return P.solve(r, x)
+        s, info = _timed(solve, args.steps, args.warmup)
+        leg = {"s_per_solve": s, "v_cycles": info["iterations"], "final_rel_residual": info["rel_residual"]}
+        if omega == 0.8:
+            coarse = []
+            for m in range(1, P.num_levels):
+                rm = torch.zeros(P.n(m) ** 3, dtype=torch.float64, device=dev)
+                P.assemble_rhs(phi, phi, rm, f_mode=_lib.CC_LAPLACIAN, level=m)
+                coarse.append(rm)
+
+            def fmg_solve():
+                x.zero_()
+                P.fmg(r, x, 2, coarse_rhs=coarse)
+                return P.solve(r, x)
+            sf, info_f = _timed(fmg_solve, args.steps, args.warmup)
+            leg["fmg2_then_vcycles"] = {"s_per_solve": sf, "v_cycles_after_fmg": info_f["iterations"],
+                                        "final_rel_residual": info_f["rel_residual"]}
+            print(f"[bench] Table 4 sphere, omega 0.8, FMG(2) then V-cycles: {sf * 1e3:.1f} ms, "
+                  f"{info_f['iterations']} V-cycles", file=sys.stderr, flush=True)
+        print(f"[bench] Table 4 sphere, omega {omega}: {s * 1e3:.1f} ms, {info['iterations']} V-cycles",
+              file=sys.stderr, flush=True)
+        out[f"omega_{omega}"] = leg
+        P.close()
+    return out
 
 
 def _multi_leg(args):
@@ -210,6 +257,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-fmg", action="store_true")
+    ap.add_argument("--no-table4", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
@@ -396,6 +444,9 @@ def main():
         out_multi = None
         if not args.no_multi:
             out_multi = _multi_leg(args)
+        out_t4 = None
+        if not args.no_table4:
+            out_t4 = _table4_leg(args)
         out_learned = None
         if not args.no_learned:
             out_learned = _learned_leg(P, dom, args, stream)
@@ -444,6 +495,7 @@ def main():
         "batched": out_batch,
         "learned": out_learned,
         "multi_geometry": out_multi,
+        "paper_table4_sphere": out_t4,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_smo1<double> (SMO-1 weighted Jacobi, level 0)",

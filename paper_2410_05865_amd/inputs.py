@@ -165,6 +165,14 @@ def sphere_workload(n: int = 32):
     return sphere_domain(n=n), sinprod_field()
 
 
+def sphere03_workload(n: int = 256):
+    """The solving-time workload of the paper's Table 4: the unit cube minus the
+    sphere of radius 0.3 at its centre.  The table states no solution or
+    boundary conditions; here Dirichlet on walls and sphere with the
+    manufactured phi = exp(x + y/2) cos(3 z)."""
+    return sphere_domain(n=n, radius=0.3, n_min=32), expcos_field()
+
+
 def ellipsoid_workload(n: int = 128, seed: int = 1):
     """Box minus 8 seeded ellipsoids; Dirichlet walls, Neumann obstacles;
     manufactured phi = exp(x + y/2) cos(3 z)."""
