@@ -2,7 +2,9 @@
 
 Cells C_i = (x_O + i h, x_O + (i+1) h) of the box R; cut cells
 C_i ∩ Ω, their volumes, the boundary patches S_i = C_i ∩ ∂Ω, and the
-interior / exterior / cut classification.  Ω is the box minus ellipsoids.
+interior / exterior / cut classification.  Ω is the box minus ellipsoids,
+or (domain.inside) the interior of one ellipsoid: its quadric is negated so
+that Ω = {psi > 0} either way, and cells away from it are exterior.
 
 Per cut cell the oracle keeps the quadrature nodes (for right-hand sides)
 and the normalised moments used by the polynomial fits (Sec. 2.3):
@@ -88,11 +90,17 @@ class LevelGeometry:
         self.n = n
         self.h = 1.0 / n
         self.origin = np.asarray(domain.origin, float)
+        self.inside = bool(getattr(domain, "inside", False))
         self.quadrics = [qd.ellipsoid_quadric(o.center, o.axes, o.rot) for o in domain.obstacles]
+        if self.inside:
+            if len(self.quadrics) != 1:
+                raise GeometryError("an interior domain is bounded by exactly one ellipsoid")
+            q = self.quadrics[0]
+            self.quadrics = [qd.Quadric(-q.Q, -q.b, -q.c)]
         N = n ** 3
         self.owner = np.full(N, -1, dtype=np.int64)
-        self.cls = np.full(N, INTERIOR, dtype=np.int8)
-        self.vol = np.full(N, self.h ** 3)
+        self.cls = np.full(N, EXTERIOR if self.inside else INTERIOR, dtype=np.int8)
+        self.vol = np.full(N, 0.0 if self.inside else self.h ** 3)
         self.cut: Dict[int, CutCell] = {}
         self._claim()
         self._classify()

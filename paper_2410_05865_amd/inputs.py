@@ -45,6 +45,7 @@ class Domain:
     wall_bc: Sequence[int] = (DIRICHLET,) * 6
     origin: Sequence[float] = (0.0, 0.0, 0.0)
     n_min: int = 16             # coarsest grid size of the multigrid hierarchy
+    inside: bool = False        # Omega = the interior of obstacles[0] instead of the box minus the obstacles
 
     @property
     def h(self) -> float:
@@ -163,6 +164,15 @@ def sphere_workload(n: int = 32):
     """Box minus sphere r=0.25 at the centre; Dirichlet everywhere;
     manufactured phi = sin(2 pi x) sin(2 pi y) sin(2 pi z)."""
     return sphere_domain(n=n), sinprod_field()
+
+
+def sphere_interior_problem(n: int = 50, n_min: int = 25):
+    """The paper's Problem 1: Poisson's equation inside the sphere of radius 0.3
+    centred at (0.5, 0.5, 0.5), Dirichlet data, exact solution
+    exp(-x^2 - y^2 - z^2) (a Gaussian with sigma^2 = 1/2 at the origin)."""
+    ob = Obstacle(np.array([0.5, 0.5, 0.5]), np.full(3, 0.3), np.eye(3), DIRICHLET)
+    dom = Domain(n=n, obstacles=[ob], wall_bc=(DIRICHLET,) * 6, n_min=n_min, inside=True)
+    return dom, gauss_field([1.0], [[0.0, 0.0, 0.0]], [math.sqrt(0.5)])
 
 
 def sphere03_workload(n: int = 256):
