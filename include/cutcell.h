@@ -60,6 +60,9 @@ typedef struct cc_domain {
   int wall_bc[6];
   int n_obst;
   const cc_obstacle* obst;
+  int inside;         /* 0: Omega = the box minus the obstacles; 1: Omega = the interior
+                         of the one obstacle (n_obst must be 1; the walls then carry no
+                         unknowns) */
 } cc_domain;
 
 /* Method parameters (Sec. 4.2 theta; Sec. 5.3 omega, nu1, nu2, eps, I_max). */

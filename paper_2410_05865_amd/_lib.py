@@ -44,7 +44,7 @@ class CcObstacle(C.Structure):
 
 class CcDomain(C.Structure):
     _fields_ = [("n", C.c_int), ("origin", C.c_double * 3), ("h", C.c_double), ("wall_bc", C.c_int * 6),
-                ("n_obst", C.c_int), ("obst", C.POINTER(CcObstacle))]
+                ("n_obst", C.c_int), ("obst", C.POINTER(CcObstacle)), ("inside", C.c_int)]
 
 
 class CcParams(C.Structure):
@@ -227,6 +227,7 @@ class Problem:
         dom.wall_bc[:] = [int(v) for v in domain.wall_bc]
         dom.n_obst = len(domain.obstacles)
         dom.obst = obs
+        dom.inside = int(bool(getattr(domain, "inside", False)))
         h = C.c_void_p()
         st = C.c_void_p(stream) if stream is not None else None
         _check(lib.cc_build(C.byref(dom), C.byref(prm), st, C.byref(h)))

@@ -1168,6 +1168,18 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
       ob.q = ellipsoid_quadric(ob.c, ob.axes, ob.rot);
       D.obst.push_back(ob);
     }
+    if (dom->inside != 0 && dom->inside != 1) fail(CC_EINVAL, "inside must be 0 or 1");
+    D.inside = dom->inside == 1;
+    if (D.inside) {
+      // Omega = the obstacle's interior: negate its quadric so that Omega = {q > 0}
+      if (D.obst.size() != 1) fail(CC_EINVAL, "an interior domain is bounded by exactly one obstacle");
+      Quadric& q = D.obst[0].q;
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) q.Q[i][j] = -q.Q[i][j];
+        q.b[i] = -q.b[i];
+      }
+      q.c = -q.c;
+    }
     std::vector<int> sizes = {D.n};
     while (sizes.back() % 2 == 0 && sizes.back() / 2 >= prm->n_min) sizes.push_back(sizes.back() / 2);
     const int M = (int)sizes.size() - 1;

@@ -106,8 +106,10 @@ void LevelHost::build(const DomainSpec& d, int n_level, double theta) {
   for (int i = 0; i < 3; ++i) origin[i] = d.origin[i];
   for (int i = 0; i < 6; ++i) wall_bc[i] = d.wall_bc[i];
   size_t n3 = (size_t)n * n * n;
-  cls.assign(n3, kInterior);
-  vol.assign(n3, h * h * h);
+  // away from the obstacles' claimed cells: interior in the box minus the
+  // obstacles, exterior for the interior of one obstacle
+  cls.assign(n3, d.inside ? kExterior : kInterior);
+  vol.assign(n3, d.inside ? 0.0 : h * h * h);
   owner.assign(n3, -1);
   claim();
   classify();

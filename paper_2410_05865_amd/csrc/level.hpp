@@ -25,6 +25,7 @@ struct DomainSpec {
   double h;
   int wall_bc[6];
   std::vector<Obstacle> obst;
+  bool inside = false;  // Omega = interior of obst[0] (its quadric negated: Omega = {q > 0} either way)
 };
 
 enum : int8_t { kExterior = 0, kInterior = 1, kCut = 2 };

@@ -58,6 +58,7 @@ def test_header_enums_match_binding():
 CASES = {
     "sphere16": lambda: inputs.sphere_domain(n=16, radius=0.25, n_min=8),
     "ellipsoid32_neumann": lambda: _ell32(),
+    "sphere_interior32": lambda: inputs.sphere_interior_problem(32, n_min=16)[0],
 }
 
 
