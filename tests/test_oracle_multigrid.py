@@ -11,12 +11,6 @@ from paper_2410_05865_amd import inputs
 
 
 @pytest.fixture(scope="module")
-def sphere32():
-    dom, phi = inputs.sphere_workload(32)
-    return Hierarchy(dom), Field(phi)
-
-
-@pytest.fixture(scope="module")
 def sphere16_two_level():
     dom, phi = inputs.sphere_workload(16)
     dom.n_min = 8
