@@ -42,7 +42,7 @@ from .geometry import (CUT, EXTERIOR, INTERIOR, LevelGeometry, MONO3, MONO4,
 from .merging import THETA, groups, merge_cells
 from .fields import Field
 
-DIRICHLET, NEUMANN = 0, 1
+DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 
 # Ghost-cell formulas: value of ghost 1 and ghost 2 beyond a wall as
 # combinations of the 4 nearest interior cells (nearest last) and the face
@@ -294,11 +294,24 @@ class Level:
                     ell[j] += e[d] * (e[d] - 1) * mom[idx[tuple(f)]]
         return ell / (h * h)
 
+    def _robin_scale(self, m: int):
+        """(alpha, beta, s) of the Robin condition on cut cell m's patch, with
+        s = h / (|alpha| h + |beta|) scaling its site row to unit size."""
+        alpha, beta = self.domain.obstacles[self.geo.cut[m].obst].robin
+        return alpha, beta, self.h / (abs(alpha) * self.h + abs(beta))
+
     def _patch_functional(self, p_target: int, m: int, bc: int):
         """Dirichlet: <<xi^a>> over the patch of cell m; Neumann:
-        <<n . grad_xi xi^a>> (xi centred at the target)."""
+        <<n . grad_xi xi^a>> (xi centred at the target); Robin (alpha phi +
+        beta dphi/dn): s (alpha <<xi^a>> + (beta / h) <<n . grad_xi xi^a>>)
+        with s = h / (|alpha| h + |beta|), which is the Dirichlet row for
+        beta = 0 and the Neumann row for alpha = 0."""
         cc = self.geo.cut[m]
         dl = tuple(int(v) for v in np.array(self.ijk(m)) - np.array(self.ijk(p_target)))
+        if bc == ROBIN:
+            alpha, beta, s = self._robin_scale(m)
+            return s * (alpha * self._patch_functional(p_target, m, DIRICHLET)
+                        + (beta / self.h) * self._patch_functional(p_target, m, NEUMANN))
         if bc == DIRICHLET:
             return shift_matrix(dl, MONO4) @ cc.sm
         S3 = shift_matrix(dl, MONO3)
@@ -471,9 +484,14 @@ class Level:
                 cc = self.geo.cut[m]
                 if bc == DIRICHLET:
                     dat = float(g.value(cc.Xs) @ cc.Ws) / cc.area
-                else:
+                elif bc == NEUMANN:
                     dn = np.sum(g.grad(cc.Xs) * cc.Ns, axis=1)
                     dat = h * float(dn @ cc.Ws) / cc.area
+                else:
+                    # Robin datum <<alpha g + beta dg/dn>> with the row's scale
+                    alpha, beta, sc = self._robin_scale(m)
+                    dn = np.sum(g.grad(cc.Xs) * cc.Ns, axis=1)
+                    dat = sc * float((alpha * g.value(cc.Xs) + beta * dn) @ cc.Ws) / cc.area
                 r[row] -= v * dat
         return r
 

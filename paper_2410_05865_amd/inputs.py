@@ -19,12 +19,13 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Sequence
+from typing import List, Sequence, Tuple
 
 import numpy as np
 
 DIRICHLET = 0
 NEUMANN = 1
+ROBIN = 2                       # alpha phi + beta dphi/dn = g (obstacle surfaces only)
 
 
 @dataclasses.dataclass
@@ -33,6 +34,7 @@ class Obstacle:
     axes: np.ndarray            # (3,) semi-axes
     rot: np.ndarray             # (3,3); column j is the direction of semi-axis j
     bc: int = DIRICHLET         # boundary condition on this obstacle's surface
+    robin: Tuple[float, float] = (1.0, 0.0)   # (alpha, beta) of a ROBIN condition
 
     def bounding_radius(self) -> float:
         return float(np.max(self.axes))

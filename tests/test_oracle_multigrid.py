@@ -114,3 +114,38 @@ def test_fourth_order_convergence(sphere32, sphere16_two_level):
         errs.append(np.max(np.abs(x - lv.region_average(F))))
     ratio = errs[0] / errs[1]
     assert ratio > 11.0, errs      # fourth order: 16 asymptotically
+
+
+def _ell32_robin(bc, robin):
+    dom = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    dom.n_min = 16
+    for ob in dom.obstacles:
+        ob.bc = bc
+        ob.robin = robin
+    return dom
+
+
+def test_robin_rows_reduce_to_dirichlet_and_neumann():
+    """A Robin condition alpha phi + beta dphi/dn with (1, 0) gives the
+    Dirichlet rows and with (0, 1) the Neumann rows (same data scaling)."""
+    from oracle.discretize import Level
+    for robin, plain in (((1.0, 0.0), inputs.DIRICHLET), ((0.0, 1.0), inputs.NEUMANN)):
+        a = Level(_ell32_robin(inputs.ROBIN, robin), 32)
+        b = Level(_ell32_robin(plain, (1.0, 0.0)), 32)
+        assert a.plg.keys() == b.plg.keys()
+        for k in a.plg:
+            assert list(a.plg[k][0]) == list(b.plg[k][0])
+            assert np.max(np.abs(np.asarray(a.plg[k][1]) - np.asarray(b.plg[k][1]))) <= 1e-12 * np.max(
+                np.abs(b.plg[k][1]))
+
+
+def test_polynomial_reproduction_robin():
+    """With Robin data on the obstacles every row is still exact on quartics."""
+    H = Hierarchy(_ell32_robin(inputs.ROBIN, (1.0, 0.3)))
+    P = Field(inputs.poly_field([(4, 0, 0, 1.0), (0, 2, 2, -2.0), (1, 1, 1, 1.0), (0, 0, 0, 1.0),
+                                 (2, 0, 1, 0.4)]))
+    lv = H.fine
+    r = lv.rhs(P.laplacian_desc(), P)
+    x, hist = H.solve(r, MGParams(tol=1e-13, max_iter=300))
+    ex = lv.region_average(P)
+    assert np.max(np.abs(x - ex)) < 1e-10 * np.max(np.abs(ex))
