@@ -40,7 +40,7 @@ enum {
   CC_ENOCONV = -7     /* max_iter V-cycles without reaching tol */
 };
 
-enum { CC_DIRICHLET = 0, CC_NEUMANN = 1 };
+enum { CC_DIRICHLET = 0, CC_NEUMANN = 1, CC_ROBIN = 2 /* obstacles only */ };
 enum { CC_FP64 = 0, CC_MIXED = 1 };
 
 /* An ellipsoid { x : (x-c)^T R diag(axes^-2) R^T (x-c) <= 1 } removed from the box.
@@ -49,7 +49,11 @@ typedef struct cc_obstacle {
   double center[3];
   double axes[3];
   double rot[9];
-  int bc;             /* CC_DIRICHLET or CC_NEUMANN on this obstacle's surface */
+  int bc;             /* CC_DIRICHLET, CC_NEUMANN or CC_ROBIN on this obstacle's surface */
+  double robin[2];    /* (alpha, beta) of CC_ROBIN: alpha phi + beta dphi/dn = g, n outward of
+                         Omega; the FV-PLG site row and its datum are scaled by
+                         h / (|alpha| h + |beta|), so (1, 0) and (0, 1) are the Dirichlet and
+                         Neumann rows (Sec. 2.3 boundary sites); ignored otherwise */
 } cc_obstacle;
 
 /* Grid and domain (Sec. 2.2).  Walls ordered -x,+x,-y,+y,-z,+z. */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libcutcell.so")
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_EGEOM, CC_EPLG, CC_ESINGULAR, CC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4}
 CC_VALUE, CC_LAPLACIAN = 0, 1
-CC_DIRICHLET, CC_NEUMANN = 0, 1
+CC_DIRICHLET, CC_NEUMANN, CC_ROBIN = 0, 1, 2
 CC_FP64, CC_MIXED = 0, 1
 HISTORY_MAX = 256
 BATCH_MAX = 64
@@ -39,7 +39,8 @@ EXPORTED = [
 
 
 class CcObstacle(C.Structure):
-    _fields_ = [("center", C.c_double * 3), ("axes", C.c_double * 3), ("rot", C.c_double * 9), ("bc", C.c_int)]
+    _fields_ = [("center", C.c_double * 3), ("axes", C.c_double * 3), ("rot", C.c_double * 9), ("bc", C.c_int),
+                ("robin", C.c_double * 2)]
 
 
 class CcDomain(C.Structure):
@@ -220,6 +221,7 @@ class Problem:
             obs[t].axes[:] = [float(v) for v in o.axes]
             obs[t].rot[:] = [float(v) for v in np.asarray(o.rot).reshape(-1)]
             obs[t].bc = int(o.bc)
+            obs[t].robin[:] = [float(v) for v in getattr(o, "robin", (1.0, 0.0))]
         dom = CcDomain()
         dom.n = domain.n
         dom.origin[:] = [float(v) for v in domain.origin]

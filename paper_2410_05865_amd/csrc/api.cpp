@@ -1162,8 +1162,14 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         if (!(o.axes[a] > 0)) fail(CC_EINVAL, "semi-axes must be positive");
       }
       for (int a = 0; a < 9; ++a) ob.rot[a] = o.rot[a];
-      if (o.bc != CC_DIRICHLET && o.bc != CC_NEUMANN) fail(CC_EINVAL, "bad obstacle bc");
+      if (o.bc != CC_DIRICHLET && o.bc != CC_NEUMANN && o.bc != CC_ROBIN) fail(CC_EINVAL, "bad obstacle bc");
       ob.bc = o.bc;
+      if (o.bc == CC_ROBIN) {
+        ob.alpha = o.robin[0];
+        ob.beta = o.robin[1];
+        if (!(std::isfinite(ob.alpha) && std::isfinite(ob.beta)) || (ob.alpha == 0.0 && ob.beta == 0.0))
+          fail(CC_EINVAL, "a Robin condition needs finite (alpha, beta), not both 0");
+      }
       ob.R = std::max(ob.axes[0], std::max(ob.axes[1], ob.axes[2]));
       ob.q = ellipsoid_quadric(ob.c, ob.axes, ob.rot);
       D.obst.push_back(ob);
@@ -1327,6 +1333,7 @@ int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mod
       for (size_t q = 0; q < vn.size(); ++q)
         s += vn.w[q] * field_value(fd, vn.x[3 * q], vn.x[3 * q + 1], vn.x[3 * q + 2], f_mode);
       cut_int[t] = s;
+      const Obstacle& ob = p->dom.obst[cd.obst];
       double acc = 0.0, area = 0.0;
       for (size_t q = 0; q < sn.w.size(); ++q) {
         const double* x = &sn.x[3 * q];
@@ -1337,11 +1344,17 @@ int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mod
           double gr[3];
           field_grad(gd, x[0], x[1], x[2], gr);
           v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
+          if (bc == CC_ROBIN) v = ob.alpha * field_value(gd, x[0], x[1], x[2], 0) + ob.beta * v;
         }
         acc += sn.w[q] * v;
         area += sn.w[q];
       }
-      cut_dat[t] = (area > 0) ? acc / area * (bc == CC_NEUMANN ? h : 1.0) : 0.0;
+      // the datum in the scale of the site row: Neumann h <<dg/dn>>, Robin
+      // h <<alpha g + beta dg/dn>> / (|alpha| h + |beta|)
+      const double scale = bc == CC_NEUMANN ? h
+                           : bc == CC_ROBIN  ? h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta))
+                                             : 1.0;
+      cut_dat[t] = (area > 0) ? acc / area * scale : 0.0;
     }
     std::map<int, size_t> cut_pos;
     for (size_t t = 0; t < cuts.size(); ++t) cut_pos[cuts[t]] = t;

@@ -612,9 +612,11 @@ void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG]
     int dl[3] = {ci[0] - ti[0], ci[1] - ti[1], ci[2] - ti[2]};
     if (st.kind == 'S') {
       const CutData& cd = cut.at(st.cell);
-      if (st.bc == CC_DIRICHLET) {
-        shift_moments4(cd.sm, dl, rowp);
-      } else {
+      // Dirichlet: <<xi^a>>; Neumann: <<n . grad_xi xi^a>>; Robin:
+      // s (alpha <<xi^a>> + (beta / h) <<n . grad_xi xi^a>>), s = h / (|alpha| h + |beta|)
+      double dir[N4], neu[N4];
+      if (st.bc != CC_NEUMANN) shift_moments4(cd.sm, dl, dir);
+      if (st.bc != CC_DIRICHLET) {
         double sh[3][N3];
         for (int d = 0; d < 3; ++d) shift_moments3(cd.sn[d], dl, sh[d]);
         for (int j = 0; j < N4; ++j) {
@@ -626,8 +628,17 @@ void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG]
             a[d] -= 1;
             v += e * sh[d][T.idx3[a[0]][a[1]][a[2]]];
           }
-          rowp[j] = v;
+          neu[j] = v;
         }
+      }
+      if (st.bc == CC_DIRICHLET) {
+        for (int j = 0; j < N4; ++j) rowp[j] = dir[j];
+      } else if (st.bc == CC_NEUMANN) {
+        for (int j = 0; j < N4; ++j) rowp[j] = neu[j];
+      } else {
+        const Obstacle& ob = dom->obst[cd.obst];
+        const double sc = h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta));
+        for (int j = 0; j < N4; ++j) rowp[j] = sc * (ob.alpha * dir[j] + (ob.beta / h) * neu[j]);
       }
     } else {
       int d = st.axis;

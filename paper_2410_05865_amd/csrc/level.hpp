@@ -15,6 +15,7 @@ namespace cc {
 struct Obstacle {
   double c[3], axes[3], rot[9];
   int bc;
+  double alpha = 1.0, beta = 0.0;  // CC_ROBIN: alpha phi + beta dphi/dn = g
   double R;   // bounding-sphere radius
   Quadric q;
 };

@@ -24,9 +24,15 @@ def _workloads():
     ell = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
     ell.wall_bc = (0, 1, 0, 0, 1, 0)
     ell.n_min = 16
+    rob = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    rob.n_min = 16
+    for ob, ab in zip(rob.obstacles, [(1.0, 0.3), (0.2, 1.0)]):     # Robin on both surfaces
+        ob.bc = inputs.ROBIN
+        ob.robin = ab
     small = inputs.sphere_domain(n=96, radius=0.1, n_min=24)   # ragged tiles, 3 levels
     return {"sphere32": (sph, inputs.sinprod_field()),
             "ellipsoid32_neumann": (ell, inputs.expcos_field()),
+            "ellipsoid32_robin": (rob, inputs.expcos_field()),
             "sphere96_ragged": (small, inputs.sinprod_field())}
 
 

@@ -59,13 +59,19 @@ CASES = {
     "sphere16": lambda: inputs.sphere_domain(n=16, radius=0.25, n_min=8),
     "ellipsoid32_neumann": lambda: _ell32(),
     "sphere_interior32": lambda: inputs.sphere_interior_problem(32, n_min=16)[0],
+    "ellipsoid32_robin": lambda: _ell32(robin=True),
 }
 
 
-def _ell32():
+def _ell32(robin=False):
     d = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
     d.wall_bc = (0, 1, 0, 0, 1, 0)
     d.n_min = 16
+    if robin:
+        # one Robin surface leaning on the value, one leaning on the flux
+        for ob, ab in zip(d.obstacles, [(1.0, 0.3), (0.2, 1.0)]):
+            ob.bc = inputs.ROBIN
+            ob.robin = ab
     return d
 
 
@@ -133,6 +139,11 @@ def test_errors_are_status_codes():
     assert e.value.code == L.CC_EINVAL and "omega" in str(e.value)
     with pytest.raises(L.CutCellError) as e:
         L.Problem(dom, device=-1, precision=7)
+    assert e.value.code == L.CC_EINVAL
+    bad = _ell32(robin=True)
+    bad.obstacles[0].robin = (0.0, 0.0)     # no condition at all
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(bad, device=-1)
     assert e.value.code == L.CC_EINVAL
     P = L.Problem(dom, device=-1)
     with pytest.raises(L.CutCellError) as e:
