@@ -59,47 +59,52 @@ __device__ __forceinline__ double block_max(double v) {
 
 // One axis of the assembled regular row (times 12 h^2): the 5-point
 // fourth-order stencil, with the ghost-substituted forms in the two cell layers
-// next to a Dirichlet (bc 0) or Neumann (bc 1) wall.  Adds the diagonal to diag.
-template <class T>
-__device__ __forceinline__ T axis_op(const T* __restrict__ x, long c, long s, int t, int n, int blo, int bhi,
-                                     T& diag) {
+// next to a Dirichlet (bc 0) or Neumann (bc 1) wall.  x(d) is the operand at
+// offset d (-3..3) along the axis; adds the diagonal to diag.
+template <class T, class X>
+__device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& diag) {
   if (t >= 2 && t <= n - 3) {
     diag += T(-30.0);
-    return -x[c - 2 * s] + T(16.0) * x[c - s] - T(30.0) * x[c] + T(16.0) * x[c + s] - x[c + 2 * s];
+    return -x(-2) + T(16.0) * x(-1) - T(30.0) * x(0) + T(16.0) * x(1) - x(2);
   }
   if (t == n - 1) {
     if (bhi == 0) {
       diag += T(-1087.0 / 12.0);
-      return (T(21.0) * x[c - 3 * s] - T(139.0) * x[c - 2 * s] + T(545.0) * x[c - s] - T(1087.0) * x[c]) /
-             T(12.0);
+      return (T(21.0) * x(-3) - T(139.0) * x(-2) + T(545.0) * x(-1) - T(1087.0) * x(0)) / T(12.0);
     }
     diag += T(-14.5);
-    return T(0.1) * x[c - 3 * s] - T(1.5) * x[c - 2 * s] + T(15.9) * x[c - s] - T(14.5) * x[c];
+    return T(0.1) * x(-3) - T(1.5) * x(-2) + T(15.9) * x(-1) - T(14.5) * x(0);
   }
   if (t == n - 2) {
     if (bhi == 0) {
       diag += T(-403.0 / 12.0);
-      return (T(-15.0) * x[c - 2 * s] + T(209.0) * x[c - s] - T(403.0) * x[c] + T(269.0) * x[c + s]) / T(12.0);
+      return (T(-15.0) * x(-2) + T(209.0) * x(-1) - T(403.0) * x(0) + T(269.0) * x(1)) / T(12.0);
     }
     diag += T(-30.9);
-    return T(-1.1) * x[c - 2 * s] + T(16.5) * x[c - s] - T(30.9) * x[c] + T(15.5) * x[c + s];
+    return T(-1.1) * x(-2) + T(16.5) * x(-1) - T(30.9) * x(0) + T(15.5) * x(1);
   }
   if (t == 0) {
     if (blo == 0) {
       diag += T(-1087.0 / 12.0);
-      return (T(21.0) * x[c + 3 * s] - T(139.0) * x[c + 2 * s] + T(545.0) * x[c + s] - T(1087.0) * x[c]) /
-             T(12.0);
+      return (T(21.0) * x(3) - T(139.0) * x(2) + T(545.0) * x(1) - T(1087.0) * x(0)) / T(12.0);
     }
     diag += T(-14.5);
-    return T(0.1) * x[c + 3 * s] - T(1.5) * x[c + 2 * s] + T(15.9) * x[c + s] - T(14.5) * x[c];
+    return T(0.1) * x(3) - T(1.5) * x(2) + T(15.9) * x(1) - T(14.5) * x(0);
   }
   // t == 1
   if (blo == 0) {
     diag += T(-403.0 / 12.0);
-    return (T(-15.0) * x[c + 2 * s] + T(209.0) * x[c + s] - T(403.0) * x[c] + T(269.0) * x[c - s]) / T(12.0);
+    return (T(-15.0) * x(2) + T(209.0) * x(1) - T(403.0) * x(0) + T(269.0) * x(-1)) / T(12.0);
   }
   diag += T(-30.9);
-  return T(-1.1) * x[c + 2 * s] + T(16.5) * x[c + s] - T(30.9) * x[c] + T(15.5) * x[c - s];
+  return T(-1.1) * x(2) + T(16.5) * x(1) - T(30.9) * x(0) + T(15.5) * x(-1);
+}
+
+// The same axis with the operand read from x at stride s around cell c.
+template <class T>
+__device__ __forceinline__ T axis_op(const T* __restrict__ x, long c, long s, int t, int n, int blo, int bhi,
+                                     T& diag) {
+  return axis_op_at<T>([&](int d) { return x[c + d * s]; }, t, n, blo, bhi, diag);
 }
 
 // (L x)_c * 12 h^2 for a phi_1 cell and its diagonal.
@@ -167,6 +172,105 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
     v += omega * (ld_stream(s + c) - a * inv) / (diag * inv);
   }
   st_stream(v, eout + c);
+}
+
+// SMO-1 marching in z: a workgroup takes a 64 x 4 cell tile of (x, y) columns
+// through kz consecutive planes.  Each thread keeps its column's operand at
+// planes k-3 .. k+3 in registers (one new plane loaded per step); each
+// wavefront (one x row) shares its row of the current plane, with 3 halo cells
+// on either side, through LDS for the x-neighbours; the y-neighbours (+-1, +-2;
+// +-3 only in the wall rows), the cell type and the right-hand side of plane
+// k+1 are loaded while plane k is computed.  All loads are unconditional at
+// clamped addresses (a clamped value is never used: every stencil reference of
+// a cell in the grid stays in the grid).  About 8 vector memory instructions
+// per cell against 15 for k_smo1, in the same arithmetic order (identical
+// results).
+constexpr int kHalo = 3;
+template <class T>
+struct SmoPlane {
+  T y[4];      // operand at y offsets -2, -1, +1, +2
+  T s;         // right-hand side
+  T h;         // halo cell (lanes 0 .. 5)
+  int type;
+};
+template <class T>
+__global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T* __restrict__ s,
+                                                const T* __restrict__ ein, T* __restrict__ eout, int kz) {
+  __shared__ T row[4][64 + 2 * kHalo];
+  const int n = L.n;
+  const int nzb = (n + kz - 1) / kz;
+  int b = blockIdx.x;
+  const int zb = b % nzb;
+  b /= nzb;
+  const int ny = (n + 3) / 4;
+  const int l = threadIdx.x, w = threadIdx.y;
+  const int j = (b % ny) * 4 + w;
+  const int i0 = (b / ny) * 64;
+  const int i = i0 + l;
+  const bool valid = i < n && j < n;
+  const long long o = batch_off(n);
+  s += o;
+  ein += o;
+  eout += o;
+  const long nn = (long)n * n;
+  const int ic = min(i, n - 1), jc = min(j, n - 1);
+  const long col = ic + (long)n * jc;
+  long ycol[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int dy = m < 2 ? m - 2 : m - 1;
+    ycol[m] = ic + (long)n * min(max(jc + dy, 0), n - 1);
+  }
+  // lanes 0..2 hold x = i0-3 .. i0-1, lanes 3..5 x = i0+64 .. i0+66, stored at
+  // row index x - i0 + 3
+  const int hl = l < kHalo ? l : l + 64;
+  const long hcol = min(max(i0 + hl - kHalo, 0), n - 1) + (long)n * jc;
+  const int k0 = zb * kz, k1 = min(k0 + kz, n);
+  auto load = [&](int kp) {
+    SmoPlane<T> P;
+    const long po = kp * nn;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) P.y[m] = ein[ycol[m] + po];
+    P.type = L.type[col + po];
+    P.s = ld_stream(s + col + po);
+    P.h = l < 2 * kHalo ? ein[hcol + po] : T(0);
+    return P;
+  };
+  T q[2 * kHalo + 1];
+#pragma unroll
+  for (int d = -kHalo; d < kHalo; ++d) q[kHalo + d] = ein[col + min(max(k0 + d, 0), n - 1) * nn];
+  SmoPlane<T> cur = load(k0);
+  const T inv = T(L.inv12h2);
+  for (int k = k0; k < k1; ++k) {
+    q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
+    const SmoPlane<T> nxt = load(min(k + 1, k1 - 1));
+    const long c = col + k * nn;
+    row[w][kHalo + l] = q[kHalo];
+    if (l < 2 * kHalo) row[w][hl] = cur.h;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T v = q[kHalo];
+    if (valid && cur.type == 1) {
+      T diag = T(0);
+      T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
+      a += axis_op_at<T>(
+          [&](int d) {
+            return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : cur.y[d < 0 ? d + 2 : d + 1];
+          },
+          j, n, L.bc[2], L.bc[3], diag);
+      a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
+      v += omega * (cur.s - a * inv) / (diag * inv);
+    }
+    if (valid) st_stream(v, eout + c);
+    // every lane's reads of this row precede the next plane's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
+    cur = nxt;
+  }
 }
 
 // Diagonal of the assembled regular row (times 12 h^2), summed over the axes in
@@ -1115,6 +1219,15 @@ inline dim3 grid3(int n) { return dim3((n + 63) / 64, (n + 3) / 4, n); }
 inline dim3 grid_tiles(int n, int nb = 1) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n, nb); }
 const dim3 kBlock3(64, 4, 1);
 inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs); }
+// SMO-1 marches in z from this grid size on (below, too few tiles to fill the
+// chip); planes per workgroup: enough workgroups for the chip, at most 32
+constexpr int kSmoMarchMin = 96;
+inline int smo_march_planes(int n) {
+  const long long tiles = (long long)((n + 63) / 64) * ((n + 3) / 4);
+  const long long want = 4096;   // workgroups
+  int kz = (int)std::min<long long>(32, std::max<long long>(8, (long long)n * tiles / want));
+  return kz;
+}
 inline long long cube(int n) { return (long long)n * n * n; }
 constexpr int kRedBlocks = 2048;   // blocks of the reductions (partial sums per block)
 
@@ -1122,7 +1235,14 @@ constexpr int kRedBlocks = 2048;   // blocks of the reductions (partial sums per
 
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_smo1<T>, grid_tiles(L.n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
+  const int n = L.n;
+  if (n < kSmoMarchMin) {
+    hipLaunchKernelGGL(k_smo1<T>, grid_tiles(n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
+    return;
+  }
+  const int kz = smo_march_planes(n);
+  const dim3 grid(((n + 63) / 64) * ((n + 3) / 4) * ((n + kz - 1) / kz), nb);
+  hipLaunchKernelGGL(k_smo1_z<T>, grid, kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
 }
 template <class T>
 void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st) {
