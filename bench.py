@@ -35,7 +35,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_05865_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_smo1_ellipsoid256_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_smo1_z_ellipsoid256_traffic.md")
 
 
 def _src_hash() -> str:
@@ -50,7 +50,7 @@ def _traffic(n: int):
         return None
     text = open(TRAFFIC_FILE).read()
     h = re.search(r"kernels\.hip sha256\[:16\]: `([0-9a-f]+)`", text)
-    v = re.search(r"k_smo1 bytes per launch \(calibrated\): `([0-9.eE+]+)`", text)
+    v = re.search(r"SMO-1 bytes per launch \(calibrated\): `([0-9.eE+]+)`", text)
     m = re.search(r"grid: `(\d+)\^3`", text)
     if not (h and v and m) or h.group(1) != _src_hash() or int(m.group(1)) != n:
         return None
@@ -498,7 +498,7 @@ def main():
         "paper_table4_sphere": out_t4,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_smo1<double> (SMO-1 weighted Jacobi, level 0)",
+            "kernel": "k_smo1_z<double> (SMO-1 weighted Jacobi, level 0)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -508,7 +508,7 @@ def main():
             "bytes_per_launch": by_smo,
         },
         "roofline_other": {
-            "k_smo1<float>": {"achieved_GBs": by_smo32 / (ms_smo32 * 1e-3) / 1e9, "ms_per_launch": ms_smo32,
+            "k_smo1_z<float>": {"achieved_GBs": by_smo32 / (ms_smo32 * 1e-3) / 1e9, "ms_per_launch": ms_smo32,
                               "bytes_per_launch": by_smo32},
             "lu_correction_level0_fp64": {"achieved_GBs": by_lu / (ms_lu * 1e-3) / 1e9, "ms_per_correction": ms_lu,
                                           "bytes_per_correction": by_lu},

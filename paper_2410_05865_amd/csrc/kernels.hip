@@ -174,42 +174,46 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
   st_stream(v, eout + c);
 }
 
-// SMO-1 marching in z: a workgroup takes a 64 x 4 cell tile of (x, y) columns
-// through kz consecutive planes.  Each thread keeps its column's operand at
-// planes k-3 .. k+3 in registers (one new plane loaded per step); each
-// wavefront (one x row) shares its row of the current plane, with 3 halo cells
-// on either side, through LDS for the x-neighbours; the y-neighbours (+-1, +-2;
-// +-3 only in the wall rows), the cell type and the right-hand side of plane
-// k+1 are loaded while plane k is computed.  All loads are unconditional at
-// clamped addresses (a clamped value is never used: every stencil reference of
-// a cell in the grid stays in the grid).  About 8 vector memory instructions
-// per cell against 15 for k_smo1, in the same arithmetic order (identical
-// results).
+// The regular-row kernels marching in z: a workgroup takes a 64 x 4 cell tile
+// of (x, y) columns through kz consecutive planes.  Each thread keeps its
+// column's operand at planes k-3 .. k+3 in registers (one new plane loaded per
+// step); each wavefront (one x row) shares its row of the current plane, with 3
+// halo cells on either side, through LDS for the x-neighbours; the
+// y-neighbours (+-1, +-2; +-3 only in the wall rows), the cell type and the
+// right-hand side of plane k+1 are loaded while plane k is computed.  All loads
+// are unconditional at clamped addresses (a clamped value is never used: every
+// stencil reference of a cell in the grid stays in the grid).  About 8 vector
+// memory instructions per cell against 15 for the one-cell-per-thread kernels,
+// in the same arithmetic order (identical results).
+//   kMarchSmo:      eout = e + omega (b - A e) / D on phi_1 cells, e elsewhere
+//   kMarchResidual: eout = b - A e on phi_1 cells, 0 elsewhere
+//   kMarchApply:    eout = A e on phi_1 cells, 0 elsewhere (b unused)
 constexpr int kHalo = 3;
+enum { kMarchSmo = 0, kMarchResidual = 1, kMarchApply = 2 };
 template <class T>
-struct SmoPlane {
+struct MarchPlane {
   T y[4];      // operand at y offsets -2, -1, +1, +2
-  T s;         // right-hand side
+  T b;         // right-hand side
   T h;         // halo cell (lanes 0 .. 5)
   int type;
 };
-template <class T>
-__global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T* __restrict__ s,
-                                                const T* __restrict__ ein, T* __restrict__ eout, int kz) {
+template <class T, int Mode>
+__device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const T* __restrict__ bv,
+                                           const T* __restrict__ ein, T* __restrict__ eout, int kz) {
   __shared__ T row[4][64 + 2 * kHalo];
   const int n = L.n;
   const int nzb = (n + kz - 1) / kz;
-  int b = blockIdx.x;
-  const int zb = b % nzb;
-  b /= nzb;
+  int blk = blockIdx.x;
+  const int zb = blk % nzb;
+  blk /= nzb;
   const int ny = (n + 3) / 4;
   const int l = threadIdx.x, w = threadIdx.y;
-  const int j = (b % ny) * 4 + w;
-  const int i0 = (b / ny) * 64;
+  const int j = (blk % ny) * 4 + w;
+  const int i0 = (blk / ny) * 64;
   const int i = i0 + l;
   const bool valid = i < n && j < n;
   const long long o = batch_off(n);
-  s += o;
+  if constexpr (Mode != kMarchApply) bv += o;
   ein += o;
   eout += o;
   const long nn = (long)n * n;
@@ -227,30 +231,33 @@ __global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T
   const long hcol = min(max(i0 + hl - kHalo, 0), n - 1) + (long)n * jc;
   const int k0 = zb * kz, k1 = min(k0 + kz, n);
   auto load = [&](int kp) {
-    SmoPlane<T> P;
+    MarchPlane<T> P;
     const long po = kp * nn;
 #pragma unroll
     for (int m = 0; m < 4; ++m) P.y[m] = ein[ycol[m] + po];
     P.type = L.type[col + po];
-    P.s = ld_stream(s + col + po);
+    if constexpr (Mode != kMarchApply)
+      P.b = ld_stream(bv + col + po);
+    else
+      P.b = T(0);
     P.h = l < 2 * kHalo ? ein[hcol + po] : T(0);
     return P;
   };
   T q[2 * kHalo + 1];
 #pragma unroll
   for (int d = -kHalo; d < kHalo; ++d) q[kHalo + d] = ein[col + min(max(k0 + d, 0), n - 1) * nn];
-  SmoPlane<T> cur = load(k0);
+  MarchPlane<T> cur = load(k0);
   const T inv = T(L.inv12h2);
   for (int k = k0; k < k1; ++k) {
     q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
-    const SmoPlane<T> nxt = load(min(k + 1, k1 - 1));
+    const MarchPlane<T> nxt = load(min(k + 1, k1 - 1));
     const long c = col + k * nn;
     row[w][kHalo + l] = q[kHalo];
     if (l < 2 * kHalo) row[w][hl] = cur.h;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    T v = q[kHalo];
+    T v = Mode == kMarchSmo ? q[kHalo] : T(0);
     if (valid && cur.type == 1) {
       T diag = T(0);
       T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
@@ -260,7 +267,12 @@ __global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T
           },
           j, n, L.bc[2], L.bc[3], diag);
       a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
-      v += omega * (cur.s - a * inv) / (diag * inv);
+      if constexpr (Mode == kMarchSmo)
+        v += omega * (cur.b - a * inv) / (diag * inv);
+      else if constexpr (Mode == kMarchResidual)
+        v = cur.b - a * inv;
+      else
+        v = a * inv;
     }
     if (valid) st_stream(v, eout + c);
     // every lane's reads of this row precede the next plane's writes
@@ -271,6 +283,20 @@ __global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T
     for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
     cur = nxt;
   }
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T* __restrict__ s,
+                                                const T* __restrict__ ein, T* __restrict__ eout, int kz) {
+  march_body<T, kMarchSmo>(L, omega, s, ein, eout, kz);
+}
+__global__ __launch_bounds__(256) void k_stencil_residual_z(StencilLevel L, const double* __restrict__ r,
+                                                            const double* __restrict__ x, double* __restrict__ s,
+                                                            int kz) {
+  march_body<double, kMarchResidual>(L, 0.0, r, x, s, kz);
+}
+__global__ __launch_bounds__(256) void k_stencil_apply_z(StencilLevel L, const double* __restrict__ x,
+                                                         double* __restrict__ y, int kz) {
+  march_body<double, kMarchApply>(L, 0.0, nullptr, x, y, kz);
 }
 
 // Diagonal of the assembled regular row (times 12 h^2), summed over the axes in
@@ -1219,7 +1245,7 @@ inline dim3 grid3(int n) { return dim3((n + 63) / 64, (n + 3) / 4, n); }
 inline dim3 grid_tiles(int n, int nb = 1) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n, nb); }
 const dim3 kBlock3(64, 4, 1);
 inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs); }
-// SMO-1 marches in z from this grid size on (below, too few tiles to fill the
+// The regular-row kernels march in z from this grid size on (below, too few tiles to fill the
 // chip); planes per workgroup: enough workgroups for the chip, at most 32
 constexpr int kSmoMarchMin = 96;
 inline int smo_march_planes(int n) {
@@ -1227,6 +1253,9 @@ inline int smo_march_planes(int n) {
   const long long want = 4096;   // workgroups
   int kz = (int)std::min<long long>(32, std::max<long long>(8, (long long)n * tiles / want));
   return kz;
+}
+inline dim3 march_grid(int n, int kz, int nb) {
+  return dim3(((n + 63) / 64) * ((n + 3) / 4) * ((n + kz - 1) / kz), nb);
 }
 inline long long cube(int n) { return (long long)n * n * n; }
 constexpr int kRedBlocks = 2048;   // blocks of the reductions (partial sums per block)
@@ -1241,8 +1270,7 @@ void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in,
     return;
   }
   const int kz = smo_march_planes(n);
-  const dim3 grid(((n + 63) / 64) * ((n + 3) / 4) * ((n + kz - 1) / kz), nb);
-  hipLaunchKernelGGL(k_smo1_z<T>, grid, kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
+  hipLaunchKernelGGL(k_smo1_z<T>, march_grid(n, kz, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
 }
 template <class T>
 void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st) {
@@ -1250,10 +1278,20 @@ void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out
 }
 void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, int nb,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n, nb), kBlock3, 0, st, L, r, x, s, 0);
+  if (L.n < kSmoMarchMin) {
+    hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n, nb), kBlock3, 0, st, L, r, x, s, 0);
+    return;
+  }
+  const int kz = smo_march_planes(L.n);
+  hipLaunchKernelGGL(k_stencil_residual_z, march_grid(L.n, kz, nb), kBlock3, 0, st, L, r, x, s, kz);
 }
 void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
+  if (L.n < kSmoMarchMin) {
+    hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
+    return;
+  }
+  const int kz = smo_march_planes(L.n);
+  hipLaunchKernelGGL(k_stencil_apply_z, march_grid(L.n, kz, 1), kBlock3, 0, st, L, x, y, kz);
 }
 void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only, int nb,
                          long long stride, hipStream_t st) {

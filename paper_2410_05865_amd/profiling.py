@@ -13,6 +13,10 @@ from collections import defaultdict
 
 import numpy as np
 
+# the SMO-1 kernel of the fine levels (z-marching) whose traffic and duration
+# the bench's roofline figure uses
+SMO_KERNEL = "k_smo1_z<double>"
+
 
 def _load(path: str, counter: str):
     con = sqlite3.connect(path)
@@ -47,8 +51,8 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
     cw, ncw, _ = by_kernel(wr, "k_copy")
     f_fac = 8.0 * n3 / (cf * 1024.0)
     w_fac = 8.0 * n3 / (cw * 1024.0)
-    sf, nsf, sgrid = by_kernel(fe, "k_smo1<double>")
-    sw, nsw, _ = by_kernel(wr, "k_smo1<double>")
+    sf, nsf, sgrid = by_kernel(fe, SMO_KERNEL)
+    sw, nsw, _ = by_kernel(wr, SMO_KERNEL)
     smo_bytes = sf * 1024.0 * f_fac + sw * 1024.0 * w_fac
     alg = 25.0 * n3
     # LU-correction sweeps: all k_lu_* dispatches, per correction (6 in the run)
@@ -56,17 +60,17 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
     lu_w = sum(v for _, k, _, v in wr if k.startswith("k_lu_"))
     n_lu = sum(1 for _, k, _, _ in fe if k.startswith("k_lu_forward"))
     lines = [
-        f"# HBM traffic of k_smo1 (SMO-1, FP64, level 0) and the level-0 LU-correction sweeps",
+        f"# HBM traffic of {SMO_KERNEL} (SMO-1, FP64, level 0) and the level-0 LU-correction sweeps",
         "",
         f"- grid: `{n}^3` (8-ellipsoid workload, seed 1)",
         f"- kernels.hip sha256[:16]: `{src_hash}`",
         f"- copy kernel (k_copy, {n3} doubles): FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per dispatch "
         f"({ncf}/{ncw} dispatches); true traffic {8 * n3 / 1024:.1f} KiB each way",
         f"- calibration factors: fetch x{f_fac:.4f}, write x{w_fac:.4f}",
-        f"- k_smo1<double>: FETCH_SIZE {sf:.1f} KiB, WRITE_SIZE {sw:.1f} KiB per dispatch ({nsf} dispatches, "
+        f"- {SMO_KERNEL}: FETCH_SIZE {sf:.1f} KiB, WRITE_SIZE {sw:.1f} KiB per dispatch ({nsf} dispatches, "
         f"grid {sgrid} work-items)",
-        f"- k_smo1 bytes per launch (calibrated): `{smo_bytes:.6e}`",
-        f"- k_smo1 algorithmic bytes per launch (25 B/cell): {alg:.6e}; measured/algorithmic = {smo_bytes / alg:.3f}",
+        f"- SMO-1 bytes per launch (calibrated): `{smo_bytes:.6e}`",
+        f"- SMO-1 algorithmic bytes per launch (25 B/cell): {alg:.6e}; measured/algorithmic = {smo_bytes / alg:.3f}",
         f"- LU sweeps: {n_lu} forward launches in the run (the build-time schedule trials included); FETCH "
         f"{lu_f:.1f} KiB, WRITE {lu_w:.1f} KiB over all k_lu_* dispatches (calibrated "
         f"{(lu_f * f_fac + lu_w * w_fac) * 1024:.6e} bytes)",
@@ -76,7 +80,7 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
 
 def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
     """Per-kernel totals from a rocprofv3 --kernel-trace database, plus the
-    average duration of the level-0 dispatches of k_smo1<double> (largest
+    average duration of the level-0 dispatches of the SMO-1 kernel (largest
     grid), which the bench's event timing of the same kernel should match."""
     con = sqlite3.connect(db)
     rows = con.execute("select name, start, end, grid_x, grid_y, grid_z from kernels").fetchall()
@@ -88,7 +92,7 @@ def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
         d = (en - st) / 1000.0
         tot[key][0] += 1
         tot[key][1] += d
-        if key == "k_smo1<double>":
+        if key == SMO_KERNEL:
             smo[(gx, gy, gz)].append(d)
     allt = sum(v[1] for v in tot.values())
     out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
@@ -98,12 +102,12 @@ def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
         g = max(smo, key=lambda k: k[0] * k[1] * k[2])
         v = smo[g]
         out.append("")
-        out.append(f"k_smo1<double> level-0 dispatches (grid {g[0]}x{g[1]}x{g[2]} work-items, {n}^3 cells): "
+        out.append(f"{SMO_KERNEL} level-0 dispatches (grid {g[0]}x{g[1]}x{g[2]} work-items, {n}^3 cells): "
                    f"{len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
     return "\n".join(out)
 
 
-def counters_summary(db: str, kernels=("k_smo1<double>", "k_copy")) -> str:
+def counters_summary(db: str, kernels=(SMO_KERNEL, "k_copy")) -> str:
     """Per-dispatch averages of every counter of a rocprofv3 --pmc database for
     the named kernels (largest grid of each: the level-0 launches)."""
     con = sqlite3.connect(db)
