@@ -1,0 +1,123 @@
+"""The stencil kernels at the full 256^3 ellipsoid workload, in the launch
+configuration the benchmark times (the z-marching kernels at level 0), checked
+through properties that hold at any size, on every cell far from the
+obstacles and the walls (the oracle cannot build a level of this size).
+
+On full-cell averages of a quartic the fourth-order regular row (Sec. 2.3) is
+exact.  So with the right-hand side set to the exact cell averages of the
+quartic's Laplacian, the operator returns them, the residual vanishes and SMO-1
+(Sec. 5.3) leaves the iterate unchanged; a perturbation d of the right-hand side
+moves SMO-1's result by omega d / D, with the regular diagonal
+D = -90 / (12 h^2).  Every input is a closed form; none comes from the library."""
+import numpy as np
+import pytest
+
+from paper_2410_05865_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 256
+# quartic terms (coefficient, (a, b, c)) of p = sum coef x^a y^b z^c
+QUARTIC = [(1.0, (4, 0, 0)), (-2.0, (2, 2, 0)), (1.0, (1, 1, 1)), (0.5, (0, 0, 3)), (1.0, (0, 2, 1)),
+           (0.7, (0, 0, 4)), (-0.3, (1, 0, 2)), (0.2, (0, 0, 0))]
+
+
+def _laplacian(terms):
+    out = []
+    for c, e in terms:
+        for d in range(3):
+            if e[d] >= 2:
+                f = list(e)
+                f[d] -= 2
+                out.append((c * e[d] * (e[d] - 1), tuple(f)))
+    return out
+
+
+def _cell_avg_1d(n, a):
+    """Averages of x^a over the cells [i h, (i + 1) h]: 3-point Gauss-Legendre,
+    exact for a <= 5."""
+    h = 1.0 / n
+    x0 = np.arange(n) * h
+    t = (0.5 - np.sqrt(0.15), 0.5, 0.5 + np.sqrt(0.15))
+    w = (5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0)
+    return sum(wk * (x0 + h * tk) ** a for wk, tk in zip(w, t))
+
+
+def _cell_avg(n, terms):
+    """n^3 array (x fastest) of the cell averages of sum coef x^a y^b z^c."""
+    out = np.zeros((n, n, n))
+    for c, (a, b, e) in terms:
+        out += c * (_cell_avg_1d(n, e)[:, None, None] * _cell_avg_1d(n, b)[None, :, None]
+                    * _cell_avg_1d(n, a)[None, None, :])
+    return out.reshape(-1)
+
+
+def _far_mask(dom, n, margin_cells=10, wall_cells=3):
+    """Cells at least margin_cells h from every obstacle (conservative: outside
+    the obstacle scaled by 1 + margin / smallest semi-axis about its centre) and
+    at least wall_cells from every wall."""
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    P = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
+    keep = np.ones(n ** 3, dtype=bool)
+    for ob in dom.obstacles:
+        y = (P - np.asarray(ob.center)) @ np.asarray(ob.rot)       # coordinates along the semi-axes
+        rho = np.sqrt(np.sum((y / np.asarray(ob.axes)) ** 2, axis=1))
+        keep &= (rho - 1.0) * float(np.min(ob.axes)) > margin_cells * h
+    ijk = np.arange(n)
+    inner = (ijk >= wall_cells) & (ijk <= n - 1 - wall_cells)
+    keep &= (inner[:, None, None] & inner[None, :, None] & inner[None, None, :]).reshape(-1)
+    return keep
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_05865_amd import _lib
+    _lib.load()
+    dom, _ = inputs.ellipsoid_workload(N, seed=1)
+    print(f"[fullsize] building the {N}^3 ellipsoid workload", flush=True)
+    P = _lib.Problem(dom)
+    e = _cell_avg(N, QUARTIC)
+    lap = _cell_avg(N, _laplacian(QUARTIC))
+    far = _far_mask(dom, N)
+    yield dom, P, e, lap, far
+    P.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_far_cells_cover_most_of_the_box(full):
+    dom, P, e, lap, far = full
+    assert far.mean() > 0.6
+
+
+def test_apply_and_residual_exact_on_quartics(full):
+    dom, P, e, lap, far = full
+    y = _dev(np.zeros(N ** 3))
+    P.apply(0, _dev(e), y)
+    scale = np.max(np.abs(lap[far]))
+    assert np.max(np.abs(y.cpu().numpy()[far] - lap[far])) < 1e-9 * scale
+    s = _dev(np.zeros(N ** 3))
+    P.residual(0, _dev(lap), _dev(e), s)
+    assert np.max(np.abs(s.cpu().numpy()[far])) < 1e-9 * scale
+
+
+def test_smo1_fixed_point_and_diagonal(full):
+    dom, P, e, lap, far = full
+    omega = P.params.omega
+    ed = _dev(e)
+    P.smo1(0, _dev(lap), ed)
+    got = ed.cpu().numpy()
+    assert np.max(np.abs(got[far] - e[far])) < 1e-12 * np.max(np.abs(e[far]))
+    d = np.random.default_rng(5).standard_normal(N ** 3)
+    ed = _dev(e)
+    P.smo1(0, _dev(lap + d), ed)
+    moved = ed.cpu().numpy()[far] - e[far]
+    want = omega * d[far] / (-90.0 * N * N / 12.0)
+    assert np.max(np.abs(moved - want)) < 1e-8 * np.max(np.abs(want))
