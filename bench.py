@@ -15,6 +15,7 @@ bounded sample (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
                     [--no-mixed] [--no-batch] [--no-fmg] [--no-table4] [--no-cpu-baseline]
+    python bench.py --large-mixed 512       # add FP64 and mixed solves of the same workload at 512^3
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
@@ -157,6 +158,42 @@ def _table4_leg(args, sec_plain_value=None):
     return out
 
 
+def _large_mixed_leg(args):
+    """The ellipsoid workload at a larger grid (512^3: 131M unknowns): FP64 and
+    mixed-precision solves to 1e-10 from the zero guess, and the max-norm
+    difference of the two solutions."""
+    import torch
+    from paper_2410_05865_amd import _lib, inputs as inp
+    n = args.large_mixed
+    dom, phi = inp.ellipsoid_workload(n, seed=args.seed)
+    t0 = time.perf_counter()
+    P = _lib.Problem(dom)
+    t_setup = time.perf_counter() - t0
+    r = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    P.assemble_rhs(phi, phi, r, f_mode=_lib.CC_LAPLACIAN)
+    x = torch.zeros_like(r)
+
+    def solve():
+        x.zero_()
+        return P.solve(r, x)
+    out = {"n": n, "unknowns": P.level_info(0)["n_unknowns"], "setup_s": t_setup}
+    sols = {}
+    for name, prec in (("fp64", _lib.CC_FP64), ("mixed", _lib.CC_MIXED)):
+        P.set_precision(prec)
+        sec, info = _timed(solve, args.steps, args.warmup)
+        sols[name] = x.clone()
+        out[name] = {"s_per_solve": sec, "v_cycles": info["iterations"], "final_rel_residual": info["rel_residual"]}
+        print(f"[bench] {n}^3 {name}: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
+    diff = float((sols["mixed"] - sols["fp64"]).abs().max())
+    out["mixed_speedup"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+    out["max_abs_diff_mixed_vs_fp64"] = diff
+    out["max_rel_diff_mixed_vs_fp64"] = diff / float(sols["fp64"].abs().max())
+    P.close()
+    del sols, r, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def _multi_leg(args):
     """16 geometries of the ellipsoid family (8 at 64^3, 8 at 128^3, seeds
     2000..2015), each with a Gaussian right-hand side, solved with GMRES(20)
@@ -259,6 +296,8 @@ def main():
     ap.add_argument("--no-fmg", action="store_true")
     ap.add_argument("--no-table4", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--large-mixed", type=int, default=0, metavar="N",
+                    help="also solve the ellipsoid workload at N^3 in FP64 and mixed precision (e.g. 512)")
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -447,6 +486,9 @@ def main():
         out_t4 = None
         if not args.no_table4:
             out_t4 = _table4_leg(args)
+        out_large = None
+        if args.large_mixed:
+            out_large = _large_mixed_leg(args)
         out_learned = None
         if not args.no_learned:
             out_learned = _learned_leg(P, dom, args, stream)
@@ -496,6 +538,7 @@ def main():
         "learned": out_learned,
         "multi_geometry": out_multi,
         "paper_table4_sphere": out_t4,
+        "mixed_large": out_large,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_smo1_z<double> (SMO-1 weighted Jacobi, level 0)",
