@@ -194,8 +194,12 @@ def _large_mixed_leg(args):
     return out
 
 
+MULTI_SIZES = (64, 96, 128, 160, 192)
+
+
 def _multi_leg(args):
-    """16 geometries of the ellipsoid family (8 at 64^3, 8 at 128^3, seeds
+    """16 geometries of the ellipsoid family of uneven sizes (64^3, 96^3,
+    128^3, 160^3, 192^3 in turn: four at 64^3, three at each other size; seeds
     2000..2015), each with a Gaussian right-hand side, solved with GMRES(20)
     one after the other and all at once (cc_solve_multi: one stream and host
     thread per problem)."""
@@ -204,7 +208,7 @@ def _multi_leg(args):
     t0 = time.perf_counter()
     probs, rs, phis, dofs = [], [], [], 0
     for i in range(16):
-        n = 64 if i < 8 else 128
+        n = MULTI_SIZES[i % len(MULTI_SIZES)]
         dom = inputs.ellipsoid_domain(n=n, seed=2000 + i)
         P = _lib.Problem(dom, krylov=args.krylov)
         r = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
@@ -235,7 +239,8 @@ def _multi_leg(args):
         P.close()
     print(f"[bench] 16 geometries: sequential {s_seq * 1e3:.0f} ms, concurrent {s_con * 1e3:.0f} ms", file=sys.stderr,
           flush=True)
-    return {"problems": "8 x 64^3 + 8 x 128^3 ellipsoid geometries (seeds 2000-2015), Gaussian right-hand sides, "
+    return {"problems": "16 ellipsoid geometries of 64^3-192^3 (4 x 64^3, 3 each of 96^3, 128^3, 160^3, 192^3; "
+                        "seeds 2000-2015), Gaussian right-hand sides, "
                         f"GMRES({args.krylov}) with the V-cycle",
             "unknowns": dofs, "setup_s": t_setup, "sequential_s": s_seq, "concurrent_s": s_con,
             "speedup": s_seq / s_con, "all_converged": all(i["converged"] for i in i_con),
