@@ -248,7 +248,16 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
   for (int d = -kHalo; d < kHalo; ++d) q[kHalo + d] = ein[col + min(max(k0 + d, 0), n - 1) * nn];
   MarchPlane<T> cur = load(k0);
   const T inv = T(L.inv12h2);
-  for (int k = k0; k < k1; ++k) {
+  // Planes in chunks of 8 with the steps unrolled: the register queue and the
+  // plane buffers then rotate by renaming, not by moves (a move out of a
+  // register whose load is in flight waits for that load).  The chunked form
+  // has a constant inner trip count, which the wavefront barriers require for
+  // unrolling; the guard is uniform over the workgroup.
+  for (int kc = k0; kc < k1; kc += 8) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+  const int k = kc + u;
+  if (k < k1) {
     q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
     const MarchPlane<T> nxt = load(min(k + 1, k1 - 1));
     const long c = col + k * nn;
@@ -282,6 +291,8 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
 #pragma unroll
     for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
     cur = nxt;
+  }
+  }
   }
 }
 template <class T>
