@@ -255,44 +255,44 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
   // unrolling; the guard is uniform over the workgroup.
   for (int kc = k0; kc < k1; kc += 8) {
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-  const int k = kc + u;
-  if (k < k1) {
-    q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
-    const MarchPlane<T> nxt = load(min(k + 1, k1 - 1));
-    const long c = col + k * nn;
-    row[w][kHalo + l] = q[kHalo];
-    if (l < 2 * kHalo) row[w][hl] = cur.h;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    T v = Mode == kMarchSmo ? q[kHalo] : T(0);
-    if (valid && cur.type == 1) {
-      T diag = T(0);
-      T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
-      a += axis_op_at<T>(
-          [&](int d) {
-            return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : cur.y[d < 0 ? d + 2 : d + 1];
-          },
-          j, n, L.bc[2], L.bc[3], diag);
-      a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
-      if constexpr (Mode == kMarchSmo)
-        v += omega * (cur.b - a * inv) / (diag * inv);
-      else if constexpr (Mode == kMarchResidual)
-        v = cur.b - a * inv;
-      else
-        v = a * inv;
-    }
-    if (valid) st_stream(v, eout + c);
-    // every lane's reads of this row precede the next plane's writes
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int u = 0; u < 8; ++u) {
+      const int k = kc + u;
+      if (k < k1) {
+        q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
+        const MarchPlane<T> nxt = load(min(k + 1, k1 - 1));
+        const long c = col + k * nn;
+        row[w][kHalo + l] = q[kHalo];
+        if (l < 2 * kHalo) row[w][hl] = cur.h;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        T v = Mode == kMarchSmo ? q[kHalo] : T(0);
+        if (valid && cur.type == 1) {
+          T diag = T(0);
+          T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
+          a += axis_op_at<T>(
+              [&](int d) {
+                return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : cur.y[d < 0 ? d + 2 : d + 1];
+              },
+              j, n, L.bc[2], L.bc[3], diag);
+          a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
+          if constexpr (Mode == kMarchSmo)
+            v += omega * (cur.b - a * inv) / (diag * inv);
+          else if constexpr (Mode == kMarchResidual)
+            v = cur.b - a * inv;
+          else
+            v = a * inv;
+        }
+        if (valid) st_stream(v, eout + c);
+        // every lane's reads of this row precede the next plane's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
-    cur = nxt;
-  }
-  }
+        for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
+        cur = nxt;
+      }
+    }
   }
 }
 template <class T>
