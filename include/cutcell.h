@@ -226,7 +226,8 @@ int cc_solve_batched(cc_problem* p, int nrhs, const double* r_dev, double* phi_d
  *   cc_restrict:   s_c = 2^-3 sum over children of (s - L e) on phi_1 children
  *   cc_prolong_add: e_f += e_c(parent) on phi_1 cells of level `level`
  *   cc_bottom_solve: e = L^(M)^-1 s on the coarsest level
- *   cc_vcycle:     e = VCycle(s) from level `level` down (e is overwritten) */
+ *   cc_vcycle:     e = VCycle(s) from level `level` down (e is overwritten)
+ * Each hook synchronises the problem's stream before it returns. */
 int cc_apply(cc_problem* p, int level, const double* x_dev, double* y_dev);
 int cc_residual(cc_problem* p, int level, const double* r_dev, const double* x_dev,
                 double* s_dev, double* maxabs);
