@@ -144,8 +144,9 @@ void cc_default_params(cc_params* p);
  * L22 on levels m < M and of L on level M, then the device upload.
  * Supported geometry: every obstacle's bounding sphere keeps the wall layer free
  * and meets no cell that another obstacle's bounding sphere meets, on every
- * level (else CC_EGEOM).  stream: hipStream_t or NULL.  *out owned by the caller
- * until cc_destroy. */
+ * level (else CC_EGEOM).  8 <= n <= 1290 (cell indices are 32-bit; else
+ * CC_EINVAL).  stream: hipStream_t or NULL.  *out owned by the caller until
+ * cc_destroy. */
 int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out);
 
 int cc_num_levels(const cc_problem* p);

@@ -1135,6 +1135,8 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (!dom || !prm || !out) fail(CC_EINVAL, "null argument");
     *out = nullptr;
     if (dom->n < 8) fail(CC_EINVAL, "n must be at least 8");
+    // cell indices are 32-bit (host arrays, FV-PLG column lists): n^3 < 2^31
+    if (dom->n > 1290) fail(CC_EINVAL, "n must be at most 1290 (32-bit cell indices)");
     if (std::fabs(dom->h * dom->n - 1.0) > 1e-12) fail(CC_EINVAL, "h must equal 1/n");
     if (dom->n_obst < 0 || (dom->n_obst > 0 && !dom->obst)) fail(CC_EINVAL, "bad obstacle list");
     if (!(prm->theta > 0 && prm->theta < 0.5)) fail(CC_EINVAL, "theta must lie in (0, 1/2)");

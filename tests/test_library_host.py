@@ -140,6 +140,10 @@ def test_errors_are_status_codes():
     with pytest.raises(L.CutCellError) as e:
         L.Problem(dom, device=-1, precision=7)
     assert e.value.code == L.CC_EINVAL
+    big = inputs.sphere_domain(n=1292, radius=0.25, n_min=8)     # n^3 beyond 32-bit cell indices
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(big, device=-1)
+    assert e.value.code == L.CC_EINVAL and "1290" in str(e.value)
     bad = _ell32(robin=True)
     bad.obstacles[0].robin = (0.0, 0.0)     # no condition at all
     with pytest.raises(L.CutCellError) as e:
