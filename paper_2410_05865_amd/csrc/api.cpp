@@ -1164,6 +1164,16 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         if (!(o.axes[a] > 0)) fail(CC_EINVAL, "semi-axes must be positive");
       }
       for (int a = 0; a < 9; ++a) ob.rot[a] = o.rot[a];
+      for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(ob.c[a])) fail(CC_EINVAL, "obstacle centre must be finite");
+      // rot's columns are the semi-axis directions: orthonormal (the bounding
+      // sphere of radius max(axes) holds only for a rotation)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double d = 0.0;
+          for (int i = 0; i < 3; ++i) d += ob.rot[3 * i + a] * ob.rot[3 * i + b];
+          if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-9)) fail(CC_EINVAL, "obstacle rot must be orthonormal");
+        }
       if (o.bc != CC_DIRICHLET && o.bc != CC_NEUMANN && o.bc != CC_ROBIN) fail(CC_EINVAL, "bad obstacle bc");
       ob.bc = o.bc;
       if (o.bc == CC_ROBIN) {

@@ -144,6 +144,11 @@ def test_errors_are_status_codes():
     with pytest.raises(L.CutCellError) as e:
         L.Problem(big, device=-1)
     assert e.value.code == L.CC_EINVAL and "1290" in str(e.value)
+    skew = _ell32()
+    skew.obstacles[0].rot = skew.obstacles[0].rot * 1.01   # not a rotation
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(skew, device=-1)
+    assert e.value.code == L.CC_EINVAL and "orthonormal" in str(e.value)
     bad = _ell32(robin=True)
     bad.obstacles[0].robin = (0.0, 0.0)     # no condition at all
     with pytest.raises(L.CutCellError) as e:
