@@ -24,9 +24,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// max that propagates NaN (fmax drops it): a norm of data holding a NaN is NaN,
+// so the callers' finiteness checks see it
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, kWave));
   return v;
 }
 
@@ -53,7 +57,7 @@ __device__ __forceinline__ double block_max(double v) {
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < nw; ++i) t = fmax(t, part[i]);
+    for (int i = 0; i < nw; ++i) t = nan_max(t, part[i]);
   return t;
 }
 
@@ -1032,13 +1036,13 @@ __global__ void k_maxabs(const double* __restrict__ v, long long count, double* 
   long long stride = (long long)gridDim.x * blockDim.x;
   v += (long long)blockIdx.y * count;
   double m = 0.0;
-  for (; i < count; i += stride) m = fmax(m, fabs(v[i]));
+  for (; i < count; i += stride) m = nan_max(m, fabs(v[i]));
   m = block_max(m);
   if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = m;
 }
 __global__ void k_max_finish(const double* __restrict__ partial, int g, unsigned long long* __restrict__ out) {
   double m = 0.0;
-  for (int i = threadIdx.x; i < g; i += blockDim.x) m = fmax(m, partial[(long long)blockIdx.x * g + i]);
+  for (int i = threadIdx.x; i < g; i += blockDim.x) m = nan_max(m, partial[(long long)blockIdx.x * g + i]);
   m = block_max(m);
   if (threadIdx.x == 0) out[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
 }
@@ -1205,7 +1209,7 @@ __global__ void __launch_bounds__(256) k_combo(long long n3, const double* __res
     const double sum = s0 + s1;
     const double o = mode == 1 ? prev + sum : (mode == 2 ? prev - sum : sum);
     if (out) out[c] = o;
-    m = fmax(m, fabs(o));
+    m = nan_max(m, fabs(o));
     q += o * o;
   }
   if (pmax) {
