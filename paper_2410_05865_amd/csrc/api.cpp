@@ -32,6 +32,14 @@ void set_last_error(const std::string& msg) { g_last_error = msg; }
     hipError_t _e = (expr);                                                                         \
     if (_e != hipSuccess) fail(CC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
   } while (0)
+// Synchronize a stream and report launch errors with it: a kernel launch that
+// fails (invalid configuration, no code object for the device) has no status
+// of its own and shows only in hipGetLastError.
+#define HIPSYNC(st)                      \
+  do {                                   \
+    HIPCHK(hipGetLastError());           \
+    HIPCHK(hipStreamSynchronize(st));    \
+  } while (0)
 
 namespace {
 
@@ -609,6 +617,7 @@ void upload(cc_problem* P) {
           HIPCHK(hipEventRecord(ev0, P->stream));
           for (int rep = 0; rep < 5; ++rep) lu_sweeps<double, double>(P->stream, L, L.d, P->dev[m].et, n3m, 1);
           HIPCHK(hipEventRecord(ev1, P->stream));
+          HIPCHK(hipGetLastError());
           HIPCHK(hipEventSynchronize(ev1));
           float t = 0.f;
           HIPCHK(hipEventElapsedTime(&t, ev0, ev1));
@@ -766,7 +775,7 @@ void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* co
 std::vector<double> read_norms(cc_problem* P, const unsigned long long* d, int nb) {
   std::vector<unsigned long long> bits(nb);
   HIPCHK(hipMemcpyAsync(bits.data(), d, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPSYNC(P->stream);
   std::vector<double> v(nb);
   for (int b = 0; b < nb; ++b) std::memcpy(&v[b], &bits[b], sizeof(double));
   return v;
@@ -851,7 +860,7 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
     done = update(false);
   }
   launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, phi, n3, nb, P->stream);
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPSYNC(P->stream);
 }
 
 // Restarted flexible GMRES(k), right-preconditioned by one V-cycle per
@@ -882,12 +891,12 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
     launch_dots_norm(n3, w, w, n3, 0, K.d, P->d_partial, st);
     double q = 0.0;
     HIPCHK(hipMemcpyAsync(&q, K.d, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPSYNC(st);
     return q;
   };
   auto put = [&](const std::vector<double>& c) {
     HIPCHK(hipMemcpyAsync(K.d, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPSYNC(st);
   };
   auto maxabs = [&](const double* v) {
     launch_zero_u64(P->d_norm, 1, st);
@@ -950,7 +959,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
         launch_dots_norm(n3, K.w, K.V, n3, j + 1, K.d, P->d_partial, st);
         std::vector<double> hw(j + 2);
         HIPCHK(hipMemcpyAsync(hw.data(), K.d, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPSYNC(st);
         h.assign(hw.begin(), hw.begin() + j + 1);
         return hw[j + 1];
       };
@@ -959,7 +968,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
         launch_combo(n3, K.V, n3, j + 1, K.d, K.w, 2, nullptr, K.d + k + 1, P->d_partial, st);
         double q = 0.0;
         HIPCHK(hipMemcpyAsync(&q, K.d + k + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPSYNC(st);
         return q;
       };
       std::vector<double> h, h2;
@@ -1002,7 +1011,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
         launch_combo(n3, K.V, n3, j + 1, K.d, nullptr, 0, K.amax, nullptr, P->d_partial, st);
         unsigned long long bits = 0;
         HIPCHK(hipMemcpyAsync(&bits, K.amax, sizeof(bits), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPSYNC(st);
         double res;
         std::memcpy(&res, &bits, sizeof(res));
         if (res < P->prm.tol * rn || hn == 0.0) {
@@ -1018,7 +1027,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
   }
   rec.iterations = cycles;
   launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, phi, n3, 1, st);
-  HIPCHK(hipStreamSynchronize(st));
+  HIPSYNC(st);
 }
 
 void fill_info(const SolveRec& rc, double seconds, cc_solve_info* info) {
@@ -1318,7 +1327,7 @@ int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mod
     launch_cell_average(n, h, L.origin, fd, f_mode, 8, r_dev, p->stream);
     std::vector<double> r(n3);
     HIPCHK(hipMemcpyAsync(r.data(), r_dev, n3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
     const double s12 = 1.0 / (12.0 * h * h);
     const double h3 = h * h * h;
     // per cut cell: integral of f over the cut region and the patch datum of g
@@ -1435,7 +1444,7 @@ int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mod
     }
     for (int rr = 0; rr < N2; ++rr) out[L.phi2[rr]] -= pcorr[rr];
     HIPCHK(hipMemcpyAsync(r_dev, out.data(), n3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1451,7 +1460,7 @@ int cc_apply(cc_problem* p, int level, const double* x, double* y) {
     DevLevel& D = p->dev[level];
     launch_stencil_apply(D.st, x, y, p->stream);
     launch_plg_residual(D.plg, nullptr, x, y, 1, 1, cube(D.st.n), p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1478,7 +1487,7 @@ int cc_smo1(cc_problem* p, int level, const double* s, double* e) {
     long long n3 = (long long)D.st.n * D.st.n * D.st.n;
     launch_smo1<double>(D.st, p->prm.omega, s, e, D.et, 1, p->stream);
     HIPCHK(hipMemcpyAsync(e, D.et, n3 * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1489,7 +1498,7 @@ int cc_smo2(cc_problem* p, int level, const double* s, double* e) {
     if (!s || !e) fail(CC_EINVAL, "null array");
     if (level == (int)p->lv.size() - 1) fail(CC_EINVAL, "the coarsest level has no LU-correction");
     smo2<double>(p, p->w64, level, s, e, 1);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1500,7 +1509,7 @@ int cc_restrict(cc_problem* p, int level, const double* s, const double* e, doub
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!s || !e || !sc) fail(CC_EINVAL, "null array");
     launch_restrict<double>(p->dev[level].st, p->dev[level + 1].st, s, e, sc, 1, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1511,7 +1520,7 @@ int cc_prolong_add(cc_problem* p, int level, const double* ec, double* ef) {
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!ec || !ef) fail(CC_EINVAL, "null array");
     launch_prolong_add<double>(p->dev[level].st, p->dev[level + 1].st.n, ec, ef, 1, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1524,7 +1533,7 @@ int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, doub
       for (size_t m = 1; m < p->dev.size(); ++m)
         if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
     fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1544,7 +1553,7 @@ int cc_fmg_batched(cc_problem* p, int nrhs, const double* r, const double* const
       const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
       fmg(p, p->wb64, r + b0 * n3, coarse_rhs, b0, phi + b0 * n3, cycles, nb);
     }
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1555,7 +1564,7 @@ int cc_fmg_restrict(cc_problem* p, int level, const double* s, double* sc) {
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!s || !sc) fail(CC_EINVAL, "null array");
     launch_fmg_restrict(p->dev[level].st, p->dev[level + 1].st, s, sc, 1, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1566,7 +1575,7 @@ int cc_fmg_prolong(cc_problem* p, int level, const double* xc, double* xf) {
     if (level + 1 >= (int)p->lv.size()) fail(CC_EINVAL, "no coarser level");
     if (!xc || !xf) fail(CC_EINVAL, "null array");
     launch_fmg_prolong(p->dev[level].st, p->dev[level + 1].st, xc, xf, 1, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1575,7 +1584,7 @@ int cc_bottom_solve(cc_problem* p, const double* s, double* e) {
     if (!p || !s || !e) fail(CC_EINVAL, "null argument");
     need_device(p);
     bottom<double>(p, p->w64, s, e, 1);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1585,7 +1594,7 @@ int cc_vcycle(cc_problem* p, int level, const double* s, double* e) {
     need_device(p);
     if (!s || !e) fail(CC_EINVAL, "null array");
     vcycle<double>(p, p->w64, level, s, e, p->dev[level].et, 1);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1642,11 +1651,11 @@ int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, co
     const double rn = read_norm(p);
     const double inv = rn > 0 ? 1.0 / rn : 0.0;
     launch_net_features(n0, m, r, inv, p->volfrac[level], p->net_x, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
     int rc = cc_net_forward(net, m, 1, p->net_x, p->net_y);
     if (rc != CC_OK) fail(rc, cc_last_error());
     launch_prolong_trilinear(p->dev[0].st, m, p->net_y, rn / phi_scale, phi, p->stream);
-    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPSYNC(p->stream);
   });
 }
 
@@ -1713,7 +1722,7 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     if (subtree != 0 && subtree != 1) fail(CC_EINVAL, "subtree must be 0 or 1");
     if (waves_cap != 0 && waves_cap < 4) fail(CC_EINVAL, "waves_cap must be 0 or at least 4");
     HIPCHK(hipSetDevice(p->device));
-    HIPCHK(hipStreamSynchronize(p->stream));  // no launch in flight reads the old task lists
+    HIPSYNC(p->stream);  // no launch in flight reads the old task lists
     DevLevel& D = p->dev[level];
     DevBuf nb;
     DevLU L = D.lu;
@@ -1860,6 +1869,7 @@ int cc_time_kernel(cc_problem* p, int which, int reps, double* ms, double* bytes
     HIPCHK(hipEventRecord(a, p->stream));
     for (int i = 0; i < reps; ++i) launch();
     HIPCHK(hipEventRecord(b, p->stream));
+    HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(b));
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, a, b));
