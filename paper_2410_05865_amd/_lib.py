@@ -258,6 +258,12 @@ class Problem:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     # -------------------------------------------------------------- info
     @property
     def num_levels(self) -> int:
@@ -478,6 +484,12 @@ class Net:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     @property
     def num_params(self) -> int:

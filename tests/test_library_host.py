@@ -154,6 +154,9 @@ def test_errors_are_status_codes():
     with pytest.raises(L.CutCellError) as e:
         L.Problem(bad, device=-1)
     assert e.value.code == L.CC_EINVAL
+    with L.Problem(dom, device=-1) as Q:          # the handle is released on leaving the block
+        assert Q.num_levels >= 2
+    assert Q._h is None
     P = L.Problem(dom, device=-1)
     with pytest.raises(L.CutCellError) as e:
         P.level_info(5)
