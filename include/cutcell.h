@@ -85,6 +85,9 @@ typedef struct cc_params {
                          flexible GMRES(k) in FP64 preconditioned by one V-cycle per
                          iteration (an FP32 V-cycle with CC_MIXED); converges also
                          where the plain iteration does not contract */
+  double pivot_tol;   /* factorizations (Sec. 5.3 LU-correction and bottom solve): a pivot
+                         below pivot_tol times the largest entry of the factored matrix is
+                         CC_ESINGULAR; default 1e-14, must lie in (0, 1e6] */
 } cc_params;
 
 /* Analytic fields (problem data).  data layout by kind:

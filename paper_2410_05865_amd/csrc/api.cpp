@@ -817,8 +817,12 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
   launch_zero_u64(W.norm, nb, P->stream);
   launch_maxabs(r, n3, nb, W.norm, P->d_partial, P->stream);
   std::vector<double> rn = read_norms(P, W.norm, nb);
-  for (int b = 0; b < nb; ++b)
+  for (int b = 0; b < nb; ++b) {
     if (!std::isfinite(rn[b])) fail(CC_EINVAL, "non-finite right-hand side");
+    // L is nonsingular: r = 0 has the solution 0, whatever the guess (the relative
+    // stopping test is undefined there)
+    if (rn[b] == 0.0) launch_zero<double>(phi + (long long)b * n3, n3, P->stream);
+  }
   launch_mask_unknowns(D0.st, phi, nb, P->stream);
   residual(P, 0, r, phi, W.s0, nb);
   launch_zero_u64(W.norm, nb, P->stream);
@@ -905,6 +909,7 @@ void gmres_loop(cc_problem* P, const double* r, double* phi, SolveRec& rec) {
   };
   const double rn = maxabs(r);
   if (!std::isfinite(rn)) fail(CC_EINVAL, "non-finite right-hand side");
+  if (rn == 0.0) launch_zero<double>(phi, n3, st);  // r = 0: the solution is 0
   launch_mask_unknowns(D0.st, phi, 1, st);
   const double nunk = (double)P->lv[0]->unknowns.size();
   rec = SolveRec{};
@@ -1137,6 +1142,7 @@ void cc_default_params(cc_params* p) {
   p->device = 0;
   p->use_graph = 1;
   p->krylov = 0;
+  p->pivot_tol = 1e-14;
 }
 
 int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out) {
@@ -1154,6 +1160,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
       fail(CC_EINVAL, "bad multigrid parameters");
     if (prm->precision != CC_FP64 && prm->precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
     if (prm->krylov < 0 || prm->krylov > 64) fail(CC_EINVAL, "krylov must lie in [0, 64]");
+    if (!(prm->pivot_tol > 0 && prm->pivot_tol <= 1e6)) fail(CC_EINVAL, "pivot_tol must lie in (0, 1e6]");
     for (int a = 0; a < 6; ++a)
       if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
     auto P = std::make_unique<cc_problem>();
@@ -1221,7 +1228,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
       std::vector<std::array<int, 3>> xyz;
       std::vector<int> orig;
       build_lu_matrix(*P->lv[m], m == M, P->lu_mat[m], xyz, orig);
-      factorize(P->lu_mat[m], xyz, prm->leaf_size, P->lu[m]);
+      factorize(P->lu_mat[m], xyz, prm->leaf_size, prm->pivot_tol, P->lu[m]);
       P->setup_s[m] = now_s() - t0;
     }
     if (P->device >= 0) {

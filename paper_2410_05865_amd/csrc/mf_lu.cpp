@@ -246,7 +246,8 @@ void front_lu(std::vector<double>& A, int f, int p, std::vector<int>& rowperm, d
 
 }  // namespace
 
-void factorize(const CSR& A, const std::vector<std::array<int, 3>>& coords, int leaf, SupernodalLU& out) {
+void factorize(const CSR& A, const std::vector<std::array<int, 3>>& coords, int leaf, double pivot_tol,
+               SupernodalLU& out) {
   const int n = A.n;
   out = SupernodalLU();
   out.n = n;
@@ -405,7 +406,7 @@ void factorize(const CSR& A, const std::vector<std::array<int, 3>>& coords, int 
         fill[c]++;
       }
   }
-  const double tiny = 1e-14 * amax;
+  const double tiny = pivot_tol * amax;
   std::vector<std::vector<double>> schur(ns);
   // numeric factorisation, by height (nodes of one height are independent)
   std::vector<std::vector<int>> by_h(out.max_height + 1);

@@ -45,8 +45,8 @@ struct SupernodalLU {
 
 // Factor A (n x n CSR) with vertex coordinates coords (grid indices) for the
 // bisection; leaves hold at most `leaf` vertices.  Throws cc::Error(CC_ESINGULAR)
-// if a pivot falls below 1e-14 times the largest entry of A.
-void factorize(const CSR& A, const std::vector<std::array<int, 3>>& coords, int leaf,
+// if a pivot falls below pivot_tol times the largest entry of A.
+void factorize(const CSR& A, const std::vector<std::array<int, 3>>& coords, int leaf, double pivot_tol,
                SupernodalLU& out);
 
 // Host check of a factorization: solves A x = b with the stored factors (the

@@ -37,10 +37,25 @@ def test_zero_rhs_converges_at_once(prob, mode):
     assert float(x.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "krylov"])
+def test_zero_rhs_from_a_nonzero_guess_returns_zero(prob, mode):
+    """L phi = 0 has the solution 0 (L is nonsingular); the relative stopping
+    test is undefined there, so the guess must not be returned unchanged."""
+    L, P, r = prob
+    P.set_precision(L.CC_MIXED if mode == "mixed" else L.CC_FP64)
+    P.set_krylov(20 if mode == "krylov" else 0)
+    x = torch.randn(r.shape, dtype=torch.float64, device="cuda")
+    info = P.solve(torch.zeros_like(r), x)
+    P.set_precision(L.CC_FP64)
+    P.set_krylov(0)
+    assert info["converged"] and info["iterations"] == 0
+    assert float(x.abs().max()) == 0.0
+
+
 def test_zero_member_of_a_batch(prob):
     L, P, r = prob
     rb = torch.stack([r, torch.zeros_like(r), 2.0 * r]).contiguous()
-    xb = torch.zeros_like(rb)
+    xb = torch.randn(rb.shape, dtype=torch.float64, device="cuda")
     infos = P.solve_batched(rb, xb)
     assert all(i["converged"] for i in infos)
     assert float(xb[1].abs().max()) == 0.0

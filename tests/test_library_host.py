@@ -168,6 +168,40 @@ def test_errors_are_status_codes():
     P.close()
 
 
+def test_geometry_plg_and_pivot_failures_are_status_codes():
+    """The three failure classes of the set-up, each forced from the host:
+    an obstacle in the wall layer and two obstacles in one cell (CC_EGEOM), a
+    domain too small for any poised lattice (CC_EPLG; the oracle fails on the
+    same domain), and a pivot threshold no pivot can meet (CC_ESINGULAR)."""
+    from oracle.discretize import Level, PLGError
+    L = _lib()
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(inputs.sphere_domain(n=16, radius=0.45, n_min=8), device=-1)
+    assert e.value.code == L.CC_EGEOM and "wall layer" in str(e.value)
+    two = inputs.sphere_domain(n=16, radius=0.2, n_min=8)
+    two.obstacles.append(inputs.Obstacle(np.array([0.5, 0.5, 0.78]), np.full(3, 0.05), np.eye(3), inputs.DIRICHLET))
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(two, device=-1)
+    assert e.value.code == L.CC_EGEOM and "two obstacles" in str(e.value)
+    ball = inputs.Obstacle(np.array([0.5, 0.5, 0.5]), np.full(3, 0.2), np.eye(3), inputs.DIRICHLET)
+    tiny = inputs.Domain(n=8, obstacles=[ball], n_min=8, inside=True)    # ~30 cells, fewer than a lattice's 35
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(tiny, device=-1)
+    assert e.value.code == L.CC_EPLG and "poised lattice" in str(e.value)
+    with pytest.raises(PLGError):
+        Level(tiny, 8)
+    dom = inputs.sphere_domain(n=16, radius=0.25, n_min=8)
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(dom, device=-1, pivot_tol=10.0)
+    assert e.value.code == L.CC_ESINGULAR and "pivot" in str(e.value)
+    for bad in (0.0, -1.0, 1e7, float("nan")):
+        with pytest.raises(L.CutCellError) as e:
+            L.Problem(dom, device=-1, pivot_tol=bad)
+        assert e.value.code == L.CC_EINVAL
+    with L.Problem(dom, device=-1, pivot_tol=1e-12) as Q:      # a stricter but attainable threshold
+        assert Q.selfcheck_lu(0) < 1e-12
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """No fallback: without the built library every entry point raises."""
     from paper_2410_05865_amd import _lib
