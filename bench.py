@@ -15,7 +15,7 @@ bounded sample (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
                     [--no-mixed] [--no-batch] [--no-fmg] [--no-table4] [--no-cpu-baseline]
-    python bench.py --large-mixed 512       # add FP64 and mixed solves of the same workload at 512^3
+    python bench.py --large-mixed 0         # skip the FP64 and mixed solves of the same workload at 512^3
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
@@ -301,8 +301,8 @@ def main():
     ap.add_argument("--no-fmg", action="store_true")
     ap.add_argument("--no-table4", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
-    ap.add_argument("--large-mixed", type=int, default=0, metavar="N",
-                    help="also solve the ellipsoid workload at N^3 in FP64 and mixed precision (e.g. 512)")
+    ap.add_argument("--large-mixed", type=int, default=512, metavar="N",
+                    help="also solve the ellipsoid workload at N^3 in FP64 and mixed precision (0: skip)")
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=1200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -361,6 +361,11 @@ def main():
 
         sec, info = _timed(solve_once, args.steps, args.warmup)
         print(f"[bench] plain FP64: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
+        x64 = x.clone()          # the FP64 solution every other leg of this workload is compared with
+
+        def vs_fp64(y):
+            d = float((y - x64).abs().max())
+            return {"max_abs_diff_vs_fp64": d, "max_rel_diff_vs_fp64": d / float(x64.abs().max())}
         out_mixed = None
         if not args.no_mixed:
             P.set_precision(_lib.CC_MIXED)
@@ -368,7 +373,8 @@ def main():
             P.set_precision(_lib.CC_FP64)
             print(f"[bench] mixed: {sec_m * 1e3:.1f} ms, {info_m['iterations']} V-cycles", file=sys.stderr, flush=True)
             out_mixed = {"s_per_solve": sec_m, "v_cycles": info_m["iterations"],
-                         "final_rel_residual": info_m["rel_residual"], "speedup_vs_plain": sec / sec_m}
+                         "final_rel_residual": info_m["rel_residual"], "speedup_vs_plain": sec / sec_m,
+                         **vs_fp64(x)}
         out_krylov = None
         if not args.no_krylov:
             P.set_krylov(args.krylov)
@@ -388,7 +394,8 @@ def main():
                       f"{info_km['iterations']} V-cycles", file=sys.stderr, flush=True)
                 out_krylov["mixed_preconditioner"] = {
                     "s_per_solve": sec_km, "v_cycles": info_km["iterations"],
-                    "final_rel_residual": info_km["rel_residual"], "speedup_vs_plain": sec / sec_km}
+                    "final_rel_residual": info_km["rel_residual"], "speedup_vs_plain": sec / sec_km,
+                    **vs_fp64(x)}
         out_fmg = None
         if not args.no_fmg:
             # full multigrid first (FP64, c V-cycles per level), then the solve from its result
@@ -427,7 +434,7 @@ def main():
                       f"{info_fg['iterations']} V-cycles after FMG", file=sys.stderr, flush=True)
                 out_fmg["then_gmres_fp32_vcycle"] = {"s_per_solve": sec_fg, "v_cycles_after_fmg": info_fg["iterations"],
                                                      "final_rel_residual": info_fg["rel_residual"],
-                                                     "speedup_vs_plain": sec / sec_fg}
+                                                     "speedup_vs_plain": sec / sec_fg, **vs_fp64(x)}
         out_batch = None
         if not args.no_batch and args.batch > 0:
             B = args.batch
@@ -450,6 +457,7 @@ def main():
                     del bm
             xb = torch.zeros_like(rb)
             res = {}
+            xb64 = None
             for prec, name in ((_lib.CC_FP64, "fp64"), (_lib.CC_MIXED, "mixed")):
                 if name == "mixed" and args.no_mixed:
                     continue
@@ -464,6 +472,11 @@ def main():
                              "v_cycles": max(i["iterations"] for i in infos),
                              "max_final_rel_residual": max(i["rel_residual"] for i in infos),
                              "speedup_per_rhs_vs_plain": sec / (sb / B)}
+                if name == "fp64":
+                    xb64 = xb.clone()
+                else:   # every member against its FP64 solution (max over members of the relative max-norm)
+                    dm = (xb - xb64).abs().amax(dim=1) / xb64.abs().amax(dim=1)
+                    res[name]["max_rel_diff_vs_fp64"] = float(dm.max())
                 print(f"[bench] batched {name}: {sb * 1e3:.0f} ms for {B} rhs", file=sys.stderr, flush=True)
                 if coarse_b:
                     def fmg_batch():
@@ -483,7 +496,7 @@ def main():
             out_batch = {"rhs": B, "rhs_recipe": f"{B} seeded mixtures of {args.batch_base} assembled right-hand "
                                                   f"sides, each f = sum of 16 seeded Gaussians (sigma U[0.02, 0.1]), "
                                                   f"g = 0", **res}
-            del rb, xb, coarse_b
+            del rb, xb, xb64, coarse_b
             torch.cuda.empty_cache()
         out_multi = None
         if not args.no_multi:
@@ -503,8 +516,13 @@ def main():
         ms_copy, by_copy = P.time_kernel(_lib.CC_TIME_COPY, args.smoother_reps)
         torch.cuda.synchronize()
 
-    achieved = by_smo / (ms_smo * 1e-3) / 1e9
     N = li0["n_unknowns"]
+    n_phi1 = N - li0["n_phi2"]
+    # algorithmic bytes of one SMO-1 sweep: read e and r, write e' for every phi_1 cell
+    # (24 B per phi_1 cell); the kernel also passes the other cells through and
+    # reads the cell type: 25 B per cell of the n^3 grid (by_smo)
+    alg_smo = 24.0 * n_phi1
+    achieved = alg_smo / (ms_smo * 1e-3) / 1e9
     cycles = info["iterations"]
     out = {
         "metric": "time to 1e-10 rel. residual at 256^3 (plain vs mixed/learned) + smoother HBM GB/s",
@@ -553,7 +571,10 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _traffic(args.n),
             "ms_per_launch": ms_smo,
-            "bytes_per_launch": by_smo,
+            "bytes_per_launch": alg_smo,
+            "bytes_per_launch_basis": f"24 B per phi_1 cell x {n_phi1} phi_1 cells (read e, r; write e')",
+            "kernel_bytes_all_cells": by_smo,
+            "kernel_achieved_all_cells_GBs": by_smo / (ms_smo * 1e-3) / 1e9,
         },
         "roofline_other": {
             "k_smo1_z<float>": {"achieved_GBs": by_smo32 / (ms_smo32 * 1e-3) / 1e9, "ms_per_launch": ms_smo32,

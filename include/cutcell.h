@@ -207,6 +207,18 @@ int cc_set_krylov(cc_problem* p, int krylov);
  * Errors: CC_EINVAL for a bad level or value. */
 int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtree, int waves_cap);
 
+/* Replace the build-time schedule of the regular-row kernels (SMO-1, the
+ * outer residual and the operator apply of Sec. 5.3, evaluated on the fly from
+ * the cell types) on `level` (-1: every level): march = 1 runs the z-marching
+ * kernels (a workgroup takes a 64 x 4 column tile through `planes` consecutive
+ * z-planes; 0: the build's count for the level's size, else 1..n), march = 0 one
+ * cell per thread, march = -1 the build's choice (marching from 96^3 on).  The
+ * result does not depend on the schedule (same arithmetic order).  Waits for
+ * the problem's stream and drops captured iterations.  Errors: CC_EINVAL. */
+int cc_set_stencil_schedule(cc_problem* p, int level, int march, int planes);
+/* The schedule in force on `level`: *march (0 or 1) and *planes. */
+int cc_get_stencil_schedule(const cc_problem* p, int level, int* march, int* planes);
+
 /* Several right-hand sides on one geometry (with krylov > 0 they are solved one
  * after the other): r_dev and phi_dev hold nrhs arrays of
  * n^3 at a stride of n^3 (batch-major).  Groups of up to CC_BATCH_MAX

@@ -32,7 +32,7 @@ EXPORTED = [
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
-    "cc_fmg_batched",
+    "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -115,6 +115,8 @@ def load() -> C.CDLL:
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
     lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
+    lib.cc_set_stencil_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    lib.cc_get_stencil_schedule.argtypes = [vp, C.c_int, P(C.c_int), P(C.c_int)]
     lib.cc_fmg.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.cc_fmg_batched.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int]
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
@@ -337,6 +339,17 @@ class Problem:
     def set_lu_schedule(self, level: int, entries_per_lane: int, subtree: int = 0, waves_cap: int = 0):
         """Override the build-time sweep schedule of one level's factorization."""
         _check(load().cc_set_lu_schedule(self._h, level, entries_per_lane, subtree, waves_cap))
+
+    def set_stencil_schedule(self, level: int = -1, march: int = -1, planes: int = 0):
+        """Override the regular-row kernel schedule (z-marching or one cell per
+        thread, planes per workgroup) of one level (-1: all)."""
+        _check(load().cc_set_stencil_schedule(self._h, level, march, planes))
+
+    def stencil_schedule(self, level: int):
+        """(march, planes) in force on `level`."""
+        m, k = C.c_int(), C.c_int()
+        _check(load().cc_get_stencil_schedule(self._h, level, C.byref(m), C.byref(k)))
+        return m.value, k.value
 
     def solve(self, r, phi) -> dict:
         self._order()

@@ -541,6 +541,7 @@ void upload(cc_problem* P) {
     D.st.inv12h2 = 1.0 / (12.0 * L.h * L.h);
     for (int a = 0; a < 6; ++a) D.st.bc[a] = L.wall_bc[a];
     D.st.type = B.upload(L.type);
+    default_stencil_schedule(L.n, D.st.march, D.st.kz);
     const int N2 = (int)L.phi2.size();
     std::vector<int> cols((size_t)N2 * kPLG);
     std::vector<double> vals((size_t)N2 * kPLG);
@@ -732,33 +733,23 @@ void residual(cc_problem* P, int m, const double* r, const double* x, double* s,
 // level-0 result; merged cells take their host's value.  nb right-hand sides
 // at a stride of n_m^3 (W sized for nb); the coarse right-hand sides of the
 // group start coarse_off arrays into coarse_rhs[m - 1].
+// crhs[m], cx[m] (m = 1..M, nb * n_m^3 doubles each): the coarse levels'
+// right-hand side (used only without coarse_rhs) and solution arrays; every
+// cell of each is written before it is read.
 void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* const* coarse_rhs, long long coarse_off,
-         double* phi, int cycles, int nb) {
+         double* phi, int cycles, int nb, const std::vector<double*>& crhs, const std::vector<double*>& cx) {
   const int M = (int)P->dev.size() - 1;
-  if ((int)P->fmg_rhs.size() != M + 1 || P->fmg_nb < nb) {
-    for (int m = 1; m < (int)P->fmg_rhs.size(); ++m) {
-      P->buf.free(P->fmg_rhs[m]);
-      P->buf.free(P->fmg_x[m]);
-    }
-    P->fmg_rhs.assign(M + 1, nullptr);
-    P->fmg_x.assign(M + 1, nullptr);
-    for (int m = 1; m <= M; ++m) {
-      P->fmg_rhs[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
-      P->fmg_x[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
-    }
-    P->fmg_nb = nb;
-  }
   std::vector<const double*> rhs(M + 1);
   std::vector<double*> x(M + 1);
   rhs[0] = r;
   x[0] = phi;
   for (int m = 1; m <= M; ++m) {
-    rhs[m] = coarse_rhs ? coarse_rhs[m - 1] + coarse_off * cube(P->dev[m].st.n) : P->fmg_rhs[m];
-    x[m] = P->fmg_x[m];
+    rhs[m] = coarse_rhs ? coarse_rhs[m - 1] + coarse_off * cube(P->dev[m].st.n) : crhs[m];
+    x[m] = cx[m];
   }
   if (!coarse_rhs)
     for (int m = 0; m < M; ++m)
-      launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], P->fmg_rhs[m + 1], nb, P->stream);
+      launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], crhs[m + 1], nb, P->stream);
   bottom<double>(P, W, rhs[M], x[M], nb);
   for (int m = M - 1; m >= 0; --m) {
     DevLevel& D = P->dev[m];
@@ -770,6 +761,24 @@ void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* co
     }
   }
   launch_copy_pairs<double>(P->dev[0].n_absorbed, P->dev[0].absorbed, phi, cube(P->dev[0].st.n), nb, P->stream);
+}
+
+// The coarse arrays of cc_fmg / cc_fmg_batched: allocated by the handle at the
+// first call (and grown for a larger group), kept until cc_destroy.
+void fmg_alloc(cc_problem* P, int nb) {
+  const int M = (int)P->dev.size() - 1;
+  if ((int)P->fmg_rhs.size() == M + 1 && P->fmg_nb >= nb) return;
+  for (int m = 1; m < (int)P->fmg_rhs.size(); ++m) {
+    P->buf.free(P->fmg_rhs[m]);
+    P->buf.free(P->fmg_x[m]);
+  }
+  P->fmg_rhs.assign(M + 1, nullptr);
+  P->fmg_x.assign(M + 1, nullptr);
+  for (int m = 1; m <= M; ++m) {
+    P->fmg_rhs[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
+    P->fmg_x[m] = P->buf.alloc<double>((size_t)cube(P->dev[m].st.n) * nb);
+  }
+  P->fmg_nb = nb;
 }
 
 std::vector<double> read_norms(cc_problem* P, const unsigned long long* d, int nb) {
@@ -1539,7 +1548,8 @@ int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, doub
     if (coarse_rhs)
       for (size_t m = 1; m < p->dev.size(); ++m)
         if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
-    fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1);
+    fmg_alloc(p, 1);
+    fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1, p->fmg_rhs, p->fmg_x);
     HIPSYNC(p->stream);
   });
 }
@@ -1555,10 +1565,11 @@ int cc_fmg_batched(cc_problem* p, int nrhs, const double* r, const double* const
         if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
     const int cap = std::min(nrhs, CC_BATCH_MAX);
     if (p->wb64.nb < cap) alloc_work(p, p->wb64, cap);
+    fmg_alloc(p, cap);
     const long long n3 = cube(p->dev[0].st.n);
     for (int b0 = 0; b0 < nrhs; b0 += CC_BATCH_MAX) {
       const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
-      fmg(p, p->wb64, r + b0 * n3, coarse_rhs, b0, phi + b0 * n3, cycles, nb);
+      fmg(p, p->wb64, r + b0 * n3, coarse_rhs, b0, phi + b0 * n3, cycles, nb, p->fmg_rhs, p->fmg_x);
     }
     HIPSYNC(p->stream);
   });
@@ -1750,6 +1761,42 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     p->w32.drop_graph();
     p->wb64.drop_graph();
     p->wb32.drop_graph();
+  });
+}
+
+int cc_set_stencil_schedule(cc_problem* p, int level, int march, int planes) {
+  return guard([&] {
+    if (!p) fail(CC_EINVAL, "null problem");
+    need_device(p);
+    const int nl = (int)p->dev.size();
+    if (level < -1 || level >= nl) fail(CC_EINVAL, "bad level");
+    if (march < -1 || march > 1) fail(CC_EINVAL, "march must be -1, 0 or 1");
+    for (int m = (level < 0 ? 0 : level); m < (level < 0 ? nl : level + 1); ++m)
+      if (planes < 0 || planes > p->dev[m].st.n) fail(CC_EINVAL, "planes must lie in [0, n] of the level");
+    HIPCHK(hipSetDevice(p->device));
+    HIPSYNC(p->stream);
+    for (int m = (level < 0 ? 0 : level); m < (level < 0 ? nl : level + 1); ++m) {
+      StencilLevel& S = p->dev[m].st;
+      int dm = 0, dk = 0;
+      default_stencil_schedule(S.n, dm, dk);
+      S.march = march < 0 ? dm : march;
+      S.kz = planes == 0 ? dk : planes;
+    }
+    // captured iterations hold the old launch shapes
+    p->w64.drop_graph();
+    p->w32.drop_graph();
+    p->wb64.drop_graph();
+    p->wb32.drop_graph();
+  });
+}
+
+int cc_get_stencil_schedule(const cc_problem* p, int level, int* march, int* planes) {
+  return guard([&] {
+    if (!p || !march || !planes) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    if (level < 0 || level >= (int)p->dev.size()) fail(CC_EINVAL, "bad level");
+    *march = p->dev[level].st.march;
+    *planes = p->dev[level].st.kz;
   });
 }
 

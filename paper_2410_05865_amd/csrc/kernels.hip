@@ -1269,6 +1269,14 @@ inline int smo_march_planes(int n) {
   int kz = (int)std::min<long long>(32, std::max<long long>(8, (long long)n * tiles / want));
   return kz;
 }
+}  // namespace
+
+void default_stencil_schedule(int n, int& march, int& kz) {
+  march = n >= kSmoMarchMin ? 1 : 0;
+  kz = smo_march_planes(n);
+}
+
+namespace {
 inline dim3 march_grid(int n, int kz, int nb) {
   return dim3(((n + 63) / 64) * ((n + 3) / 4) * ((n + kz - 1) / kz), nb);
 }
@@ -1280,11 +1288,11 @@ constexpr int kRedBlocks = 2048;   // blocks of the reductions (partial sums per
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st) {
   const int n = L.n;
-  if (n < kSmoMarchMin) {
+  if (!L.march) {
     hipLaunchKernelGGL(k_smo1<T>, grid_tiles(n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
     return;
   }
-  const int kz = smo_march_planes(n);
+  const int kz = L.kz;
   hipLaunchKernelGGL(k_smo1_z<T>, march_grid(n, kz, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
 }
 template <class T>
@@ -1293,19 +1301,19 @@ void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out
 }
 void launch_stencil_residual(const StencilLevel& L, const double* r, const double* x, double* s, int nb,
                              hipStream_t st) {
-  if (L.n < kSmoMarchMin) {
+  if (!L.march) {
     hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n, nb), kBlock3, 0, st, L, r, x, s, 0);
     return;
   }
-  const int kz = smo_march_planes(L.n);
+  const int kz = L.kz;
   hipLaunchKernelGGL(k_stencil_residual_z, march_grid(L.n, kz, nb), kBlock3, 0, st, L, r, x, s, kz);
 }
 void launch_stencil_apply(const StencilLevel& L, const double* x, double* y, hipStream_t st) {
-  if (L.n < kSmoMarchMin) {
+  if (!L.march) {
     hipLaunchKernelGGL(k_stencil_residual, grid_tiles(L.n), kBlock3, 0, st, L, (const double*)nullptr, x, y, 1);
     return;
   }
-  const int kz = smo_march_planes(L.n);
+  const int kz = L.kz;
   hipLaunchKernelGGL(k_stencil_apply_z, march_grid(L.n, kz, 1), kBlock3, 0, st, L, x, y, kz);
 }
 void launch_plg_residual(const PlgRows& P, const double* r, const double* x, double* s, int apply_only, int nb,

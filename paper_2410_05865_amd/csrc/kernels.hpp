@@ -18,7 +18,12 @@ struct StencilLevel {
   double inv12h2;        // 1 / (12 h^2)
   int bc[6];             // wall conditions -x,+x,-y,+y,-z,+z
   const uint8_t* type;   // 0 no unknown, 1 phi_1, 2 phi_2
+  int march;             // regular-row kernels (SMO-1, residual, apply): 1 march in z, 0 one cell per thread
+  int kz;                // planes per workgroup of the marching kernels
 };
+
+// The build's choice of the regular-row kernel schedule for an n^3 level.
+void default_stencil_schedule(int n, int& march, int& kz);
 
 // FV-PLG rows of one level, ELL layout (entry j of row r at j * N2 + r).
 struct PlgRows {

@@ -148,6 +148,65 @@ def test_one_vcycle(pair):
     assert _rel(_host(e)[lv.unknowns], ref) < 1e-12
 
 
+# regular-row kernel schedules: (march, planes per workgroup); march 0 is one
+# cell per thread.  8, 16 and 32 planes are the counts the build picks for
+# 96^3-192^3, 256^3 and 512^3 grids (one, two and four unrolled chunks of 8);
+# 5 leaves a ragged last chunk and z-block; 96 is one z-block per column.
+SCHEDULES = [(0, 0), (1, 8), (1, 16), (1, 32), (1, 5), (1, 96)]
+_ORACLE_SOLUTIONS = {}
+
+
+def _oracle_solution(name, H, F):
+    if name not in _ORACLE_SOLUTIONS:
+        r = H.fine.rhs(F.laplacian_desc(), F)
+        x, hist = H.solve(r, MGParams(tol=1e-10))
+        _ORACLE_SOLUTIONS[name] = (r, x, hist)
+    return _ORACLE_SOLUTIONS[name]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=[f"march{m}_kz{k}" for m, k in SCHEDULES])
+def test_stencil_schedules_match_oracle(pair, sched):
+    """Every regular-row kernel schedule (the z-marching kernels forced on every
+    level, including the 32^3 workloads' Neumann and Robin cases) against the
+    oracle, element by element: apply, residual and SMO-1 on every level, one
+    V-cycle, and the converged solve."""
+    name, dom, F, H, P = pair
+    march, planes = sched
+    for m, lv in enumerate(H.levels):
+        P.set_stencil_schedule(m, march, min(planes, lv.n))
+        got = P.stencil_schedule(m)
+        assert got[0] == march and (not march or got[1] == min(planes, lv.n))
+    try:
+        rng = np.random.default_rng(11)
+        for m, lv in enumerate(H.levels):
+            x = rng.standard_normal(lv.N)
+            y = _dev(np.zeros(lv.n ** 3))
+            P.apply(m, _dev(lv.to_grid(x)), y)
+            ref = lv.L @ x
+            assert _rel(_host(y)[lv.unknowns], ref) < 1e-12, m
+            rr = rng.standard_normal(lv.N)
+            s = _dev(np.zeros(lv.n ** 3))
+            P.residual(m, _dev(lv.to_grid(rr)), _dev(lv.to_grid(x)), s)
+            assert _rel(_host(s)[lv.unknowns], rr - ref) < 1e-12, m
+            if m < len(H.levels) - 1:
+                e = _dev(lv.to_grid(x))
+                P.smo1(m, _dev(lv.to_grid(rr)), e)
+                assert _rel(_host(e)[lv.unknowns], H.ops[m].smo1(x, rr, P.params.omega)) < 1e-13, m
+        lv = H.fine
+        s = rng.standard_normal(lv.N)
+        e = _dev(np.zeros(lv.n ** 3))
+        P.vcycle(0, _dev(lv.to_grid(s)), e)
+        ref = H.vcycle(0, s, MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
+        assert _rel(_host(e)[lv.unknowns], ref) < 1e-12
+        r_or, x_or, hist = _oracle_solution(name, H, F)
+        phi = _dev(np.zeros(lv.n ** 3))
+        info = P.solve(_dev(lv.to_grid(r_or)), phi)
+        assert info["converged"] and info["iterations"] == len(hist) - 1
+        assert _rel(_host(phi)[lv.unknowns], x_or) < 1e-11
+    finally:
+        P.set_stencil_schedule(-1, -1, 0)
+
+
 @pytest.mark.parametrize("graph", [0, 1])
 def test_converged_solve_matches_oracle(pair, graph):
     """Same stopping rule (max-norm relative residual < 1e-10) on both sides:
@@ -156,14 +215,13 @@ def test_converged_solve_matches_oracle(pair, graph):
     from paper_2410_05865_amd import _lib
     lv = H.fine
     Q = _lib.Problem(dom, use_graph=graph)
-    r_or = lv.rhs(F.laplacian_desc(), F)
+    r_or, x_or, hist = _oracle_solution(name, H, F)
     r = _dev(np.zeros(lv.n ** 3))
     Q.assemble_rhs(F.desc, F.desc, r, f_mode=_lib.CC_LAPLACIAN)
     assert _rel(_host(r)[lv.unknowns], r_or) < 1e-12
     phi = _dev(np.zeros(lv.n ** 3))
     info = Q.solve(r, phi)
     assert info["converged"] and info["rel_residual"] < 1e-10
-    x_or, hist = H.solve(r_or, MGParams(tol=1e-10))
     assert info["iterations"] == len(hist) - 1
     got = _host(phi)
     assert _rel(got[lv.unknowns], x_or) < 1e-11
