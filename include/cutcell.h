@@ -88,6 +88,9 @@ typedef struct cc_params {
   double pivot_tol;   /* factorizations (Sec. 5.3 LU-correction and bottom solve): a pivot
                          below pivot_tol times the largest entry of the factored matrix is
                          CC_ESINGULAR; default 1e-14, must lie in (0, 1e6] */
+  int fit_on_device;  /* 1 (default): the FV-PLG weighted least-squares fits (Sec. 2.3) run on
+                         the GPU in FP64 (one wavefront per row, Householder QR); 0: on the
+                         host (a host-only handle always fits on the host) */
 } cc_params;
 
 /* Analytic fields (problem data).  data layout by kind:

@@ -52,7 +52,7 @@ class CcParams(C.Structure):
     _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("n_min", C.c_int), ("max_iter", C.c_int), ("tol", C.c_double), ("precision", C.c_int),
                 ("leaf_size", C.c_int), ("device", C.c_int), ("use_graph", C.c_int), ("krylov", C.c_int),
-                ("pivot_tol", C.c_double)]
+                ("pivot_tol", C.c_double), ("fit_on_device", C.c_int)]
 
 
 class CcField(C.Structure):

@@ -1152,6 +1152,7 @@ void cc_default_params(cc_params* p) {
   p->use_graph = 1;
   p->krylov = 0;
   p->pivot_tol = 1e-14;
+  p->fit_on_device = 1;
 }
 
 int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_problem** out) {
@@ -1170,6 +1171,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (prm->precision != CC_FP64 && prm->precision != CC_MIXED) fail(CC_EINVAL, "precision must be CC_FP64 or CC_MIXED");
     if (prm->krylov < 0 || prm->krylov > 64) fail(CC_EINVAL, "krylov must lie in [0, 64]");
     if (!(prm->pivot_tol > 0 && prm->pivot_tol <= 1e6)) fail(CC_EINVAL, "pivot_tol must lie in (0, 1e6]");
+    if (prm->fit_on_device != 0 && prm->fit_on_device != 1) fail(CC_EINVAL, "fit_on_device must be 0 or 1");
     for (int a = 0; a < 6; ++a)
       if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
     auto P = std::make_unique<cc_problem>();
@@ -1230,16 +1232,6 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     P->lu.resize(sizes.size());
     P->lu_mat.resize(sizes.size());
     P->setup_s.resize(sizes.size());
-    for (int m = 0; m <= M; ++m) {
-      double t0 = now_s();
-      P->lv[m] = std::make_unique<LevelHost>();
-      P->lv[m]->build(D, sizes[m], prm->theta);
-      std::vector<std::array<int, 3>> xyz;
-      std::vector<int> orig;
-      build_lu_matrix(*P->lv[m], m == M, P->lu_mat[m], xyz, orig);
-      factorize(P->lu_mat[m], xyz, prm->leaf_size, prm->pivot_tol, P->lu[m]);
-      P->setup_s[m] = now_s() - t0;
-    }
     if (P->device >= 0) {
       HIPCHK(hipSetDevice(P->device));
       if (stream) {
@@ -1248,7 +1240,33 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         HIPCHK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
         P->own_stream = true;
       }
-      upload(P.get());
+    }
+    // the FV-PLG least-squares fits on the device (a handle with a device and
+    // fit_on_device), else on the host
+    struct DeviceLsq : PlgLsqSolver {
+      hipStream_t st;
+      void solve(int nsys, const int* off, const double* A, const double* ell, double* y, int* ok) override {
+        plg_lsq_device(nsys, off, A, ell, y, ok, st);
+      }
+    } dlsq;
+    dlsq.st = P->stream;
+    PlgLsqSolver* lsq = (P->device >= 0 && prm->fit_on_device) ? &dlsq : nullptr;
+    try {
+      for (int m = 0; m <= M; ++m) {
+        double t0 = now_s();
+        P->lv[m] = std::make_unique<LevelHost>();
+        P->lv[m]->build(D, sizes[m], prm->theta, lsq);
+        std::vector<std::array<int, 3>> xyz;
+        std::vector<int> orig;
+        build_lu_matrix(*P->lv[m], m == M, P->lu_mat[m], xyz, orig);
+        factorize(P->lu_mat[m], xyz, prm->leaf_size, prm->pivot_tol, P->lu[m]);
+        P->setup_s[m] = now_s() - t0;
+      }
+      if (P->device >= 0) upload(P.get());
+    } catch (...) {
+      P->buf.release();
+      if (P->own_stream) (void)hipStreamDestroy(P->stream);
+      throw;
     }
     *out = P.release();
   });

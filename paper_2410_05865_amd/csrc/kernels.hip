@@ -9,6 +9,7 @@
 #include <stdexcept>
 #include <vector>
 
+#include "common.hpp"
 #include "kernels.hpp"
 #include "quadrature.hpp"
 
@@ -1540,5 +1541,129 @@ template void launch_lu_backward_sub<double, float>(const LuDev&, const LuSub&, 
 template void launch_lu_backward_sub<float, float>(const LuDev&, const LuSub&, float*, long long, int, hipStream_t);
 template void launch_gather<double, double>(int, const int*, const double*, long long, double*, int, hipStream_t);
 template void launch_gather<float, double>(int, const int*, const float*, long long, double*, int, hipStream_t);
+
+// ------------------------------------------------ FV-PLG least-squares fits
+// The weighted fit of an FV-PLG row (Sec. 2.3, with the lattice of Sec. 4.1):
+// the row is c = ell^T (W^1/2 A)^+ W^1/2, i.e. c_i = w_i^1/2 y_i with y the
+// minimum-norm solution of (W^1/2 A)^T y = ell.  One wavefront per system:
+// Householder QR of the m x 35 matrix B = W^1/2 A in LDS (column-major, the
+// reflector of column k kept below its diagonal), R^T u = ell by forward
+// substitution, then y = Q [u; 0] by the reflectors in reverse.
+constexpr int kLsqCols = 35;
+__global__ void __launch_bounds__(64) k_plg_lsq(int nsys, const int* __restrict__ off, const double* __restrict__ A,
+                                                const double* __restrict__ ell, double* __restrict__ y,
+                                                int* __restrict__ ok, int mmax) {
+  extern __shared__ double lds[];
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  const int lane = threadIdx.x;
+  const int r0 = off[s], m = off[s + 1] - r0;
+  // column stride odd in doubles, so the lanes' columns fall in different banks
+  const int ms = mmax | 1;
+  double* a = lds;                                  // a[c * ms + r]
+  double* yv = lds + (size_t)kLsqCols * ms;         // y (m)
+  __shared__ double vd[kLsqCols], vv[kLsqCols], rd[kLsqCols], u[kLsqCols];
+  const double* As = A + (size_t)r0 * kLsqCols;
+  double amax = 0.0;
+  for (int idx = lane; idx < m * kLsqCols; idx += kWave) {
+    const double v = As[idx];
+    a[(idx % kLsqCols) * ms + idx / kLsqCols] = v;
+    amax = fmax(amax, fabs(v));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, kWave));
+  __syncthreads();
+  bool good = m >= kLsqCols;
+  for (int k = 0; k < kLsqCols && good; ++k) {
+    double* ak = a + (size_t)k * ms;
+    double part = 0.0;
+    for (int r = k + lane; r < m; r += kWave) part += ak[r] * ak[r];
+    const double nrm2 = wave_sum(part);
+    const double nrm = sqrt(nrm2);
+    const double x0 = ak[k];
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    const double v0 = x0 - alpha;
+    const double vn = v0 * v0 + (nrm2 - x0 * x0);   // |x - alpha e_k|^2
+    __syncthreads();
+    if (lane == 0) {
+      vd[k] = v0;
+      vv[k] = vn;
+      rd[k] = vn > 0.0 ? alpha : x0;
+    }
+    // columns c > k, one lane each: c <- c - (2 v.c / v.v) v
+    const int c = lane;
+    if (vn > 0.0 && c > k && c < kLsqCols) {
+      double* ac = a + (size_t)c * ms;
+      double dot = v0 * ac[k];
+      for (int r = k + 1; r < m; ++r) dot += ak[r] * ac[r];
+      const double f = 2.0 * dot / vn;
+      ac[k] -= f * v0;
+      for (int r = k + 1; r < m; ++r) ac[r] -= f * ak[r];
+    }
+    __syncthreads();
+    if (!(fabs(rd[k]) > 1e-13 * amax)) good = false;
+  }
+  if (!good) {
+    if (lane == 0) ok[s] = 0;
+    return;
+  }
+  // R^T u = ell: R[i][k] = a[k][i] for i < k, R[k][k] = rd[k]
+  for (int k = 0; k < kLsqCols; ++k) {
+    double part = lane < k ? a[(size_t)k * ms + lane] * u[lane] : 0.0;
+    const double sdot = wave_sum(part);
+    if (lane == 0) u[k] = (ell[(size_t)s * kLsqCols + k] - sdot) / rd[k];
+    __syncthreads();
+  }
+  for (int r = lane; r < m; r += kWave) yv[r] = r < kLsqCols ? u[r] : 0.0;
+  __syncthreads();
+  for (int k = kLsqCols - 1; k >= 0; --k) {
+    if (!(vv[k] > 0.0)) continue;
+    const double* ak = a + (size_t)k * ms;
+    double part = 0.0;
+    for (int r = k + 1 + lane; r < m; r += kWave) part += ak[r] * yv[r];
+    const double dot = wave_sum(part) + vd[k] * yv[k];
+    const double f = 2.0 * dot / vv[k];
+    __syncthreads();
+    for (int r = k + 1 + lane; r < m; r += kWave) yv[r] -= f * ak[r];
+    if (lane == 0) yv[k] -= f * vd[k];
+    __syncthreads();
+  }
+  for (int r = lane; r < m; r += kWave) y[r0 + r] = yv[r];
+  if (lane == 0) ok[s] = 1;
+}
+
+void plg_lsq_device(int nsys, const int* off, const double* A, const double* ell, double* y, int* ok,
+                    hipStream_t st) {
+  if (nsys <= 0) return;
+  int mmax = 0;
+  for (int s = 0; s < nsys; ++s) mmax = std::max(mmax, off[s + 1] - off[s]);
+  const size_t lds = ((size_t)kLsqCols * (mmax | 1) + mmax) * sizeof(double);
+  if (lds > 60 * 1024) fail(CC_EPLG, "an FV-PLG fit with " + std::to_string(mmax) + " sites exceeds the device kernel's LDS");
+  const long long rows = off[nsys];
+  int* d_off = nullptr;
+  int* d_ok = nullptr;
+  double *d_A = nullptr, *d_ell = nullptr, *d_y = nullptr;
+  auto chk = [](hipError_t e) {
+    if (e != hipSuccess) fail(CC_EDEVICE, std::string("FV-PLG fits: ") + hipGetErrorString(e));
+  };
+  chk(hipMalloc(&d_off, (nsys + 1) * sizeof(int)));
+  chk(hipMalloc(&d_ok, nsys * sizeof(int)));
+  chk(hipMalloc(&d_A, rows * kLsqCols * sizeof(double)));
+  chk(hipMalloc(&d_ell, (size_t)nsys * kLsqCols * sizeof(double)));
+  chk(hipMalloc(&d_y, rows * sizeof(double)));
+  chk(hipMemcpyAsync(d_off, off, (nsys + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  chk(hipMemcpyAsync(d_A, A, rows * kLsqCols * sizeof(double), hipMemcpyHostToDevice, st));
+  chk(hipMemcpyAsync(d_ell, ell, (size_t)nsys * kLsqCols * sizeof(double), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_plg_lsq, dim3(nsys), dim3(kWave), lds, st, nsys, d_off, d_A, d_ell, d_y, d_ok, mmax);
+  chk(hipGetLastError());
+  chk(hipMemcpyAsync(y, d_y, rows * sizeof(double), hipMemcpyDeviceToHost, st));
+  chk(hipMemcpyAsync(ok, d_ok, nsys * sizeof(int), hipMemcpyDeviceToHost, st));
+  chk(hipStreamSynchronize(st));
+  (void)hipFree(d_off);
+  (void)hipFree(d_ok);
+  (void)hipFree(d_A);
+  (void)hipFree(d_ell);
+  (void)hipFree(d_y);
+}
 
 }  // namespace cc

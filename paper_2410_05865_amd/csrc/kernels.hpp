@@ -187,4 +187,11 @@ void launch_net_features(int n0, int m, const double* r, double inv_norm, const 
 void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
                               hipStream_t st);
 
+// FV-PLG weighted least-squares fits on the device (setup): nsys systems, system
+// s the rows off[s] .. off[s+1] of A (35 doubles each, weighted); y receives the
+// minimum-norm solutions of A_s^T y = ell_s, ok[s] = 0 for a rank-deficient A_s.
+// Host arrays; allocates device buffers, synchronises st.
+void plg_lsq_device(int nsys, const int* off, const double* A, const double* ell, double* y, int* ok,
+                    hipStream_t st);
+
 }  // namespace cc

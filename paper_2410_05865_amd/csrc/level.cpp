@@ -99,7 +99,7 @@ const std::vector<int>& LevelHost::members(int p, std::vector<int>& tmp) const {
 }
 
 // ------------------------------------------------------------- build
-void LevelHost::build(const DomainSpec& d, int n_level, double theta) {
+void LevelHost::build(const DomainSpec& d, int n_level, double theta, PlgLsqSolver* lsq) {
   dom = &d;
   n = n_level;
   h = 1.0 / n;
@@ -115,7 +115,7 @@ void LevelHost::build(const DomainSpec& d, int n_level, double theta) {
   classify();
   merge(theta);
   split();
-  rows();
+  rows(lsq);
 }
 
 void LevelHost::claim() {
@@ -567,12 +567,12 @@ static bool min_norm_solve(std::vector<double>& M, int m, const double ell[N4], 
   return true;
 }
 
-void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG],
-                        std::vector<Site>& out) const {
+void LevelHost::plg_system(int p, int row, const int cells[kPLG], std::vector<double>& M, std::vector<double>& sw,
+                           double ell[N4], std::vector<Site>& sites) const {
   const MonoTable& T = mono();
   int ti[3];
   ijk(p, ti[0], ti[1], ti[2]);
-  std::vector<Site> sites;
+  sites.clear();
   std::vector<int> tmp;
   for (int t = 0; t < kPLG; ++t) {
     const std::vector<int>& mem = members(cells[t], tmp);
@@ -591,8 +591,8 @@ void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG]
           sites.push_back({row, 'W', cells[t], wall_bc[2 * d + (side > 0 ? 1 : 0)], d, side, 0.0});
   }
   const int m = kPLG + (int)sites.size();
-  std::vector<double> M((size_t)m * N4);
-  std::vector<double> sw(m);
+  M.assign((size_t)m * N4, 0.0);
+  sw.assign(m, 0.0);
   auto weight = [&](int cell) {
     int ci[3];
     ijk(cell, ci[0], ci[1], ci[2]);
@@ -662,7 +662,7 @@ void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG]
   }
   for (int r = 0; r < m; ++r)
     for (int j = 0; j < N4; ++j) M[(size_t)r * N4 + j] *= sw[r];
-  double mom[N4], ell[N4];
+  double mom[N4];
   group_moments(p, p, mom);
   for (int j = 0; j < N4; ++j) {
     double v = 0.0;
@@ -675,17 +675,9 @@ void LevelHost::plg_row(int p, int row, const int cells[kPLG], double vals[kPLG]
     }
     ell[j] = v / (h * h);
   }
-  std::vector<double> y;
-  if (!min_norm_solve(M, m, ell, y))
-    fail(CC_EPLG, "rank-deficient least-squares fit at cell " + std::to_string(p));
-  for (int t = 0; t < kPLG; ++t) vals[t] = sw[t] * y[t];
-  for (size_t s = 0; s < sites.size(); ++s) {
-    sites[s].coef = sw[kPLG + s] * y[kPLG + s];
-    out.push_back(sites[s]);
-  }
 }
 
-void LevelHost::rows() {
+void LevelHost::rows(PlgLsqSolver* lsq) {
   const size_t N2 = phi2.size();
   plg_cols.assign(N2 * kPLG, 0);
   plg_vals.assign(N2 * kPLG, 0.0);
@@ -693,20 +685,71 @@ void LevelHost::rows() {
   std::vector<std::vector<Site>> tsites(N2);
   int err_code = 0;
   std::string err_msg;
-#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
-  for (long r = 0; r < (long)N2; ++r) {
-    if (err_code) continue;
-    try {
-      int* cells = &plg_cols[(size_t)r * kPLG];
-      plg_select(phi2[r], cells);
-      plg_row(phi2[r], (int)r, cells, &plg_vals[(size_t)r * kPLG], tsites[r]);
-    } catch (const Error& e) {
+  auto record = [&](const Error& e) {
 #pragma omp critical
-      {
-        if (!err_code) {
-          err_code = e.code;
-          err_msg = e.what();
+    {
+      if (!err_code) {
+        err_code = e.code;
+        err_msg = e.what();
+      }
+    }
+  };
+  // the row's value from the fit: c_t = sw_t y_t for the 35 cells, then the sites
+  auto finish = [&](long r, const std::vector<double>& sw, const double* y) {
+    for (int t = 0; t < kPLG; ++t) plg_vals[(size_t)r * kPLG + t] = sw[t] * y[t];
+    for (size_t s = 0; s < tsites[r].size(); ++s) tsites[r][s].coef = sw[kPLG + s] * y[kPLG + s];
+  };
+  if (!lsq) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+    for (long r = 0; r < (long)N2; ++r) {
+      if (err_code) continue;
+      try {
+        int* cells = &plg_cols[(size_t)r * kPLG];
+        plg_select(phi2[r], cells);
+        std::vector<double> M, sw, y;
+        double ell[N4];
+        plg_system(phi2[r], (int)r, cells, M, sw, ell, tsites[r]);
+        if (!min_norm_solve(M, (int)sw.size(), ell, y))
+          fail(CC_EPLG, "rank-deficient least-squares fit at cell " + std::to_string(phi2[r]));
+        finish(r, sw, y.data());
+      } catch (const Error& e) {
+        record(e);
+      }
+    }
+  } else {
+    // the systems in chunks: assembled on the host, solved by lsq (the device)
+    const long chunk = 16384;
+    std::vector<std::vector<double>> Ms, sws;
+    std::vector<double> A, ellv, y;
+    std::vector<int> off, ok;
+    for (long r0 = 0; r0 < (long)N2 && !err_code; r0 += chunk) {
+      const long nr = std::min<long>(chunk, (long)N2 - r0);
+      Ms.assign(nr, {});
+      sws.assign(nr, {});
+      ellv.assign((size_t)nr * N4, 0.0);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+      for (long k = 0; k < nr; ++k) {
+        if (err_code) continue;
+        const long r = r0 + k;
+        try {
+          int* cells = &plg_cols[(size_t)r * kPLG];
+          plg_select(phi2[r], cells);
+          plg_system(phi2[r], (int)r, cells, Ms[k], sws[k], &ellv[(size_t)k * N4], tsites[r]);
+        } catch (const Error& e) {
+          record(e);
         }
+      }
+      if (err_code) break;
+      off.assign(nr + 1, 0);
+      for (long k = 0; k < nr; ++k) off[k + 1] = off[k] + (int)sws[k].size();
+      A.assign((size_t)off[nr] * N4, 0.0);
+      for (long k = 0; k < nr; ++k) std::copy(Ms[k].begin(), Ms[k].end(), A.begin() + (size_t)off[k] * N4);
+      y.assign(off[nr], 0.0);
+      ok.assign(nr, 0);
+      lsq->solve((int)nr, off.data(), A.data(), ellv.data(), y.data(), ok.data());
+      for (long k = 0; k < nr; ++k) {
+        if (!ok[k]) fail(CC_EPLG, "rank-deficient least-squares fit at cell " + std::to_string(phi2[r0 + k]));
+        finish(r0 + k, sws[k], &y[off[k]]);
       }
     }
   }

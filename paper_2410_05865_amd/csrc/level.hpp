@@ -54,6 +54,16 @@ struct Site {
 
 constexpr int kPLG = 35;
 
+// Batched solver of the FV-PLG weighted least-squares problems: for system s
+// (rows off[s] .. off[s+1] of A, each 35 doubles, already scaled by the square
+// roots of the weights) the minimum-norm y with A^T y = ell[35 s ..], written
+// to y[off[s] ..]; ok[s] = 0 where A is rank-deficient (a diagonal entry of R
+// below 1e-13 times max |A|).  Used by LevelHost::build when given.
+struct PlgLsqSolver {
+  virtual void solve(int nsys, const int* off, const double* A, const double* ell, double* y, int* ok) = 0;
+  virtual ~PlgLsqSolver() = default;
+};
+
 struct LevelHost {
   int n = 0;
   double h = 0, origin[3] = {0, 0, 0};
@@ -83,7 +93,8 @@ struct LevelHost {
   }
   const std::vector<int>& members(int p, std::vector<int>& tmp) const;
 
-  void build(const DomainSpec& d, int n_level, double theta);
+  // lsq: where the FV-PLG fits run (null: on the host)
+  void build(const DomainSpec& d, int n_level, double theta, PlgLsqSolver* lsq = nullptr);
 
   // Regular-row wall data term of a phi_1 cell: coefficients multiplying the wall
   // datum of each (axis, side) it touches; used by the right-hand side.
@@ -94,10 +105,13 @@ struct LevelHost {
   void classify();
   void merge(double theta);
   void split();
-  void rows();
+  void rows(PlgLsqSolver* lsq);
   bool regular_ok(int p) const;
   void plg_select(int p, int cells[kPLG]) const;
-  void plg_row(int p, int row, const int cells[kPLG], double vals[kPLG], std::vector<Site>& out) const;
+  // the weighted system of the row of phi_2 cell p: M (m x 35, row-major, rows
+  // scaled by sw), sw (m), ell (35), the boundary sites (coef unset)
+  void plg_system(int p, int row, const int cells[kPLG], std::vector<double>& M, std::vector<double>& sw,
+                  double ell[N4], std::vector<Site>& sites) const;
   void group_moments(int target, int cell, double out[N4]) const;
 };
 

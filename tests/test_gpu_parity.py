@@ -79,6 +79,23 @@ def test_integer_decisions_identical(pair):
             assert np.max(np.abs(np.asarray(ov) - vals[r])) <= 1e-11 * np.max(np.abs(ov))
 
 
+def test_device_fits_match_host_fits(pair):
+    """The FV-PLG least-squares fits run on the GPU (Householder QR, one
+    wavefront per row) for a device handle and on the host for a host-only
+    one: same stencils, coefficients to rounding (both QR, different
+    summation orders), on every level."""
+    name, dom, F, H, P = pair
+    from paper_2410_05865_amd import _lib
+    with _lib.Problem(dom, device=-1) as Q:
+        for m in range(P.num_levels):
+            c1, k1, v1 = P.export_plg(m)
+            c2, k2, v2 = Q.export_plg(m)
+            assert np.array_equal(c1, c2) and np.array_equal(k1, k2)
+            if len(v2):
+                gap = np.max(np.abs(v1 - v2), axis=1) / np.max(np.abs(v2), axis=1)
+                assert gap.max() < 1e-12, (m, gap.max())
+
+
 def test_apply_and_residual(pair):
     name, dom, F, H, P = pair
     rng = np.random.default_rng(1)
