@@ -139,6 +139,11 @@ typedef struct cc_level_info {
                              wavefront caps */
   int lu_waves_cap;       /* device sweeps: wavefronts per height launch at most (chosen at build;
                              0: no cap) */
+  int stencil_march;      /* regular-row kernels (SMO-1, residual, apply): 1 z-marching, 0 one cell
+                             per thread (chosen at build by timing, or cc_set_stencil_schedule) */
+  int stencil_planes;     /* z-planes per workgroup of the marching kernels */
+  double stencil_tune_us[5]; /* the build-time trials: us per FP64 SMO-1 sweep, one cell per thread
+                             at [0], marching with 4, 8, 16, 32 planes at [1..4] (0: not tried) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */
@@ -168,6 +173,14 @@ int cc_assemble_rhs(cc_problem* p, const cc_field* f, int f_mode, const cc_field
  * doubles): the right-hand sides of the coarse levels for cc_fmg. */
 int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mode, const cc_field* g,
                           double* r_dev);
+
+/* cc_assemble_rhs_level for nf problems on the same geometry at once: field k
+ * is f[k] (f_mode as above) with boundary data g[k] (g_per_field = 1) or g[0]
+ * for all (g_per_field = 0; g may be NULL: zero data).  Each cut cell's
+ * quadrature rule is built once for all fields.  r_dev: nf arrays of n_m^3
+ * doubles at stride n_m^3 (device).  Errors: CC_EINVAL. */
+int cc_assemble_rhs_batched(cc_problem* p, int level, int nf, const cc_field* f, int f_mode, const cc_field* g,
+                            int g_per_field, double* r_dev);
 
 /* Multigrid (Sec. 5.3): phi <- phi + VCycle(r - L phi) until the max-norm relative
  * residual < tol or max_iter.  phi_dev is the initial guess on entry and the
@@ -214,8 +227,10 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
  * outer residual and the operator apply of Sec. 5.3, evaluated on the fly from
  * the cell types) on `level` (-1: every level): march = 1 runs the z-marching
  * kernels (a workgroup takes a 64 x 4 column tile through `planes` consecutive
- * z-planes; 0: the build's count for the level's size, else 1..n), march = 0 one
- * cell per thread, march = -1 the build's choice (marching from 96^3 on).  The
+ * z-planes; 0: the build's count, else 1..n), march = 0 one cell per thread,
+ * march = -1 the build's choice.  At cc_build the library times one cell per
+ * thread and marching with 4, 8, 16 and 32 planes on the device and keeps the
+ * fastest (cc_level_info.stencil_*).  The
  * result does not depend on the schedule (same arithmetic order).  Waits for
  * the problem's stream and drops captured iterations.  Errors: CC_EINVAL. */
 int cc_set_stencil_schedule(cc_problem* p, int level, int march, int planes);

@@ -33,6 +33,7 @@ EXPORTED = [
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
     "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule",
+    "cc_assemble_rhs_batched",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -69,7 +70,8 @@ class CcLevelInfo(C.Structure):
                 ("n_merged", C.c_longlong), ("lu_vars", C.c_longlong), ("lu_entries", C.c_longlong),
                 ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double),
                 ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int),
-                ("lu_tune_ms", C.c_double * 10), ("lu_waves_cap", C.c_int)]
+                ("lu_tune_ms", C.c_double * 10), ("lu_waves_cap", C.c_int), ("stencil_march", C.c_int),
+                ("stencil_planes", C.c_int), ("stencil_tune_us", C.c_double * 5)]
 
 
 class CutCellError(RuntimeError):
@@ -101,6 +103,7 @@ def load() -> C.CDLL:
     lib.cc_get_level_info.argtypes = [vp, C.c_int, P(CcLevelInfo)]
     lib.cc_assemble_rhs.argtypes = [vp, P(CcField), C.c_int, P(CcField), vp]
     lib.cc_assemble_rhs_level.argtypes = [vp, C.c_int, P(CcField), C.c_int, P(CcField), vp]
+    lib.cc_assemble_rhs_batched.argtypes = [vp, C.c_int, C.c_int, P(CcField), C.c_int, P(CcField), C.c_int, vp]
     lib.cc_solve.argtypes = [vp, vp, vp, P(CcSolveInfo)]
     lib.cc_apply.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_residual.argtypes = [vp, C.c_int, vp, vp, vp, P(C.c_double)]
@@ -321,6 +324,30 @@ class Problem:
         gs, gk = _field(g)
         _check(load().cc_assemble_rhs_level(self._h, level, C.byref(fs), f_mode, C.byref(gs),
                                             _ptr(r, self.n(level) ** 3)))
+
+    def assemble_rhs_batched(self, fs, gs, r, f_mode: int = CC_VALUE, level: int = 0):
+        """r (nf, n_m^3) <- the right-hand sides of the fields fs (list of
+        descriptors) with boundary data gs (one descriptor for all, or a list of
+        nf, or None for zero data), each cut cell's quadrature rule built once."""
+        self._order()
+        nf = len(fs)
+        fa = (CcField * nf)()
+        keep = []
+        for k, f in enumerate(fs):
+            st, data = _field(f)
+            fa[k] = st
+            keep.append(data)
+        per = isinstance(gs, (list, tuple))
+        glist = list(gs) if per else [gs]
+        if per and len(glist) != nf:
+            raise ValueError("one boundary field per right-hand side expected")
+        ga = (CcField * len(glist))()
+        for k, g in enumerate(glist):
+            st, data = _field(g)
+            ga[k] = st
+            keep.append(data)
+        _check(load().cc_assemble_rhs_batched(self._h, level, nf, fa, f_mode, ga, 1 if per else 0,
+                                              _ptr(r, nf * self.n(level) ** 3)))
 
     @staticmethod
     def _info(info: CcSolveInfo, rc: int) -> dict:

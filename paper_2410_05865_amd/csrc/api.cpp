@@ -141,8 +141,12 @@ void lu_sweeps(hipStream_t st, const DevLU& L, const LuDev& F, TO* out, long lon
   if (L.sub_on) launch_lu_backward_sub<T, TO>(F, L.sub, out, ostride, nb, st);
 }
 
+constexpr int kStencilTrials = 5;  // one cell per thread; marching with 4, 8, 16, 32 planes
+
 struct DevLevel {
   StencilLevel st{};
+  float stencil_tune_us[kStencilTrials] = {};  // build-time trials: us per FP64 SMO-1 sweep
+  int tuned_march = 0, tuned_kz = 8;           // the schedule the trials chose
   PlgRows plg{};
   DevLU lu;
   DevBuf sched;  // device task lists of lu's current schedule
@@ -645,6 +649,40 @@ void upload(cc_problem* P) {
     std::copy(L.tune_ms, L.tune_ms + 10, keep.tune_ms);
     L = keep;
     P->dev[m].sched = std::move(keep_buf);
+  }
+  // Regular-row kernel schedule per level (the stencil autotuner): one cell per
+  // thread, or the z-marching kernels with 4, 8, 16 or 32 planes per workgroup;
+  // time 5 FP64 SMO-1 sweeps of each on this device and keep the fastest (every
+  // schedule gives the same result).
+  for (int m = 0; m <= M; ++m) {
+    DevLevel& D = P->dev[m];
+    StencilLevel& S = D.st;
+    float best = 1e30f;
+    int bm = S.march, bk = S.kz;
+    for (int c = 0; c < kStencilTrials; ++c) {
+      const int march = c == 0 ? 0 : 1;
+      const int kz = c == 0 ? S.kz : (2 << c);      // 4, 8, 16, 32
+      D.stencil_tune_us[c] = 0.f;
+      if (march && kz > S.n) continue;
+      S.march = march;
+      S.kz = kz;
+      launch_smo1<double>(S, P->prm.omega, D.s, D.e, D.et, 1, P->stream);
+      HIPCHK(hipEventRecord(ev0, P->stream));
+      for (int rep = 0; rep < 5; ++rep) launch_smo1<double>(S, P->prm.omega, D.s, D.e, D.et, 1, P->stream);
+      HIPCHK(hipEventRecord(ev1, P->stream));
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventSynchronize(ev1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, ev0, ev1));
+      D.stencil_tune_us[c] = t * 1000.f / 5.f;
+      if (t < best) {
+        best = t;
+        bm = march;
+        bk = kz;
+      }
+    }
+    S.march = D.tuned_march = bm;
+    S.kz = D.tuned_kz = bk;
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
@@ -1296,6 +1334,9 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_entries_per_lane = dev ? (int)p->dev[level].lu.epl : 0;
     info->lu_waves_cap = dev && p->dev[level].lu.wcap < (1 << 30) ? p->dev[level].lu.wcap : 0;
     for (int k = 0; k < 10; ++k) info->lu_tune_ms[k] = dev ? p->dev[level].lu.tune_ms[k] : 0.0;
+    info->stencil_march = dev ? p->dev[level].st.march : 0;
+    info->stencil_planes = dev ? p->dev[level].st.kz : 0;
+    for (int k = 0; k < 5; ++k) info->stencil_tune_us[k] = dev ? p->dev[level].stencil_tune_us[k] : 0.0;
   });
 }
 
@@ -1346,6 +1387,189 @@ int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* 
   });
 }
 
+// r = f - N g on level `level` for nf fields at once (Sec. 2.4): cell averages of
+// f_k (or of Delta f_k) on the device; on the host, one quadrature rule per cut
+// cell serves every field (cut-cell integrals of f_k, patch data of g_k), then
+// the merged groups' averages, the wall-ghost terms of regular rows and the
+// boundary sites of FV-PLG rows; the host results reach the device as sparse
+// overwrites (special and absorbed cells) and additions (boundary terms), so
+// no full array crosses PCIe.  r_dev holds nf arrays of n_m^3 at stride n_m^3.
+static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<FieldDesc>& fds, int f_mode,
+                         const std::vector<FieldDesc>& gds, double* r_dev) {
+  const LevelHost& L = *p->lv[level];
+  const int n = L.n;
+  const double h = L.h;
+  const long long n3 = (long long)n * n * n;
+  for (int k = 0; k < nf; ++k) launch_cell_average(n, h, L.origin, fds[k], f_mode, 8, r_dev + k * n3, p->stream);
+  const double s12 = 1.0 / (12.0 * h * h);
+  const double h3 = h * h * h;
+  // full cells inside merged groups: their device averages
+  std::vector<int> special;
+  for (int c : L.unknowns)
+    if (L.cut.count(c) || L.groups.count(c)) special.push_back(c);
+  std::vector<int> full_members;
+  {
+    std::vector<int> tmp;
+    for (int c : special)
+      for (int m : L.members(c, tmp))
+        if (!L.cut.count(m)) full_members.push_back(m);
+    std::sort(full_members.begin(), full_members.end());
+    full_members.erase(std::unique(full_members.begin(), full_members.end()), full_members.end());
+  }
+  DevBuf tmpb;
+  std::vector<double> fm_val((size_t)full_members.size() * nf);
+  if (!full_members.empty()) {
+    int* d_cells = tmpb.upload(full_members);
+    double* d_vals = tmpb.alloc<double>(fm_val.size());
+    launch_gather<double, double>((int)full_members.size(), d_cells, r_dev, n3, d_vals, nf, p->stream);
+    HIPCHK(hipMemcpyAsync(fm_val.data(), d_vals, fm_val.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  }
+  HIPSYNC(p->stream);
+  std::map<int, size_t> fm_pos;
+  for (size_t t = 0; t < full_members.size(); ++t) fm_pos[full_members[t]] = t;
+  // per cut cell and field: integral of f over the cut region and the patch
+  // datum of g (Dirichlet: <<g>>, Neumann: h <<dg/dn>>, Robin: scaled), from
+  // one quadrature pass
+  std::vector<int> cuts;
+  for (const auto& kv : L.cut) cuts.push_back(kv.first);
+  std::vector<double> cut_int(cuts.size() * nf), cut_dat(cuts.size() * nf);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long t = 0; t < (long)cuts.size(); ++t) {
+    int m = cuts[t];
+    const CutData& cd = L.cut.at(m);
+    const Obstacle& ob = p->dom.obst[cd.obst];
+    int bc = ob.bc;
+    int ii[3];
+    L.ijk(m, ii[0], ii[1], ii[2]);
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = L.origin[a] + h * ii[a];
+      hi[a] = lo[a] + h;
+    }
+    NodeSet vn;
+    SurfaceSet sn;
+    region_rules(lo, hi, 3, ob.q, kQuadOrder, vn, &sn);
+    // the datum in the scale of the site row: Neumann h <<dg/dn>>, Robin
+    // h <<alpha g + beta dg/dn>> / (|alpha| h + |beta|)
+    const double scale = bc == CC_NEUMANN ? h
+                         : bc == CC_ROBIN  ? h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta))
+                                           : 1.0;
+    for (int k = 0; k < nf; ++k) {
+      double s = 0.0;
+      for (size_t q = 0; q < vn.size(); ++q)
+        s += vn.w[q] * field_value(fds[k], vn.x[3 * q], vn.x[3 * q + 1], vn.x[3 * q + 2], f_mode);
+      cut_int[t * nf + k] = s;
+      double acc = 0.0, area = 0.0;
+      for (size_t q = 0; q < sn.w.size(); ++q) {
+        const double* x = &sn.x[3 * q];
+        double v;
+        if (bc == CC_DIRICHLET) {
+          v = field_value(gds[k], x[0], x[1], x[2], 0);
+        } else {
+          double gr[3];
+          field_grad(gds[k], x[0], x[1], x[2], gr);
+          v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
+          if (bc == CC_ROBIN) v = ob.alpha * field_value(gds[k], x[0], x[1], x[2], 0) + ob.beta * v;
+        }
+        acc += sn.w[q] * v;
+        area += sn.w[q];
+      }
+      cut_dat[t * nf + k] = (area > 0) ? acc / area * scale : 0.0;
+    }
+  }
+  std::map<int, size_t> cut_pos;
+  for (size_t t = 0; t < cuts.size(); ++t) cut_pos[cuts[t]] = t;
+  auto cell_integral = [&](int m, int k) -> double {
+    auto it = cut_pos.find(m);
+    return (it == cut_pos.end()) ? fm_val[fm_pos.at(m) * nf + k] * h3 : cut_int[it->second * nf + k];
+  };
+  // overwrites: special cells (region averages), absorbed cells (0)
+  std::vector<int> set_cells = special;
+  std::vector<double> set_vals(special.size() * nf);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long t = 0; t < (long)special.size(); ++t) {
+    int c = special[t];
+    std::vector<int> tmp;
+    const std::vector<int>& mem = L.members(c, tmp);
+    double vol = 0.0;
+    for (int m : mem) vol += L.vol[m];
+    for (int k = 0; k < nf; ++k) {
+      double tot = 0.0;
+      for (int m : mem) tot += cell_integral(m, k);
+      set_vals[t * nf + k] = tot / vol;
+    }
+  }
+  for (long long c = 0; c < n3; ++c)
+    if (L.host[c] != (int)c) {
+      set_cells.push_back((int)c);
+      for (int k = 0; k < nf; ++k) set_vals.push_back(0.0);
+    }
+  // additions: wall-ghost terms of regular rows, boundary sites of FV-PLG rows
+  std::vector<int> wall_cells;
+  for (int c : L.unknowns) {
+    if (L.type[c] != kPhi1) continue;
+    int ii[3];
+    L.ijk(c, ii[0], ii[1], ii[2]);
+    bool near = false;
+    for (int d = 0; d < 3; ++d) near = near || ii[d] <= 1 || ii[d] >= n - 2;
+    if (near) wall_cells.push_back(c);
+  }
+  const int N2 = (int)L.phi2.size();
+  std::vector<int> add_cells = wall_cells;
+  add_cells.insert(add_cells.end(), L.phi2.begin(), L.phi2.end());
+  std::vector<double> add_vals(add_cells.size() * nf, 0.0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long t = 0; t < (long)wall_cells.size(); ++t) {
+    int c = wall_cells[t];
+    int ii[3];
+    L.ijk(c, ii[0], ii[1], ii[2]);
+    for (int k = 0; k < nf; ++k) {
+      double corr = 0.0;
+      for (int d = 0; d < 3; ++d)
+        for (int side : {-1, 1}) {
+          int layer = side > 0 ? n - 1 - ii[d] : ii[d];
+          if (layer > 1) continue;
+          int bc = L.wall_bc[2 * d + (side > 0 ? 1 : 0)];
+          double dat = face_average(L, gds[k], c, d, side, bc == CC_NEUMANN);
+          corr += wall_coef(layer, bc, h) * s12 * dat;
+        }
+      add_vals[t * nf + k] = -corr;
+    }
+  }
+  std::vector<std::vector<size_t>> by_row(N2);
+  for (size_t s = 0; s < L.sites.size(); ++s) by_row[L.sites[s].row].push_back(s);
+  const size_t w0 = wall_cells.size();
+#pragma omp parallel for schedule(dynamic, 8)
+  for (long rr = 0; rr < N2; ++rr) {
+    for (int k = 0; k < nf; ++k) {
+      double corr = 0.0;
+      for (size_t si : by_row[rr]) {
+        const Site& st = L.sites[si];
+        double dat;
+        if (st.kind == 'W') {
+          dat = face_average(L, gds[k], st.cell, st.axis, st.side, st.bc == CC_NEUMANN);
+          if (st.bc == CC_NEUMANN) dat *= h;
+        } else {
+          dat = cut_dat[cut_pos.at(st.cell) * nf + k];
+        }
+        corr += st.coef * dat;
+      }
+      add_vals[(w0 + rr) * nf + k] = -corr;
+    }
+  }
+  if (!set_cells.empty()) {
+    int* d_c = tmpb.upload(set_cells);
+    double* d_v = tmpb.upload(set_vals);
+    launch_scatter_values((int)set_cells.size(), d_c, d_v, r_dev, n3, nf, 0, p->stream);
+  }
+  if (!add_cells.empty()) {
+    int* d_c = tmpb.upload(add_cells);
+    double* d_v = tmpb.upload(add_vals);
+    launch_scatter_values((int)add_cells.size(), d_c, d_v, r_dev, n3, nf, 1, p->stream);
+  }
+  HIPSYNC(p->stream);
+}
+
 int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mode, const cc_field* g,
                           double* r_dev) {
   return guard([&] {
@@ -1353,132 +1577,26 @@ int cc_assemble_rhs_level(cc_problem* p, int level, const cc_field* f, int f_mod
     check_level(p, level);
     need_device(p);
     if (f_mode != CC_VALUE && f_mode != CC_LAPLACIAN) fail(CC_EINVAL, "bad f_mode");
-    FieldDesc fd = to_desc(f), gd = to_desc(g);
-    const LevelHost& L = *p->lv[level];
-    const int n = L.n;
-    const double h = L.h;
-    const size_t n3 = (size_t)n * n * n;
-    launch_cell_average(n, h, L.origin, fd, f_mode, 8, r_dev, p->stream);
-    std::vector<double> r(n3);
-    HIPCHK(hipMemcpyAsync(r.data(), r_dev, n3 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-    HIPSYNC(p->stream);
-    const double s12 = 1.0 / (12.0 * h * h);
-    const double h3 = h * h * h;
-    // per cut cell: integral of f over the cut region and the patch datum of g
-    // (Dirichlet: <<g>>, Neumann: h <<dg/dn>>), from one quadrature pass
-    std::vector<int> cuts;
-    for (const auto& kv : L.cut) cuts.push_back(kv.first);
-    std::vector<double> cut_int(cuts.size()), cut_dat(cuts.size());
-#pragma omp parallel for schedule(dynamic, 8)
-    for (long t = 0; t < (long)cuts.size(); ++t) {
-      int m = cuts[t];
-      const CutData& cd = L.cut.at(m);
-      int bc = p->dom.obst[cd.obst].bc;
-      int ii[3];
-      L.ijk(m, ii[0], ii[1], ii[2]);
-      double lo[3], hi[3];
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = L.origin[a] + h * ii[a];
-        hi[a] = lo[a] + h;
-      }
-      NodeSet vn;
-      SurfaceSet sn;
-      region_rules(lo, hi, 3, p->dom.obst[cd.obst].q, kQuadOrder, vn, &sn);
-      double s = 0.0;
-      for (size_t q = 0; q < vn.size(); ++q)
-        s += vn.w[q] * field_value(fd, vn.x[3 * q], vn.x[3 * q + 1], vn.x[3 * q + 2], f_mode);
-      cut_int[t] = s;
-      const Obstacle& ob = p->dom.obst[cd.obst];
-      double acc = 0.0, area = 0.0;
-      for (size_t q = 0; q < sn.w.size(); ++q) {
-        const double* x = &sn.x[3 * q];
-        double v;
-        if (bc == CC_DIRICHLET) {
-          v = field_value(gd, x[0], x[1], x[2], 0);
-        } else {
-          double gr[3];
-          field_grad(gd, x[0], x[1], x[2], gr);
-          v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
-          if (bc == CC_ROBIN) v = ob.alpha * field_value(gd, x[0], x[1], x[2], 0) + ob.beta * v;
-        }
-        acc += sn.w[q] * v;
-        area += sn.w[q];
-      }
-      // the datum in the scale of the site row: Neumann h <<dg/dn>>, Robin
-      // h <<alpha g + beta dg/dn>> / (|alpha| h + |beta|)
-      const double scale = bc == CC_NEUMANN ? h
-                           : bc == CC_ROBIN  ? h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta))
-                                             : 1.0;
-      cut_dat[t] = (area > 0) ? acc / area * scale : 0.0;
+    HIPCHK(hipSetDevice(p->device));
+    assemble_rhs(p, level, 1, {to_desc(f)}, f_mode, {to_desc(g)}, r_dev);
+  });
+}
+
+int cc_assemble_rhs_batched(cc_problem* p, int level, int nf, const cc_field* f, int f_mode, const cc_field* g,
+                            int g_per_field, double* r_dev) {
+  return guard([&] {
+    if (!p || !r_dev || !f || nf < 1) fail(CC_EINVAL, "bad argument");
+    check_level(p, level);
+    need_device(p);
+    if (f_mode != CC_VALUE && f_mode != CC_LAPLACIAN) fail(CC_EINVAL, "bad f_mode");
+    if (g_per_field != 0 && g_per_field != 1) fail(CC_EINVAL, "g_per_field must be 0 or 1");
+    HIPCHK(hipSetDevice(p->device));
+    std::vector<FieldDesc> fds(nf), gds(nf);
+    for (int k = 0; k < nf; ++k) {
+      fds[k] = to_desc(f + k);
+      gds[k] = to_desc(g ? (g_per_field ? g + k : g) : nullptr);
     }
-    std::map<int, size_t> cut_pos;
-    for (size_t t = 0; t < cuts.size(); ++t) cut_pos[cuts[t]] = t;
-    auto cell_integral = [&](int m) -> double {
-      auto it = cut_pos.find(m);
-      return (it == cut_pos.end()) ? r[m] * h3 : cut_int[it->second];
-    };
-    std::vector<int> special;
-    for (int c : L.unknowns)
-      if (L.cut.count(c) || L.groups.count(c)) special.push_back(c);
-    std::vector<double> fbar(special.size());
-#pragma omp parallel for schedule(dynamic, 8)
-    for (long t = 0; t < (long)special.size(); ++t) {
-      int c = special[t];
-      std::vector<int> tmp;
-      const std::vector<int>& mem = L.members(c, tmp);
-      double tot = 0.0, vol = 0.0;
-      for (int m : mem) {
-        tot += cell_integral(m);
-        vol += L.vol[m];
-      }
-      fbar[t] = tot / vol;
-    }
-    std::vector<double> out = r;
-    for (size_t t = 0; t < special.size(); ++t) out[special[t]] = fbar[t];
-    for (size_t c = 0; c < n3; ++c)
-      if (L.host[c] != (int)c) out[c] = 0.0;
-    // wall-ghost terms of regular rows
-#pragma omp parallel for schedule(dynamic, 64)
-    for (long t = 0; t < (long)L.unknowns.size(); ++t) {
-      int c = L.unknowns[t];
-      if (L.type[c] != kPhi1) continue;
-      int ii[3];
-      L.ijk(c, ii[0], ii[1], ii[2]);
-      double corr = 0.0;
-      for (int d = 0; d < 3; ++d)
-        for (int side : {-1, 1}) {
-          int layer = side > 0 ? n - 1 - ii[d] : ii[d];
-          if (layer > 1) continue;
-          int bc = L.wall_bc[2 * d + (side > 0 ? 1 : 0)];
-          double dat = face_average(L, gd, c, d, side, bc == CC_NEUMANN);
-          corr += wall_coef(layer, bc, h) * s12 * dat;
-        }
-      out[c] -= corr;
-    }
-    // boundary sites of FV-PLG rows
-    const int N2 = (int)L.phi2.size();
-    std::vector<double> pcorr(N2, 0.0);
-    std::vector<std::vector<size_t>> by_row(N2);
-    for (size_t s = 0; s < L.sites.size(); ++s) by_row[L.sites[s].row].push_back(s);
-#pragma omp parallel for schedule(dynamic, 8)
-    for (long rr = 0; rr < N2; ++rr) {
-      double corr = 0.0;
-      for (size_t si : by_row[rr]) {
-        const Site& st = L.sites[si];
-        double dat;
-        if (st.kind == 'W') {
-          dat = face_average(L, gd, st.cell, st.axis, st.side, st.bc == CC_NEUMANN);
-          if (st.bc == CC_NEUMANN) dat *= h;
-        } else {
-          dat = cut_dat[cut_pos.at(st.cell)];
-        }
-        corr += st.coef * dat;
-      }
-      pcorr[rr] = corr;
-    }
-    for (int rr = 0; rr < N2; ++rr) out[L.phi2[rr]] -= pcorr[rr];
-    HIPCHK(hipMemcpyAsync(r_dev, out.data(), n3 * sizeof(double), hipMemcpyHostToDevice, p->stream));
-    HIPSYNC(p->stream);
+    assemble_rhs(p, level, nf, fds, f_mode, gds, r_dev);
   });
 }
 
@@ -1795,10 +1913,8 @@ int cc_set_stencil_schedule(cc_problem* p, int level, int march, int planes) {
     HIPSYNC(p->stream);
     for (int m = (level < 0 ? 0 : level); m < (level < 0 ? nl : level + 1); ++m) {
       StencilLevel& S = p->dev[m].st;
-      int dm = 0, dk = 0;
-      default_stencil_schedule(S.n, dm, dk);
-      S.march = march < 0 ? dm : march;
-      S.kz = planes == 0 ? dk : planes;
+      S.march = march < 0 ? p->dev[m].tuned_march : march;
+      S.kz = planes == 0 ? p->dev[m].tuned_kz : planes;
     }
     // captured iterations hold the old launch shapes
     p->w64.drop_graph();

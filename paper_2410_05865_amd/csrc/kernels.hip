@@ -1446,6 +1446,20 @@ void launch_copy_pairs(int count, const int2* pairs, T* a, long long stride, int
 }
 template void launch_copy_pairs<double>(int, const int2*, double*, long long, int, hipStream_t);
 template void launch_copy_pairs<float>(int, const int2*, float*, long long, int, hipStream_t);
+__global__ void k_scatter_values(int count, const int* __restrict__ cells, const double* __restrict__ vals,
+                                 double* __restrict__ a, long long stride, int nb, int add) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)count * nb) return;
+  const int v = (int)(t / nb), b = (int)(t % nb);
+  double* dst = a + b * stride + cells[v];
+  *dst = add ? *dst + vals[t] : vals[t];
+}
+void launch_scatter_values(int count, const int* cells, const double* vals, double* a, long long stride, int nb,
+                           int add, hipStream_t st) {
+  if (count == 0 || nb == 0) return;
+  hipLaunchKernelGGL(k_scatter_values, dim3(blocks((long long)count * nb, 256)), dim3(256), 0, st, count, cells, vals,
+                     a, stride, nb, add);
+}
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_values, dim3(blocks(count, 256)), dim3(256), 0, st, count, cells, vals, a);

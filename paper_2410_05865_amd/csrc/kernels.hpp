@@ -170,6 +170,9 @@ void launch_copy_pairs(int count, const int2* pairs, T* a, long long stride, int
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q,
                          double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
+// a[b * stride + cells[v]] = vals[v * nb + b] (add = 0) or += it (add = 1), nb arrays
+void launch_scatter_values(int count, const int* cells, const double* vals, double* a, long long stride, int nb,
+                           int add, hipStream_t st);
 void launch_copy(long long count, const double* src, double* dst, hipStream_t st);
 // Krylov helpers over n3-element FP64 vectors stored `stride` apart (partial:
 // reduction scratch as for launch_maxabs):

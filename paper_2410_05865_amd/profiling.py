@@ -18,6 +18,19 @@ import numpy as np
 SMO_KERNEL = "k_smo1_z<double>"
 
 
+def _last_run(seq, key):
+    """Indices of the trailing run of consecutive entries of `seq` (dispatch
+    order) whose kernel is `key`: the timing hook's back-to-back launches,
+    which come after the build-time schedule trials of the same kernel."""
+    idx = [i for i, (k, *_rest) in enumerate(seq) if k == key]
+    if not idx:
+        return []
+    run = [idx[-1]]
+    while run[-1] - 1 >= 0 and seq[run[-1] - 1][0] == key:
+        run.append(run[-1] - 1)
+    return run[::-1]
+
+
 def _load(path: str, counter: str):
     con = sqlite3.connect(path)
     rows = con.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
@@ -37,18 +50,17 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
     wr = _load(write_db, "WRITE_SIZE")
     n3 = n ** 3
 
-    def by_kernel(rows, prefix, largest=True):
-        g = defaultdict(list)
-        for _, k, grid, v in rows:
-            if k.startswith(prefix):
-                g[grid].append(v)
-        if not g:
-            raise ValueError(f"no dispatch of {prefix}")
-        grid = max(g) if largest else min(g)
-        return float(np.mean(g[grid])), len(g[grid]), grid
+    def by_kernel(rows, key):
+        """mean counter of the timing hook's launches of `key` (the last run)"""
+        seq = [(k, grid, v) for _, k, grid, v in rows]
+        run = _last_run(seq, key)
+        if not run:
+            raise ValueError(f"no dispatch of {key}")
+        return float(np.mean([seq[i][2] for i in run])), len(run), seq[run[-1]][1]
 
     cf, ncf, _ = by_kernel(fe, "k_copy")
     cw, ncw, _ = by_kernel(wr, "k_copy")
+    # SMO-1: the timing hook's launches (the tuned level-0 schedule)
     f_fac = 8.0 * n3 / (cf * 1024.0)
     w_fac = 8.0 * n3 / (cw * 1024.0)
     sf, nsf, sgrid = by_kernel(fe, SMO_KERNEL)
@@ -80,51 +92,58 @@ def traffic_summary(fetch_db: str, write_db: str, n: int, src_hash: str) -> str:
 
 def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
     """Per-kernel totals from a rocprofv3 --kernel-trace database, plus the
-    average duration of the level-0 dispatches of the SMO-1 kernel (largest
-    grid), which the bench's event timing of the same kernel should match."""
+    average duration of the level-0 SMO-1 launches of the bench's timing hook
+    (the last run of back-to-back dispatches of the kernel, after the
+    build-time schedule trials), which the bench's event timing of the same
+    launches should match."""
     con = sqlite3.connect(db)
-    rows = con.execute("select name, start, end, grid_x, grid_y, grid_z from kernels").fetchall()
+    rows = con.execute("select name, start, end, grid_x, grid_y, grid_z from kernels order by start").fetchall()
     tot = defaultdict(lambda: [0, 0.0])
-    smo = defaultdict(list)
+    seq = []
     for name, st, en, gx, gy, gz in rows:
         m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
         key = (m.group(1) + (m.group(2) or "")) if m else name.split("(")[0][:40]
         d = (en - st) / 1000.0
         tot[key][0] += 1
         tot[key][1] += d
-        if key == SMO_KERNEL:
-            smo[(gx, gy, gz)].append(d)
+        seq.append((key, (gx, gy, gz), d))
     allt = sum(v[1] for v in tot.values())
     out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
     for k, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1])[:top]:
         out.append(f"| {k} | {c} | {t / 1000:.2f} | {t / c:.1f} | {100 * t / allt:.1f} |")
-    if smo:
-        g = max(smo, key=lambda k: k[0] * k[1] * k[2])
-        v = smo[g]
+    run = _last_run(seq, SMO_KERNEL)
+    if run:
+        v = [seq[i][2] for i in run]
+        g = seq[run[-1]][1]
         out.append("")
-        out.append(f"{SMO_KERNEL} level-0 dispatches (grid {g[0]}x{g[1]}x{g[2]} work-items, {n}^3 cells): "
-                   f"{len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
+        out.append(f"{SMO_KERNEL} level-0 dispatches of the timing hook (grid {g[0]}x{g[1]}x{g[2]} work-items, "
+                   f"{n}^3 cells): {len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
     return "\n".join(out)
 
 
 def counters_summary(db: str, kernels=(SMO_KERNEL, "k_copy")) -> str:
     """Per-dispatch averages of every counter of a rocprofv3 --pmc database for
-    the named kernels (largest grid of each: the level-0 launches)."""
+    the named kernels (the timing hook's launches: the last run of
+    back-to-back dispatches of each)."""
     con = sqlite3.connect(db)
-    rows = con.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
-    acc = defaultdict(lambda: defaultdict(list))
-    for name, grid, cname, val in rows:
+    rows = con.execute("select dispatch_id, kernel_name, grid_size, counter_name, value from counters_collection "
+                       "order by dispatch_id").fetchall()
+    disp = {}
+    for did, name, grid, cname, val in rows:
         m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
         key = (m.group(1) + (m.group(2) or "")) if m else name[:40]
-        acc[(key, int(grid))][cname].append(float(val))
+        d = disp.setdefault(did, (key, int(grid), defaultdict(list)))
+        d[2][cname].append(float(val))
+    seq = [disp[k] for k in sorted(disp)]
     out = []
     for k in kernels:
-        grids = [g for (kk, g) in acc if kk == k]
-        if not grids:
+        run = _last_run(seq, k)
+        if not run:
             continue
-        g = max(grids)
-        d = acc[(k, g)]
-        n = max(len(v) for v in d.values())
-        out.append(f"- {k} (grid {g} work-items, {n} dispatches): "
-                   + ", ".join(f"{c} {np.mean(v):.4g}" for c, v in sorted(d.items())))
+        acc = defaultdict(list)
+        for i in run:
+            for c, v in seq[i][2].items():
+                acc[c] += v
+        out.append(f"- {k} (grid {seq[run[-1]][1]} work-items, {len(run)} dispatches): "
+                   + ", ".join(f"{c} {np.mean(v):.4g}" for c, v in sorted(acc.items())))
     return "\n".join(out)

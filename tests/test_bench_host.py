@@ -57,36 +57,46 @@ def test_traffic_summary_calibrates_with_the_copy_kernel(tmp_path):
     n3 = n ** 3
     true_kib = 8.0 * n3 / 1024.0
     # FETCH_SIZE reads half the true bytes, WRITE_SIZE all of them (as measured on the part)
-    fe = [(1, COPY, n3 // 4, "FETCH_SIZE", true_kib / 2), (2, SMO, 4 * n3 // 16, "FETCH_SIZE", 1.5 * true_kib),
-          (3, SMO, n3 // 64, "FETCH_SIZE", 1.0), (4, LU, 100, "FETCH_SIZE", 10.0)]
-    wr = [(1, COPY, n3 // 4, "WRITE_SIZE", true_kib), (2, SMO, 4 * n3 // 16, "WRITE_SIZE", true_kib),
-          (3, SMO, n3 // 64, "WRITE_SIZE", 1.0), (4, LU, 100, "WRITE_SIZE", 2.0)]
+    # build-time trials of other schedules first (dispatches 1-3), then the timing
+    # hook: two back-to-back smoother launches, the copy kernel, the LU sweeps
+    fe = [(1, SMO, 8 * n3 // 16, "FETCH_SIZE", 9.0), (2, SMO, 8 * n3 // 16, "FETCH_SIZE", 9.0),
+          (3, LU, 100, "FETCH_SIZE", 3.0),
+          (4, SMO, 4 * n3 // 16, "FETCH_SIZE", 1.5 * true_kib), (5, SMO, 4 * n3 // 16, "FETCH_SIZE", 1.5 * true_kib),
+          (6, COPY, n3 // 4, "FETCH_SIZE", true_kib / 2), (7, LU, 100, "FETCH_SIZE", 10.0)]
+    wr = [(1, SMO, 8 * n3 // 16, "WRITE_SIZE", 9.0), (2, SMO, 8 * n3 // 16, "WRITE_SIZE", 9.0),
+          (3, LU, 100, "WRITE_SIZE", 1.0),
+          (4, SMO, 4 * n3 // 16, "WRITE_SIZE", true_kib), (5, SMO, 4 * n3 // 16, "WRITE_SIZE", true_kib),
+          (6, COPY, n3 // 4, "WRITE_SIZE", true_kib), (7, LU, 100, "WRITE_SIZE", 2.0)]
     _counter_db(tmp_path / "f.db", fe)
     _counter_db(tmp_path / "w.db", wr)
     text = profiling.traffic_summary(str(tmp_path / "f.db"), str(tmp_path / "w.db"), n, "abc")
     by = float(re.search(r"SMO-1 bytes per launch \(calibrated\): `([0-9.e+]+)`", text).group(1))
-    # largest grid of the smoother: 3 x 8 B per cell read after calibration, 8 B written
+    # the hook's launches: 3 x 8 B per cell read after calibration, 8 B written
     assert by == pytest.approx(32.0 * n3)
+    assert "(2 dispatches, grid" in text
     assert "measured/algorithmic = 1.280" in text
     assert "fetch x2.0000, write x1.0000" in text
 
 
-def test_kernel_stats_take_the_level0_dispatches(tmp_path):
+def test_kernel_stats_take_the_timing_hooks_dispatches(tmp_path):
     con = sqlite3.connect(tmp_path / "t.db")
     con.execute("create table kernels (name text, start int, end int, grid_x int, grid_y int, grid_z int)")
-    rows = [(SMO, 0, 120_000, 262144, 4, 1), (SMO, 200_000, 326_000, 262144, 4, 1),
-            (SMO, 400_000, 420_000, 32768, 4, 1), (LU, 500_000, 510_000, 1024, 1, 1)]
+    # a trial (another schedule), a solve's launch between other kernels, then the hook's run of two
+    rows = [(SMO, 0, 20_000, 32768, 4, 1), (LU, 30_000, 40_000, 1024, 1, 1),
+            (SMO, 50_000, 60_000, 32768, 4, 1), (LU, 70_000, 80_000, 1024, 1, 1),
+            (SMO, 100_000, 220_000, 262144, 4, 1), (SMO, 300_000, 426_000, 262144, 4, 1)]
     con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?)", rows)
     con.commit()
     con.close()
     text = profiling.kernel_stats_summary(str(tmp_path / "t.db"), n=256)
-    assert "| k_smo1_z<double> | 3 | 0.27 |" in text
+    assert "| k_smo1_z<double> | 4 | 0.28 |" in text
     assert "2 dispatches, average 123.0 us" in text
 
 
-def test_counter_summary_averages_the_largest_grid(tmp_path):
-    rows = [(1, SMO, 1000, "TA_BUSY_avr", 10.0), (2, SMO, 1000, "TA_BUSY_avr", 20.0),
-            (3, SMO, 10, "TA_BUSY_avr", 99.0), (4, COPY, 500, "TA_BUSY_avr", 5.0)]
+def test_counter_summary_averages_the_timing_hooks_launches(tmp_path):
+    rows = [(1, SMO, 10, "TA_BUSY_avr", 99.0), (2, COPY, 500, "TA_BUSY_avr", 7.0),
+            (3, SMO, 1000, "TA_BUSY_avr", 10.0), (4, SMO, 1000, "TA_BUSY_avr", 20.0),
+            (5, COPY, 500, "TA_BUSY_avr", 5.0)]
     _counter_db(tmp_path / "c.db", rows)
     text = profiling.counters_summary(str(tmp_path / "c.db"))
     assert "k_smo1_z<double> (grid 1000 work-items, 2 dispatches): TA_BUSY_avr 15" in text

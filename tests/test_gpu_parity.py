@@ -96,6 +96,21 @@ def test_device_fits_match_host_fits(pair):
                 assert gap.max() < 1e-12, (m, gap.max())
 
 
+def test_stencil_autotuner_choice(pair):
+    """The build times the regular-row schedules (one cell per thread, marching
+    with 4-32 planes) and keeps the fastest one it tried."""
+    name, dom, F, H, P = pair
+    for m in range(P.num_levels):
+        info = P.level_info(m)
+        t = info["stencil_tune_us"]
+        assert t[0] > 0 and info["stencil_march"] in (0, 1)
+        tried = [(0, t[0])] + [(2 << c, t[c]) for c in range(1, 5) if t[c] > 0]
+        best = min(v for _, v in tried)
+        chosen = t[0] if info["stencil_march"] == 0 else t[{4: 1, 8: 2, 16: 3, 32: 4}[info["stencil_planes"]]]
+        assert chosen == best
+        assert P.stencil_schedule(m) == (info["stencil_march"], info["stencil_planes"])
+
+
 def test_apply_and_residual(pair):
     name, dom, F, H, P = pair
     rng = np.random.default_rng(1)
