@@ -288,6 +288,21 @@ int cc_bottom_solve(cc_problem* p, const double* s_dev, double* e_dev);
  * coarse levels' arrays.  Synchronizes the problem's stream.
  * Errors: CC_EINVAL. */
 int cc_fmg(cc_problem* p, const double* r_dev, const double* const* coarse_rhs, double* phi_dev, int cycles);
+/* cc_fmg without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and result as cc_fmg, with the coarse
+ * levels' solution arrays (and, when coarse_rhs is NULL, their restricted
+ * right-hand sides) carved from one fixed device array per GPU of
+ * 6 Mi doubles (48 MiB), held until the process ends.  Problems whose coarse
+ * levels need more (sum over levels m >= 1 of n_m^3 doubles, twice that
+ * without coarse_rhs; 256^3 fits, 512^3 does not) get CC_EINVAL, and nothing
+ * runs.  Every array of the scratch is written in full before it is read, so it
+ * needs no clearing between calls.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other host threads) race and
+ * must be serialised by the caller.  The V-cycles use the handle's work
+ * arrays (allocated at cc_build).  Synchronizes the problem's stream.
+ * Errors: CC_EINVAL, CC_EDEVICE. */
+int cc_fmg_noalloc(cc_problem* p, const double* r, const double* const* coarse_rhs, double* phi, int cycles);
 /* cc_fmg for nrhs right-hand sides at a stride of n^3 (groups of up to
  * CC_BATCH_MAX share each level's V-cycles, as in cc_solve_batched);
  * coarse_rhs[m - 1] then holds nrhs arrays of n_m^3 doubles.  Start

@@ -32,7 +32,7 @@ EXPORTED = [
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
-    "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule",
+    "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc",
     "cc_assemble_rhs_batched",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
@@ -122,6 +122,7 @@ def load() -> C.CDLL:
     lib.cc_get_stencil_schedule.argtypes = [vp, C.c_int, P(C.c_int), P(C.c_int)]
     lib.cc_fmg.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.cc_fmg_batched.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int]
+    lib.cc_fmg_noalloc.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
@@ -448,6 +449,18 @@ class Problem:
                 raise ValueError("one right-hand side per coarser level expected")
             arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, self.n(m + 1) ** 3) for m, t in enumerate(coarse_rhs)])
         _check(load().cc_fmg(self._h, _ptr(r, n3), arr, _ptr(phi, n3), cycles))
+
+    def fmg_noalloc(self, r, phi, cycles: int = 2, coarse_rhs=None):
+        """fmg() through cc_fmg_noalloc: no device allocation, the coarse arrays in
+        the library's fixed per-GPU scratch (calls on one GPU must not overlap)."""
+        self._order()
+        n3 = self.n() ** 3
+        arr = None
+        if coarse_rhs is not None:
+            if len(coarse_rhs) != self.num_levels - 1:
+                raise ValueError("one right-hand side per coarser level expected")
+            arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, self.n(m + 1) ** 3) for m, t in enumerate(coarse_rhs)])
+        _check(load().cc_fmg_noalloc(self._h, _ptr(r, n3), arr, _ptr(phi, n3), cycles))
 
     def fmg_batched(self, r, phi, cycles: int = 2, coarse_rhs=None):
         """FMG for r of shape (nrhs, n^3) into phi of the same shape; coarse_rhs:

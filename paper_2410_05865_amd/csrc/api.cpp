@@ -1272,6 +1272,11 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     P->setup_s.resize(sizes.size());
     if (P->device >= 0) {
       HIPCHK(hipSetDevice(P->device));
+      {  // resolve this device's copy of the allocation-free entry points' scratch
+        double* s = nullptr;
+        long long c = 0;
+        noalloc_scratch(P->device, &s, &c);
+      }
       if (stream) {
         P->stream = (hipStream_t)stream;
       } else {
@@ -1686,6 +1691,43 @@ int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, doub
         if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
     fmg_alloc(p, 1);
     fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1, p->fmg_rhs, p->fmg_x);
+    HIPSYNC(p->stream);
+  });
+}
+
+int cc_fmg_noalloc(cc_problem* p, const double* r, const double* const* coarse_rhs, double* phi, int cycles) {
+  return guard([&] {
+    if (!p || !r || !phi) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    if (cycles < 1 || cycles > 64) fail(CC_EINVAL, "cycles must lie in [1, 64]");
+    if (coarse_rhs)
+      for (size_t m = 1; m < p->dev.size(); ++m)
+        if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
+    HIPCHK(hipSetDevice(p->device));
+    double* base = nullptr;
+    long long cap = 0;
+    noalloc_scratch(p->device, &base, &cap);
+    // layout: the solution arrays of levels 1..M, then (without coarse_rhs) their
+    // right-hand sides
+    const int M = (int)p->dev.size() - 1;
+    long long need = 0;
+    for (int m = 1; m <= M; ++m) need += cube(p->dev[m].st.n);
+    if (!coarse_rhs) need *= 2;
+    if (need > cap)
+      fail(CC_EINVAL, "cc_fmg_noalloc: the coarse levels need " + std::to_string(need) +
+                          " doubles of scratch, more than the " + std::to_string(cap) + " it holds");
+    std::vector<double*> cx(M + 1, nullptr), crhs(M + 1, nullptr);
+    double* q = base;
+    for (int m = 1; m <= M; ++m) {
+      cx[m] = q;
+      q += cube(p->dev[m].st.n);
+    }
+    if (!coarse_rhs)
+      for (int m = 1; m <= M; ++m) {
+        crhs[m] = q;
+        q += cube(p->dev[m].st.n);
+      }
+    fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1, crhs, cx);
     HIPSYNC(p->stream);
   });
 }

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdexcept>
 #include <vector>
 
@@ -1678,6 +1679,34 @@ void plg_lsq_device(int nsys, const int* off, const double* A, const double* ell
   (void)hipFree(d_A);
   (void)hipFree(d_ell);
   (void)hipFree(d_y);
+}
+
+// The allocation-free entry points' scratch.  In host code `scratch` names a
+// host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns for the current device may reach a kernel or a
+// copy.  Each GPU holds its own copy of the array at its own address.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void noalloc_scratch(int device, double** ptr, long long* capacity) {
+  if (device < 0 || device >= kMaxDevices) fail(CC_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) fail(CC_EDEVICE, "scratch: the device is not current");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      fail(CC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  *capacity = kNoAllocScratchDoubles;
 }
 
 }  // namespace cc

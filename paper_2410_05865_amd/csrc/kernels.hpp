@@ -197,4 +197,12 @@ void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, dou
 void plg_lsq_device(int nsys, const int* off, const double* A, const double* ell, double* y, int* ok,
                     hipStream_t st);
 
+// Scratch of the allocation-free entry points: one fixed device array per GPU
+// (kNoAllocScratchDoubles doubles, held until the process ends).  The first call
+// on a device, with that device current, resolves the array's device address
+// on it (hipGetSymbolAddress) and keeps it; later calls return the kept
+// address.  Throws cc::Error(CC_EDEVICE) if the address cannot be resolved.
+constexpr long long kNoAllocScratchDoubles = 6LL << 20;   // 48 MiB
+void noalloc_scratch(int device, double** ptr, long long* capacity);
+
 }  // namespace cc
