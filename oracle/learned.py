@@ -1,7 +1,7 @@
 """Reference of the learned-guess network (test infrastructure; not from the
 paper: the learned initial guess is an addition on top of its method).
 
-Plain numpy, FP64: a 3-level 3D U-Net written from its definition, with
+Plain numpy, FP64: a 3D U-Net of 3 or 4 levels written from its definition, with
 the gradient of the masked mean-square loss by the chain rule.  Optionally the
 BF16 rounding of the device path is applied at the same points (inputs,
 weights, stored activations and activation gradients) so that the device can
@@ -21,17 +21,33 @@ from __future__ import annotations
 import numpy as np
 
 
-def layer_shapes(C: int):
-    return [(16, C), (C, 2 * C), (2 * C, 2 * C), (4 * C, 2 * C), (3 * C, C), (C, 16)]
+def widths(C: int, depth: int = 3):
+    """Channels of the encoder levels 0 .. depth-1 (the last is the bottleneck):
+    C on the upper levels, 2C on the two coarsest."""
+    return [C if l < depth - 2 else 2 * C for l in range(depth)]
 
 
-def num_params(C: int) -> int:
-    return sum(27 * ci * co + co for ci, co in layer_shapes(C))
+def layer_shapes(C: int, depth: int = 3):
+    """(Cin, Cout) of every layer in parameter order: the encoder convolutions
+    of levels 0 .. depth-2, the bottleneck, the decoder convolutions of levels
+    depth-2 .. 0 (input: the upsampled coarser result beside the skip), the
+    output convolution."""
+    w = widths(C, depth)
+    shapes = [(16, w[0])]
+    shapes += [(w[l - 1], w[l]) for l in range(1, depth - 1)]
+    shapes.append((w[depth - 2], w[depth - 1]))
+    shapes += [(w[l + 1] + w[l], w[l]) for l in range(depth - 2, -1, -1)]
+    shapes.append((w[0], 16))
+    return shapes
 
 
-def unpack(params: np.ndarray, C: int):
+def num_params(C: int, depth: int = 3) -> int:
+    return sum(27 * ci * co + co for ci, co in layer_shapes(C, depth))
+
+
+def unpack(params: np.ndarray, C: int, depth: int = 3):
     out, off = [], 0
-    for ci, co in layer_shapes(C):
+    for ci, co in layer_shapes(C, depth):
         W = params[off:off + 27 * co * ci].reshape(27, co, ci)
         off += 27 * co * ci
         b = params[off:off + co]
@@ -86,75 +102,76 @@ def up(x):
     return x.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
 
 
-def forward(params, x2, C: int, bf16: bool = False):
+def forward(params, x2, C: int, bf16: bool = False, depth: int = 3):
     """x2: (nb, n, n, n, 2) -> y (nb, n, n, n) and the cache for the gradient."""
     rb = round_bf16 if bf16 else (lambda a: a)
-    L = [(rb(W), b) for W, b in unpack(np.asarray(params, dtype=np.float64), C)]
+    L = [(rb(W), b) for W, b in unpack(np.asarray(params, dtype=np.float64), C, depth)]
     x = np.zeros(x2.shape[:4] + (16,))
     x[..., :2] = rb(x2)
     relu = lambda a: np.maximum(a, 0.0)
-    e1 = rb(relu(conv(x, *L[0])))
-    p1 = rb(pool(e1))
-    e2 = rb(relu(conv(p1, *L[1])))
-    p2 = rb(pool(e2))
-    bt = rb(relu(conv(p2, *L[2])))
-    cat2 = np.concatenate([up(bt), e2], axis=-1)
-    d2 = rb(relu(conv(cat2, *L[3])))
-    cat1 = np.concatenate([up(d2), e1], axis=-1)
-    d1 = rb(relu(conv(cat1, *L[4])))
-    y = conv(d1, *L[5])[..., 0]
-    cache = dict(L=L, x=x, e1=e1, p1=p1, e2=e2, p2=p2, bt=bt, cat2=cat2, d2=d2, cat1=cat1, d1=d1)
+    D = depth
+    ins, e, p = [], [], []
+    h = x
+    for l in range(D - 1):                      # encoder: conv, then 2x2x2 average pooling
+        ins.append(h)
+        e.append(rb(relu(conv(h, *L[l]))))
+        p.append(rb(pool(e[l])))
+        h = p[l]
+    bt = rb(relu(conv(h, *L[D - 1])))           # bottleneck
+    d, cats = [None] * (D - 1), [None] * (D - 1)
+    cur = bt
+    for l in range(D - 2, -1, -1):              # decoder: nearest upsampling beside the skip
+        cats[l] = np.concatenate([up(cur), e[l]], axis=-1)
+        d[l] = rb(relu(conv(cats[l], *L[2 * D - 2 - l])))
+        cur = d[l]
+    y = conv(d[0], *L[2 * D - 1])[..., 0]
+    cache = dict(L=L, ins=ins, e=e, p=p, bt=bt, d=d, cats=cats)
     return y, cache
 
 
-def loss_and_grad(params, x2, t, mask, C: int, bf16: bool = False):
+def loss_and_grad(params, x2, t, mask, C: int, bf16: bool = False, depth: int = 3):
     """Masked mean-square loss and its gradient with respect to params (flat)."""
     rb = round_bf16 if bf16 else (lambda a: a)
-    y, c = forward(params, x2, C, bf16)
+    y, c = forward(params, x2, C, bf16, depth)
     L = c["L"]
+    D = depth
+    w = widths(C, D)
     m = np.asarray(mask, dtype=bool)
     cnt = max(int(m.sum()), 1)
-    d = np.where(m, y - t, 0.0)
-    loss = float((d * d).sum() / cnt)
+    dd = np.where(m, y - t, 0.0)
+    loss = float((dd * dd).sum() / cnt)
     gy = np.zeros(y.shape + (16,))
-    gy[..., 0] = rb(2.0 * d / cnt)
-    grads = [None] * 6
-    gd1, gW, gb = conv_grad(c["d1"], L[5][0], gy)
-    grads[5] = (gW, gb)
-    gd1 = np.where(c["d1"] > 0, rb(gd1), 0.0)
-    gcat1, gW, gb = conv_grad(c["cat1"], L[4][0], gd1)
-    grads[4] = (gW, gb)
-    gcat1 = rb(gcat1)
-    C2 = 2 * C
-    gu1, ge1_skip = gcat1[..., :C2], gcat1[..., C2:]
-    nb, n = gu1.shape[0], gu1.shape[1]
-    gd2 = rb(gu1.reshape(nb, n // 2, 2, n // 2, 2, n // 2, 2, C2).sum(axis=(2, 4, 6)))
-    gd2 = np.where(c["d2"] > 0, gd2, 0.0)
-    gcat2, gW, gb = conv_grad(c["cat2"], L[3][0], gd2)
-    grads[3] = (gW, gb)
-    gcat2 = rb(gcat2)
-    gu2, ge2_skip = gcat2[..., :C2], gcat2[..., C2:]
-    m2 = gu2.shape[1]
-    gbt = rb(gu2.reshape(nb, m2 // 2, 2, m2 // 2, 2, m2 // 2, 2, C2).sum(axis=(2, 4, 6)))
-    gbt = np.where(c["bt"] > 0, gbt, 0.0)
-    gp2, gW, gb = conv_grad(c["p2"], L[2][0], gbt)
-    grads[2] = (gW, gb)
-    gp2 = rb(gp2)
-    ge2 = rb(ge2_skip + up(gp2) / 8.0)
-    ge2 = np.where(c["e2"] > 0, ge2, 0.0)
-    gp1, gW, gb = conv_grad(c["p1"], L[1][0], ge2)
-    grads[1] = (gW, gb)
-    gp1 = rb(gp1)
-    ge1 = rb(ge1_skip + up(gp1) / 8.0)
-    ge1 = np.where(c["e1"] > 0, ge1, 0.0)
-    _, gW, gb = conv_grad(c["x"], L[0][0], ge1)
-    grads[0] = (gW, gb)
+    gy[..., 0] = rb(2.0 * dd / cnt)
+    grads = [None] * (2 * D)
+    gd, gW, gb = conv_grad(c["d"][0], L[2 * D - 1][0], gy)
+    grads[2 * D - 1] = (gW, gb)
+    g = np.where(c["d"][0] > 0, rb(gd), 0.0)
+    skips = [None] * (D - 1)
+    for l in range(D - 1):                      # decoder, finest level first
+        gcat, gW, gb = conv_grad(c["cats"][l], L[2 * D - 2 - l][0], g)
+        grads[2 * D - 2 - l] = (gW, gb)
+        gcat = rb(gcat)
+        wu = w[l + 1]
+        gu, skips[l] = gcat[..., :wu], gcat[..., wu:]
+        nb, n = gu.shape[0], gu.shape[1]
+        gnext = rb(gu.reshape(nb, n // 2, 2, n // 2, 2, n // 2, 2, wu).sum(axis=(2, 4, 6)))
+        act = c["bt"] if l + 1 == D - 1 else c["d"][l + 1]
+        g = np.where(act > 0, gnext, 0.0)
+    gp, gW, gb = conv_grad(c["p"][D - 2], L[D - 1][0], g)   # bottleneck
+    grads[D - 1] = (gW, gb)
+    gp = rb(gp)
+    for l in range(D - 2, -1, -1):              # encoder, coarsest level first
+        ge = rb(skips[l] + up(gp) / 8.0)
+        ge = np.where(c["e"][l] > 0, ge, 0.0)
+        gin, gW, gb = conv_grad(c["ins"][l], L[l][0], ge)
+        grads[l] = (gW, gb)
+        gp = rb(gin)
     flat = np.concatenate([np.concatenate([gW.reshape(-1), gb]) for gW, gb in grads])
     return loss, flat
 
 
-def forward_loss(params, x2, t, mask, C: int, bf16: bool = False) -> float:
-    y, _ = forward(params, x2, C, bf16)
+def forward_loss(params, x2, t, mask, C: int, bf16: bool = False, depth: int = 3) -> float:
+    y, _ = forward(params, x2, C, bf16, depth)
     m = np.asarray(mask, dtype=bool)
     d = np.where(m, y - t, 0.0)
     return float((d * d).sum() / max(int(m.sum()), 1))

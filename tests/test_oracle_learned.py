@@ -53,41 +53,49 @@ def test_bf16_rounding():
     assert abs(got[4] - 3.140625) < 1e-12
 
 
-@pytest.mark.parametrize("C", [16])
-def test_gradient_matches_finite_differences(C):
+# central-difference steps: a step crosses ReLU kinks of the activations it
+# moves (the first layer's biases move a whole channel), which the 4-level net
+# has more of, so its step is smaller; the loss is O(0.05), rounding stays far
+# below the tolerance
+@pytest.mark.parametrize("C,depth,per_layer,eps", [(16, 3, 12, 1e-6), (16, 4, 8, 1e-7)])
+def test_gradient_matches_finite_differences(C, depth, per_layer, eps):
     rng = np.random.default_rng(2)
     n, nb = 16, 1
-    npar = ol.num_params(C)
+    npar = ol.num_params(C, depth)
+    last = 2 * depth - 1
     params = rng.standard_normal(npar) * 0.2
-    # zero the padded slots, as in the library
+    # zero the padded slots, as in the library; the 4-level weights scaled by
+    # their fan-in so that activations stay of order one through 8 layers
     off = 0
-    for li, (ci, co) in enumerate(ol.layer_shapes(C)):
+    for li, (ci, co) in enumerate(ol.layer_shapes(C, depth)):
+        if depth > 3:
+            params[off:off + 27 * co * ci] *= 5.0 / np.sqrt(27.0 * ci)
         W = params[off:off + 27 * co * ci].reshape(27, co, ci)
         if li == 0:
             W[:, :, 2:] = 0.0
-        if li == 5:
+        if li == last:
             W[:, 1:, :] = 0.0
         off += 27 * co * ci + co
     x = rng.standard_normal((nb, n, n, n, 2))
     t = rng.standard_normal((nb, n, n, n)) * 0.1
     mask = rng.random((nb, n, n, n)) < 0.8
-    loss, g = ol.loss_and_grad(params, x, t, mask, C)
+    loss, g = ol.loss_and_grad(params, x, t, mask, C, depth=depth)
     # a sample of parameters from every layer (weights and biases)
     idx, off = [], 0
-    for li, (ci, co) in enumerate(ol.layer_shapes(C)):
+    for li, (ci, co) in enumerate(ol.layer_shapes(C, depth)):
         nW = 27 * co * ci
-        cand = [off + k for k in rng.integers(0, nW, 12)]
+        k_ = per_layer
+        cand = [off + k for k in rng.integers(0, nW, k_)]
         if li == 0:
-            cand = [off + (k // 16) * 16 + k % 2 for k in rng.integers(0, nW, 12)]   # real input slots
-        if li == 5:
-            cand = [off + (tap * co + 0) * ci + c for tap, c in zip(rng.integers(0, 27, 12), rng.integers(0, ci, 12))]
-        idx += cand + [off + nW + int(rng.integers(0, co if li < 5 else 1))]
+            cand = [off + (k // 16) * 16 + k % 2 for k in rng.integers(0, nW, k_)]   # real input slots
+        if li == last:
+            cand = [off + (tap * co + 0) * ci + c for tap, c in zip(rng.integers(0, 27, k_), rng.integers(0, ci, k_))]
+        idx += cand + [off + nW + int(rng.integers(0, co if li < last else 1))]
         off += nW + co
-    eps = 1e-6
     for k in idx:
         p1 = params.copy()
         p1[k] += eps
         p2 = params.copy()
         p2[k] -= eps
-        fd = (ol.forward_loss(p1, x, t, mask, C) - ol.forward_loss(p2, x, t, mask, C)) / (2 * eps)
+        fd = (ol.forward_loss(p1, x, t, mask, C, depth=depth) - ol.forward_loss(p2, x, t, mask, C, depth=depth)) / (2 * eps)
         assert abs(fd - g[k]) <= 1e-6 + 1e-5 * abs(fd), (k, fd, g[k])
