@@ -34,6 +34,7 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+T_START = time.perf_counter()
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_2410_05865_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_smo1_z_ellipsoid256_traffic.md")
@@ -172,9 +173,9 @@ def _table4_leg(args, sec_plain_value=None):
             sf, info_f = _timed(fmg_solve, args.steps, args.warmup)
             leg["fmg2_then_vcycles"] = {"s_per_solve": sf, "v_cycles_after_fmg": info_f["iterations"],
                                         "final_rel_residual": info_f["rel_residual"]}
-            print(f"[bench] Table 4 sphere, omega 0.8, FMG(2) then V-cycles: {sf * 1e3:.1f} ms, "
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 sphere, omega 0.8, FMG(2) then V-cycles: {sf * 1e3:.1f} ms, "
                   f"{info_f['iterations']} V-cycles", file=sys.stderr, flush=True)
-        print(f"[bench] Table 4 sphere, omega {omega}: {s * 1e3:.1f} ms, {info['iterations']} V-cycles",
+        print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 sphere, omega {omega}: {s * 1e3:.1f} ms, {info['iterations']} V-cycles",
               file=sys.stderr, flush=True)
         out[f"omega_{omega}"] = leg
         P.close()
@@ -206,7 +207,7 @@ def _large_mixed_leg(args):
         sec, info = _timed(solve, args.steps, args.warmup)
         sols[name] = x.clone()
         out[name] = {"s_per_solve": sec, "v_cycles": info["iterations"], "final_rel_residual": info["rel_residual"]}
-        print(f"[bench] {n}^3 {name}: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
+        print(f"[bench {time.perf_counter() - T_START:6.1f} s] {n}^3 {name}: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
     diff = float((sols["mixed"] - sols["fp64"]).abs().max())
     out["mixed_speedup"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
     out["max_abs_diff_mixed_vs_fp64"] = diff
@@ -260,7 +261,7 @@ def _multi_leg(args):
     s_con, i_con = _timed(conc, 1, 1)
     for P in probs:
         P.close()
-    print(f"[bench] 16 geometries: sequential {s_seq * 1e3:.0f} ms, concurrent {s_con * 1e3:.0f} ms", file=sys.stderr,
+    print(f"[bench {time.perf_counter() - T_START:6.1f} s] 16 geometries: sequential {s_seq * 1e3:.0f} ms, concurrent {s_con * 1e3:.0f} ms", file=sys.stderr,
           flush=True)
     return {"problems": "16 ellipsoid geometries of 64^3-192^3 (4 x 64^3, 3 each of 96^3, 128^3, 160^3, 192^3; "
                         "seeds 2000-2015), Gaussian right-hand sides, "
@@ -270,41 +271,67 @@ def _multi_leg(args):
             "v_cycles": [i["iterations"] for i in i_con]}
 
 
-def _learned_leg(P, dom, args, stream):
-    """Train the learned guess on solver-generated pairs (64^3 problems of the
-    same family, network on their 32^3 level; a 3-level U-Net on a 64^3 grid
-    does not see far enough to learn the global solve), then solve a held-out
-    Gaussian right-hand side on the benchmark problem from a zero guess and from
-    the network's guess (inferred on its 32^3 level and interpolated)."""
+def _learned_leg(P, dom, phi, r_plain, coarse, args, stream):
+    """The learned initial guess: a depth-4, 32-channel U-Net (581k parameters,
+    BF16 MFMA) trained on solver-generated pairs from 128^3 problems of the
+    family (network on their 32^3 level), then the benchmark problem solved for
+    held-out Gaussian right-hand sides from the zero guess, from the network's
+    guess (inferred on its 32^3 level, interpolated), and after FMG(2)."""
     import torch
     from paper_2410_05865_amd import _lib, inputs, learned
-    log = lambda s: print(s, file=sys.stderr, flush=True)
-    net, info = learned.fit(n_fine=64, level=1, geometries=6, rhs_per_geometry=32,
-                            steps=args.learned_steps, seed=3, log=log)
+    log = lambda s_: print(s_, file=sys.stderr, flush=True)
+    net, info = learned.fit(n_fine=128, level=2, geometries=args.learned_geometries,
+                            rhs_per_geometry=args.learned_rhs, steps=args.learned_steps, base_channels=32, depth=4,
+                            seed=3, log=log)
     level = next(m for m in range(P.num_levels) if P.n(m) == 32)
     n3 = args.n ** 3
+    out = {"train": info, "rhs": "f = sum of 16 seeded Gaussians (seeds 9000 ..), g = 0", "held_out": []}
     with torch.cuda.stream(stream):
-        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
-        P.assemble_rhs(inputs.gaussian_rhs(dom, seed=999), None, r)
-        phi = torch.zeros_like(r)
+        fields = [inputs.gaussian_rhs(dom, seed=9000 + k) for k in range(args.learned_eval)]
+        rb = torch.zeros(len(fields), n3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs_batched(fields, None, rb)
+        cb = []
+        for m in range(1, P.num_levels):
+            bm = torch.zeros(len(fields), P.n(m) ** 3, dtype=torch.float64, device="cuda")
+            P.assemble_rhs_batched(fields, None, bm, level=m)
+            cb.append(bm)
+        phi_ = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        for k in range(len(fields)):
+            r = rb[k].contiguous()
+            crs = [c[k].contiguous() for c in cb]
 
-        def zero_guess():
-            phi.zero_()
-            return P.solve(r, phi)
+            def zero_guess():
+                phi_.zero_()
+                return P.solve(r, phi_)
 
-        def learned_guess():
-            P.learned_guess(net, level, learned.PHI_SCALE, r, phi)
-            return P.solve(r, phi)
+            def learned_guess():
+                P.learned_guess(net, level, learned.PHI_SCALE, r, phi_)
+                return P.solve(r, phi_)
 
-        s0, i0 = _timed(zero_guess, args.steps, args.warmup)
-        s1, i1 = _timed(learned_guess, args.steps, args.warmup)
+            def fmg2():
+                phi_.zero_()
+                P.fmg(r, phi_, 2, coarse_rhs=crs)
+                return P.solve(r, phi_)
+            s0, i0 = _timed(zero_guess, 1, 1)
+            s1, i1 = _timed(learned_guess, 1, 1)
+            s2, i2 = _timed(fmg2, 1, 1)
+            out["held_out"].append({"zero_guess": {"s": s0, "v_cycles": i0["iterations"]},
+                                    "learned_guess": {"s_incl_inference": s1, "v_cycles": i1["iterations"],
+                                                      "initial_rel_residual": i1["history"][0]},
+                                    "fmg2": {"s": s2, "v_cycles_after_fmg": i2["iterations"]}})
     net.close()
-    log(f"[bench] learned guess: {i0['iterations']} -> {i1['iterations']} V-cycles, {s0 * 1e3:.1f} -> {s1 * 1e3:.1f} ms")
-    return {"train": info, "rhs": "f = sum of 16 seeded Gaussians (seed 999), g = 0",
-            "zero_guess": {"s_per_solve": s0, "v_cycles": i0["iterations"]},
-            "learned_guess": {"s_per_solve_incl_inference": s1, "v_cycles": i1["iterations"],
-                              "initial_rel_residual": i1["history"][0]},
-            "speedup_vs_zero_guess": s0 / s1}
+    ho = out["held_out"]
+    t0 = float(np.mean([h["zero_guess"]["s"] for h in ho]))
+    t1 = float(np.mean([h["learned_guess"]["s_incl_inference"] for h in ho]))
+    t2 = float(np.mean([h["fmg2"]["s"] for h in ho]))
+    out["mean_v_cycles"] = {"zero_guess": float(np.mean([h["zero_guess"]["v_cycles"] for h in ho])),
+                            "learned_guess": float(np.mean([h["learned_guess"]["v_cycles"] for h in ho])),
+                            "fmg2_then": float(np.mean([h["fmg2"]["v_cycles_after_fmg"] for h in ho]))}
+    out["speedup_vs_zero_guess"] = t0 / t1
+    out["speedup_vs_fmg2"] = t2 / t1
+    log(f"[bench {time.perf_counter() - T_START:6.1f} s] learned guess: V-cycles {out['mean_v_cycles']}, "
+        f"{t0 * 1e3:.1f} / {t1 * 1e3:.1f} / {t2 * 1e3:.1f} ms (zero / learned / FMG(2))")
+    return out
 
 
 def main():
@@ -325,7 +352,11 @@ def main():
     ap.add_argument("--large-mixed", type=int, default=512, metavar="N",
                     help="also solve the ellipsoid workload at N^3 in FP64 and mixed precision (0: skip)")
     ap.add_argument("--krylov", type=int, default=20)
-    ap.add_argument("--learned-steps", type=int, default=1200)
+    ap.add_argument("--learned-steps", type=int, default=2000)
+    ap.add_argument("--learned-geometries", type=int, default=16,
+                    help="128^3 geometries the training pairs come from")
+    ap.add_argument("--learned-rhs", type=int, default=125, help="right-hand sides per training geometry")
+    ap.add_argument("--learned-eval", type=int, default=10, help="held-out right-hand sides at the benchmark size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=64)
     ap.add_argument("--smoother-reps", type=int, default=50)
@@ -381,7 +412,7 @@ def main():
             return P.solve(r, x)
 
         sec, info = _timed(solve_once, args.steps, args.warmup)
-        print(f"[bench] plain FP64: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
+        print(f"[bench {time.perf_counter() - T_START:6.1f} s] plain FP64: {sec * 1e3:.1f} ms, {info['iterations']} V-cycles", file=sys.stderr, flush=True)
         x64 = x.clone()          # the FP64 solution every other leg of this workload is compared with
 
         def vs_fp64(y):
@@ -392,7 +423,7 @@ def main():
             P.set_precision(_lib.CC_MIXED)
             sec_m, info_m = _timed(solve_once, args.steps, args.warmup)
             P.set_precision(_lib.CC_FP64)
-            print(f"[bench] mixed: {sec_m * 1e3:.1f} ms, {info_m['iterations']} V-cycles", file=sys.stderr, flush=True)
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] mixed: {sec_m * 1e3:.1f} ms, {info_m['iterations']} V-cycles", file=sys.stderr, flush=True)
             out_mixed = {"s_per_solve": sec_m, "v_cycles": info_m["iterations"],
                          "final_rel_residual": info_m["rel_residual"], "speedup_vs_plain": sec / sec_m,
                          **vs_fp64(x)}
@@ -401,7 +432,7 @@ def main():
             P.set_krylov(args.krylov)
             sec_k, info_k = _timed(solve_once, args.steps, args.warmup)
             P.set_krylov(0)
-            print(f"[bench] GMRES({args.krylov}): {sec_k * 1e3:.1f} ms, {info_k['iterations']} V-cycles", file=sys.stderr,
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] GMRES({args.krylov}): {sec_k * 1e3:.1f} ms, {info_k['iterations']} V-cycles", file=sys.stderr,
                   flush=True)
             out_krylov = {"restart": args.krylov, "s_per_solve": sec_k, "v_cycles": info_k["iterations"],
                           "final_rel_residual": info_k["rel_residual"], "speedup_vs_plain": sec / sec_k}
@@ -411,7 +442,7 @@ def main():
                 sec_km, info_km = _timed(solve_once, args.steps, args.warmup)
                 P.set_precision(_lib.CC_FP64)
                 P.set_krylov(0)
-                print(f"[bench] GMRES({args.krylov}) + FP32 V-cycle: {sec_km * 1e3:.1f} ms, "
+                print(f"[bench {time.perf_counter() - T_START:6.1f} s] GMRES({args.krylov}) + FP32 V-cycle: {sec_km * 1e3:.1f} ms, "
                       f"{info_km['iterations']} V-cycles", file=sys.stderr, flush=True)
                 out_krylov["mixed_preconditioner"] = {
                     "s_per_solve": sec_km, "v_cycles": info_km["iterations"],
@@ -434,7 +465,7 @@ def main():
                     P.fmg(r, x, c, coarse_rhs=coarse)
                     return P.solve(r, x)
                 sec_f, info_f = _timed(fmg_solve, args.steps, args.warmup)
-                print(f"[bench] FMG({cyc}) + plain FP64: {sec_f * 1e3:.1f} ms, {info_f['iterations']} V-cycles after "
+                print(f"[bench {time.perf_counter() - T_START:6.1f} s] FMG({cyc}) + plain FP64: {sec_f * 1e3:.1f} ms, {info_f['iterations']} V-cycles after "
                       f"FMG", file=sys.stderr, flush=True)
                 legs[str(cyc)] = {"s_per_solve": sec_f, "v_cycles_after_fmg": info_f["iterations"],
                                   "final_rel_residual": info_f["rel_residual"], "speedup_vs_plain": sec / sec_f}
@@ -451,7 +482,7 @@ def main():
                 sec_fg, info_fg = _timed(fmg_gmres, args.steps, args.warmup)
                 P.set_precision(_lib.CC_FP64)
                 P.set_krylov(0)
-                print(f"[bench] FMG({best}) + GMRES({args.krylov}) with the FP32 V-cycle: {sec_fg * 1e3:.1f} ms, "
+                print(f"[bench {time.perf_counter() - T_START:6.1f} s] FMG({best}) + GMRES({args.krylov}) with the FP32 V-cycle: {sec_fg * 1e3:.1f} ms, "
                       f"{info_fg['iterations']} V-cycles after FMG", file=sys.stderr, flush=True)
                 out_fmg["then_gmres_fp32_vcycle"] = {"s_per_solve": sec_fg, "v_cycles_after_fmg": info_fg["iterations"],
                                                      "final_rel_residual": info_fg["rel_residual"],
@@ -467,7 +498,7 @@ def main():
             rb = torch.zeros(B, n3, dtype=torch.float64, device=dev)
             P.assemble_rhs_batched(fields, None, rb)
             t_as = time.perf_counter() - t_as
-            print(f"[bench] {B} right-hand sides assembled in {t_as:.1f} s", file=sys.stderr, flush=True)
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] {B} right-hand sides assembled in {t_as:.1f} s", file=sys.stderr, flush=True)
             # each coarser level's right-hand sides of the same problems, for FMG
             coarse_b = []
             if not args.no_fmg:
@@ -497,7 +528,7 @@ def main():
                 else:   # every member against its FP64 solution (max over members of the relative max-norm)
                     dm = (xb - xb64).abs().amax(dim=1) / xb64.abs().amax(dim=1)
                     res[name]["max_rel_diff_vs_fp64"] = float(dm.max())
-                print(f"[bench] batched {name}: {sb * 1e3:.0f} ms for {B} rhs", file=sys.stderr, flush=True)
+                print(f"[bench {time.perf_counter() - T_START:6.1f} s] batched {name}: {sb * 1e3:.0f} ms for {B} rhs", file=sys.stderr, flush=True)
                 if coarse_b:
                     def fmg_batch():
                         xb.zero_()
@@ -510,7 +541,7 @@ def main():
                         "v_cycles_after_fmg": max(i["iterations"] for i in infos_f),
                         "max_final_rel_residual": max(i["rel_residual"] for i in infos_f),
                         "speedup_per_rhs_vs_plain": sec / (sf / B)}
-                    print(f"[bench] batched {name} after FMG(2): {sf * 1e3:.0f} ms for {B} rhs, "
+                    print(f"[bench {time.perf_counter() - T_START:6.1f} s] batched {name} after FMG(2): {sf * 1e3:.0f} ms for {B} rhs, "
                           f"{max(i['iterations'] for i in infos_f)} V-cycles", file=sys.stderr, flush=True)
             P.set_precision(_lib.CC_FP64)
             out_batch = {"rhs": B, "rhs_recipe": f"{B} independent right-hand sides, f_k = sum of 16 seeded "
@@ -529,7 +560,7 @@ def main():
             out_large = _large_mixed_leg(args)
         out_learned = None
         if not args.no_learned:
-            out_learned = _learned_leg(P, dom, args, stream)
+            out_learned = _learned_leg(P, dom, phi, None, None, args, stream)
         ms_smo, by_smo = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
         ms_smo32, by_smo32 = P.time_kernel(_lib.CC_TIME_SMO1_F32, args.smoother_reps)
         ms_lu, by_lu = P.time_kernel(_lib.CC_TIME_LU, 10)

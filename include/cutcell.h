@@ -139,11 +139,15 @@ typedef struct cc_level_info {
                              wavefront caps */
   int lu_waves_cap;       /* device sweeps: wavefronts per height launch at most (chosen at build;
                              0: no cap) */
-  int stencil_march;      /* regular-row kernels (SMO-1, residual, apply): 1 z-marching, 0 one cell
-                             per thread (chosen at build by timing, or cc_set_stencil_schedule) */
+  int stencil_march;      /* regular-row kernels (SMO-1, residual, apply): 0 one cell per thread,
+                             1 z-marching, 2 z-marching in the XCD-aware tile order (chosen at build
+                             by timing, or cc_set_stencil_schedule) */
   int stencil_planes;     /* z-planes per workgroup of the marching kernels */
-  double stencil_tune_us[5]; /* the build-time trials: us per FP64 SMO-1 sweep, one cell per thread
-                             at [0], marching with 4, 8, 16, 32 planes at [1..4] (0: not tried) */
+  double stencil_tune_us[9]; /* the build-time trials: us per FP64 SMO-1 sweep, one cell per thread
+                             at [0], marching with 4, 8, 16, 32 planes at [1..4], the same in the
+                             XCD-aware order at [5..8] (0: not tried) */
+  long long n_near;       /* phi_1 cells within 3 cells of a phi_2 cell along an axis: the near
+                             SMO-1 sweep (cc_set_overlap) */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */
@@ -208,6 +212,15 @@ int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r_d
  * CC_MIXED); the build-time value is cc_params.precision. */
 int cc_set_precision(cc_problem* p, int precision);
 
+/* Overlap of SMO-1 with the LU-correction (Sec. 5.3 smoothing steps; default
+ * on): every SMO-1 that follows an SMO-2 runs as a far sweep (the phi_1 rows
+ * that read no phi_2 cell, and the cells without an unknown) on a side stream,
+ * concurrently with that SMO-2, and a near sweep (cc_level_info.n_near cells)
+ * after it; the next SMO-2 waits for both.  Same arithmetic, same result; on = 0
+ * runs every SMO-1 as one sweep.  Waits for the problem's stream and drops
+ * captured iterations.  Errors: CC_EINVAL. */
+int cc_set_overlap(cc_problem* p, int on);
+
 /* Switch between the plain multigrid iteration (0) and GMRES(k) preconditioned
  * by the V-cycle (k in 1..64) for later solves; build-time value cc_params.krylov. */
 int cc_set_krylov(cc_problem* p, int krylov);
@@ -227,9 +240,11 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
  * outer residual and the operator apply of Sec. 5.3, evaluated on the fly from
  * the cell types) on `level` (-1: every level): march = 1 runs the z-marching
  * kernels (a workgroup takes a 64 x 4 column tile through `planes` consecutive
- * z-planes; 0: the build's count, else 1..n), march = 0 one cell per thread,
- * march = -1 the build's choice.  At cc_build the library times one cell per
- * thread and marching with 4, 8, 16 and 32 planes on the device and keeps the
+ * z-planes; 0: the build's count, else 1..n), march = 2 the same with the
+ * tiles handed to the 8 XCDs in contiguous ranges (z-blocks of a column on one
+ * XCD, one after the other), march = 0 one cell per thread, march = -1 the
+ * build's choice.  At cc_build the library times one cell per thread and both
+ * marching orders with 4, 8, 16 and 32 planes on the device and keeps the
  * fastest (cc_level_info.stencil_*).  The
  * result does not depend on the schedule (same arithmetic order).  Waits for
  * the problem's stream and drops captured iterations.  Errors: CC_EINVAL. */
@@ -358,22 +373,25 @@ const char* cc_last_error(void);
  * Learned initial guess (an addition on top of the paper's method: the
  * multigrid solve stays the judge, the network only supplies phi_0).
  *
- * A 3-level 3D U-Net with base width C (16 or 32): two input channels (the
- * scaled right-hand side and a geometry channel), one output channel, 3x3x3
- * convolutions with bias, 2x2x2 average pooling, nearest upsampling and skip
- * connections (see the architecture in csrc/net.hip).  Weights are kept in FP32
- * with a BF16 copy; activations are BF16; convolutions accumulate in FP32 on
- * MFMA.  Tensors are channel-last:
+ * A 3D U-Net of `depth` levels (3 or 4) with base width C (16 or 32; encoder
+ * channels C on the upper levels, 2C on the two coarsest): two input channels
+ * (the scaled right-hand side and a geometry channel), one output channel,
+ * 3x3x3 convolutions with bias, 2x2x2 average pooling, nearest upsampling and
+ * skip connections (see the architecture in csrc/net.hip; depth 4 with C = 32
+ * has 581k parameters).  Weights are kept in FP32 with a BF16 copy;
+ * activations are BF16; convolutions accumulate in FP32 on MFMA (gfx950's
+ * double-K BF16 instruction where the input channels allow).  Tensors are
+ * channel-last:
  *   x:      nb x n^3 x 2 FP32 (device), voxel i + n (j + n k)
  *   y, t:   nb x n^3 FP32 (device)
  *   mask:   nb x n^3 bytes (device), nonzero where the loss counts
- * n must be a multiple of 16.  Work runs on `stream` (NULL: the default
+ * n must be a multiple of 2^(depth+1).  Work runs on `stream` (NULL: the default
  * stream); every call synchronises it.  Parameters are one flat FP32 array in
  * layer order, each layer W[27][Cout][Cin] (tap = (dz+1) 9 + (dy+1) 3 + (dx+1))
  * then bias[Cout]; the first layer has 16 input slots (2 used) and the last 16
  * outputs (1 used; the others are held at zero). */
 typedef struct cc_net cc_net;
-int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_net** out);
+int cc_net_create(int base_channels, int depth, unsigned long long seed, void* stream, cc_net** out);
 long long cc_net_num_params(const cc_net* net);
 int cc_net_get_params(const cc_net* net, float* host);
 int cc_net_set_params(cc_net* net, const float* host);
@@ -388,8 +406,20 @@ int cc_net_loss_grad(cc_net* net, int n, int nb, const float* x_dev, const float
 int cc_net_adam_step(cc_net* net, float lr, float beta1, float beta2, float eps);
 void cc_net_destroy(cc_net* net);
 
+/* Training pairs for the network from nrhs solved problems on this geometry
+ * (r_dev, phi_dev: nrhs arrays of n^3 doubles at stride n^3 on the device: the
+ * right-hand sides and their solutions), on level `level` (m^3 cells): per pair
+ * b and level cell V,
+ *   x[b][V] = (mean of r_b over V's fine cells / max|r_b|, volume fraction of V),
+ *   t[b][V] = phi_scale * (mean of phi_b over V's fine cells with an unknown) / max|r_b|,
+ *   mask[b][V] = 1 where V holds a fine cell with an unknown, else 0;
+ * x_dev: nrhs x m^3 x 2 floats, t_dev: nrhs x m^3 floats, mask_dev: nrhs x m^3
+ * bytes (device).  Synchronises the problem's stream.  Errors: CC_EINVAL. */
+int cc_net_pairs(cc_problem* p, int level, int nrhs, const double* r_dev, const double* phi_dev, double phi_scale,
+                 float* x_dev, float* t_dev, unsigned char* mask_dev);
+
 /* Initial guess for cc_solve from the network, evaluated on level `level` of
- * the problem (m cells per axis, a multiple of 16): the features are the mean of
+ * the problem (m cells per axis, a multiple of 2^(depth+1)): the features are the mean of
  * r over each level cell scaled by 1 / max|r| and the cell's volume fraction;
  * the output y is turned into phi = y * max|r| / phi_scale at the level cells
  * and interpolated trilinearly to the level-0 unknowns (other cells get 0).

@@ -32,7 +32,7 @@ EXPORTED = [
     "cc_vcycle", "cc_export_cells", "cc_export_plg", "cc_selfcheck_lu", "cc_export_lu_nodes", "cc_time_kernel",
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
-    "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc",
+    "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc", "cc_set_overlap", "cc_net_pairs",
     "cc_assemble_rhs_batched",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
@@ -71,7 +71,7 @@ class CcLevelInfo(C.Structure):
                 ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double),
                 ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int),
                 ("lu_tune_ms", C.c_double * 10), ("lu_waves_cap", C.c_int), ("stencil_march", C.c_int),
-                ("stencil_planes", C.c_int), ("stencil_tune_us", C.c_double * 5)]
+                ("stencil_planes", C.c_int), ("stencil_tune_us", C.c_double * 9), ("n_near", C.c_longlong)]
 
 
 class CutCellError(RuntimeError):
@@ -117,6 +117,7 @@ def load() -> C.CDLL:
     lib.cc_export_lu_nodes.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
     lib.cc_set_precision.argtypes = [vp, C.c_int]
     lib.cc_set_krylov.argtypes = [vp, C.c_int]
+    lib.cc_set_overlap.argtypes = [vp, C.c_int]
     lib.cc_set_lu_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
     lib.cc_set_stencil_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     lib.cc_get_stencil_schedule.argtypes = [vp, C.c_int, P(C.c_int), P(C.c_int)]
@@ -126,7 +127,7 @@ def load() -> C.CDLL:
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
-    lib.cc_net_create.argtypes = [C.c_int, C.c_ulonglong, vp, P(vp)]
+    lib.cc_net_create.argtypes = [C.c_int, C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
     lib.cc_net_num_params.restype = C.c_longlong
     lib.cc_net_get_params.argtypes = [vp, vp]
@@ -135,6 +136,7 @@ def load() -> C.CDLL:
     lib.cc_net_loss_grad.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, P(C.c_double), vp]
     lib.cc_net_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.cc_learned_guess.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp]
+    lib.cc_net_pairs.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_double, vp, vp, vp]
     lib.cc_net_destroy.argtypes = [vp]
     lib.cc_net_destroy.restype = None
     lib.cc_solve_batched.argtypes = [vp, C.c_int, vp, vp, P(CcSolveInfo)]
@@ -368,6 +370,10 @@ class Problem:
         """Override the build-time sweep schedule of one level's factorization."""
         _check(load().cc_set_lu_schedule(self._h, level, entries_per_lane, subtree, waves_cap))
 
+    def set_overlap(self, on: int):
+        """Far SMO-1 sweeps beside the LU-correction (1, default) or whole sweeps (0)."""
+        _check(load().cc_set_overlap(self._h, on))
+
     def set_stencil_schedule(self, level: int = -1, march: int = -1, planes: int = 0):
         """Override the regular-row kernel schedule (z-marching or one cell per
         thread, planes per workgroup) of one level (-1: all)."""
@@ -495,6 +501,22 @@ class Problem:
         n3 = self.n(level) ** 3
         _check(load().cc_vcycle(self._h, level, _ptr(s, n3), _ptr(e, n3)))
 
+    def net_pairs(self, level: int, r, phi, phi_scale: float):
+        """Training pairs (x (nrhs, m^3, 2) float32, t (nrhs, m^3) float32,
+        mask (nrhs, m^3) uint8, device tensors) of the solved problems
+        r, phi (nrhs, n^3) on level `level` (cc_net_pairs)."""
+        import torch
+        self._order()
+        nrhs = r.shape[0]
+        n3 = self.n() ** 3
+        m3 = self.n(level) ** 3
+        x = torch.empty(nrhs, m3, 2, dtype=torch.float32, device=r.device)
+        t = torch.empty(nrhs, m3, dtype=torch.float32, device=r.device)
+        mask = torch.empty(nrhs, m3, dtype=torch.uint8, device=r.device)
+        _check(load().cc_net_pairs(self._h, level, nrhs, _ptr(r, nrhs * n3), _ptr(phi, nrhs * n3), phi_scale,
+                                   C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), C.c_void_p(mask.data_ptr())))
+        return x, t, mask
+
     def learned_guess(self, net: "Net", level: int, phi_scale: float, r, phi):
         """phi <- the network's guess (see cc_learned_guess)."""
         self._order()
@@ -521,12 +543,13 @@ def _dptr(t, dtype, numel):
 class Net:
     """The learned-guess U-Net of the library (cc_net_*)."""
 
-    def __init__(self, base_channels: int = 16, seed: int = 0, stream=None):
+    def __init__(self, base_channels: int = 16, seed: int = 0, stream=None, depth: int = 3):
         h = C.c_void_p()
-        _check(load().cc_net_create(base_channels, seed, C.c_void_p(stream) if stream is not None else None,
+        _check(load().cc_net_create(base_channels, depth, seed, C.c_void_p(stream) if stream is not None else None,
                                     C.byref(h)))
         self._h = h
         self.C = base_channels
+        self.depth = depth
 
     def close(self):
         if getattr(self, "_h", None):

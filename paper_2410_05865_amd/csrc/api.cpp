@@ -141,12 +141,15 @@ void lu_sweeps(hipStream_t st, const DevLU& L, const LuDev& F, TO* out, long lon
   if (L.sub_on) launch_lu_backward_sub<T, TO>(F, L.sub, out, ostride, nb, st);
 }
 
-constexpr int kStencilTrials = 5;  // one cell per thread; marching with 4, 8, 16, 32 planes
+constexpr int kStencilTrials = 9;  // one cell per thread; marching with 4, 8, 16, 32 planes, in the
+                                   // launch order and in the XCD-aware tile order
 
 struct DevLevel {
   StencilLevel st{};
   float stencil_tune_us[kStencilTrials] = {};  // build-time trials: us per FP64 SMO-1 sweep
   int tuned_march = 0, tuned_kz = 8;           // the schedule the trials chose
+  int* near = nullptr;                         // phi_1 cells of zone 1 (the near SMO-1 sweep)
+  int n_near = 0;
   PlgRows plg{};
   DevLU lu;
   DevBuf sched;  // device task lists of lu's current schedule
@@ -233,10 +236,14 @@ struct cc_problem {
   cc::Work<double> wb64;        // batched
   cc::Work<float> wb32;
   std::vector<float*> volfrac;  // learned guess: per-level volume fractions (uploaded on demand)
+  unsigned long long* pair_norm = nullptr;  // training pairs: max|r| of each right-hand side of a group
   float* net_x = nullptr;
   float* net_y = nullptr;
   long long net_cells = 0;
   cc::Krylov kr;                // GMRES acceleration (cc_params.krylov > 0)
+  hipStream_t stream2 = nullptr;  // side stream: the far SMO-1 sweeps beside the LU-correction
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int overlap = 1;              // split SMO-1 into far and near sweeps around each SMO-2
   std::vector<double*> fmg_rhs;  // full multigrid: right-hand side and solution of levels 1..M
   std::vector<double*> fmg_x;    // (allocated on the first cc_fmg, for fmg_nb arrays)
   int fmg_nb = 0;
@@ -546,6 +553,38 @@ void upload(cc_problem* P) {
     for (int a = 0; a < 6; ++a) D.st.bc[a] = L.wall_bc[a];
     D.st.type = B.upload(L.type);
     default_stencil_schedule(L.n, D.st.march, D.st.kz);
+    // zone 1: phi_2 cells, and phi_1 cells with a phi_2 cell within 3 cells along
+    // an axis (every cell a regular row reads, ghost fills included, lies there)
+    D.st.zone = nullptr;
+    D.near = nullptr;
+    D.n_near = 0;
+    if (!L.phi2.empty()) {
+      const int nn = L.n;
+      std::vector<uint8_t> zone((size_t)nn * nn * nn, 0);
+      std::vector<int> near;
+      for (int c : L.phi2) zone[c] = 1;
+      for (int c : L.unknowns) {
+        if (L.type[c] != kPhi1) continue;
+        int ii[3];
+        L.ijk(c, ii[0], ii[1], ii[2]);
+        bool hit = false;
+        for (int d = 0; d < 3 && !hit; ++d)
+          for (int o = -3; o <= 3 && !hit; ++o) {
+            if (o == 0) continue;
+            int q[3] = {ii[0], ii[1], ii[2]};
+            q[d] += o;
+            if (q[d] < 0 || q[d] >= nn) continue;
+            hit = L.type[L.idx(q[0], q[1], q[2])] == kPhi2;
+          }
+        if (hit) {
+          zone[c] = 1;
+          near.push_back(c);
+        }
+      }
+      D.st.zone = B.upload(zone);
+      D.near = B.upload(near);
+      D.n_near = (int)near.size();
+    }
     const int N2 = (int)L.phi2.size();
     std::vector<int> cols((size_t)N2 * kPLG);
     std::vector<double> vals((size_t)N2 * kPLG);
@@ -660,8 +699,8 @@ void upload(cc_problem* P) {
     float best = 1e30f;
     int bm = S.march, bk = S.kz;
     for (int c = 0; c < kStencilTrials; ++c) {
-      const int march = c == 0 ? 0 : 1;
-      const int kz = c == 0 ? S.kz : (2 << c);      // 4, 8, 16, 32
+      const int march = c == 0 ? 0 : (c <= 4 ? 1 : 2);
+      const int kz = c == 0 ? S.kz : (2 << ((c - 1) % 4 + 1));      // 4, 8, 16, 32
       D.stencil_tune_us[c] = 0.f;
       if (march && kz > S.n) continue;
       S.march = march;
@@ -732,14 +771,38 @@ void vcycle(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, T* tmp, in
   const double om = P->prm.omega;
   T* cur = e;
   T* oth = tmp;
-  if (P->prm.nu1 == 0) launch_zero<T>(e, n3 * nb, P->stream);
-  for (int it = 0; it < P->prm.nu1; ++it) {
-    if (it == 0)  // from e = 0 the sweep is e = omega D^-1 s (no stencil reads)
-      launch_smo1_first<T>(D.st, om, s, oth, nb, P->stream);
-    else
-      launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
+  // SMO-1 after an SMO-2 splits in two: the far sweep (rows that read no phi_2
+  // cell) needs only the previous SMO-1, so it runs on the side stream beside
+  // the LU-correction; the near sweep follows the LU-correction on the main
+  // stream, and the next SMO-2 waits for both.
+  const bool split = P->overlap && D.st.zone && P->stream2;
+  auto smoothing = [&](int nu) {
+    for (int it = 0; it < nu; ++it) {
+      const bool more = it + 1 < nu;
+      if (more && split) {
+        HIPCHK(hipEventRecord(P->ev_fork, P->stream));
+        HIPCHK(hipStreamWaitEvent(P->stream2, P->ev_fork, 0));
+        launch_smo1_far<T>(D.st, om, s, cur, oth, nb, P->stream2);
+        HIPCHK(hipEventRecord(P->ev_join, P->stream2));
+      }
+      smo2<T>(P, W, m, s, cur, nb);
+      if (!more) break;
+      if (split) {
+        launch_smo1_near<T>(D.st, om, s, cur, oth, D.near, D.n_near, nb, P->stream);
+        HIPCHK(hipStreamWaitEvent(P->stream, P->ev_join, 0));
+      } else {
+        launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
+      }
+      std::swap(cur, oth);
+    }
+  };
+  if (P->prm.nu1 == 0) {
+    launch_zero<T>(e, n3 * nb, P->stream);
+  } else {
+    // from e = 0 the first sweep is e = omega D^-1 s (no stencil reads)
+    launch_smo1_first<T>(D.st, om, s, oth, nb, P->stream);
     std::swap(cur, oth);
-    smo2<T>(P, W, m, s, cur, nb);
+    smoothing(P->prm.nu1);
   }
   DevLevel& C = P->dev[m + 1];
   launch_restrict<T>(D.st, C.st, s, cur, W.s[m + 1], nb, P->stream);
@@ -747,10 +810,10 @@ void vcycle(cc_problem* P, const Work<T>& W, int m, const T* s, T* e, T* tmp, in
   // merged coarse cells take their host's value before the prolongation
   launch_copy_pairs<T>(C.n_absorbed, C.absorbed, W.e[m + 1], cube(C.st.n), nb, P->stream);
   launch_prolong_add<T>(D.st, C.st.n, W.e[m + 1], cur, nb, P->stream);
-  for (int it = 0; it < P->prm.nu2; ++it) {
+  if (P->prm.nu2 > 0) {
     launch_smo1<T>(D.st, om, s, cur, oth, nb, P->stream);
     std::swap(cur, oth);
-    smo2<T>(P, W, m, s, cur, nb);
+    smoothing(P->prm.nu2);
   }
   if (cur != e) HIPCHK(hipMemcpyAsync(e, cur, n3 * nb * sizeof(T), hipMemcpyDeviceToDevice, P->stream));
 }
@@ -1283,6 +1346,10 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         HIPCHK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
         P->own_stream = true;
       }
+      // the side stream of the far SMO-1 sweeps (default priority) and its events
+      HIPCHK(hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
     }
     // the FV-PLG least-squares fits on the device (a handle with a device and
     // fit_on_device), else on the host
@@ -1309,6 +1376,9 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     } catch (...) {
       P->buf.release();
       if (P->own_stream) (void)hipStreamDestroy(P->stream);
+      if (P->stream2) (void)hipStreamDestroy(P->stream2);
+      if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+      if (P->ev_join) (void)hipEventDestroy(P->ev_join);
       throw;
     }
     *out = P.release();
@@ -1339,9 +1409,10 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_entries_per_lane = dev ? (int)p->dev[level].lu.epl : 0;
     info->lu_waves_cap = dev && p->dev[level].lu.wcap < (1 << 30) ? p->dev[level].lu.wcap : 0;
     for (int k = 0; k < 10; ++k) info->lu_tune_ms[k] = dev ? p->dev[level].lu.tune_ms[k] : 0.0;
+    info->n_near = dev ? p->dev[level].n_near : 0;
     info->stencil_march = dev ? p->dev[level].st.march : 0;
     info->stencil_planes = dev ? p->dev[level].st.kz : 0;
-    for (int k = 0; k < 5; ++k) info->stencil_tune_us[k] = dev ? p->dev[level].stencil_tune_us[k] : 0.0;
+    for (int k = 0; k < kStencilTrials; ++k) info->stencil_tune_us[k] = dev ? p->dev[level].stencil_tune_us[k] : 0.0;
   });
 }
 
@@ -1820,6 +1891,42 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
   return rc;
 }
 
+// volume fractions of a level's cells on the device (uploaded on first use)
+static void level_volfrac(cc_problem* p, int level) {
+  if ((int)p->volfrac.size() <= level) p->volfrac.resize(level + 1, nullptr);
+  if (p->volfrac[level]) return;
+  const LevelHost& Lm = *p->lv[level];
+  const long long m3 = cube(Lm.n);
+  std::vector<float> vf(m3);
+  const double h3 = Lm.h * Lm.h * Lm.h;
+  for (long long c = 0; c < m3; ++c) vf[c] = (float)(Lm.vol[c] / h3);
+  p->volfrac[level] = p->buf.upload(vf);
+}
+
+int cc_net_pairs(cc_problem* p, int level, int nrhs, const double* r, const double* phi, double phi_scale, float* x,
+                 float* t, unsigned char* mask) {
+  return guard([&] {
+    if (!p || !r || !phi || !x || !t || !mask || nrhs < 1) fail(CC_EINVAL, "bad argument");
+    need_device(p);
+    check_level(p, level);
+    if (!(phi_scale > 0)) fail(CC_EINVAL, "phi_scale must be positive");
+    HIPCHK(hipSetDevice(p->device));
+    const int m = p->lv[level]->n, n0 = p->lv[0]->n;
+    level_volfrac(p, level);
+    const long long n3 = cube(n0);
+    for (int b0 = 0; b0 < nrhs; b0 += CC_BATCH_MAX) {
+      const int nb = std::min(CC_BATCH_MAX, nrhs - b0);
+      if (!p->pair_norm) p->pair_norm = p->buf.alloc<unsigned long long>(CC_BATCH_MAX);
+      launch_zero_u64(p->pair_norm, nb, p->stream);
+      launch_maxabs(r + b0 * n3, n3, nb, p->pair_norm, p->d_partial, p->stream);
+      const long long o = (long long)b0 * cube(m);
+      launch_net_pairs(n0, m, nb, r + b0 * n3, phi + b0 * n3, p->dev[0].st.type, p->pair_norm, p->volfrac[level],
+                       phi_scale, x + 2 * o, t + o, mask + o, p->stream);
+    }
+    HIPSYNC(p->stream);
+  });
+}
+
 int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r, double* phi) {
   return guard([&] {
     if (!p || !net || !r || !phi) fail(CC_EINVAL, "null argument");
@@ -1828,15 +1935,8 @@ int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, co
     if (!(phi_scale > 0)) fail(CC_EINVAL, "phi_scale must be positive");
     const LevelHost& Lm = *p->lv[level];
     const int m = Lm.n, n0 = p->lv[0]->n;
-    if (m % 16 != 0) fail(CC_EINVAL, "the network level needs a multiple of 16 cells per axis");
     const long long m3 = cube(m);
-    if ((int)p->volfrac.size() <= level) p->volfrac.resize(level + 1, nullptr);
-    if (!p->volfrac[level]) {
-      std::vector<float> vf(m3);
-      const double h3 = Lm.h * Lm.h * Lm.h;
-      for (long long c = 0; c < m3; ++c) vf[c] = (float)(Lm.vol[c] / h3);
-      p->volfrac[level] = p->buf.upload(vf);
-    }
+    level_volfrac(p, level);
     if (p->net_cells < m3) {
       p->net_x = p->buf.alloc<float>(2 * m3);
       p->net_y = p->buf.alloc<float>(m3);
@@ -1899,6 +1999,22 @@ int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r, 
   return worst;
 }
 
+int cc_set_overlap(cc_problem* p, int on) {
+  return guard([&] {
+    if (!p) fail(CC_EINVAL, "null problem");
+    need_device(p);
+    if (on != 0 && on != 1) fail(CC_EINVAL, "on must be 0 or 1");
+    HIPCHK(hipSetDevice(p->device));
+    HIPSYNC(p->stream);
+    p->overlap = on;
+    // captured iterations hold the old launch structure
+    p->w64.drop_graph();
+    p->w32.drop_graph();
+    p->wb64.drop_graph();
+    p->wb32.drop_graph();
+  });
+}
+
 int cc_set_krylov(cc_problem* p, int krylov) {
   return guard([&] {
     if (!p) fail(CC_EINVAL, "null problem");
@@ -1948,7 +2064,7 @@ int cc_set_stencil_schedule(cc_problem* p, int level, int march, int planes) {
     need_device(p);
     const int nl = (int)p->dev.size();
     if (level < -1 || level >= nl) fail(CC_EINVAL, "bad level");
-    if (march < -1 || march > 1) fail(CC_EINVAL, "march must be -1, 0 or 1");
+    if (march < -1 || march > 2) fail(CC_EINVAL, "march must be -1, 0, 1 or 2");
     for (int m = (level < 0 ? 0 : level); m < (level < 0 ? nl : level + 1); ++m)
       if (planes < 0 || planes > p->dev[m].st.n) fail(CC_EINVAL, "planes must lie in [0, n] of the level");
     HIPCHK(hipSetDevice(p->device));
@@ -2115,6 +2231,7 @@ void cc_destroy(cc_problem* p) {
   if (p->device >= 0) {
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->stream2) (void)hipStreamSynchronize(p->stream2);
     p->w64.drop_graph();
     for (DevLevel& d : p->dev) d.sched.release();
     p->kr.own.release();
@@ -2122,6 +2239,9 @@ void cc_destroy(cc_problem* p) {
     p->wb64.release();
     p->wb32.release();
     p->buf.release();
+    if (p->stream2) (void)hipStreamDestroy(p->stream2);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->own_stream) (void)hipStreamDestroy(p->stream);
   }
   delete p;

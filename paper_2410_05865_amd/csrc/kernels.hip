@@ -158,7 +158,7 @@ __device__ __forceinline__ void tile_ijk(int n, int& i, int& j, int& k) {
 }
 __device__ __forceinline__ long long batch_off(int n) { return (long long)blockIdx.y * n * n * n; }
 
-template <class T>
+template <class T, bool Far = false>
 __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T* __restrict__ ein,
                        T* __restrict__ eout) {
   const int n = L.n;
@@ -170,6 +170,7 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
   ein += o;
   eout += o;
   long c = i + (long)n * (j + (long)n * k);
+  if (Far && L.zone[c]) return;
   T v = ein[c];
   if (L.type[c] == 1) {
     T diag;
@@ -177,6 +178,28 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
     T a = regular_row<T>(L, ein, i, j, k, c, diag);
     v += omega * (ld_stream(s + c) - a * inv) / (diag * inv);
   }
+  st_stream(v, eout + c);
+}
+
+// SMO-1 on a list of phi_1 cells (the near sweep), one thread each, the
+// arithmetic of k_smo1.
+template <class T>
+__global__ void k_smo1_list(StencilLevel L, T omega, const T* __restrict__ s, const T* __restrict__ ein,
+                            T* __restrict__ eout, const int* __restrict__ cells, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const int n = L.n;
+  const long long o = batch_off(n);
+  s += o;
+  ein += o;
+  eout += o;
+  const long c = cells[t];
+  const int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((long)n * n));
+  T v = ein[c];
+  T diag;
+  const T inv = T(L.inv12h2);
+  T a = regular_row<T>(L, ein, i, j, k, c, diag);
+  v += omega * (ld_stream(s + c) - a * inv) / (diag * inv);
   st_stream(v, eout + c);
 }
 
@@ -192,10 +215,11 @@ __global__ void k_smo1(StencilLevel L, T omega, const T* __restrict__ s, const T
 // memory instructions per cell against 15 for the one-cell-per-thread kernels,
 // in the same arithmetic order (identical results).
 //   kMarchSmo:      eout = e + omega (b - A e) / D on phi_1 cells, e elsewhere
+//   kMarchSmoFar:   the same, written only where zone is 0
 //   kMarchResidual: eout = b - A e on phi_1 cells, 0 elsewhere
 //   kMarchApply:    eout = A e on phi_1 cells, 0 elsewhere (b unused)
 constexpr int kHalo = 3;
-enum { kMarchSmo = 0, kMarchResidual = 1, kMarchApply = 2 };
+enum { kMarchSmo = 0, kMarchResidual = 1, kMarchApply = 2, kMarchSmoFar = 3 };
 template <class T>
 struct MarchPlane {
   T y[4];      // operand at y offsets -2, -1, +1, +2
@@ -203,13 +227,23 @@ struct MarchPlane {
   T h;         // halo cell (lanes 0 .. 5)
   int type;
 };
+// Workgroups go to the 8 XCDs round-robin (workgroup w to XCD w mod 8).  The
+// XCD-aware order gives XCD x one contiguous range of tiles, in order: the
+// z-blocks of a column then follow each other on one XCD (the 3 halo planes
+// each shares with the next one come from that XCD's L2) and neighbouring
+// columns run there at the same time (the y-halo rows).  A bijection of
+// [0, T): XCD x receives q + (x < T mod 8) workgroups, q = T / 8.
+__device__ __forceinline__ int xcd_tile(int w, int T) {
+  const int q = T / 8, rem = T % 8, x = w % 8;
+  return x * q + min(x, rem) + w / 8;
+}
 template <class T, int Mode>
 __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const T* __restrict__ bv,
                                            const T* __restrict__ ein, T* __restrict__ eout, int kz) {
   __shared__ T row[4][64 + 2 * kHalo];
   const int n = L.n;
   const int nzb = (n + kz - 1) / kz;
-  int blk = blockIdx.x;
+  int blk = L.march == 2 ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
   const int zb = blk % nzb;
   blk /= nzb;
   const int ny = (n + 3) / 4;
@@ -272,7 +306,7 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        T v = Mode == kMarchSmo ? q[kHalo] : T(0);
+        T v = (Mode == kMarchSmo || Mode == kMarchSmoFar) ? q[kHalo] : T(0);
         if (valid && cur.type == 1) {
           T diag = T(0);
           T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
@@ -282,14 +316,14 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
               },
               j, n, L.bc[2], L.bc[3], diag);
           a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
-          if constexpr (Mode == kMarchSmo)
+          if constexpr (Mode == kMarchSmo || Mode == kMarchSmoFar)
             v += omega * (cur.b - a * inv) / (diag * inv);
           else if constexpr (Mode == kMarchResidual)
             v = cur.b - a * inv;
           else
             v = a * inv;
         }
-        if (valid) st_stream(v, eout + c);
+        if (valid && (Mode != kMarchSmoFar || L.zone[c] == 0)) st_stream(v, eout + c);
         // every lane's reads of this row precede the next plane's writes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -305,6 +339,11 @@ template <class T>
 __global__ __launch_bounds__(256) void k_smo1_z(StencilLevel L, T omega, const T* __restrict__ s,
                                                 const T* __restrict__ ein, T* __restrict__ eout, int kz) {
   march_body<T, kMarchSmo>(L, omega, s, ein, eout, kz);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_smo1_far_z(StencilLevel L, T omega, const T* __restrict__ s,
+                                                    const T* __restrict__ ein, T* __restrict__ eout, int kz) {
+  march_body<T, kMarchSmoFar>(L, omega, s, ein, eout, kz);
 }
 __global__ __launch_bounds__(256) void k_stencil_residual_z(StencilLevel L, const double* __restrict__ r,
                                                             const double* __restrict__ x, double* __restrict__ s,
@@ -1110,6 +1149,44 @@ __global__ void k_set_values(int count, const int* __restrict__ cells, const dou
 
 // Learned-guess features on a coarse level of m^3 cells: x[V][0] = mean of r
 // over the V's (n0/m)^3 fine cells times inv_norm, x[V][1] = volume fraction.
+// Training pairs of the learned guess on an m^3 level of an n0^3 problem, for
+// nb right-hand sides (r, phi: nb arrays of n0^3) with max|r_b| in norm[b] (bit
+// patterns): x[b][V] = (mean of r_b over V's fine cells / max|r_b|, volume
+// fraction), t[b][V] = phi_scale * (mean of phi_b over V's fine cells that
+// carry an unknown) / max|r_b|, mask[b][V] = 1 where V holds such a cell.
+__global__ void k_net_pairs(int n0, int m, const double* __restrict__ r, const double* __restrict__ phi,
+                            const uint8_t* __restrict__ type0, const unsigned long long* __restrict__ norm,
+                            const float* __restrict__ volfrac, double phi_scale, float* __restrict__ x,
+                            float* __restrict__ t, uint8_t* __restrict__ mask) {
+  const long long m3 = (long long)m * m * m, n3 = (long long)n0 * n0 * n0;
+  const long long V = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (V >= m3) return;
+  r += b * n3;
+  phi += b * n3;
+  const int f = n0 / m;
+  const int I = (int)(V % m), J = (int)((V / m) % m), K = (int)(V / ((long long)m * m));
+  double sr = 0.0, sp = 0.0;
+  int cnt = 0;
+  for (int dz = 0; dz < f; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const long long c = (I * f + dx) + (long long)n0 * ((J * f + dy) + (long long)n0 * (K * f + dz));
+        sr += r[c];
+        if (type0[c] != 0) {
+          sp += phi[c];
+          ++cnt;
+        }
+      }
+  const double rn = __longlong_as_double((long long)norm[b]);
+  const double inv = rn > 0.0 ? 1.0 / rn : 0.0;
+  const long long o = b * m3 + V;
+  x[2 * o] = (float)(sr / ((double)f * f * f) * inv);
+  x[2 * o + 1] = volfrac[V];
+  t[o] = cnt > 0 ? (float)(phi_scale * (sp / cnt) * inv) : 0.f;
+  mask[o] = cnt > 0 ? 1 : 0;
+}
+
 __global__ void k_net_features(int n0, int m, const double* __restrict__ r, double inv_norm,
                                const float* __restrict__ volfrac, float* __restrict__ x) {
   long long V = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1298,6 +1375,24 @@ void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in,
   hipLaunchKernelGGL(k_smo1_z<T>, march_grid(n, kz, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
 }
 template <class T>
+void launch_smo1_far(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb,
+                     hipStream_t st) {
+  const int n = L.n;
+  if (!L.march) {
+    hipLaunchKernelGGL((k_smo1<T, true>), grid_tiles(n, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out);
+    return;
+  }
+  const int kz = L.kz;
+  hipLaunchKernelGGL(k_smo1_far_z<T>, march_grid(n, kz, nb), kBlock3, 0, st, L, T(omega), s, e_in, e_out, kz);
+}
+template <class T>
+void launch_smo1_near(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, const int* cells,
+                      int count, int nb, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_smo1_list<T>, dim3(blocks(count, 256), nb), dim3(256), 0, st, L, T(omega), s, e_in, e_out,
+                     cells, count);
+}
+template <class T>
 void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st) {
   hipLaunchKernelGGL(k_smo1_first<T>, grid_tiles(L.n, nb), kBlock3, 0, st, L, T(omega), s, e_out);
 }
@@ -1465,6 +1560,13 @@ void launch_set_values(int count, const int* cells, const double* vals, double* 
   if (count == 0) return;
   hipLaunchKernelGGL(k_set_values, dim3(blocks(count, 256)), dim3(256), 0, st, count, cells, vals, a);
 }
+void launch_net_pairs(int n0, int m, int nb, const double* r, const double* phi, const uint8_t* type0,
+                      const unsigned long long* norm, const float* volfrac, double phi_scale, float* x, float* t,
+                      uint8_t* mask, hipStream_t st) {
+  const long long m3 = (long long)m * m * m;
+  hipLaunchKernelGGL(k_net_pairs, dim3(blocks(m3, 256), nb), dim3(256), 0, st, n0, m, r, phi, type0, norm, volfrac,
+                     phi_scale, x, t, mask);
+}
 void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
                          hipStream_t st) {
   const long long m3 = (long long)m * m * m;
@@ -1533,6 +1635,9 @@ void launch_cell_average(int n, double h, const double* origin, const FieldDesc&
 #define CC_INST(T)                                                                                            \
   template void launch_smo1<T>(const StencilLevel&, double, const T*, const T*, T*, int, hipStream_t);        \
   template void launch_smo1_first<T>(const StencilLevel&, double, const T*, T*, int, hipStream_t);           \
+  template void launch_smo1_far<T>(const StencilLevel&, double, const T*, const T*, T*, int, hipStream_t);    \
+  template void launch_smo1_near<T>(const StencilLevel&, double, const T*, const T*, T*, const int*, int, int, \
+                                    hipStream_t);                                                             \
   template void launch_restrict<T>(const StencilLevel&, const StencilLevel&, const T*, const T*, T*, int,     \
                                    hipStream_t);                                                              \
   template void launch_prolong_add<T>(const StencilLevel&, int, const T*, T*, int, hipStream_t);              \

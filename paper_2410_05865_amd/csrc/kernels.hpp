@@ -18,8 +18,11 @@ struct StencilLevel {
   double inv12h2;        // 1 / (12 h^2)
   int bc[6];             // wall conditions -x,+x,-y,+y,-z,+z
   const uint8_t* type;   // 0 no unknown, 1 phi_1, 2 phi_2
-  int march;             // regular-row kernels (SMO-1, residual, apply): 1 march in z, 0 one cell per thread
+  int march;             // regular-row kernels (SMO-1, residual, apply): 1 march in z, 2 march in z with the
+                         // XCD-aware tile order, 0 one cell per thread
   int kz;                // planes per workgroup of the marching kernels
+  const uint8_t* zone;   // 1: a phi_2 cell or a phi_1 cell whose row reads within 3 cells of one (the far
+                         // sweep leaves these to the near sweep); null on levels without phi_2 cells
 };
 
 // The build's choice of the regular-row kernel schedule for an n^3 level.
@@ -111,6 +114,17 @@ void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in,
 // first sweep of a level from e = 0: e_out = omega D^-1 s on phi_1 cells, 0 elsewhere
 template <class T>
 void launch_smo1_first(const StencilLevel& L, double omega, const T* s, T* e_out, int nb, hipStream_t st);
+// SMO-1 split in two for overlap with the LU-correction: the far sweep writes
+// every cell whose zone is 0 (phi_1 rows that read no phi_2 cell, and cells
+// without an unknown, passed through), the near sweep the listed phi_1 cells of
+// zone 1 (phi_2 cells are left alone: the next SMO-2 overwrites them).  Both
+// compute exactly what launch_smo1 computes for their cells.
+template <class T>
+void launch_smo1_far(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb,
+                     hipStream_t st);
+template <class T>
+void launch_smo1_near(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, const int* cells,
+                      int count, int nb, hipStream_t st);
 template <class T>
 void launch_restrict(const StencilLevel& F, const StencilLevel& C, const T* s, const T* e, T* sc, int nb,
                      hipStream_t st);
@@ -187,6 +201,10 @@ void launch_dots_norm(long long n3, const double* w, const double* V, long long 
 // trilinear prolongation of the network output to the level-0 unknowns
 void launch_net_features(int n0, int m, const double* r, double inv_norm, const float* volfrac, float* x,
                          hipStream_t st);
+// training pairs (features, targets, mask) of nb solved problems on an m^3 level
+void launch_net_pairs(int n0, int m, int nb, const double* r, const double* phi, const uint8_t* type0,
+                      const unsigned long long* norm, const float* volfrac, double phi_scale, float* x, float* t,
+                      uint8_t* mask, hipStream_t st);
 void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
                               hipStream_t st);
 

@@ -3,22 +3,25 @@
 // to a scaled solution.  The multigrid solve stays the judge: the network only
 // supplies phi_0.  Not part of the paper's method; an addition on top of it.
 //
-// Architecture (C = base channels, grid n divisible by 16):
-//   e1 = relu(conv(x, 16 -> C))             n      (x: 2 input channels padded to 16)
-//   e2 = relu(conv(pool(e1), C -> 2C))      n/2
-//   b  = relu(conv(pool(e2), 2C -> 2C))     n/4
-//   d2 = relu(conv([up(b), e2], 4C -> 2C))  n/2
-//   d1 = relu(conv([up(d2), e1], 3C -> C))  n
-//   y  = conv(d1, C -> 16)[channel 0]       n      (output channels 1..15 held at 0)
+// Architecture (C = base channels, D = 3 or 4 levels, grid n divisible by
+// 2^(D+1)); encoder channels w_l = C on the upper levels, 2C on the two coarsest:
+//   e_0 = relu(conv(x, 16 -> w_0))                       n      (x: 2 input channels padded to 16)
+//   e_l = relu(conv(pool(e_{l-1}), w_{l-1} -> w_l))      n/2^l, l = 1 .. D-2
+//   b   = relu(conv(pool(e_{D-2}), w_{D-2} -> w_{D-1}))  n/2^(D-1)
+//   d_l = relu(conv([up(d_{l+1}), e_l], w_{l+1} + w_l -> w_l))   l = D-2 .. 0 (d_{D-1} = b)
+//   y   = conv(d_0, w_0 -> 16)[channel 0]                n      (output channels 1..15 held at 0)
 // conv: 3x3x3, zero padding, bias; pool: 2x2x2 average; up: nearest.
+// D = 3 with C = 32 has 521k parameters, D = 4 with C = 32 581k.
 //
 // Activations are channel-last ([batch][voxel][channel], voxel i + n (j + n k)).
-// A conv is an implicit GEMM (voxels x taps*Cin x Cout) on
-// v_mfma_f32_16x16x16_bf16: a wavefront computes 16 voxels x Cout.  Backward:
-// data gradients are the forward conv of the output gradient with the
-// transposed, flipped kernel; weight gradients are a GEMM over voxels staged
-// through LDS, one workgroup per (tap, voxel range), accumulated with FP32
-// atomics.
+// A conv is an implicit GEMM (voxels x taps*Cin x Cout): a wavefront computes
+// 16 voxels x Cout, on v_mfma_f32_16x16x32_bf16 (gfx950's double-K BF16 MFMA,
+// 32 input channels per instruction) where Cin is a multiple of 32, else on
+// v_mfma_f32_16x16x16_bf16.  Backward: data gradients are the forward conv of
+// the output gradient with the transposed, flipped kernel; weight gradients
+// are a GEMM over voxels staged through LDS (32 voxels per MFMA), one
+// workgroup per (tap, voxel range) writing per-range partials that a second
+// kernel adds in a fixed order (no atomics: training is reproducible).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -41,7 +44,16 @@ namespace {
   } while (0)
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// D (16 x 16) += A (16 x 32) B (32 x 16) in BF16: lane l holds A[l % 16][8 (l / 16) + t]
+// and B[8 (l / 16) + t][l % 16], t = 0..7, and D[4 (l / 16) + q][l % 16], q = 0..3
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                  0);
+}
 
 __host__ __device__ inline uint16_t f2bf(float f) {
   uint32_t u;
@@ -64,7 +76,7 @@ struct View {
 
 // ---------------------------------------------------------------- conv forward
 // grid: nb * n^3 / 64 blocks of 256 threads (4 waves x 16 voxels).
-template <int NT>
+template <int NT, bool K32>
 __global__ void __launch_bounds__(256) k_conv_fwd(int n, View in, int cin, const uint16_t* __restrict__ wt,
                                                   const float* __restrict__ bias, int relu, View out,
                                                   float* __restrict__ out32) {
@@ -85,15 +97,30 @@ __global__ void __launch_bounds__(256) k_conv_fwd(int n, View in, int cin, const
     const int ii = i + dx, jj = j + dy, kk = k + dz;
     const bool inside = ii >= 0 && ii < n && jj >= 0 && jj < n && kk >= 0 && kk < n;
     const long long vn = b * n3 + ii + (long long)n * (jj + (long long)n * kk);
-    const uint16_t* arow = in.p + vn * in.cs + in.co + 4 * kg;
-    const uint16_t* wrow = wt + ((long long)tap * cout + r) * cin + 4 * kg;
-    for (int ci0 = 0; ci0 < cin; ci0 += 16) {
-      v4s a = v4s{0, 0, 0, 0};
-      if (inside) a = *reinterpret_cast<const v4s*>(arow + ci0);
+    if constexpr (K32) {
+      // 32 input channels per instruction: lane group kg holds channels 8 kg .. 8 kg + 7
+      const uint16_t* arow = in.p + vn * in.cs + in.co + 8 * kg;
+      const uint16_t* wrow = wt + ((long long)tap * cout + r) * cin + 8 * kg;
+      for (int ci0 = 0; ci0 < cin; ci0 += 32) {
+        v8s a = v8s{0, 0, 0, 0, 0, 0, 0, 0};
+        if (inside) a = *reinterpret_cast<const v8s*>(arow + ci0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const v4s bw = *reinterpret_cast<const v4s*>(wrow + (long long)t * 16 * cin + ci0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+          const v8s bw = *reinterpret_cast<const v8s*>(wrow + (long long)t * 16 * cin + ci0);
+          acc[t] = mfma32(a, bw, acc[t]);
+        }
+      }
+    } else {
+      const uint16_t* arow = in.p + vn * in.cs + in.co + 4 * kg;
+      const uint16_t* wrow = wt + ((long long)tap * cout + r) * cin + 4 * kg;
+      for (int ci0 = 0; ci0 < cin; ci0 += 16) {
+        v4s a = v4s{0, 0, 0, 0};
+        if (inside) a = *reinterpret_cast<const v4s*>(arow + ci0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const v4s bw = *reinterpret_cast<const v4s*>(wrow + (long long)t * 16 * cin + ci0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+        }
       }
     }
   }
@@ -163,15 +190,15 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(int n, long long nvox, View 
       if (tile >= ntile) break;
       const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
 #pragma unroll
-      for (int ks = 0; ks < kWgChunk; ks += 16) {
-        v4s a, bw;
+      for (int ks = 0; ks < kWgChunk; ks += 32) {
+        v8s a, bw;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int vv = ks + 4 * kg + q;
+        for (int q = 0; q < 8; ++q) {
+          const int vv = ks + 8 * kg + q;
           a[q] = (short)lg[vv * cout + m0 + r];
           bw[q] = (short)li[vv * cin + n0 + r];
         }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[t], 0, 0, 0);
+        acc[t] = mfma32(a, bw, acc[t]);
       }
     }
   }
@@ -389,8 +416,10 @@ using namespace cc;
 
 struct cc_net {
   int C = 16;
+  int depth = 3;              // levels of the U-Net (3 or 4)
   hipStream_t stream = nullptr;
-  std::vector<Layer> layers;
+  std::vector<Layer> layers;  // encoder 0 .. depth-2, bottleneck, decoder depth-2 .. 0, output
+  std::vector<int> width;     // channels of the encoder levels 0 .. depth-1
   long long np = 0;
   DevMem pmem;                // parameters and optimizer state
   float* w = nullptr;         // FP32 master weights
@@ -401,13 +430,13 @@ struct cc_net {
   uint16_t* wb = nullptr;     // BF16 copy
   uint16_t* wf = nullptr;     // flipped transpose scratch (largest layer)
   long long step = 0;
-  // activations for (n, nb)
+  // activations for (n, nb), per level l: CAT[l] = [up(coarser result) | e_l]
+  // (the encoder output written beside the upsampled decoder input), P[l] the
+  // pooled e_l, DD[l] the decoder output; BT the bottleneck
   int an = 0, anb = 0;
   DevMem amem;
-  uint16_t *X0 = nullptr, *CAT1 = nullptr, *P1 = nullptr, *CAT2 = nullptr, *P2 = nullptr, *BT = nullptr,
-           *D2 = nullptr, *D1 = nullptr, *Y = nullptr;
-  uint16_t *GY = nullptr, *GD1 = nullptr, *GCAT1 = nullptr, *GD2 = nullptr, *GCAT2 = nullptr, *GBT = nullptr,
-           *GP2 = nullptr, *GP1 = nullptr;
+  uint16_t *X0 = nullptr, *BT = nullptr, *Y = nullptr, *GY = nullptr, *GBT = nullptr;
+  std::vector<uint16_t*> CAT, P, DD, GCAT, GP, GDD;
   float* Y32 = nullptr;
   float* red = nullptr;       // [0] loss sum, [1] mask count
   float* part = nullptr;      // per-split / per-block gradient and loss partials
@@ -416,19 +445,28 @@ struct cc_net {
 namespace cc {
 namespace {
 
-void launch_conv(cc_net* N, int n, int nb, View in, int cin, const uint16_t* wt, const float* bias, int cout,
-                 int relu, View out, float* out32) {
+template <bool K32>
+void launch_conv_k(cc_net* N, int n, int nb, View in, int cin, const uint16_t* wt, const float* bias, int cout,
+                   int relu, View out, float* out32) {
   const long long nvox = (long long)nb * n * n * n;
   dim3 grid((unsigned)(nvox / 64)), block(256);
   switch (cout / 16) {
-    case 1: hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
-    case 2: hipLaunchKernelGGL(k_conv_fwd<2>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
-    case 3: hipLaunchKernelGGL(k_conv_fwd<3>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
-    case 4: hipLaunchKernelGGL(k_conv_fwd<4>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
-    case 6: hipLaunchKernelGGL(k_conv_fwd<6>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
-    case 8: hipLaunchKernelGGL(k_conv_fwd<8>, grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<1, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<2, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<3, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd<4, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd<6, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
+    case 8: hipLaunchKernelGGL((k_conv_fwd<8, K32>), grid, block, 0, N->stream, n, in, cin, wt, bias, relu, out, out32); break;
     default: fail(CC_EINVAL, "unsupported channel count");
   }
+}
+// the double-K instruction where the input channels come in whole groups of 32
+void launch_conv(cc_net* N, int n, int nb, View in, int cin, const uint16_t* wt, const float* bias, int cout,
+                 int relu, View out, float* out32) {
+  if (cin % 32 == 0)
+    launch_conv_k<true>(N, n, nb, in, cin, wt, bias, cout, relu, out, out32);
+  else
+    launch_conv_k<false>(N, n, nb, in, cin, wt, bias, cout, relu, out, out32);
 }
 
 // gradients of one conv layer: dW, db from (in, g); gin = conv(g, flipped W) if gin.p
@@ -454,39 +492,50 @@ void conv_backward(cc_net* N, const Layer& L, int n, int nb, View in, View g, Vi
   }
 }
 
+// layer indices: encoder l (0 .. D-2), bottleneck D-1, decoder l at 2D-2-l, output 2D-1
+inline int level_of_layer(int D, int li) {
+  if (li < D - 1) return li;
+  if (li == D - 1) return D - 1;
+  if (li < 2 * D - 1) return 2 * D - 2 - li;
+  return 0;
+}
+
 void ensure_acts(cc_net* N, int n, int nb) {
   if (N->an == n && N->anb == nb) return;
   N->amem.release();
-  const int C = N->C;
-  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  const int D = N->depth;
+  const std::vector<int>& w = N->width;
   DevMem& A = N->amem;
-  N->X0 = A.alloc<uint16_t>(v1 * 16);
-  N->CAT1 = A.alloc<uint16_t>(v1 * 3 * C);
-  N->P1 = A.alloc<uint16_t>(v2 * C);
-  N->CAT2 = A.alloc<uint16_t>(v2 * 4 * C);
-  N->P2 = A.alloc<uint16_t>(v4 * 2 * C);
-  N->BT = A.alloc<uint16_t>(v4 * 2 * C);
-  N->D2 = A.alloc<uint16_t>(v2 * 2 * C);
-  N->D1 = A.alloc<uint16_t>(v1 * C);
-  N->Y = A.alloc<uint16_t>(v1 * 16);
-  N->GY = A.alloc<uint16_t>(v1 * 16);
-  N->GD1 = A.alloc<uint16_t>(v1 * C);
-  N->GCAT1 = A.alloc<uint16_t>(v1 * 3 * C);
-  N->GD2 = A.alloc<uint16_t>(v2 * 2 * C);
-  N->GCAT2 = A.alloc<uint16_t>(v2 * 4 * C);
-  N->GBT = A.alloc<uint16_t>(v4 * 2 * C);
-  N->GP2 = A.alloc<uint16_t>(v4 * 2 * C);
-  N->GP1 = A.alloc<uint16_t>(v2 * C);
-  N->Y32 = A.alloc<float>(v1);
+  std::vector<long long> v(D);
+  for (int l = 0; l < D; ++l) v[l] = ((long long)nb * n * n * n) >> (3 * l);
+  N->X0 = A.alloc<uint16_t>(v[0] * 16);
+  N->Y = A.alloc<uint16_t>(v[0] * 16);
+  N->GY = A.alloc<uint16_t>(v[0] * 16);
+  N->BT = A.alloc<uint16_t>(v[D - 1] * w[D - 1]);
+  N->GBT = A.alloc<uint16_t>(v[D - 1] * w[D - 1]);
+  N->CAT.assign(D - 1, nullptr);
+  N->P.assign(D - 1, nullptr);
+  N->DD.assign(D - 1, nullptr);
+  N->GCAT.assign(D - 1, nullptr);
+  N->GP.assign(D - 1, nullptr);
+  N->GDD.assign(D - 1, nullptr);
+  for (int l = 0; l < D - 1; ++l) {
+    N->CAT[l] = A.alloc<uint16_t>(v[l] * (w[l + 1] + w[l]));
+    N->GCAT[l] = A.alloc<uint16_t>(v[l] * (w[l + 1] + w[l]));
+    N->P[l] = A.alloc<uint16_t>(v[l + 1] * w[l]);
+    N->GP[l] = A.alloc<uint16_t>(v[l + 1] * w[l]);
+    N->DD[l] = A.alloc<uint16_t>(v[l] * w[l]);
+    N->GDD[l] = A.alloc<uint16_t>(v[l] * w[l]);
+  }
+  N->Y32 = A.alloc<float>(v[0]);
   N->red = A.alloc<float>(2);
   // partials: the largest of splits x 27 cout cin over the layers (at their
   // resolutions), the bias partials, and two per-block loss arrays
   {
-    static const int level_of[6] = {0, 1, 2, 1, 0, 0};
-    long long need = 2LL * nblk(v1);
+    long long need = 2LL * nblk(v[0]);
     for (size_t li = 0; li < N->layers.size(); ++li) {
       const Layer& L = N->layers[li];
-      const long long nv = v1 >> (3 * level_of[li]);
+      const long long nv = v[level_of_layer(D, (int)li)];
       need = std::max(need, (long long)wgrad_splits(nv) * 27 * L.cout * L.cin);
       need = std::max(need, (long long)kBiasBlocks * L.cout);
     }
@@ -496,59 +545,96 @@ void ensure_acts(cc_net* N, int n, int nb) {
   N->anb = nb;
 }
 
+// views of level l: the concatenation, its upsampled part and its skip part
+inline View cat_view(cc_net* N, int l) { return View{N->CAT[l], N->width[l + 1] + N->width[l], 0}; }
+inline View skip_view(cc_net* N, int l) {
+  return View{N->CAT[l], N->width[l + 1] + N->width[l], N->width[l + 1]};
+}
+inline View gcat_view(cc_net* N, int l) { return View{N->GCAT[l], N->width[l + 1] + N->width[l], 0}; }
+inline View gskip_view(cc_net* N, int l) {
+  return View{N->GCAT[l], N->width[l + 1] + N->width[l], N->width[l + 1]};
+}
+
 void forward(cc_net* N, int n, int nb, const float* x) {
-  const int C = N->C;
-  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  const int D = N->depth;
+  const std::vector<int>& w = N->width;
   hipStream_t st = N->stream;
   const std::vector<Layer>& L = N->layers;
-  hipLaunchKernelGGL(k_pack, dim3(nblk(v1 * 16)), dim3(256), 0, st, v1, x, N->X0);
-  const View x0{N->X0, 16, 0}, e1{N->CAT1, 3 * C, 2 * C}, u1{N->CAT1, 3 * C, 0}, cat1{N->CAT1, 3 * C, 0};
-  const View p1{N->P1, C, 0}, e2{N->CAT2, 4 * C, 2 * C}, u2{N->CAT2, 4 * C, 0}, cat2{N->CAT2, 4 * C, 0};
-  const View p2{N->P2, 2 * C, 0}, bt{N->BT, 2 * C, 0}, d2{N->D2, 2 * C, 0}, d1{N->D1, C, 0}, y{N->Y, 16, 0};
-  launch_conv(N, n, nb, x0, 16, N->wb + L[0].offW, N->w + L[0].offB, C, 1, e1, nullptr);
-  hipLaunchKernelGGL(k_pool, dim3(nblk(v2 * C)), dim3(256), 0, st, n, nb, e1, p1, C);
-  launch_conv(N, n / 2, nb, p1, C, N->wb + L[1].offW, N->w + L[1].offB, 2 * C, 1, e2, nullptr);
-  hipLaunchKernelGGL(k_pool, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, n / 2, nb, e2, p2, 2 * C);
-  launch_conv(N, n / 4, nb, p2, 2 * C, N->wb + L[2].offW, N->w + L[2].offB, 2 * C, 1, bt, nullptr);
-  hipLaunchKernelGGL(k_up, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n / 2, nb, bt, u2, 2 * C);
-  launch_conv(N, n / 2, nb, cat2, 4 * C, N->wb + L[3].offW, N->w + L[3].offB, 2 * C, 1, d2, nullptr);
-  hipLaunchKernelGGL(k_up, dim3(nblk(v1 * 2 * C)), dim3(256), 0, st, n, nb, d2, u1, 2 * C);
-  launch_conv(N, n, nb, cat1, 3 * C, N->wb + L[4].offW, N->w + L[4].offB, C, 1, d1, nullptr);
-  launch_conv(N, n, nb, d1, C, N->wb + L[5].offW, N->w + L[5].offB, 16, 0, y, N->Y32);
+  const long long v0 = (long long)nb * n * n * n;
+  hipLaunchKernelGGL(k_pack, dim3(nblk(v0 * 16)), dim3(256), 0, st, v0, x, N->X0);
+  // encoder: conv + ReLU into the skip slot, then 2x2x2 average pooling
+  View in{N->X0, 16, 0};
+  int cin = 16;
+  for (int l = 0; l < D - 1; ++l) {
+    const int nl = n >> l;
+    launch_conv(N, nl, nb, in, cin, N->wb + L[l].offW, N->w + L[l].offB, w[l], 1, skip_view(N, l), nullptr);
+    const long long vn = ((long long)nb * nl * nl * nl) / 8;
+    hipLaunchKernelGGL(k_pool, dim3(nblk(vn * w[l])), dim3(256), 0, st, nl, nb, skip_view(N, l), View{N->P[l], w[l], 0},
+                       w[l]);
+    in = View{N->P[l], w[l], 0};
+    cin = w[l];
+  }
+  const int nc = n >> (D - 1);
+  launch_conv(N, nc, nb, in, cin, N->wb + L[D - 1].offW, N->w + L[D - 1].offB, w[D - 1], 1, View{N->BT, w[D - 1], 0},
+              nullptr);
+  // decoder: nearest upsampling of the coarser result beside the skip, conv + ReLU
+  View cur{N->BT, w[D - 1], 0};
+  for (int l = D - 2; l >= 0; --l) {
+    const int nl = n >> l;
+    const long long vl = (long long)nb * nl * nl * nl;
+    hipLaunchKernelGGL(k_up, dim3(nblk(vl * w[l + 1])), dim3(256), 0, st, nl, nb, cur, cat_view(N, l), w[l + 1]);
+    const Layer& Ld = L[2 * D - 2 - l];
+    launch_conv(N, nl, nb, cat_view(N, l), w[l + 1] + w[l], N->wb + Ld.offW, N->w + Ld.offB, w[l], 1,
+                View{N->DD[l], w[l], 0}, nullptr);
+    cur = View{N->DD[l], w[l], 0};
+  }
+  const Layer& Lo = L[2 * D - 1];
+  launch_conv(N, n, nb, cur, w[0], N->wb + Lo.offW, N->w + Lo.offB, 16, 0, View{N->Y, 16, 0}, N->Y32);
 }
 
 void backward(cc_net* N, int n, int nb) {
-  const int C = N->C;
-  const long long v1 = (long long)nb * n * n * n, v2 = v1 / 8, v4 = v1 / 64;
+  const int D = N->depth;
+  const std::vector<int>& w = N->width;
   hipStream_t st = N->stream;
   const std::vector<Layer>& L = N->layers;
-  const View x0{N->X0, 16, 0}, e1{N->CAT1, 3 * C, 2 * C}, cat1{N->CAT1, 3 * C, 0};
-  const View p1{N->P1, C, 0}, e2{N->CAT2, 4 * C, 2 * C}, cat2{N->CAT2, 4 * C, 0};
-  const View p2{N->P2, 2 * C, 0}, bt{N->BT, 2 * C, 0}, d2{N->D2, 2 * C, 0}, d1{N->D1, C, 0};
-  const View gy{N->GY, 16, 0}, gd1{N->GD1, C, 0}, gcat1{N->GCAT1, 3 * C, 0}, gu1{N->GCAT1, 3 * C, 0},
-      ge1{N->GCAT1, 3 * C, 2 * C};
-  const View gd2{N->GD2, 2 * C, 0}, gcat2{N->GCAT2, 4 * C, 0}, gu2{N->GCAT2, 4 * C, 0}, ge2{N->GCAT2, 4 * C, 2 * C};
-  const View gbt{N->GBT, 2 * C, 0}, gp2{N->GP2, 2 * C, 0}, gp1{N->GP1, C, 0};
   const View none{nullptr, 0, 0};
-  conv_backward(N, L[5], n, nb, d1, gy, gd1);
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v1 * C)), dim3(256), 0, st, v1, C, gd1, d1);
-  conv_backward(N, L[4], n, nb, cat1, gd1, gcat1);
-  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n, nb, gu1, gd2, 2 * C);
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, v2, 2 * C, gd2, d2);
-  conv_backward(N, L[3], n / 2, nb, cat2, gd2, gcat2);
-  hipLaunchKernelGGL(k_up_bwd, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, n / 2, nb, gu2, gbt, 2 * C);
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v4 * 2 * C)), dim3(256), 0, st, v4, 2 * C, gbt, bt);
-  conv_backward(N, L[2], n / 4, nb, p2, gbt, gp2);
-  hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, n / 2, nb, gp2, ge2, 2 * C);
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v2 * 2 * C)), dim3(256), 0, st, v2, 2 * C, ge2, e2);
-  conv_backward(N, L[1], n / 2, nb, p1, ge2, gp1);
-  hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblk(v1 * C)), dim3(256), 0, st, n, nb, gp1, ge1, C);
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(v1 * C)), dim3(256), 0, st, v1, C, ge1, e1);
-  conv_backward(N, L[0], n, nb, x0, ge1, none);
+  auto vox = [&](int l) { return ((long long)nb * n * n * n) >> (3 * l); };
+  // output layer, then the decoder from the finest level down
+  conv_backward(N, L[2 * D - 1], n, nb, View{N->DD[0], w[0], 0}, View{N->GY, 16, 0}, View{N->GDD[0], w[0], 0});
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(vox(0) * w[0])), dim3(256), 0, st, vox(0), w[0], View{N->GDD[0], w[0], 0},
+                     View{N->DD[0], w[0], 0});
+  for (int l = 0; l < D - 1; ++l) {
+    const int nl = n >> l;
+    conv_backward(N, L[2 * D - 2 - l], nl, nb, cat_view(N, l), View{N->GDD[l], w[l], 0}, gcat_view(N, l));
+    // the upsampled part's gradient, summed over each parent's 8 children
+    const bool bott = l + 1 == D - 1;
+    const View gnext = bott ? View{N->GBT, w[D - 1], 0} : View{N->GDD[l + 1], w[l + 1], 0};
+    const View act = bott ? View{N->BT, w[D - 1], 0} : View{N->DD[l + 1], w[l + 1], 0};
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblk(vox(l + 1) * w[l + 1])), dim3(256), 0, st, nl, nb, gcat_view(N, l), gnext,
+                       w[l + 1]);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(vox(l + 1) * w[l + 1])), dim3(256), 0, st, vox(l + 1), w[l + 1], gnext,
+                       act);
+  }
+  // bottleneck, then the encoder from the coarsest level up
+  conv_backward(N, L[D - 1], n >> (D - 1), nb, View{N->P[D - 2], w[D - 2], 0}, View{N->GBT, w[D - 1], 0},
+                View{N->GP[D - 2], w[D - 2], 0});
+  for (int l = D - 2; l >= 0; --l) {
+    const int nl = n >> l;
+    hipLaunchKernelGGL(k_pool_bwd_add, dim3(nblk(vox(l) * w[l])), dim3(256), 0, st, nl, nb, View{N->GP[l], w[l], 0},
+                       gskip_view(N, l), w[l]);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(vox(l) * w[l])), dim3(256), 0, st, vox(l), w[l], gskip_view(N, l),
+                       skip_view(N, l));
+    const View in = l == 0 ? View{N->X0, 16, 0} : View{N->P[l - 1], w[l - 1], 0};
+    const View gin = l == 0 ? none : View{N->GP[l - 1], w[l - 1], 0};
+    conv_backward(N, L[l], nl, nb, in, gskip_view(N, l), gin);
+  }
 }
 
-void check_shape(int n, int nb) {
-  if (n < 16 || n % 16 != 0) fail(CC_EINVAL, "grid size must be a positive multiple of 16");
+void check_shape(const cc_net* N, int n, int nb) {
+  // the coarsest level (n / 2^(depth-1)) must hold whole 64-voxel groups per sample
+  const int q = 4 << (N->depth - 1);
+  if (n < q || n % q != 0)
+    fail(CC_EINVAL, "grid size must be a positive multiple of " + std::to_string(q) + " for this depth");
   if (nb < 1) fail(CC_EINVAL, "batch must be positive");
 }
 
@@ -574,20 +660,29 @@ int net_guard(F&& f) {
 
 extern "C" {
 
-int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_net** out) {
+int cc_net_create(int base_channels, int depth, unsigned long long seed, void* stream, cc_net** out) {
   return net_guard([&] {
     if (!out) fail(CC_EINVAL, "null output");
     *out = nullptr;
     if (base_channels != 16 && base_channels != 32) fail(CC_EINVAL, "base_channels must be 16 or 32");
+    if (depth != 3 && depth != 4) fail(CC_EINVAL, "depth must be 3 or 4");
     auto N = std::make_unique<cc_net>();
     N->C = base_channels;
+    N->depth = depth;
     N->stream = (hipStream_t)stream;
-    const int C = base_channels;
-    const int io[6][2] = {{16, C}, {C, 2 * C}, {2 * C, 2 * C}, {4 * C, 2 * C}, {3 * C, C}, {C, 16}};
+    const int C = base_channels, D = depth;
+    // encoder channels: C on the upper levels, 2C on the two coarsest
+    for (int l = 0; l < D; ++l) N->width.push_back(l < D - 2 ? C : 2 * C);
+    const std::vector<int>& wd = N->width;
+    std::vector<std::pair<int, int>> io = {{16, wd[0]}};
+    for (int l = 1; l < D - 1; ++l) io.push_back({wd[l - 1], wd[l]});
+    io.push_back({wd[D - 2], wd[D - 1]});
+    for (int l = D - 2; l >= 0; --l) io.push_back({wd[l + 1] + wd[l], wd[l]});
+    io.push_back({wd[0], 16});
     long long off = 0;
     for (auto& p : io) {
-      Layer L{p[0], p[1], off, off + 27LL * p[0] * p[1]};
-      off = L.offB + p[1];
+      Layer L{p.first, p.second, off, off + 27LL * p.first * p.second};
+      off = L.offB + p.second;
       N->layers.push_back(L);
     }
     N->np = off;
@@ -597,6 +692,7 @@ int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_n
     std::vector<float> w(off, 0.f);
     std::vector<uint8_t> frozen(off, 0);
     std::mt19937_64 rng(seed);
+    const size_t last = N->layers.size() - 1;
     for (size_t li = 0; li < N->layers.size(); ++li) {
       const Layer& L = N->layers[li];
       const int real_in = li == 0 ? 2 : L.cin;
@@ -605,12 +701,12 @@ int cc_net_create(int base_channels, unsigned long long seed, void* stream, cc_n
         for (int co = 0; co < L.cout; ++co)
           for (int ci = 0; ci < L.cin; ++ci) {
             long long e = L.offW + ((long long)tap * L.cout + co) * L.cin + ci;
-            bool pad = (li == 0 && ci >= 2) || (li == 5 && co >= 1);
+            bool pad = (li == 0 && ci >= 2) || (li == last && co >= 1);
             w[e] = pad ? 0.f : nd(rng);
-            if (li == 5 && co >= 1) frozen[e] = 1;
+            if (li == last && co >= 1) frozen[e] = 1;
           }
       for (int co = 0; co < L.cout; ++co)
-        if (li == 5 && co >= 1) frozen[L.offB + co] = 1;
+        if (li == last && co >= 1) frozen[L.offB + co] = 1;
     }
     DevMem& P = N->pmem;
     N->w = P.alloc<float>(off);
@@ -655,7 +751,7 @@ int cc_net_set_params(cc_net* N, const float* host) {
 int cc_net_forward(cc_net* N, int n, int nb, const float* x, float* y) {
   return net_guard([&] {
     if (!N || !x || !y) fail(CC_EINVAL, "null argument");
-    check_shape(n, nb);
+    check_shape(N, n, nb);
     ensure_acts(N, n, nb);
     forward(N, n, nb, x);
     const long long v1 = (long long)nb * n * n * n;
@@ -668,7 +764,7 @@ int cc_net_loss_grad(cc_net* N, int n, int nb, const float* x, const float* targ
                      double* loss, float* grad_host) {
   return net_guard([&] {
     if (!N || !x || !target || !mask) fail(CC_EINVAL, "null argument");
-    check_shape(n, nb);
+    check_shape(N, n, nb);
     ensure_acts(N, n, nb);
     const long long v1 = (long long)nb * n * n * n;
     hipStream_t st = N->stream;
@@ -680,9 +776,10 @@ int cc_net_loss_grad(cc_net* N, int n, int nb, const float* x, const float* targ
                        N->GY);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, 1LL, nbk, N->part + nbk, N->red);
     // gradient buffers that are accumulated into must start at zero
-    const int C = N->C;
-    hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(v1 * 3 * C)), dim3(256), 0, st, v1 * 3 * C, N->GCAT1);
-    hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(v1 / 8 * 4 * C)), dim3(256), 0, st, v1 / 8 * 4 * C, N->GCAT2);
+    for (int l = 0; l < N->depth - 1; ++l) {
+      const long long cnt = (v1 >> (3 * l)) * (N->width[l + 1] + N->width[l]);
+      hipLaunchKernelGGL(k_fill0_u16, dim3(nblk(cnt)), dim3(256), 0, st, cnt, N->GCAT[l]);
+    }
     hipLaunchKernelGGL(k_fill0, dim3(nblk(N->np)), dim3(256), 0, st, N->np, N->g);
     backward(N, n, nb);
     float red[2];

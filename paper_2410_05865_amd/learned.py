@@ -1,15 +1,17 @@
 """Training data and training loop of the learned initial guess.
 
 Pairs come from the solver itself: for each seeded geometry of the ellipsoid
-family, right-hand sides f = sums of seeded Gaussians (g = 0) are assembled,
-solved to 1e-10 with the batched multigrid solve, and reduced to the level
-the network works on (m cells per axis):
+family, independent right-hand sides f = sums of 16 seeded Gaussians (g = 0)
+are assembled in one batched call, solved to 1e-10 with the batched multigrid
+solve, and reduced by the library (cc_net_pairs) to the level the network
+works on (m cells per axis):
   features  x[V] = (mean of r over V) / max|r|,  volume fraction of V
   target    t[V] = PHI_SCALE * (mean of phi over the unknown cells of V) / max|r|
   mask      V holds at least one unknown cell.
 The network (cc_net_*, the library's BF16-MFMA kernels) is trained with Adam
 on the masked mean-square loss; at solve time `Problem.learned_guess` builds
 the same features on the device and interpolates the output to the fine grid.
+PyTorch only holds the device arrays and picks the mini-batches.
 """
 from __future__ import annotations
 
@@ -22,29 +24,24 @@ from . import _lib, inputs
 PHI_SCALE = 100.0
 
 
-def _block_mean(a, n: int, m: int):
-    f = n // m
-    return a.view(-1, m, f, m, f, m, f).mean(dim=(2, 4, 6)).reshape(a.shape[0], m ** 3)
-
-
-def make_pairs(n_fine: int = 128, level: int = 1, geometries: int = 8, rhs_per_geometry: int = 32,
-               base: int = 4, seed: int = 0, log=None):
+def make_pairs(n_fine: int = 128, level: int = 2, geometries: int = 8, rhs_per_geometry: int = 64,
+               seed: int = 0, log=None):
     """Solver-generated (features, target, mask) at level `level` of n_fine
-    problems; returns float32/uint8 CUDA tensors (S, m^3, 2), (S, m^3), (S, m^3)."""
+    problems (geometry seeds 10000 + 100 seed + g, right-hand-side seeds drawn
+    from `seed`); returns float32/uint8 CUDA tensors (S, m^3, 2), (S, m^3),
+    (S, m^3) and the number of geometries used."""
     import torch
     xs, ts, ms = [], [], []
     rng = np.random.default_rng(seed)
+    used = 0
     for g in range(geometries):
         t0 = time.perf_counter()
         dom = inputs.ellipsoid_domain(n=n_fine, seed=10_000 + seed * 100 + g)
         P = _lib.Problem(dom)
         n3 = n_fine ** 3
-        m = P.n(level)
-        basis = torch.zeros(base, n3, dtype=torch.float64, device="cuda")
-        for k in range(base):
-            P.assemble_rhs(inputs.gaussian_rhs(dom, seed=int(rng.integers(1 << 30))), None, basis[k])
-        coef = torch.from_numpy(rng.uniform(-1.0, 1.0, size=(rhs_per_geometry, base))).cuda()
-        r = (coef @ basis).contiguous()
+        fields = [inputs.gaussian_rhs(dom, seed=int(rng.integers(1 << 30))) for _ in range(rhs_per_geometry)]
+        r = torch.zeros(rhs_per_geometry, n3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs_batched(fields, None, r)
         phi = torch.zeros_like(r)
         infos = P.solve_batched(r, phi)
         if not all(i["converged"] for i in infos):
@@ -54,23 +51,16 @@ def make_pairs(n_fine: int = 128, level: int = 1, geometries: int = 8, rhs_per_g
                 log(f"[learned] geometry {g}: solve did not converge, skipped")
             P.close()
             continue
-        typ, _, _ = P.export_cells(0)
-        unk = torch.from_numpy((typ != 0).astype(np.float64)).cuda()
-        _, _, vf = P.export_cells(level)
-        rn = r.abs().amax(dim=1, keepdim=True)
-        x = torch.zeros(rhs_per_geometry, m ** 3, 2, dtype=torch.float32, device="cuda")
-        x[:, :, 0] = (_block_mean(r, n_fine, m) / rn).float()
-        x[:, :, 1] = torch.from_numpy(vf.astype(np.float32)).cuda()
-        num = _block_mean(phi * unk, n_fine, m)
-        den = _block_mean(unk.expand_as(phi), n_fine, m)
-        t = torch.where(den > 0, num / den.clamp_min(1e-30), torch.zeros_like(num)) * PHI_SCALE / rn
+        x, t, mask = P.net_pairs(level, r, phi, PHI_SCALE)
         xs.append(x)
-        ts.append(t.float())
-        ms.append((den > 0).to(torch.uint8))
+        ts.append(t)
+        ms.append(mask)
+        used += 1
+        del r, phi
         P.close()
         if log:
             log(f"[learned] geometry {g}: {rhs_per_geometry} pairs in {time.perf_counter() - t0:.1f} s")
-    return torch.cat(xs), torch.cat(ts), torch.cat(ms)
+    return torch.cat(xs), torch.cat(ts), torch.cat(ms), used
 
 
 def train(net, x, t, mask, m: int, steps: int = 400, batch: int = 4, lr: float = 1e-3, seed: int = 0,
@@ -94,25 +84,25 @@ def train(net, x, t, mask, m: int, steps: int = 400, batch: int = 4, lr: float =
 
 
 def relative_error(net, x, t, mask, m: int):
-    """Masked max-norm relative error of the network on the pairs."""
+    """Masked max-norm relative error of the network on the pairs (on the host)."""
     import torch
     y = torch.zeros(x.shape[0], m ** 3, dtype=torch.float32, device="cuda")
     for s in range(x.shape[0]):
         net.forward(x[s:s + 1].contiguous(), y[s:s + 1], m, 1)
-    mk = mask.bool()
-    err = ((y - t).abs() * mk).amax(dim=1) / ((t.abs() * mk).amax(dim=1).clamp_min(1e-30))
-    return err.cpu().numpy()
+    yh, th, mk = y.cpu().numpy(), t.cpu().numpy(), mask.cpu().numpy().astype(bool)
+    err = np.max(np.abs(yh - th) * mk, axis=1) / np.maximum(np.max(np.abs(th) * mk, axis=1), 1e-30)
+    return err
 
 
-def fit(n_fine: int = 128, level: int = 1, geometries: int = 8, rhs_per_geometry: int = 32, steps: int = 2000,
-        batch: int = 8, lr: float = 1e-3, base_channels: int = 16, seed: int = 0, log=None):
+def fit(n_fine: int = 128, level: int = 2, geometries: int = 8, rhs_per_geometry: int = 64, steps: int = 2000,
+        batch: int = 8, lr: float = 1e-3, base_channels: int = 16, depth: int = 3, seed: int = 0, log=None):
     """Generate pairs and train a network (Adam, learning rate lr for half of
     the steps, lr/3 and lr/10 for a quarter each).  Returns (net, info)."""
     t0 = time.perf_counter()
-    x, t, mask = make_pairs(n_fine, level, geometries, rhs_per_geometry, seed=seed, log=log)
+    x, t, mask, used = make_pairs(n_fine, level, geometries, rhs_per_geometry, seed=seed, log=log)
     t_data = time.perf_counter() - t0
     m = round(x.shape[1] ** (1.0 / 3.0))
-    net = _lib.Net(base_channels, seed=seed + 1)
+    net = _lib.Net(base_channels, seed=seed + 1, depth=depth)
     t1 = time.perf_counter()
     hist = []
     for phase, (st, l) in enumerate(((steps // 2, lr), (steps // 4, lr / 3), (steps - steps // 2 - steps // 4, lr / 10))):
@@ -120,7 +110,8 @@ def fit(n_fine: int = 128, level: int = 1, geometries: int = 8, rhs_per_geometry
                       log_every=max(1, steps // 4))
     t_train = time.perf_counter() - t1
     err = relative_error(net, x[: min(32, x.shape[0])], t[: min(32, x.shape[0])], mask[: min(32, x.shape[0])], m)
-    info = {"pairs": int(x.shape[0]), "grid": m, "data_s": t_data, "train_s": t_train, "steps": steps,
+    info = {"pairs": int(x.shape[0]), "geometries": used, "fine_grid": n_fine, "grid": m, "depth": depth,
+            "base_channels": base_channels, "data_s": t_data, "train_s": t_train, "steps": steps,
             "first_loss": hist[0], "final_loss": hist[-1], "train_median_rel_err": float(np.median(err)),
             "params": net.num_params}
     return net, info

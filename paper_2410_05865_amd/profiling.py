@@ -118,6 +118,27 @@ def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
         out.append("")
         out.append(f"{SMO_KERNEL} level-0 dispatches of the timing hook (grid {g[0]}x{g[1]}x{g[2]} work-items, "
                    f"{n}^3 cells): {len(v)} dispatches, average {np.mean(v):.1f} us, median {np.median(v):.1f} us")
+    # the level-0 LU-correction of the timing hook: the last run of consecutive
+    # k_lu_* dispatches holds whole corrections of equal length; per launch
+    # position (forward heights up, then backward heights down) the mean duration
+    lu = [i for i, s in enumerate(seq) if s[0].startswith("k_lu_")]
+    if lu:
+        tail = [lu[-1]]
+        while tail[-1] - 1 >= 0 and seq[tail[-1] - 1][0].startswith("k_lu_"):
+            tail.append(tail[-1] - 1)
+        tail = tail[::-1]
+        # launches per correction: the pattern repeats; find the period
+        names = [seq[i][0] for i in tail]
+        per = next((p for p in range(2, len(names) // 2 + 1)
+                    if len(names) % p == 0 and names == names[:p] * (len(names) // p)), len(names))
+        reps = len(names) // per
+        d = np.array([seq[i][2] for i in tail]).reshape(reps, per)
+        # the first correction warms up
+        m = d[1:].mean(axis=0) if reps > 1 else d[0]
+        out.append("")
+        out.append(f"Level-0 LU-correction of the timing hook ({reps} corrections of {per} launches, the first "
+                   f"left out of the means): {m.sum():.1f} us per correction; launches in order (us): "
+                   + ", ".join(f"{x:.1f}" for x in m))
     return "\n".join(out)
 
 

@@ -77,10 +77,11 @@ def test_integer_decisions_identical(case):
     assert gap.max() < 1e-11
 
 
-@pytest.mark.parametrize("sched", [(-1, 0), (1, 8), (1, 16)])
+@pytest.mark.parametrize("sched", [(-1, 0), (1, 8), (1, 16), (2, 16)])
 def test_steps_match_oracle(case, sched):
     """(-1, 0): the build's autotuned schedule; (1, 8) and (1, 16): the
-    z-marching kernels with one and two unrolled chunks of 8 planes."""
+    z-marching kernels with one and two unrolled chunks of 8 planes; (2, 16):
+    the same in the XCD-aware tile order."""
     L, P, g, phi, x, r = case
     P.set_stencil_schedule(0, *sched)
     try:

@@ -31,31 +31,32 @@ def _inputs(n, nb, seed):
     return x, t, mask, dev(x), dev(t), dev(mask)
 
 
-@pytest.mark.parametrize("C", [16, 32])
-def test_forward_and_gradients_match_reference(C):
+@pytest.mark.parametrize("C,depth,n,nb", [(16, 3, 16, 2), (32, 3, 16, 2), (32, 4, 32, 1)])
+def test_forward_and_gradients_match_reference(C, depth, n, nb):
     """The device network equals the reference with the same BF16 rounding
     points to a few BF16 ulps (FP32 versus FP64 accumulation can move a rounding
-    by one ulp), and the exact-arithmetic reference to BF16 accuracy."""
+    by one ulp), and the exact-arithmetic reference to BF16 accuracy; layers
+    whose input channels come in groups of 32 run on the double-K MFMA."""
     L = _lib()
-    n, nb = 16, 2
-    net = L.Net(C, seed=3)
+    net = L.Net(C, seed=3, depth=depth)
     params = net.get_params().astype(np.float64)
-    assert params.size == ol.num_params(C)
+    assert params.size == ol.num_params(C, depth)
     x, t, mask, xd, td, md = _inputs(n, nb, 5)
-    print(f"[learned] C={C} forward", flush=True)
+    print(f"[learned] C={C} depth={depth} forward", flush=True)
     y = torch.zeros(nb, n ** 3, dtype=torch.float32, device="cuda")
     net.forward(xd, y, n, nb)
     yg = y.cpu().numpy().reshape(nb, n, n, n)
-    y_bf, _ = ol.forward(params, x.astype(np.float64), C, bf16=True)
-    y_ex, _ = ol.forward(params, x.astype(np.float64), C, bf16=False)
+    y_bf, _ = ol.forward(params, x.astype(np.float64), C, bf16=True, depth=depth)
+    y_ex, _ = ol.forward(params, x.astype(np.float64), C, bf16=False, depth=depth)
     assert _rel(yg, y_bf) < 2e-2
     assert _rel(yg, y_ex) < 5e-2
     print(f"  forward rel err vs bf16 ref {_rel(yg, y_bf):.2e}, vs exact {_rel(yg, y_ex):.2e}", flush=True)
     loss, g = net.loss_grad(xd, td, md, n, nb, want_grad=True)
-    loss_bf, g_bf = ol.loss_and_grad(params, x.astype(np.float64), t.astype(np.float64), mask, C, bf16=True)
+    loss_bf, g_bf = ol.loss_and_grad(params, x.astype(np.float64), t.astype(np.float64), mask, C, bf16=True,
+                                     depth=depth)
     assert loss == pytest.approx(loss_bf, rel=1e-2)
     off = 0
-    for li, (ci, co) in enumerate(ol.layer_shapes(C)):
+    for li, (ci, co) in enumerate(ol.layer_shapes(C, depth)):
         for name, size in (("W", 27 * ci * co), ("b", co)):
             a, b = g[off:off + size].astype(np.float64), g_bf[off:off + size]
             off += size
@@ -104,21 +105,20 @@ def test_training_is_reproducible():
 
 
 def test_learned_guess_in_solve():
-    """Train on solver-generated pairs (64^3 problems, network on the 32^3
-    level), then solve held-out problems from the network's guess.  The guessed
-    solves reach the same tolerance and the same solution; the V-cycles saved
-    are reported (a few percent here: the coarse prediction carries ~25% error
-    and its interpolation adds high-frequency residual that the first V-cycle
-    removes), and on average the guess does not cost V-cycles."""
+    """Train on solver-generated pairs (64^3 problems, network on their 32^3
+    level; pairs built by the library from batched assembly and solves), then
+    solve held-out problems from the network's guess.  The guessed solves reach
+    the same tolerance and the same solution, and on average they take fewer
+    V-cycles than from the zero guess."""
     L = _lib()
     from paper_2410_05865_amd import inputs, learned
     log = lambda s: print(s, flush=True)
-    net, info = learned.fit(n_fine=64, level=1, geometries=6, rhs_per_geometry=32, steps=1200, seed=2, log=log)
+    net, info = learned.fit(n_fine=64, level=1, geometries=6, rhs_per_geometry=64, steps=1500, seed=2, log=log)
     log(f"[learned] {info}")
-    assert info["pairs"] >= 64
+    assert info["pairs"] >= 128
     assert info["final_loss"] < 0.1 * info["first_loss"]
     gains = []
-    for s in range(3):
+    for s in range(4):
         dom = inputs.ellipsoid_domain(n=64, seed=777 + s)
         P = L.Problem(dom)
         r = torch.zeros(64 ** 3, dtype=torch.float64, device="cuda")
@@ -136,5 +136,5 @@ def test_learned_guess_in_solve():
         gains.append(i0["iterations"] - i1["iterations"])
         P.close()
     log(f"[learned] V-cycles saved per solve: {gains}")
-    assert np.mean(gains) >= 0
+    assert np.mean(gains) > 0
     net.close()

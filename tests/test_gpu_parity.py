@@ -103,10 +103,11 @@ def test_stencil_autotuner_choice(pair):
     for m in range(P.num_levels):
         info = P.level_info(m)
         t = info["stencil_tune_us"]
-        assert t[0] > 0 and info["stencil_march"] in (0, 1)
-        tried = [(0, t[0])] + [(2 << c, t[c]) for c in range(1, 5) if t[c] > 0]
-        best = min(v for _, v in tried)
-        chosen = t[0] if info["stencil_march"] == 0 else t[{4: 1, 8: 2, 16: 3, 32: 4}[info["stencil_planes"]]]
+        assert t[0] > 0 and info["stencil_march"] in (0, 1, 2)
+        best = min(v for v in t if v > 0)
+        slot = {4: 1, 8: 2, 16: 3, 32: 4}
+        mk = info["stencil_march"]
+        chosen = t[0] if mk == 0 else t[slot[info["stencil_planes"]] + (4 if mk == 2 else 0)]
         assert chosen == best
         assert P.stencil_schedule(m) == (info["stencil_march"], info["stencil_planes"])
 
@@ -180,11 +181,43 @@ def test_one_vcycle(pair):
     assert _rel(_host(e)[lv.unknowns], ref) < 1e-12
 
 
+def test_overlap_matches_whole_sweeps(pair):
+    """SMO-1 split into a far sweep beside the LU-correction and a near sweep
+    after it computes what the whole sweep computes: one V-cycle and the
+    converged solve agree with overlap off and with the oracle."""
+    name, dom, F, H, P = pair
+    rng = np.random.default_rng(12)
+    lv = H.fine
+    s = _dev(lv.to_grid(rng.standard_normal(lv.N)))
+    out = {}
+    for on in (0, 1):
+        P.set_overlap(on)
+        e = _dev(np.zeros(lv.n ** 3))
+        P.vcycle(0, s, e)
+        out[on] = _host(e)[lv.unknowns]
+    P.set_overlap(1)
+    assert _rel(out[1], out[0]) < 1e-13
+    ref = H.vcycle(0, _host(s)[lv.unknowns], MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
+    assert _rel(out[1], ref) < 1e-12
+    r_or, x_or, hist = _oracle_solution(name, H, F)
+    sols = {}
+    for on in (0, 1):
+        P.set_overlap(on)
+        phi = _dev(np.zeros(lv.n ** 3))
+        info = P.solve(_dev(lv.to_grid(r_or)), phi)
+        assert info["converged"] and info["iterations"] == len(hist) - 1
+        sols[on] = _host(phi)[lv.unknowns]
+    P.set_overlap(1)
+    assert _rel(sols[1], sols[0]) < 1e-12
+    assert _rel(sols[1], x_or) < 1e-11
+
+
 # regular-row kernel schedules: (march, planes per workgroup); march 0 is one
 # cell per thread.  8, 16 and 32 planes are the counts the build picks for
 # 96^3-192^3, 256^3 and 512^3 grids (one, two and four unrolled chunks of 8);
-# 5 leaves a ragged last chunk and z-block; 96 is one z-block per column.
-SCHEDULES = [(0, 0), (1, 8), (1, 16), (1, 32), (1, 5), (1, 96)]
+# 5 leaves a ragged last chunk and z-block; 96 is one z-block per column;
+# march 2 hands the tiles to the XCDs in contiguous ranges.
+SCHEDULES = [(0, 0), (1, 8), (1, 16), (1, 32), (1, 5), (1, 96), (2, 16), (2, 5)]
 _ORACLE_SOLUTIONS = {}
 
 
