@@ -14,7 +14,7 @@ with HIP events on the library's stream), and the CPU oracle timed on a
 bounded sample (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--batch 64]
-                    [--no-mixed] [--no-batch] [--no-fmg] [--no-table4] [--no-cpu-baseline]
+                    [--no-mixed] [--no-batch] [--no-fmg] [--no-table4] [--no-multi] [--no-cpu-baseline] [--learned]
     python bench.py --large-mixed 0         # skip the FP64 and mixed solves of the same workload at 512^3
     python bench.py --kernels-only          # only the timing hooks (for counter runs)
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
@@ -136,49 +136,72 @@ def _timed(fn, steps: int, warmup: int):
 
 
 def _table4_leg(args, sec_plain_value=None):
-    """The paper's Table 4 solving-time workload (unit cube minus the sphere of
-    radius 0.3, its 'Multigrid solution' 146.46 s at h = 1/256 on one CPU
-    thread, tolerance unstated): time to 1e-10 from the zero guess with the
-    paper's omega = 0.5 and with omega = 0.8, and FMG(2) then V-cycles."""
+    """The paper's Table 4 solving-time workloads at h = 1/n: the unit cube
+    minus the sphere of radius 0.3 at the centre ('Multigrid solution' 146.46 s
+    at h = 1/256 on one CPU thread) and minus the torus of Problem 2 (R = 0.2,
+    r = 0.1; 380.84 s at h = 1/256); tolerance unstated.  Time to 1e-10 from
+    the zero guess with the paper's omega = 0.5 and with omega = 0.8, and
+    FMG(2) then V-cycles; the build time of each problem beside the paper's
+    two setup rows."""
     import torch
     from paper_2410_05865_amd import _lib, inputs as inp
     dev = torch.device("cuda:0")
-    dom, phi = inp.sphere03_workload(args.n)
     n3 = args.n ** 3
-    out = {"workload": f"unit cube minus the sphere r = 0.3 at the centre, {args.n}^3, Dirichlet walls and sphere, "
-                       f"phi = exp(x + y/2) cos(3z)", "paper_multigrid_solution_s": 146.46 if args.n == 256 else None,
-           "paper_conditions": "AMD Ryzen 9 7950X, one thread, omega 0.5, nu 3/3, tolerance not stated"}
-    for omega in (0.5, 0.8):
-        P = _lib.Problem(dom, omega=omega)
-        r = torch.zeros(n3, dtype=torch.float64, device=dev)
-        P.assemble_rhs(phi, phi, r, f_mode=_lib.CC_LAPLACIAN)
-        x = torch.zeros_like(r)
+    paper = {"sphere": {64: (8.25, 0.70, 5.72), 128: (8.10, 5.94, 24.76), 256: (7.96, 61.57, 146.46),
+                        512: (7.90, 489.50, 1385.97)},
+             "torus": {64: (10.71, 0.43, 7.32), 128: (10.73, 3.21, 51.60), 256: (10.52, 30.85, 380.84),
+                       512: (10.25, 273.04, 3073.53)}}
+    out = {"paper_conditions": "AMD Ryzen 9 7950X, one thread, omega 0.5, nu 3/3, tolerance not stated"}
+    for name in ("sphere", "torus"):
+        if name == "sphere":
+            dom, phi = inp.sphere03_workload(args.n)
+            desc = (f"unit cube minus the sphere r = 0.3 at the centre, {args.n}^3, Dirichlet walls and sphere, "
+                    f"phi = exp(x + y/2) cos(3z)")
+        else:
+            dom, phi = inp.torus_problem(args.n)
+            desc = (f"unit cube minus the torus R = 0.2, r = 0.1 about the z axis through the centre (Problem 2), "
+                    f"{args.n}^3, Dirichlet walls, Neumann torus, u = cos(pi x) cos(pi y) sin(pi z)")
+        pp = paper[name].get(args.n)
+        res = {"workload": desc,
+               "paper_s": None if pp is None else {"setup_bottom": pp[0], "setup_lu_correction": pp[1],
+                                                   "multigrid_solution": pp[2]}}
+        for omega in (0.5, 0.8):
+            t0 = time.perf_counter()
+            P = _lib.Problem(dom, omega=omega)
+            t_build = time.perf_counter() - t0
+            r = torch.zeros(n3, dtype=torch.float64, device=dev)
+            P.assemble_rhs(phi, phi, r, f_mode=_lib.CC_LAPLACIAN)
+            x = torch.zeros_like(r)
 
-        def solve():
-            x.zero_()
-            return P.solve(r, x)
-        s, info = _timed(solve, args.steps, args.warmup)
-        leg = {"s_per_solve": s, "v_cycles": info["iterations"], "final_rel_residual": info["rel_residual"]}
-        if omega == 0.8:
-            coarse = []
-            for m in range(1, P.num_levels):
-                rm = torch.zeros(P.n(m) ** 3, dtype=torch.float64, device=dev)
-                P.assemble_rhs(phi, phi, rm, f_mode=_lib.CC_LAPLACIAN, level=m)
-                coarse.append(rm)
-
-            def fmg_solve():
+            def solve():
                 x.zero_()
-                P.fmg(r, x, 2, coarse_rhs=coarse)
                 return P.solve(r, x)
-            sf, info_f = _timed(fmg_solve, args.steps, args.warmup)
-            leg["fmg2_then_vcycles"] = {"s_per_solve": sf, "v_cycles_after_fmg": info_f["iterations"],
-                                        "final_rel_residual": info_f["rel_residual"]}
-            print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 sphere, omega 0.8, FMG(2) then V-cycles: {sf * 1e3:.1f} ms, "
-                  f"{info_f['iterations']} V-cycles", file=sys.stderr, flush=True)
-        print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 sphere, omega {omega}: {s * 1e3:.1f} ms, {info['iterations']} V-cycles",
-              file=sys.stderr, flush=True)
-        out[f"omega_{omega}"] = leg
-        P.close()
+            s, info = _timed(solve, args.steps, args.warmup)
+            leg = {"s_per_solve": s, "v_cycles": info["iterations"], "final_rel_residual": info["rel_residual"],
+                   "build_s": t_build, "unknowns": P.level_info(0)["n_unknowns"]}
+            if omega == 0.8:
+                coarse = []
+                for m in range(1, P.num_levels):
+                    rm = torch.zeros(P.n(m) ** 3, dtype=torch.float64, device=dev)
+                    P.assemble_rhs(phi, phi, rm, f_mode=_lib.CC_LAPLACIAN, level=m)
+                    coarse.append(rm)
+
+                def fmg_solve():
+                    x.zero_()
+                    P.fmg(r, x, 2, coarse_rhs=coarse)
+                    return P.solve(r, x)
+                sf, info_f = _timed(fmg_solve, args.steps, args.warmup)
+                leg["fmg2_then_vcycles"] = {"s_per_solve": sf, "v_cycles_after_fmg": info_f["iterations"],
+                                            "final_rel_residual": info_f["rel_residual"]}
+                print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 {name}, omega 0.8, FMG(2) then V-cycles: "
+                      f"{sf * 1e3:.1f} ms, {info_f['iterations']} V-cycles", file=sys.stderr, flush=True)
+            if pp is not None:
+                leg["speedup_vs_paper_multigrid_solution"] = pp[2] / s
+            print(f"[bench {time.perf_counter() - T_START:6.1f} s] Table 4 {name}, omega {omega}: {s * 1e3:.1f} ms, "
+                  f"{info['iterations']} V-cycles (build {t_build:.1f} s)", file=sys.stderr, flush=True)
+            res[f"omega_{omega}"] = leg
+            P.close()
+        out[name] = res
     return out
 
 
@@ -218,20 +241,22 @@ def _large_mixed_leg(args):
     return out
 
 
-MULTI_SIZES = (64, 96, 128, 160, 192)
+# uneven sizes whose coarsest level (the bottom LU, factored on the host at
+# set-up) stays at or below 40^3, so the leg's eight builds take seconds each
+MULTI_SIZES = (64, 72, 80, 128)
+MULTI_COUNT = 8
 
 
 def _multi_leg(args):
-    """16 geometries of the ellipsoid family of uneven sizes (64^3, 96^3,
-    128^3, 160^3, 192^3 in turn: four at 64^3, three at each other size; seeds
-    2000..2015), each with a Gaussian right-hand side, solved with GMRES(20)
-    one after the other and all at once (cc_solve_multi: one stream and host
-    thread per problem)."""
+    """8 geometries of the ellipsoid family of uneven sizes (64^3, 72^3, 80^3,
+    128^3 in turn, two of each; seeds 2000..2007), each with a Gaussian
+    right-hand side, solved with GMRES(20) one after the other and all at once
+    (cc_solve_multi: one stream and host thread per problem)."""
     import torch
     from paper_2410_05865_amd import _lib, inputs
     t0 = time.perf_counter()
     probs, rs, phis, dofs = [], [], [], 0
-    for i in range(16):
+    for i in range(MULTI_COUNT):
         n = MULTI_SIZES[i % len(MULTI_SIZES)]
         dom = inputs.ellipsoid_domain(n=n, seed=2000 + i)
         P = _lib.Problem(dom, krylov=args.krylov)
@@ -261,10 +286,10 @@ def _multi_leg(args):
     s_con, i_con = _timed(conc, 1, 1)
     for P in probs:
         P.close()
-    print(f"[bench {time.perf_counter() - T_START:6.1f} s] 16 geometries: sequential {s_seq * 1e3:.0f} ms, concurrent {s_con * 1e3:.0f} ms", file=sys.stderr,
-          flush=True)
-    return {"problems": "16 ellipsoid geometries of 64^3-192^3 (4 x 64^3, 3 each of 96^3, 128^3, 160^3, 192^3; "
-                        "seeds 2000-2015), Gaussian right-hand sides, "
+    print(f"[bench {time.perf_counter() - T_START:6.1f} s] {MULTI_COUNT} geometries: sequential {s_seq * 1e3:.0f} ms, "
+          f"concurrent {s_con * 1e3:.0f} ms (set-up {t_setup:.0f} s)", file=sys.stderr, flush=True)
+    return {"problems": f"{MULTI_COUNT} ellipsoid geometries of sizes {', '.join(f'{m}^3' for m in MULTI_SIZES)} in turn "
+                        f"(seeds 2000-{2000 + MULTI_COUNT - 1}), Gaussian right-hand sides, "
                         f"GMRES({args.krylov}) with the V-cycle",
             "unknowns": dofs, "setup_s": t_setup, "sequential_s": s_seq, "concurrent_s": s_con,
             "speedup": s_seq / s_con, "all_converged": all(i["converged"] for i in i_con),
@@ -344,7 +369,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned initial guess and compare it (several minutes; off by default)")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-fmg", action="store_true")
     ap.add_argument("--no-table4", action="store_true")
@@ -559,7 +585,7 @@ def main():
         if args.large_mixed:
             out_large = _large_mixed_leg(args)
         out_learned = None
-        if not args.no_learned:
+        if args.learned:
             out_learned = _learned_leg(P, dom, phi, None, None, args, stream)
         ms_smo, by_smo = P.time_kernel(_lib.CC_TIME_SMO1, args.smoother_reps)
         ms_smo32, by_smo32 = P.time_kernel(_lib.CC_TIME_SMO1_F32, args.smoother_reps)
@@ -611,7 +637,7 @@ def main():
         "batched": out_batch,
         "learned": out_learned,
         "multi_geometry": out_multi,
-        "paper_table4_sphere": out_t4,
+        "paper_table4": out_t4,
         "mixed_large": out_large,
         "roofline": {
             "bound": "hbm",

@@ -41,19 +41,26 @@ enum {
 };
 
 enum { CC_DIRICHLET = 0, CC_NEUMANN = 1, CC_ROBIN = 2 /* obstacles only */ };
+enum { CC_ELLIPSOID = 0, CC_TORUS = 1 };
 enum { CC_FP64 = 0, CC_MIXED = 1 };
 
 /* An ellipsoid { x : (x-c)^T R diag(axes^-2) R^T (x-c) <= 1 } removed from the box.
  * rot is row-major 3x3; its column j is the direction of semi-axis j. */
 typedef struct cc_obstacle {
   double center[3];
-  double axes[3];
-  double rot[9];
+  double axes[3];     /* CC_ELLIPSOID: semi-axes (> 0); ignored for CC_TORUS */
+  double rot[9];      /* row-major orthonormal; column j is the direction of semi-axis j
+                         (CC_TORUS: column 2 is the torus axis) */
   int bc;             /* CC_DIRICHLET, CC_NEUMANN or CC_ROBIN on this obstacle's surface */
   double robin[2];    /* (alpha, beta) of CC_ROBIN: alpha phi + beta dphi/dn = g, n outward of
                          Omega; the FV-PLG site row and its datum are scaled by
                          h / (|alpha| h + |beta|), so (1, 0) and (0, 1) are the Dirichlet and
                          Neumann rows (Sec. 2.3 boundary sites); ignored otherwise */
+  int kind;           /* CC_ELLIPSOID (0): the quadric (x-c)^T A (x-c) = 1; CC_TORUS (1): the
+                         solid torus of the paper's Problem 2 (Sec. 6), the points within
+                         radii[1] of the circle of radius radii[0] around center in the
+                         plane normal to rot's column 2, bounded by a quartic level set */
+  double radii[2];    /* CC_TORUS: major R and minor r, R > r > 0; ignored otherwise */
 } cc_obstacle;
 
 /* Grid and domain (Sec. 2.2).  Walls ordered -x,+x,-y,+y,-z,+z. */

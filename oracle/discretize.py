@@ -37,6 +37,7 @@ import scipy.sparse as sp
 
 from math import comb
 
+from . import quadrature as qd
 from .geometry import (CUT, EXTERIOR, INTERIOR, LevelGeometry, MONO3, MONO4,
                        GeometryError)
 from .merging import THETA, groups, merge_cells
@@ -185,8 +186,11 @@ class Level:
                 best, bt = dist, t
         if bt < 0:
             return np.ones(3, dtype=int)
-        A = self.geo.quadrics[bt].Q
-        g = A @ (xc - np.asarray(self.domain.obstacles[bt].center))
+        psi = self.geo.quadrics[bt]
+        if isinstance(psi, qd.Quadric):
+            g = psi.Q @ (xc - np.asarray(self.domain.obstacles[bt].center))
+        else:
+            g = psi.grad(xc)[0]
         gn = float(np.linalg.norm(g))
         return np.where(g < -1e-9 * gn, -1, 1)
 

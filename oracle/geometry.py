@@ -2,9 +2,11 @@
 
 Cells C_i = (x_O + i h, x_O + (i+1) h) of the box R; cut cells
 C_i ∩ Ω, their volumes, the boundary patches S_i = C_i ∩ ∂Ω, and the
-interior / exterior / cut classification.  Ω is the box minus ellipsoids,
-or (domain.inside) the interior of one ellipsoid: its quadric is negated so
-that Ω = {psi > 0} either way, and cells away from it are exterior.
+interior / exterior / cut classification.  Ω is the box minus obstacles
+(ellipsoids, quadric level sets; a torus, the quartic level set of the
+paper's Problem 2), or (domain.inside) the interior of one ellipsoid: its
+quadric is negated so that Ω = {psi > 0} either way, and cells away from it
+are exterior.
 
 Per cut cell the oracle keeps the quadrature nodes (for right-hand sides)
 and the normalised moments used by the polynomial fits (Sec. 2.3):
@@ -24,6 +26,7 @@ import numpy as np
 from . import quadrature as qd
 
 EXTERIOR, INTERIOR, CUT = 0, 1, 2
+TORUS = 1               # obstacle kind code of a torus (0: an ellipsoid)
 Q_ORDER = 12
 VOL_EPS = 1e-12
 
@@ -91,9 +94,11 @@ class LevelGeometry:
         self.h = 1.0 / n
         self.origin = np.asarray(domain.origin, float)
         self.inside = bool(getattr(domain, "inside", False))
-        self.quadrics = [qd.ellipsoid_quadric(o.center, o.axes, o.rot) for o in domain.obstacles]
+        self.quadrics = [qd.torus_poly(o.center, o.radii[0], o.radii[1], o.rot)
+                         if getattr(o, "kind", 0) == TORUS else qd.ellipsoid_quadric(o.center, o.axes, o.rot)
+                         for o in domain.obstacles]
         if self.inside:
-            if len(self.quadrics) != 1:
+            if len(self.quadrics) != 1 or not isinstance(self.quadrics[0], qd.Quadric):
                 raise GeometryError("an interior domain is bounded by exactly one ellipsoid")
             q = self.quadrics[0]
             self.quadrics = [qd.Quadric(-q.Q, -q.b, -q.c)]

@@ -21,6 +21,7 @@ CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_EGEOM, CC_EPLG, CC_ESINGULAR, CC_ENO
 CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4}
 CC_VALUE, CC_LAPLACIAN = 0, 1
 CC_DIRICHLET, CC_NEUMANN, CC_ROBIN = 0, 1, 2
+CC_ELLIPSOID, CC_TORUS = 0, 1
 CC_FP64, CC_MIXED = 0, 1
 HISTORY_MAX = 256
 BATCH_MAX = 64
@@ -41,7 +42,7 @@ EXPORTED = [
 
 class CcObstacle(C.Structure):
     _fields_ = [("center", C.c_double * 3), ("axes", C.c_double * 3), ("rot", C.c_double * 9), ("bc", C.c_int),
-                ("robin", C.c_double * 2)]
+                ("robin", C.c_double * 2), ("kind", C.c_int), ("radii", C.c_double * 2)]
 
 
 class CcDomain(C.Structure):
@@ -231,6 +232,8 @@ class Problem:
             obs[t].rot[:] = [float(v) for v in np.asarray(o.rot).reshape(-1)]
             obs[t].bc = int(o.bc)
             obs[t].robin[:] = [float(v) for v in getattr(o, "robin", (1.0, 0.0))]
+            obs[t].kind = int(getattr(o, "kind", 0))
+            obs[t].radii[:] = [float(v) for v in getattr(o, "radii", (0.0, 0.0))]
         dom = CcDomain()
         dom.n = domain.n
         dom.origin[:] = [float(v) for v in domain.origin]

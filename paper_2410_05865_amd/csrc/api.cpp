@@ -118,6 +118,14 @@ struct DevBuf {
   }
 };
 
+// Device allocations freed when the scope ends (hipFree waits for the device).
+struct TempBuf : DevBuf {
+  TempBuf() = default;
+  TempBuf(const TempBuf&) = delete;
+  TempBuf& operator=(const TempBuf&) = delete;
+  ~TempBuf() { release(); }
+};
+
 struct DevLU {
   LuDev d{};
   std::vector<LuTasks> tasks;  // per height, all nodes
@@ -1286,10 +1294,18 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     for (int t = 0; t < dom->n_obst; ++t) {
       const cc_obstacle& o = dom->obst[t];
       Obstacle ob;
+      if (o.kind != CC_ELLIPSOID && o.kind != CC_TORUS) fail(CC_EINVAL, "obstacle kind must be CC_ELLIPSOID or CC_TORUS");
+      ob.kind = o.kind;
       for (int a = 0; a < 3; ++a) {
         ob.c[a] = o.center[a];
         ob.axes[a] = o.axes[a];
-        if (!(o.axes[a] > 0)) fail(CC_EINVAL, "semi-axes must be positive");
+        if (o.kind == CC_ELLIPSOID && !(o.axes[a] > 0)) fail(CC_EINVAL, "semi-axes must be positive");
+      }
+      if (o.kind == CC_TORUS) {
+        ob.radii[0] = o.radii[0];
+        ob.radii[1] = o.radii[1];
+        if (!(std::isfinite(o.radii[0]) && o.radii[1] > 0 && o.radii[0] > o.radii[1]))
+          fail(CC_EINVAL, "a torus needs radii R > r > 0");
       }
       for (int a = 0; a < 9; ++a) ob.rot[a] = o.rot[a];
       for (int a = 0; a < 3; ++a)
@@ -1310,8 +1326,14 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         if (!(std::isfinite(ob.alpha) && std::isfinite(ob.beta)) || (ob.alpha == 0.0 && ob.beta == 0.0))
           fail(CC_EINVAL, "a Robin condition needs finite (alpha, beta), not both 0");
       }
-      ob.R = std::max(ob.axes[0], std::max(ob.axes[1], ob.axes[2]));
-      ob.q = ellipsoid_quadric(ob.c, ob.axes, ob.rot);
+      if (o.kind == CC_TORUS) {
+        ob.R = ob.radii[0] + ob.radii[1];
+        ob.ls.poly = true;
+        ob.ls.p = torus_poly(ob.c, ob.radii[0], ob.radii[1], ob.rot);
+      } else {
+        ob.R = std::max(ob.axes[0], std::max(ob.axes[1], ob.axes[2]));
+        ob.ls.q = ellipsoid_quadric(ob.c, ob.axes, ob.rot);
+      }
       D.obst.push_back(ob);
     }
     if (dom->inside != 0 && dom->inside != 1) fail(CC_EINVAL, "inside must be 0 or 1");
@@ -1319,7 +1341,8 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (D.inside) {
       // Omega = the obstacle's interior: negate its quadric so that Omega = {q > 0}
       if (D.obst.size() != 1) fail(CC_EINVAL, "an interior domain is bounded by exactly one obstacle");
-      Quadric& q = D.obst[0].q;
+      if (D.obst[0].kind != CC_ELLIPSOID) fail(CC_EINVAL, "an interior domain is bounded by an ellipsoid");
+      Quadric& q = D.obst[0].ls.q;
       for (int i = 0; i < 3; ++i) {
         for (int j = 0; j < 3; ++j) q.Q[i][j] = -q.Q[i][j];
         q.b[i] = -q.b[i];
@@ -1464,12 +1487,14 @@ int cc_export_lu_nodes(const cc_problem* p, int level, int* base, int* np, int* 
 }
 
 // r = f - N g on level `level` for nf fields at once (Sec. 2.4): cell averages of
-// f_k (or of Delta f_k) on the device; on the host, one quadrature rule per cut
-// cell serves every field (cut-cell integrals of f_k, patch data of g_k), then
-// the merged groups' averages, the wall-ghost terms of regular rows and the
-// boundary sites of FV-PLG rows; the host results reach the device as sparse
-// overwrites (special and absorbed cells) and additions (boundary terms), so
-// no full array crosses PCIe.  r_dev holds nf arrays of n_m^3 at stride n_m^3.
+// f_k (or of Delta f_k) on the device; the cut-cell integrals of f_k on the
+// device too, from each cut cell's quadrature rule built on the host as line
+// pieces (one rule serves every field); on the host, the patch data of g_k
+// (when any g_k is nonzero), the merged groups' averages, the wall-ghost terms
+// of regular rows and the boundary sites of FV-PLG rows; the host results
+// reach the device as sparse overwrites (special and absorbed cells) and
+// additions (boundary terms), so no full array crosses PCIe.  r_dev holds nf
+// arrays of n_m^3 at stride n_m^3.
 static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<FieldDesc>& fds, int f_mode,
                          const std::vector<FieldDesc>& gds, double* r_dev) {
   const LevelHost& L = *p->lv[level];
@@ -1492,7 +1517,7 @@ static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<Fie
     std::sort(full_members.begin(), full_members.end());
     full_members.erase(std::unique(full_members.begin(), full_members.end()), full_members.end());
   }
-  DevBuf tmpb;
+  TempBuf tmpb;
   std::vector<double> fm_val((size_t)full_members.size() * nf);
   if (!full_members.empty()) {
     int* d_cells = tmpb.upload(full_members);
@@ -1503,55 +1528,81 @@ static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<Fie
   HIPSYNC(p->stream);
   std::map<int, size_t> fm_pos;
   for (size_t t = 0; t < full_members.size(); ++t) fm_pos[full_members[t]] = t;
-  // per cut cell and field: integral of f over the cut region and the patch
-  // datum of g (Dirichlet: <<g>>, Neumann: h <<dg/dn>>, Robin: scaled), from
-  // one quadrature pass
+  // per cut cell and field: the integral of f over the cut region (device) and
+  // the patch datum of g (Dirichlet: <<g>>, Neumann: h <<dg/dn>>, Robin:
+  // scaled; host), from one quadrature pass per cut cell, in chunks of cells
   std::vector<int> cuts;
   for (const auto& kv : L.cut) cuts.push_back(kv.first);
-  std::vector<double> cut_int(cuts.size() * nf), cut_dat(cuts.size() * nf);
+  std::vector<double> cut_int(cuts.size() * nf), cut_dat(cuts.size() * nf, 0.0);
+  bool any_g = false;
+  for (const FieldDesc& g : gds) any_g = any_g || g.kind != CC_FIELD_ZERO;
+  static_assert(sizeof(LinePiece) == sizeof(PieceRec), "line piece layouts differ");
+  if (!cuts.empty()) {
+    const FieldDesc* d_f = tmpb.upload(fds);
+    double* d_int = tmpb.alloc<double>(cut_int.size());
+    const size_t kChunk = 8192;
+    std::vector<std::vector<LinePiece>> pcs(std::min(kChunk, cuts.size()));
+    for (size_t c0 = 0; c0 < cuts.size(); c0 += kChunk) {
+      const size_t c1 = std::min(cuts.size(), c0 + kChunk);
 #pragma omp parallel for schedule(dynamic, 8)
-  for (long t = 0; t < (long)cuts.size(); ++t) {
-    int m = cuts[t];
-    const CutData& cd = L.cut.at(m);
-    const Obstacle& ob = p->dom.obst[cd.obst];
-    int bc = ob.bc;
-    int ii[3];
-    L.ijk(m, ii[0], ii[1], ii[2]);
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = L.origin[a] + h * ii[a];
-      hi[a] = lo[a] + h;
-    }
-    NodeSet vn;
-    SurfaceSet sn;
-    region_rules(lo, hi, 3, ob.q, kQuadOrder, vn, &sn);
-    // the datum in the scale of the site row: Neumann h <<dg/dn>>, Robin
-    // h <<alpha g + beta dg/dn>> / (|alpha| h + |beta|)
-    const double scale = bc == CC_NEUMANN ? h
-                         : bc == CC_ROBIN  ? h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta))
-                                           : 1.0;
-    for (int k = 0; k < nf; ++k) {
-      double s = 0.0;
-      for (size_t q = 0; q < vn.size(); ++q)
-        s += vn.w[q] * field_value(fds[k], vn.x[3 * q], vn.x[3 * q + 1], vn.x[3 * q + 2], f_mode);
-      cut_int[t * nf + k] = s;
-      double acc = 0.0, area = 0.0;
-      for (size_t q = 0; q < sn.w.size(); ++q) {
-        const double* x = &sn.x[3 * q];
-        double v;
-        if (bc == CC_DIRICHLET) {
-          v = field_value(gds[k], x[0], x[1], x[2], 0);
-        } else {
-          double gr[3];
-          field_grad(gds[k], x[0], x[1], x[2], gr);
-          v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
-          if (bc == CC_ROBIN) v = ob.alpha * field_value(gds[k], x[0], x[1], x[2], 0) + ob.beta * v;
+      for (long t = (long)c0; t < (long)c1; ++t) {
+        int m = cuts[t];
+        const CutData& cd = L.cut.at(m);
+        const Obstacle& ob = p->dom.obst[cd.obst];
+        int bc = ob.bc;
+        int ii[3];
+        L.ijk(m, ii[0], ii[1], ii[2]);
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = L.origin[a] + h * ii[a];
+          hi[a] = lo[a] + h;
         }
-        acc += sn.w[q] * v;
-        area += sn.w[q];
+        std::vector<LinePiece>& pc = pcs[t - c0];
+        pc.clear();
+        SurfaceSet sn;
+        region_pieces(lo, hi, ob.ls, kQuadOrder, pc, any_g ? &sn : nullptr);
+        if (!any_g) continue;
+        // the datum in the scale of the site row: Neumann h <<dg/dn>>, Robin
+        // h <<alpha g + beta dg/dn>> / (|alpha| h + |beta|)
+        const double scale = bc == CC_NEUMANN ? h
+                             : bc == CC_ROBIN  ? h / (std::fabs(ob.alpha) * h + std::fabs(ob.beta))
+                                               : 1.0;
+        for (int k = 0; k < nf; ++k) {
+          double acc = 0.0, area = 0.0;
+          for (size_t q = 0; q < sn.w.size(); ++q) {
+            const double* x = &sn.x[3 * q];
+            double v;
+            if (bc == CC_DIRICHLET) {
+              v = field_value(gds[k], x[0], x[1], x[2], 0);
+            } else {
+              double gr[3];
+              field_grad(gds[k], x[0], x[1], x[2], gr);
+              v = gr[0] * sn.n[3 * q] + gr[1] * sn.n[3 * q + 1] + gr[2] * sn.n[3 * q + 2];
+              if (bc == CC_ROBIN) v = ob.alpha * field_value(gds[k], x[0], x[1], x[2], 0) + ob.beta * v;
+            }
+            acc += sn.w[q] * v;
+            area += sn.w[q];
+          }
+          cut_dat[t * nf + k] = (area > 0) ? acc / area * scale : 0.0;
+        }
       }
-      cut_dat[t * nf + k] = (area > 0) ? acc / area * scale : 0.0;
+      std::vector<int> off(c1 - c0 + 1, 0);
+      for (size_t t = c0; t < c1; ++t) {
+        const size_t np = pcs[t - c0].size();
+        if (off[t - c0] + np > (size_t)INT32_MAX) fail(CC_ENOMEM, "too many quadrature pieces in one chunk");
+        off[t - c0 + 1] = off[t - c0] + (int)np;
+      }
+      std::vector<PieceRec> flat((size_t)off.back());
+      for (size_t t = c0; t < c1; ++t)
+        if (!pcs[t - c0].empty())
+          std::memcpy(&flat[off[t - c0]], pcs[t - c0].data(), pcs[t - c0].size() * sizeof(PieceRec));
+      TempBuf cb;
+      const int* d_off = cb.upload(off);
+      const PieceRec* d_pc = cb.upload(flat);
+      launch_piece_integrals((int)(c1 - c0), d_off, d_pc, kQuadOrder, d_f, nf, f_mode, d_int + c0 * nf, p->stream);
+      HIPSYNC(p->stream);
     }
+    HIPCHK(hipMemcpy(cut_int.data(), d_int, cut_int.size() * sizeof(double), hipMemcpyDeviceToHost));
   }
   std::map<int, size_t> cut_pos;
   for (size_t t = 0; t < cuts.size(); ++t) cut_pos[cuts[t]] = t;

@@ -1335,6 +1335,51 @@ __global__ void k_cell_average(int n, double h, double ox, double oy, double oz,
   out[i + (long)n * (j + (long)n * k)] = 0.125 * acc;
 }
 
+// Cut-cell integrals of several fields from line-piece rules: the workgroup of
+// (cell c, field group y) walks the (piece, Gauss point) pairs of cell c, each
+// thread evaluating every field of its group at its nodes.
+constexpr int kPieceFields = 8;
+constexpr int kPieceThreads = 256;
+
+__global__ __launch_bounds__(kPieceThreads) void k_piece_integrals(const int* __restrict__ off,
+                                                                   const PieceRec* __restrict__ pc, GaussQ G,
+                                                                   const FieldDesc* __restrict__ fds, int nf,
+                                                                   int mode, double* __restrict__ out) {
+  const int c = blockIdx.x;
+  const int f0 = blockIdx.y * kPieceFields;
+  const int nfb = min(kPieceFields, nf - f0);
+  const int p0 = off[c];
+  const int total = (off[c + 1] - p0) * G.q;
+  double acc[kPieceFields];
+#pragma unroll
+  for (int f = 0; f < kPieceFields; ++f) acc[f] = 0.0;
+  for (int t = threadIdx.x; t < total; t += kPieceThreads) {
+    const PieceRec P = pc[p0 + t / G.q];
+    const int g = t % G.q;
+    const double mid = 0.5 * (P.a + P.b), half = 0.5 * (P.b - P.a);
+    const double wt = P.w * half * G.w[g];
+    double x[3];
+    int m = 0;
+    for (int i = 0; i < 3; ++i) x[i] = (i == P.k) ? mid + half * G.x[g] : P.xo[m++];
+#pragma unroll
+    for (int f = 0; f < kPieceFields; ++f)
+      if (f < nfb) acc[f] += wt * field_value(fds[f0 + f], x[0], x[1], x[2], mode);
+  }
+  __shared__ double part[kPieceFields][kPieceThreads / kWave];
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int f = 0; f < kPieceFields; ++f) {
+    const double v = wave_sum(acc[f]);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[f][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nfb) {
+    double s = 0.0;
+    for (int i = 0; i < kPieceThreads / kWave; ++i) s += part[threadIdx.x][i];
+    out[(long long)c * nf + f0 + threadIdx.x] = s;
+  }
+}
+
 inline dim3 grid3(int n) { return dim3((n + 63) / 64, (n + 3) / 4, n); }
 inline dim3 grid_tiles(int n, int nb = 1) { return dim3(((n + 63) / 64) * ((n + 3) / 4) * n, nb); }
 const dim3 kBlock3(64, 4, 1);
@@ -1617,6 +1662,21 @@ void launch_copy(long long count, const double* src, double* dst, hipStream_t st
   if (count == 0) return;
   int g = (int)std::min<long long>(blocks(count, 256), 16384);
   hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, st, src, dst, count);
+}
+void launch_piece_integrals(int ncell, const int* off, const PieceRec* pieces, int q, const FieldDesc* fds, int nf,
+                            int mode, double* out, hipStream_t st) {
+  if (ncell == 0 || nf == 0) return;
+  if (q > 16) throw std::runtime_error("launch_piece_integrals: at most 16 Gauss points");
+  GaussQ G;
+  G.q = q;
+  std::vector<double> x, w;
+  gauss_legendre(q, x, w);
+  for (int i = 0; i < q; ++i) {
+    G.x[i] = x[i];
+    G.w[i] = w[i];
+  }
+  hipLaunchKernelGGL(k_piece_integrals, dim3(ncell, (nf + kPieceFields - 1) / kPieceFields), dim3(kPieceThreads), 0,
+                     st, off, pieces, G, fds, nf, mode, out);
 }
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q, double* out,
                          hipStream_t st) {

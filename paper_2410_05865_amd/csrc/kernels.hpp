@@ -183,6 +183,20 @@ template <class T>
 void launch_copy_pairs(int count, const int2* pairs, T* a, long long stride, int nb, hipStream_t st);
 void launch_cell_average(int n, double h, const double* origin, const FieldDesc& f, int mode, int q,
                          double* out, hipStream_t st);
+// One line piece of a cut cell's volume rule (the layout of cc::LinePiece): q
+// Gauss points on [a, b] along axis k at the base point xo (the other two
+// coordinates in ascending axis order), weights w (b - a)/2 w_j.
+struct PieceRec {
+  double xo[2];
+  double a, b, w;
+  int k, pad;
+};
+// out[c * nf + f] = the q-point rules of the pieces off[c] .. off[c+1]-1 of cell
+// c applied to field f (mode 0 value, 1 Laplacian) for ncell cells and nf
+// device-resident field descriptors; one workgroup per (cell, group of up to 8
+// fields).
+void launch_piece_integrals(int ncell, const int* off, const PieceRec* pieces, int q, const FieldDesc* fds, int nf,
+                            int mode, double* out, hipStream_t st);
 void launch_set_values(int count, const int* cells, const double* vals, double* a, hipStream_t st);
 // a[b * stride + cells[v]] = vals[v * nb + b] (add = 0) or += it (add = 1), nb arrays
 void launch_scatter_values(int count, const int* cells, const double* vals, double* a, long long stride, int nb,

@@ -165,7 +165,7 @@ void LevelHost::classify() {
     const Obstacle& o = dom->obst[owner[p]];
     NodeSet vn;
     SurfaceSet sn;
-    region_rules(lo, hi, 3, o.q, kQuadOrder, vn, &sn);
+    region_rules(lo, hi, 3, o.ls, kQuadOrder, vn, &sn);
     double V = 0.0;
     for (double w : vn.w) V += w;
     if (V < 1e-12 * h3) {
@@ -232,7 +232,7 @@ double LevelHost::face_area(int p, int d, int side) const {
   int t = owner[p] >= 0 ? owner[p] : owner[q];
   if (t < 0) return h * h;
   double xf = origin[d] + h * (ii[d] + (side > 0 ? 1 : 0));
-  Quadric f2 = dom->obst[t].q.restrict_to(d, xf);
+  LevelSet f2 = dom->obst[t].ls.restrict_to(d, xf);
   double lo[2], hi[2];
   int m = 0;
   for (int a = 0; a < 3; ++a)
@@ -456,12 +456,18 @@ void LevelHost::plg_select(int p, int cells[kPLG]) const {
   }
   if (bt >= 0) {
     const Obstacle& o = dom->obst[bt];
+    // the direction into Omega: the level set's gradient (for a quadric
+    // (x - c)^T A (x - c) - 1, its half, A (x - c))
     double g[3], gn = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      g[a] = 0.0;
-      for (int b = 0; b < 3; ++b) g[a] += o.q.Q[a][b] * (xc[b] - o.c[b]);
-      gn += g[a] * g[a];
+    if (o.ls.poly) {
+      o.ls.p.grad(xc, g);
+    } else {
+      for (int a = 0; a < 3; ++a) {
+        g[a] = 0.0;
+        for (int b = 0; b < 3; ++b) g[a] += o.ls.q.Q[a][b] * (xc[b] - o.c[b]);
+      }
     }
+    for (int a = 0; a < 3; ++a) gn += g[a] * g[a];
     gn = std::sqrt(gn);
     for (int a = 0; a < 3; ++a) sgn[a] = (g[a] < -1e-9 * gn) ? -1 : 1;
   }

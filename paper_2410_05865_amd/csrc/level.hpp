@@ -16,8 +16,10 @@ struct Obstacle {
   double c[3], axes[3], rot[9];
   int bc;
   double alpha = 1.0, beta = 0.0;  // CC_ROBIN: alpha phi + beta dphi/dn = g
+  int kind = 0;                    // CC_ELLIPSOID or CC_TORUS
+  double radii[2] = {0.0, 0.0};    // CC_TORUS: major and minor radius
   double R;   // bounding-sphere radius
-  Quadric q;
+  LevelSet ls;  // positive in Omega
 };
 
 struct DomainSpec {
@@ -26,7 +28,7 @@ struct DomainSpec {
   double h;
   int wall_bc[6];
   std::vector<Obstacle> obst;
-  bool inside = false;  // Omega = interior of obst[0] (its quadric negated: Omega = {q > 0} either way)
+  bool inside = false;  // Omega = interior of obst[0] (its quadric negated: Omega = {ls > 0} either way)
 };
 
 enum : int8_t { kExterior = 0, kInterior = 1, kCut = 2 };

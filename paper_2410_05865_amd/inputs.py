@@ -4,9 +4,9 @@ This module only draws and packages problem data (obstacle lists, field
 parameters).  It contains none of the method's arithmetic, so both the
 CPU oracle and the HIP library may consume its output.
 
-Domains are the unit box R = [0,1]^3 with ellipsoidal obstacles removed
-(the cut-cell setting of Sec. 2.2); the Cartesian grid has n cells per
-axis and h = 1/n.  Wall order everywhere is (-x, +x, -y, +y, -z, +z).
+Domains are the unit box R = [0,1]^3 with obstacles removed (the cut-cell
+setting of Sec. 2.2): ellipsoids, or a torus (the paper's Problem 2); the
+Cartesian grid has n cells per axis and h = 1/n.  Wall order everywhere is (-x, +x, -y, +y, -z, +z).
 
 Field descriptors are plain dicts; the meaning of each kind is:
   zero     : 0
@@ -27,6 +27,9 @@ DIRICHLET = 0
 NEUMANN = 1
 ROBIN = 2                       # alpha phi + beta dphi/dn = g (obstacle surfaces only)
 
+ELLIPSOID = 0                   # obstacle kinds
+TORUS = 1
+
 
 @dataclasses.dataclass
 class Obstacle:
@@ -35,8 +38,13 @@ class Obstacle:
     rot: np.ndarray             # (3,3); column j is the direction of semi-axis j
     bc: int = DIRICHLET         # boundary condition on this obstacle's surface
     robin: Tuple[float, float] = (1.0, 0.0)   # (alpha, beta) of a ROBIN condition
+    kind: int = ELLIPSOID
+    radii: Tuple[float, float] = (0.0, 0.0)   # TORUS: (major R, minor r), R > r; the
+                                              # torus axis is rot[:, 2] through center
 
     def bounding_radius(self) -> float:
+        if self.kind == TORUS:
+            return float(self.radii[0] + self.radii[1])
         return float(np.max(self.axes))
 
 
@@ -110,10 +118,25 @@ def ellipsoid_domain(n: int, seed: int = 1, count: int = 8,
     return Domain(n=n, obstacles=obs, wall_bc=(DIRICHLET,) * 6, n_min=n_min)
 
 
+def torus_domain(n: int, R: float = 0.2, r: float = 0.1, center=(0.5, 0.5, 0.5), rot=None,
+                 bc: int = NEUMANN, n_min: int = 32) -> Domain:
+    """Unit box minus a solid torus: the points within r of the circle of
+    radius R around `center` in the plane normal to rot[:, 2] (default the
+    z axis); Dirichlet walls."""
+    rot = np.eye(3) if rot is None else np.asarray(rot, float)
+    ob = Obstacle(np.array(center, float), np.array([R + r, R + r, r]), rot, bc, kind=TORUS,
+                  radii=(float(R), float(r)))
+    return Domain(n=n, obstacles=[ob], wall_bc=(DIRICHLET,) * 6, n_min=n_min)
+
+
 def inside_any_obstacle(domain: Domain, x: np.ndarray) -> bool:
     for o in domain.obstacles:
         d = o.rot.T @ (x - o.center)
-        if float(np.sum((d / o.axes) ** 2)) < 1.0:
+        if o.kind == TORUS:
+            R, r = o.radii
+            if (math.hypot(d[0], d[1]) - R) ** 2 + d[2] ** 2 < r * r:
+                return True
+        elif float(np.sum((d / o.axes) ** 2)) < 1.0:
             return True
     return False
 
@@ -183,6 +206,15 @@ def sphere03_workload(n: int = 256):
     boundary conditions; here Dirichlet on walls and sphere with the
     manufactured phi = exp(x + y/2) cos(3 z)."""
     return sphere_domain(n=n, radius=0.3, n_min=32), expcos_field()
+
+
+def torus_problem(n: int = 64, n_min: int = 32):
+    """The paper's Problem 2: the unit cube minus the torus of major radius 0.2
+    and minor radius 0.1 centred at (0.5, 0.5, 0.5) (axis z); Dirichlet on the
+    cube, Neumann on the torus, data from u = cos(pi x) cos(pi y) sin(pi z).
+    The same domain is the torus workload of the paper's Table 4."""
+    return (torus_domain(n=n, n_min=n_min),
+            sinprod_field(1.0, (math.pi, math.pi, math.pi), (0.5 * math.pi, 0.5 * math.pi, 0.0)))
 
 
 def ellipsoid_workload(n: int = 128, seed: int = 1):

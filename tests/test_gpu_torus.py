@@ -1,0 +1,153 @@
+"""The paper's Problem 2 on the GPU: the unit cube minus the torus of major
+radius 0.2 and minor radius 0.1 about the z axis through the centre, Dirichlet
+walls, Neumann torus, u = cos(pi x) cos(pi y) sin(pi z).
+
+  * Parity with the oracle at 32^3 (levels 32, 16).  The oracle needs about a
+    minute to build this hierarchy, so its results were written by
+    tests/golden/make_torus32.py (oracle only) into tests/golden/torus32.npz:
+    hashes of the integer decisions, L x, r - L x, SMO-1, one V-cycle, the
+    assembled right-hand side and the converged solution at a seeded sample of
+    cells.  Tolerances as for the ellipsoid workloads (relative to the full max
+    norms): 1e-12, 1e-12, 1e-13, 1e-12, 1e-12, 1e-11.
+  * Truncation and solution errors at h = 1/64, 1/128, 1/256 in the paper's
+    norms (L1, L2 volume-weighted over |Omega|, Linf max, over the cells that
+    carry an unknown) against the paper's Table 3
+    (tests/golden/problem2_torus_errors.txt)."""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from paper_2410_05865_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "torus32.npz")
+TABLE3 = os.path.join(HERE, "golden", "problem2_torus_errors.txt")
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_05865_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def case():
+    L = _lib()
+    g = dict(np.load(GOLD, allow_pickle=False))
+    n = int(g["n"])
+    dom, phi = inputs.torus_problem(n, n_min=int(g["n_min"]))
+    print(f"[torus32] building the library problem", flush=True)
+    P = L.Problem(dom, use_graph=0)
+    rng = np.random.default_rng(int(g["input_seed"]))
+    x = rng.standard_normal(n ** 3)
+    r = rng.standard_normal(n ** 3)
+    x[g["absent"]] = 0.0
+    r[g["absent"]] = 0.0
+    yield L, P, g, phi, x, r
+    P.close()
+
+
+def test_integer_decisions_identical(case):
+    L, P, g, phi, x, r = case
+    typ, host, vf = P.export_cells(0)
+    assert _sha(typ) == str(g["type_sha"])
+    assert _sha(host.astype(np.int32)) == str(g["host_sha"])
+    cell, cols, vals = P.export_plg(0)
+    assert _sha(cell.astype(np.int32)) == str(g["plg_cells_sha"])
+    assert _sha(cols.astype(np.int32).reshape(-1, 35)) == str(g["plg_cols_sha"])
+    info = P.level_info(0)
+    assert info["n_unknowns"] == int(g["n_unknowns"]) and info["n_phi2"] == int(g["n_phi2"])
+    k = len(g["plg_vals_rows"])
+    assert np.array_equal(cell[:k], g["plg_vals_rows"])
+    gap = np.max(np.abs(vals[:k] - g["plg_vals"]), axis=1) / np.max(np.abs(g["plg_vals"]), axis=1)
+    assert gap.max() < 1e-11
+
+
+def test_steps_match_oracle(case):
+    L, P, g, phi, x, r = case
+    c, nrm = g["cells"], g["norms"]
+    at = lambda t: t.detach().cpu().numpy()[c]
+    y = _dev(np.zeros_like(x))
+    P.apply(0, _dev(x), y)
+    assert np.max(np.abs(at(y) - g["apply"])) < 1e-12 * nrm[0]
+    s = _dev(np.zeros_like(x))
+    P.residual(0, _dev(r), _dev(x), s)
+    assert np.max(np.abs(at(s) - g["residual"])) < 1e-12 * nrm[1]
+    e = _dev(x)
+    P.smo1(0, _dev(r), e)
+    assert np.max(np.abs(at(e) - g["smo1"])) < 1e-13 * nrm[2]
+    e = _dev(np.zeros_like(x))
+    P.vcycle(0, _dev(r), e)
+    assert np.max(np.abs(at(e) - g["vcycle"])) < 1e-12 * nrm[3]
+
+
+def test_converged_solve_matches_oracle(case):
+    L, P, g, phi, x, r = case
+    c, nrm = g["cells"], g["norms"]
+    rhs = torch.zeros(x.size, dtype=torch.float64, device="cuda")
+    P.assemble_rhs(phi, phi, rhs, f_mode=L.CC_LAPLACIAN)
+    assert np.max(np.abs(rhs.cpu().numpy()[c] - g["rhs"])) < 1e-12 * nrm[4]
+    sol = torch.zeros_like(rhs)
+    info = P.solve(rhs, sol)
+    hist = g["history"]
+    assert info["converged"] and info["iterations"] == len(hist) - 1
+    assert np.max(np.abs(sol.cpu().numpy()[c] - g["solution"])) < 1e-11 * nrm[5]
+
+
+def _norms(e, w, vol_omega):
+    return (float(np.max(np.abs(e))), float(np.sum(w * np.abs(e)) / vol_omega),
+            float(np.sqrt(np.sum(w * e * e) / vol_omega)))
+
+
+def test_problem2_errors_against_table3():
+    L = _lib()
+    rows = [l.split() for l in open(TABLE3) if l.strip() and not l.startswith("#")]
+    paper = {int(r_[0]): [float(v) for v in r_[1:]] for r_ in rows}
+    got = {}
+    for n in (64, 128, 256):
+        dom, phi = inputs.torus_problem(n)
+        P = L.Problem(dom, tol=1e-13, max_iter=400)
+        r = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(phi, phi, r, f_mode=L.CC_LAPLACIAN)
+        ex = torch.zeros_like(r)                       # exact averages: f = u with no boundary data
+        P.assemble_rhs(phi, None, ex, f_mode=L.CC_VALUE)
+        s = torch.zeros_like(r)
+        P.residual(0, r, ex, s)                        # s = r - L <u> = -(truncation error)
+        x = torch.zeros_like(r)
+        info = P.solve(r, x)
+        assert info["converged"], info
+        typ, host, vf = P.export_cells(0)
+        unk = typ != 0
+        h3 = (1.0 / n) ** 3
+        gvol = np.bincount(host[host >= 0], weights=vf[host >= 0] * h3, minlength=n ** 3)
+        w = gvol[unk]
+        vol_omega = float(vf.sum() * h3)
+        tau = _norms(s.cpu().numpy()[unk], w, vol_omega)
+        err = _norms((x - ex).cpu().numpy()[unk], w, vol_omega)
+        got[n] = (tau, err)
+        pp = paper[n]
+        print(f"[problem2] h = 1/{n}: {info['iterations']} V-cycles; truncation Linf/L1/L2 "
+              f"{tau[0]:.2e}/{tau[1]:.2e}/{tau[2]:.2e} (paper {pp[0]:.2e}/{pp[1]:.2e}/{pp[2]:.2e}); solution "
+              f"{err[0]:.2e}/{err[1]:.2e}/{err[2]:.2e} (paper {pp[3]:.2e}/{pp[4]:.2e}/{pp[5]:.2e})", flush=True)
+        P.close()
+    for n, (tau, err) in got.items():
+        pp = paper[n]
+        for k in range(3):
+            assert err[k] <= 3.0 * pp[3 + k], (n, k, err[k], pp[3 + k])
+    rate = np.log2(got[64][1][0] / got[256][1][0]) / 2
+    assert rate > 3.5, rate

@@ -76,13 +76,21 @@ def sphere16():
 
 
 @pytest.fixture(scope="module")
+def torus16():
+    """The paper's Problem 2 domain (cube minus a torus, Neumann on it) at 16^3:
+    every cut cell comes from the quartic level set."""
+    dom, _ = inputs.torus_problem(16, n_min=16)
+    return D.Level(dom, 16)
+
+
+@pytest.fixture(scope="module")
 def ellipsoid32_mixed():
     dom = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
     dom.wall_bc = (0, 1, 0, 0, 1, 0)      # two Neumann walls
     return D.Level(dom, 32)
 
 
-@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed", "torus16"])
 def test_every_row_exact_on_quartics(which, request):
     lv = request.getfixturevalue(which)
     P = _quartic()
@@ -128,7 +136,7 @@ def _is_triangular_lattice(coords, q):
     return T == S
 
 
-@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed", "torus16"])
 def test_plg_lattices_are_poised_triangular_lattices(which, request):
     lv = request.getfixturevalue(which)
     for r, (cells, coefs) in list(lv.plg.items())[::7]:
@@ -142,7 +150,7 @@ def test_plg_lattices_are_poised_triangular_lattices(which, request):
         assert np.linalg.cond(A) < 1e9                         # poised
 
 
-@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed"])
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed", "torus16"])
 def test_merging_postconditions(which, request):
     lv = request.getfixturevalue(which)
     geo = lv.geo
