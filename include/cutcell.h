@@ -220,7 +220,7 @@ int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r_d
 int cc_set_precision(cc_problem* p, int precision);
 
 /* Overlap of SMO-1 with the LU-correction (Sec. 5.3 smoothing steps; default
- * on): every SMO-1 that follows an SMO-2 runs as a far sweep (the phi_1 rows
+ * off): every SMO-1 that follows an SMO-2 runs as a far sweep (the phi_1 rows
  * that read no phi_2 cell, and the cells without an unknown) on a side stream,
  * concurrently with that SMO-2, and a near sweep (cc_level_info.n_near cells)
  * after it; the next SMO-2 waits for both.  Same arithmetic, same result; on = 0

@@ -374,7 +374,7 @@ class Problem:
         _check(load().cc_set_lu_schedule(self._h, level, entries_per_lane, subtree, waves_cap))
 
     def set_overlap(self, on: int):
-        """Far SMO-1 sweeps beside the LU-correction (1, default) or whole sweeps (0)."""
+        """Far SMO-1 sweeps beside the LU-correction (1) or whole sweeps (0, default)."""
         _check(load().cc_set_overlap(self._h, on))
 
     def set_stencil_schedule(self, level: int = -1, march: int = -1, planes: int = 0):

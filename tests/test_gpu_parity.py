@@ -195,7 +195,7 @@ def test_overlap_matches_whole_sweeps(pair):
         e = _dev(np.zeros(lv.n ** 3))
         P.vcycle(0, s, e)
         out[on] = _host(e)[lv.unknowns]
-    P.set_overlap(1)
+    P.set_overlap(0)
     assert _rel(out[1], out[0]) < 1e-13
     ref = H.vcycle(0, _host(s)[lv.unknowns], MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
     assert _rel(out[1], ref) < 1e-12
@@ -207,7 +207,7 @@ def test_overlap_matches_whole_sweeps(pair):
         info = P.solve(_dev(lv.to_grid(r_or)), phi)
         assert info["converged"] and info["iterations"] == len(hist) - 1
         sols[on] = _host(phi)[lv.unknowns]
-    P.set_overlap(1)
+    P.set_overlap(0)
     assert _rel(sols[1], sols[0]) < 1e-12
     assert _rel(sols[1], x_or) < 1e-11
 
