@@ -105,9 +105,11 @@ typedef struct cc_params {
  *   CC_FIELD_SINPROD (amp, k0, k1, k2, p0, p1, p2): amp prod_d sin(k_d x_d + p_d)
  *   CC_FIELD_EXPCOS  (amp, a, b, c, p): amp exp(a x + b y) cos(c z + p)
  *   CC_FIELD_GAUSS   n_terms x (amp, mu0, mu1, mu2, sigma)
+ *   CC_FIELD_XSINEXP (amp): amp x sin(y) e^z (harmonic; the function of the paper's
+ *                    geometry accuracy test, Sec. 6.1, with amp = 10)
  * The library copies what it needs; data may be freed after the call. */
 enum { CC_FIELD_ZERO = 0, CC_FIELD_POLY = 1, CC_FIELD_SINPROD = 2, CC_FIELD_EXPCOS = 3,
-       CC_FIELD_GAUSS = 4 };
+       CC_FIELD_GAUSS = 4, CC_FIELD_XSINEXP = 5 };
 enum { CC_VALUE = 0, CC_LAPLACIAN = 1 };
 typedef struct cc_field {
   int kind;
@@ -336,6 +338,25 @@ int cc_fmg_batched(cc_problem* p, int nrhs, const double* r_dev, const double* c
 int cc_fmg_restrict(cc_problem* p, int level, const double* s_dev, double* sc_dev);
 int cc_fmg_prolong(cc_problem* p, int level, const double* xc_dev, double* xf_dev);
 int cc_vcycle(cc_problem* p, int level, const double* s_dev, double* e_dev);
+
+/* The paper's boundary fitting (Sec. 3.1) on the cut cells of `level`, as a
+ * check of the exact geometry the solver uses (the geometry accuracy test of
+ * Sec. 6.1, Table 1).  Per cut cell, in ascending cell index
+ * (cc_level_info.n_cut cells): points of the exact boundary inside the cell
+ * (the surface nodes of a 4-point-per-piece height-function rule), the height
+ * axis w of the patch's mean normal (u < v the other two), the least-squares
+ * quadratic W = a U^2 + b U V + c V^2 + d U + e V + g in the cell-centred
+ * coordinates scaled by h (minimum-norm; singular values below 1e-12 of the
+ * largest dropped), and the fitted region {s (W - p(U, V)) > 0}, s putting
+ * Omega's side positive, integrated with the same 12-point height-function
+ * rule as the exact one.  Outputs (host arrays, caller-owned, each may be
+ * NULL): cell[n_cut], axis[n_cut] (-1 where the patch gives fewer than 6
+ * points; its other outputs are NaN), coef[6 n_cut] (a, b, c, d, e, g), and
+ * exact[4 n_cut], fitted[4 n_cut]: volume, patch area, the average of u over
+ * the region and over the patch.  Host-only; works on host-only handles.
+ * Errors: CC_EINVAL (bad level or field). */
+int cc_fit_patches(const cc_problem* p, int level, const cc_field* u, int* cell, int* axis, double* coef,
+                   double* exact, double* fitted);
 
 /* Host copies of a level's integer decisions and rows (Sec. 2.2-2.4), for
  * exact comparison.  Any pointer may be NULL.

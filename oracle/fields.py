@@ -42,6 +42,8 @@ class Field:
                 r2 = (x - mu[0]) ** 2 + (y - mu[1]) ** 2 + (z - mu[2]) ** 2
                 out += A * np.exp(-r2 / (2 * s * s))
             return out
+        if k == "xsinexp":
+            return d["amp"] * x * np.sin(y) * np.exp(z)
         raise ValueError(k)
 
     def grad(self, X: np.ndarray) -> np.ndarray:
@@ -81,6 +83,12 @@ class Field:
                 g = A * np.exp(-np.sum(dx * dx, axis=1) / (2 * s * s))
                 G += (-dx / (s * s)) * g[:, None]
             return G
+        if k == "xsinexp":
+            A = d["amp"]
+            G[:, 0] = A * np.sin(y) * np.exp(z)
+            G[:, 1] = A * x * np.cos(y) * np.exp(z)
+            G[:, 2] = A * x * np.sin(y) * np.exp(z)
+            return G
         raise ValueError(k)
 
     def laplacian_desc(self) -> "Field":
@@ -105,6 +113,8 @@ class Field:
             return Field({"kind": "poly", "terms": [(*kk, v) for kk, v in acc.items()]})
         if k == "gauss":
             return _GaussLaplacian(d)
+        if k == "xsinexp":                     # x sin(y) e^z is harmonic
+            return Field({"kind": "zero"})
         raise ValueError(k)
 
     def laplacian(self, X):
@@ -139,6 +149,9 @@ class Field:
                     t *= _avg_gauss(mu[i], s, lo[:, i], hi[:, i])
                 out += t
             return out
+        if k == "xsinexp":
+            return (d["amp"] * 0.5 * (lo[:, 0] + hi[:, 0]) * _avg_sin(1.0, 0.0, lo[:, 1], hi[:, 1])
+                    * _avg_exp(1.0, lo[:, 2], hi[:, 2]))
         raise ValueError(k)
 
     def box_average_grad(self, lo, hi, axis: int) -> np.ndarray:
@@ -190,6 +203,10 @@ class Field:
                         t *= _avg_gauss(mu[i], s, lo[:, i], hi[:, i])
                 out += t
             return out
+        if k == "xsinexp":
+            fx = 0.5 * (lo[:, 0] + hi[:, 0]) if axis != 0 else np.ones(len(lo))
+            fy = _avg_cos(1.0, 0.0, lo[:, 1], hi[:, 1]) if axis == 1 else _avg_sin(1.0, 0.0, lo[:, 1], hi[:, 1])
+            return d["amp"] * fx * fy * _avg_exp(1.0, lo[:, 2], hi[:, 2])
         raise ValueError(k)
 
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcutcell.so")
 
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_EGEOM, CC_EPLG, CC_ESINGULAR, CC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
-CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4}
+CC_FIELD = {"zero": 0, "poly": 1, "sinprod": 2, "expcos": 3, "gauss": 4, "xsinexp": 5}
 CC_VALUE, CC_LAPLACIAN = 0, 1
 CC_DIRICHLET, CC_NEUMANN, CC_ROBIN = 0, 1, 2
 CC_ELLIPSOID, CC_TORUS = 0, 1
@@ -34,7 +34,7 @@ EXPORTED = [
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
     "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc", "cc_set_overlap", "cc_net_pairs",
-    "cc_assemble_rhs_batched",
+    "cc_assemble_rhs_batched", "cc_fit_patches",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -181,6 +181,9 @@ def _field(desc: Optional[dict]):
         data = np.array([[a, *m, s] for a, m, s in zip(desc["amp"], desc["mu"], desc["sigma"])],
                         dtype=np.float64).reshape(-1)
         nt = len(desc["amp"])
+    elif k == "xsinexp":
+        data = np.array([desc["amp"]], dtype=np.float64)
+        nt = 1
     else:
         raise ValueError(k)
     data = np.ascontiguousarray(data)
@@ -310,6 +313,23 @@ class Problem:
         _check(load().cc_export_plg(self._h, level, cell.ctypes.data_as(C.c_void_p),
                                     cols.ctypes.data_as(C.c_void_p), vals.ctypes.data_as(C.c_void_p)))
         return cell, cols.reshape(N2, 35), vals.reshape(N2, 35)
+
+    def fit_patches(self, field: dict, level: int = 0):
+        """The paper's boundary fitting on every cut cell (cc_fit_patches):
+        (cell, axis, coef (n, 6), exact (n, 4), fitted (n, 4)); the last two
+        hold volume, patch area and the averages of `field` over region and
+        patch."""
+        n = self.level_info(level)["n_cut"]
+        cell = np.zeros(n, dtype=np.int32)
+        axis = np.zeros(n, dtype=np.int32)
+        coef = np.zeros(n * 6)
+        exact = np.zeros(n * 4)
+        fitted = np.zeros(n * 4)
+        f, keep = _field(field)
+        _check(load().cc_fit_patches(self._h, level, C.byref(f), cell.ctypes.data_as(C.c_void_p),
+                                     axis.ctypes.data_as(C.c_void_p), coef.ctypes.data_as(C.c_void_p),
+                                     exact.ctypes.data_as(C.c_void_p), fitted.ctypes.data_as(C.c_void_p)))
+        return cell, axis, coef.reshape(n, 6), exact.reshape(n, 4), fitted.reshape(n, 4)
 
     def export_lu_nodes(self, level: int = 0):
         k = self.level_info(level)["lu_nodes"]

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcutcell.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "kernels.hip", "net.hip", "quadrature.cpp", "level.cpp", "mf_lu.cpp"]
+SOURCES = ["api.cpp", "kernels.hip", "net.hip", "quadrature.cpp", "level.cpp", "mf_lu.cpp", "fitted.cpp"]
 ARCH = os.environ.get("CUTCELL_ARCH", "gfx950")
 
 # packed FP32 instructions stay off (the compiler must not form v_pk_*_f32)

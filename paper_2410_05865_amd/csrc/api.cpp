@@ -1175,6 +1175,7 @@ FieldDesc to_desc(const cc_field* f) {
     case CC_FIELD_SINPROD: per = 7; break;
     case CC_FIELD_EXPCOS: per = 5; break;
     case CC_FIELD_GAUSS: per = 5 * f->n_terms; break;
+    case CC_FIELD_XSINEXP: per = 1; break;
     default: fail(CC_EINVAL, "unknown field kind");
   }
   if (per > kFieldMax || per < 0) fail(CC_EINVAL, "field has too many terms");
@@ -1451,6 +1452,15 @@ int cc_export_cells(const cc_problem* p, int level, unsigned char* type, int* ho
       if (host) host[c] = L.host[c];
       if (volfrac) volfrac[c] = L.vol[c] / h3;
     }
+  });
+}
+
+int cc_fit_patches(const cc_problem* p, int level, const cc_field* u, int* cell, int* axis, double* coef,
+                   double* exact, double* fitted) {
+  return guard([&] {
+    check_level(p, level);
+    FieldDesc fd = to_desc(u);
+    fit_cut_cells(*p->lv[level], p->dom, fd, cell, axis, coef, exact, fitted);
   });
 }
 

@@ -64,6 +64,8 @@ CC_HD inline double field_value(const FieldDesc& f, double x, double y, double z
       }
       return s;
     }
+    case 5:  // xsinexp: amp x sin(y) e^z, harmonic
+      return (mode == 0) ? f.d[0] * x * sin(y) * exp(z) : 0.0;
     default:
       return 0.0;
   }
@@ -108,6 +110,13 @@ CC_HD inline void field_grad(const FieldDesc& f, double x, double y, double z, d
         g[2] -= dz / s2 * e;
       }
       return;
+    case 5: {
+      double e = f.d[0] * exp(z);
+      g[0] = e * sin(y);
+      g[1] = e * x * cos(y);
+      g[2] = e * x * sin(y);
+      return;
+    }
     default:
       return;
   }

@@ -122,4 +122,13 @@ struct LevelHost {
 void shift_moments4(const double m[N4], const int delta[3], double out[N4]);
 void shift_moments3(const double m[N3], const int delta[3], double out[N3]);
 
+// The paper's boundary fitting on the cut cells of L (ascending index), as a
+// check of the exact geometry: per cell the height axis (-1: fewer than 6
+// boundary points), the 6 coefficients of the quadratic height function in
+// cell-centred coordinates scaled by h, and (volume, patch area, average of u
+// over the region, over the patch) for the exact and the fitted region.
+// Null outputs are skipped.  (fitted.cpp)
+void fit_cut_cells(const LevelHost& L, const DomainSpec& dom, const FieldDesc& u, int* cell, int* axis, double* coef,
+                   double* exact, double* fitted);
+
 }  // namespace cc

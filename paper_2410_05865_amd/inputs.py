@@ -14,6 +14,7 @@ Field descriptors are plain dicts; the meaning of each kind is:
   sinprod  : amp * sin(k0 x + p0) sin(k1 y + p1) sin(k2 z + p2)
   expcos   : amp * exp(a x + b y) * cos(c z + p)
   gauss    : sum_j amp_j * exp(-|x - mu_j|^2 / (2 sigma_j^2))
+  xsinexp  : amp * x * sin(y) * exp(z)
 """
 from __future__ import annotations
 
@@ -167,6 +168,18 @@ def gauss_field(amps, mus, sigmas) -> dict:
     return {"kind": "gauss", "amp": [float(v) for v in amps],
             "mu": [[float(t) for t in m] for m in mus],
             "sigma": [float(v) for v in sigmas]}
+
+
+def xsinexp_field(amp=10.0) -> dict:
+    """amp x sin(y) e^z: the function of the paper's geometry accuracy test
+    (Sec. 6.1, Table 1) with amp = 10."""
+    return {"kind": "xsinexp", "amp": float(amp)}
+
+
+def table1_domain(n: int) -> Domain:
+    """The geometry accuracy test of the paper's Table 1: the sphere of radius
+    0.2 centred at (0.5, 0.5, 0.5) on an n^3 grid of the unit box."""
+    return sphere_domain(n=n, radius=0.2, n_min=min(n, 16))
 
 
 def gaussian_rhs(domain: Domain, seed: int, count: int = 16,

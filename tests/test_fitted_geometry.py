@@ -1,0 +1,133 @@
+"""The paper's geometry front end (Sec. 3.1 boundary fitting; the accuracy
+test of Sec. 6.1, Table 1) on both sides (CPU only):
+
+  * the oracle's fit reproduces a quadratic height-function surface exactly
+    (coefficients, volume, area and averages of the fitted region);
+  * the library's cc_fit_patches (host) against the oracle on the sphere of
+    radius 0.2 at 16^3 and 32^3: same cut cells and height axes, fitted-region
+    results within 1e-9, exact ones within 1e-11 (coefficients of tiny
+    patches are ill-conditioned: 1e-6 absolute);
+  * Table 1 with the library at h = 1/64, 1/128, 1/256: third order in L1 and
+    L2 for both averages (the paper's Corollaries of Sec. 3.1), the volume error
+    of a patch O(h^5) and its area error O(h^4); the cell-average errors no
+    larger than the paper's (tests/golden/table1_sphere_errors.txt).  The
+    boundary-patch (face) averages come out 10-25x above the paper's, at the
+    same order: the paper does not say which boundary points it fits."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle.quadrature as qd
+from oracle import fitted
+from oracle.fields import Field
+from paper_2410_05865_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE1 = os.path.join(HERE, "golden", "table1_sphere_errors.txt")
+
+
+def _lib():
+    from paper_2410_05865_amd import _lib
+    try:
+        _lib.load()
+    except Exception as e:      # the library is built by __graft_entry__.build()
+        pytest.skip(f"library not built: {e}")
+    return _lib
+
+
+def _height_quadric(lo, hi, w, coef, s):
+    """s (W - p(U, V)) h with (U, V, W) the cell-centred coordinates / h."""
+    u, v = [i for i in range(3) if i != w]
+    c = 0.5 * (lo + hi)
+    h = hi[0] - lo[0]
+    A2, B2, C2, D1, E1, G0 = coef
+
+    class _Psi:
+        pass
+    # build through the same algebra as a plain function, then as a Quadric by sampling:
+    # a quadric is fixed by its values, so fit its 10 coefficients to 30 points
+    rng = np.random.default_rng(0)
+    X = lo + (hi - lo) * rng.uniform(-1.0, 2.0, (30, 3))
+    P = (X - c) / h
+    val = s * (P[:, w] - (A2 * P[:, u] ** 2 + B2 * P[:, u] * P[:, v] + C2 * P[:, v] ** 2 + D1 * P[:, u]
+                          + E1 * P[:, v] + G0)) * h
+    M = np.stack([X[:, 0] ** 2, X[:, 1] ** 2, X[:, 2] ** 2, 2 * X[:, 0] * X[:, 1], 2 * X[:, 0] * X[:, 2],
+                  2 * X[:, 1] * X[:, 2], X[:, 0], X[:, 1], X[:, 2], np.ones(30)], axis=1)
+    k = np.linalg.lstsq(M, val, rcond=None)[0]
+    Q = np.array([[k[0], k[3], k[4]], [k[3], k[1], k[5]], [k[4], k[5], k[2]]])
+    return qd.Quadric(Q, k[6:9], k[9])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fit_reproduces_quadratic_surfaces(seed):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 32
+    lo = np.array([0.3, 0.4, 0.5])
+    hi = lo + h
+    w = seed % 3
+    coef = np.concatenate([rng.uniform(-0.4, 0.4, 3), rng.uniform(-0.4, 0.4, 2), rng.uniform(-0.15, 0.15, 1)])
+    s = 1.0 if seed % 2 else -1.0
+    psi = _height_quadric(lo, hi, w, coef, s)
+    F = Field(inputs.xsinexp_field())
+    got = fitted.fit_patch(psi, lo, hi)
+    assert got is not None
+    gw, gcoef, gpsi = got
+    assert gw == w
+    assert np.max(np.abs(gcoef - coef)) < 1e-10
+    ex = fitted.patch_averages(psi, lo, hi, F)
+    fi = fitted.patch_averages(gpsi, lo, hi, F)
+    assert 0 < ex[0] < h ** 3 and ex[1] > 0
+    assert np.allclose(ex, fi, rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_library_fits_match_oracle(n):
+    L = _lib()
+    fd = inputs.xsinexp_field()
+    dom = inputs.table1_domain(n)
+    P = L.Problem(dom, device=-1)
+    cell, axis, coef, ex, fi = P.fit_patches(fd)
+    P.close()
+    rows = fitted.cut_cell_fits(dom, n, Field(fd))
+    assert np.array_equal(cell, [r[0] for r in rows])
+    assert np.array_equal(axis, [r[1] for r in rows])
+    assert np.all(axis >= 0)
+    assert np.max(np.abs(coef - np.array([r[2] for r in rows]))) < 1e-6
+    oex = np.array([r[3] for r in rows])
+    ofi = np.array([r[4] for r in rows])
+    assert np.max(np.abs(ex - oex) / np.abs(oex)) < 1e-11
+    assert np.max(np.abs(fi - ofi) / np.abs(ofi)) < 1e-9
+
+
+def _norms(e):
+    e = np.abs(e)
+    return np.array([e.max(), e.mean(), np.sqrt(np.mean(e * e))])
+
+
+def test_table1_orders_and_magnitudes():
+    L = _lib()
+    fd = inputs.xsinexp_field()
+    rows = [l.split() for l in open(TABLE1) if l.strip() and not l.startswith("#")]
+    paper = {int(r[0]): np.array([float(v) for v in r[1:]]) for r in rows}
+    res = {}
+    for n in (64, 128, 256):
+        P = L.Problem(inputs.table1_domain(n), device=-1)
+        cell, axis, coef, ex, fi = P.fit_patches(fd)
+        P.close()
+        assert np.all(axis >= 0) and np.all(fi[:, :2] > 0)
+        h = 1.0 / n
+        cellerr = _norms(ex[:, 2] - fi[:, 2])
+        faceerr = _norms(ex[:, 3] - fi[:, 3])
+        res[n] = (cellerr, faceerr, np.max(np.abs(ex[:, 0] - fi[:, 0])) / h ** 5,
+                  np.max(np.abs(ex[:, 1] - fi[:, 1])) / h ** 4)
+        print(f"[table1] h = 1/{n}: cell Linf/L1/L2 {cellerr[0]:.2e}/{cellerr[1]:.2e}/{cellerr[2]:.2e} "
+              f"(paper {paper[n][0]:.2e}/{paper[n][1]:.2e}/{paper[n][2]:.2e}); face {faceerr[0]:.2e}/"
+              f"{faceerr[1]:.2e}/{faceerr[2]:.2e} (paper {paper[n][3]:.2e}/{paper[n][4]:.2e}/{paper[n][5]:.2e}); "
+              f"max |dV|/h^5 {res[n][2]:.3g}, max |dA|/h^4 {res[n][3]:.3g}", flush=True)
+        assert np.all(cellerr <= paper[n][:3])
+    for k in (1, 2):
+        assert np.log2(res[64][0][k] / res[256][0][k]) / 2 > 2.7
+        assert np.log2(res[64][1][k] / res[256][1][k]) / 2 > 2.7
+    # O(h^5) volumes and O(h^4) areas: the scaled maxima stay bounded
+    assert res[256][2] < 2.0 * res[64][2] and res[256][3] < 2.0 * res[64][3]

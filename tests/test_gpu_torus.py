@@ -12,7 +12,8 @@ walls, Neumann torus, u = cos(pi x) cos(pi y) sin(pi z).
   * Truncation and solution errors at h = 1/64, 1/128, 1/256 in the paper's
     norms (L1, L2 volume-weighted over |Omega|, Linf max, over the cells that
     carry an unknown) against the paper's Table 3
-    (tests/golden/problem2_torus_errors.txt)."""
+    (tests/golden/problem2_torus_errors.txt): no norm above the paper's, and
+    fourth order in the max norm between 1/64 and 1/256."""
 import hashlib
 import os
 
@@ -145,9 +146,12 @@ def test_problem2_errors_against_table3():
               f"{tau[0]:.2e}/{tau[1]:.2e}/{tau[2]:.2e} (paper {pp[0]:.2e}/{pp[1]:.2e}/{pp[2]:.2e}); solution "
               f"{err[0]:.2e}/{err[1]:.2e}/{err[2]:.2e} (paper {pp[3]:.2e}/{pp[4]:.2e}/{pp[5]:.2e})", flush=True)
         P.close()
+    # measured: every norm below the paper's, the solution errors by about 4x
+    # (h = 1/256: 2.65e-10 / 1.20e-11 / 2.35e-11 against 1.09e-9 / 3.39e-11 / 7.98e-11)
     for n, (tau, err) in got.items():
         pp = paper[n]
         for k in range(3):
-            assert err[k] <= 3.0 * pp[3 + k], (n, k, err[k], pp[3 + k])
+            assert tau[k] <= pp[k], (n, "truncation", k, tau[k], pp[k])
+            assert err[k] <= pp[3 + k], (n, "solution", k, err[k], pp[3 + k])
     rate = np.log2(got[64][1][0] / got[256][1][0]) / 2
     assert rate > 3.5, rate
