@@ -40,7 +40,7 @@ enum {
   CC_ENOCONV = -7     /* max_iter V-cycles without reaching tol */
 };
 
-enum { CC_DIRICHLET = 0, CC_NEUMANN = 1, CC_ROBIN = 2 /* obstacles only */ };
+enum { CC_DIRICHLET = 0, CC_NEUMANN = 1, CC_ROBIN = 2 };
 enum { CC_ELLIPSOID = 0, CC_TORUS = 1 };
 enum { CC_FP64 = 0, CC_MIXED = 1 };
 
@@ -63,7 +63,8 @@ typedef struct cc_obstacle {
   double radii[2];    /* CC_TORUS: major R and minor r, R > r > 0; ignored otherwise */
 } cc_obstacle;
 
-/* Grid and domain (Sec. 2.2).  Walls ordered -x,+x,-y,+y,-z,+z. */
+/* Grid and domain (Sec. 2.2).  Walls ordered -x,+x,-y,+y,-z,+z; each CC_DIRICHLET,
+ * CC_NEUMANN or CC_ROBIN. */
 typedef struct cc_domain {
   int n;              /* cells per axis on the finest level */
   double origin[3];   /* x_O */
@@ -74,6 +75,13 @@ typedef struct cc_domain {
   int inside;         /* 0: Omega = the box minus the obstacles; 1: Omega = the interior
                          of the one obstacle (n_obst must be 1; the walls then carry no
                          unknowns) */
+  double wall_robin[6][2]; /* (alpha, beta) of each CC_ROBIN wall: alpha phi + beta dphi/dn = g
+                         on the wall, n out of the box; the two ghost cells beyond it are
+                         filled from the quartic that matches the 4 nearest cell averages
+                         and the condition (Sec. 2.3 ghost formulas, with the Robin face
+                         condition in place of the Dirichlet or Neumann one), so (1, 0)
+                         and (0, 1) give the Dirichlet and Neumann walls; FV-PLG wall sites
+                         are scaled as on obstacles; ignored for other walls */
 } cc_domain;
 
 /* Method parameters (Sec. 4.2 theta; Sec. 5.3 omega, nu1, nu2, eps, I_max). */

@@ -55,6 +55,40 @@ GHOST_NEUMANN = {1: ((1, -5, 9, 5), 12, 10.0),
 STENCIL5 = {-2: -1.0, -1: 16.0, 0: -30.0, 1: 16.0, 2: -1.0}
 
 
+def robin_ghost_rule(alpha: float, beta: float, h: float):
+    """Ghost-cell formulas beyond a wall with the condition alpha phi + beta
+    dphi/dn = g (n out of the box), derived as the Dirichlet and Neumann ones
+    are: in units of h along the wall normal (the wall at 0, interior cells
+    [j-1, j], j = 1..4, ghost g = [-g, 1-g]), the quartic P whose averages over
+    the 4 interior cells are A_1..A_4 and with alpha P(0) - (beta/h) P'(0) = D,
+    D the face average of g; each ghost average of P is a combination of the
+    A_j and D.  Returns {g: (coefficients of A_4, A_3, A_2, A_1, coefficient of
+    D)}."""
+    def avg(k, a, b):
+        return (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+    M = np.zeros((5, 5))
+    for j in range(1, 5):
+        M[j - 1] = [avg(k, j - 1, j) for k in range(5)]
+    M[4] = [alpha, -beta / h, 0.0, 0.0, 0.0]
+    out = {}
+    for g in (1, 2):
+        m = np.array([avg(k, -g, 1 - g) for k in range(5)])
+        r = np.linalg.solve(M.T, m)          # ghost = r . (A_1, .., A_4, D)
+        out[g] = (tuple(r[3::-1]), float(r[4]))
+    return out
+
+
+def ghost_rule(bc: int, robin, h: float):
+    """{g: (coefficients of the 4 interior cells farthest first, datum
+    coefficient)} for a Dirichlet (datum <g>), Neumann (datum <dphi/dn>) or
+    Robin (datum <alpha g + beta dg/dn>) wall."""
+    if bc == DIRICHLET:
+        return {g: (tuple(c / den for c in cs), dat / den) for g, (cs, dat, den) in GHOST_DIRICHLET.items()}
+    if bc == NEUMANN:
+        return {g: (tuple(c / den for c in cs), dat * h / den) for g, (cs, dat, den) in GHOST_NEUMANN.items()}
+    return robin_ghost_rule(robin[0], robin[1], h)
+
+
 class PLGError(RuntimeError):
     pass
 
@@ -101,6 +135,7 @@ class Level:
         self.uidx = np.full(n ** 3, -1, dtype=np.int64)
         self.uidx[self.unknowns] = np.arange(self.N)
         self.wall_bc = list(domain.wall_bc)
+        self.wall_robin = [tuple(map(float, ab)) for ab in getattr(domain, "wall_robin", ((1.0, 0.0),) * 6)]
         n3 = n ** 3
         self.plain = np.zeros(n3, dtype=bool)
         for p, mem in self.groups.items():
@@ -163,16 +198,15 @@ class Level:
                     continue
                 side = 1 if t >= n else -1
                 g = t - (n - 1) if side > 0 else -t     # ghost number 1 or 2
-                bc = self.wall_bc[2 * d + (1 if side > 0 else 0)]
-                coefs, dat, den = (GHOST_DIRICHLET if bc == DIRICHLET else GHOST_NEUMANN)[g]
+                wall = 2 * d + (1 if side > 0 else 0)
+                coefs, datum = ghost_rule(self.wall_bc[wall], self.wall_robin[wall], h)[g]
                 # interior cells, farthest first: for the upper wall n-4..n-1
                 line = list(range(n - 4, n)) if side > 0 else [3, 2, 1, 0]
                 for cc, tt in zip(coefs, line):
                     q = list(ijk)
                     q[d] = tt
                     key = self.idx(*q)
-                    cols[key] = cols.get(key, 0.0) + c5 * s * cc / den
-                datum = dat / den if bc == DIRICHLET else dat * h / den
+                    cols[key] = cols.get(key, 0.0) + c5 * s * cc
                 walls.append((d, side, c5 * s * datum))
         return cols, walls
 
@@ -354,9 +388,20 @@ class Level:
                         sites.append(("W", c, bc, (d, side)))
         return cells, sites
 
+    def _wall_robin_scale(self, d: int, side: int):
+        """(alpha, beta, s) of a Robin wall, s = h / (|alpha| h + |beta|)."""
+        alpha, beta = self.wall_robin[2 * d + (1 if side > 0 else 0)]
+        return alpha, beta, self.h / (abs(alpha) * self.h + abs(beta))
+
     def _wall_functional(self, p_target: int, c: int, bc: int, d: int, side: int):
         """Dirichlet: <xi^a> over the wall face of cell c; Neumann:
-        <n . grad_xi xi^a> there (n = side e_d); xi centred at the target."""
+        <n . grad_xi xi^a> there (n = side e_d); Robin: s (alpha <xi^a> +
+        (beta / h) <n . grad_xi xi^a>), scaled as on obstacle patches; xi
+        centred at the target."""
+        if bc == ROBIN:
+            alpha, beta, sc = self._wall_robin_scale(d, side)
+            return sc * (alpha * self._wall_functional(p_target, c, DIRICHLET, d, side)
+                         + (beta / self.h) * self._wall_functional(p_target, c, NEUMANN, d, side))
         dl = np.array(self.ijk(c)) - np.array(self.ijk(p_target))
         xf = dl[d] + 0.5 * side                    # face position in xi_d
         def avg(k, delta):                         # mean of (t + delta)^k on [-1/2, 1/2]
@@ -466,7 +511,11 @@ class Level:
         lo[d] = hi[d] = xw
         if bc == DIRICHLET:
             return float(field.box_average(lo[None], hi[None])[0])
-        return side * float(field.box_average_grad(lo[None], hi[None], d)[0])
+        dn = side * float(field.box_average_grad(lo[None], hi[None], d)[0])
+        if bc == NEUMANN:
+            return dn
+        alpha, beta = self.wall_robin[2 * d + (1 if side > 0 else 0)]
+        return alpha * float(field.box_average(lo[None], hi[None])[0]) + beta * dn
 
     def rhs(self, f: Field, g: Field) -> np.ndarray:
         """r = f_avg - N g: cell averages of f minus the boundary-data terms."""
@@ -481,8 +530,10 @@ class Level:
                 if kind == "W":
                     d, side = extra
                     dat = self.wall_datum(g, m, d, side, bc)
-                    if bc != DIRICHLET:
+                    if bc == NEUMANN:
                         dat *= h
+                    elif bc == ROBIN:
+                        dat *= self._wall_robin_scale(d, side)[2]
                     r[row] -= v * dat
                     continue
                 cc = self.geo.cut[m]

@@ -47,7 +47,8 @@ class CcObstacle(C.Structure):
 
 class CcDomain(C.Structure):
     _fields_ = [("n", C.c_int), ("origin", C.c_double * 3), ("h", C.c_double), ("wall_bc", C.c_int * 6),
-                ("n_obst", C.c_int), ("obst", C.POINTER(CcObstacle)), ("inside", C.c_int)]
+                ("n_obst", C.c_int), ("obst", C.POINTER(CcObstacle)), ("inside", C.c_int),
+                ("wall_robin", (C.c_double * 2) * 6)]
 
 
 class CcParams(C.Structure):
@@ -245,6 +246,9 @@ class Problem:
         dom.n_obst = len(domain.obstacles)
         dom.obst = obs
         dom.inside = int(bool(getattr(domain, "inside", False)))
+        for w, ab in enumerate(getattr(domain, "wall_robin", ((1.0, 0.0),) * 6)):
+            dom.wall_robin[w][0] = float(ab[0])
+            dom.wall_robin[w][1] = float(ab[1])
         h = C.c_void_p()
         st = C.c_void_p(stream) if stream is not None else None
         _check(lib.cc_build(C.byref(dom), C.byref(prm), st, C.byref(h)))

@@ -48,8 +48,8 @@ double now_s() {
 }
 
 // Regular-row entries of a phi_1 cell (coefficients times 12 h^2), same tables
-// as the device stencil.
-void regular_entries(int n, const int bc[6], int i, int j, int k, std::map<int, double>& row) {
+// as the device stencil; Robin walls take the level's assembled wall rows.
+void regular_entries(int n, const int bc[6], const WallRows wr[6], int i, int j, int k, std::map<int, double>& row) {
   int ii[3] = {i, j, k};
   long stride[3] = {1, n, (long)n * n};
   long c = i + (long)n * (j + (long)n * k);
@@ -61,28 +61,23 @@ void regular_entries(int n, const int bc[6], int i, int j, int k, std::map<int, 
     if (t >= 2 && t <= n - 3) {
       add(-2, -1.0); add(-1, 16.0); add(0, -30.0); add(1, 16.0); add(2, -1.0);
     } else if (t == n - 1) {
-      if (bhi == 0) { add(-3, 21.0 / 12); add(-2, -139.0 / 12); add(-1, 545.0 / 12); add(0, -1087.0 / 12); }
+      if (bhi == CC_ROBIN) { for (int q = 0; q < 4; ++q) add(-q, wr[2 * d + 1].lay[0][q]); }
+      else if (bhi == 0) { add(-3, 21.0 / 12); add(-2, -139.0 / 12); add(-1, 545.0 / 12); add(0, -1087.0 / 12); }
       else { add(-3, 0.1); add(-2, -1.5); add(-1, 15.9); add(0, -14.5); }
     } else if (t == n - 2) {
-      if (bhi == 0) { add(-2, -15.0 / 12); add(-1, 209.0 / 12); add(0, -403.0 / 12); add(1, 269.0 / 12); }
+      if (bhi == CC_ROBIN) { for (int q = 0; q < 4; ++q) add(1 - q, wr[2 * d + 1].lay[1][q]); }
+      else if (bhi == 0) { add(-2, -15.0 / 12); add(-1, 209.0 / 12); add(0, -403.0 / 12); add(1, 269.0 / 12); }
       else { add(-2, -1.1); add(-1, 16.5); add(0, -30.9); add(1, 15.5); }
     } else if (t == 0) {
-      if (blo == 0) { add(3, 21.0 / 12); add(2, -139.0 / 12); add(1, 545.0 / 12); add(0, -1087.0 / 12); }
+      if (blo == CC_ROBIN) { for (int q = 0; q < 4; ++q) add(q, wr[2 * d].lay[0][q]); }
+      else if (blo == 0) { add(3, 21.0 / 12); add(2, -139.0 / 12); add(1, 545.0 / 12); add(0, -1087.0 / 12); }
       else { add(3, 0.1); add(2, -1.5); add(1, 15.9); add(0, -14.5); }
     } else {  // t == 1
-      if (blo == 0) { add(2, -15.0 / 12); add(1, 209.0 / 12); add(0, -403.0 / 12); add(-1, 269.0 / 12); }
+      if (blo == CC_ROBIN) { for (int q = 0; q < 4; ++q) add(q - 1, wr[2 * d].lay[1][q]); }
+      else if (blo == 0) { add(2, -15.0 / 12); add(1, 209.0 / 12); add(0, -403.0 / 12); add(-1, 269.0 / 12); }
       else { add(2, -1.1); add(1, 16.5); add(0, -30.9); add(-1, 15.5); }
     }
   }
-}
-
-// Wall-datum coefficient (times 12 h^2) of a regular row at layer t of axis
-// length n next to a wall of condition bc: Dirichlet datum <g>, Neumann datum
-// <dphi/dn> (outward).  0 if not next to that wall.
-double wall_coef(int layer, int bc, double h) {
-  if (layer == 0) return bc == CC_DIRICHLET ? 55.0 : 13.2 * h;
-  if (layer == 1) return bc == CC_DIRICHLET ? -5.0 : -1.2 * h;
-  return 0.0;
 }
 
 struct DevBuf {
@@ -292,7 +287,7 @@ void build_lu_matrix(const LevelHost& L, bool bottom, CSR& A, std::vector<std::a
     xyz[t] = {i, j, k};
     std::map<int, double> row;
     if (L.type[c] == kPhi1) {
-      regular_entries(n, L.wall_bc, i, j, k, row);
+      regular_entries(n, L.wall_bc, L.wall, i, j, k, row);
       for (auto& kv : row) kv.second *= s12;
     } else {
       int r = plg_row[c];
@@ -559,7 +554,11 @@ void upload(cc_problem* P) {
     DevLevel& D = P->dev[m];
     D.st.n = L.n;
     D.st.inv12h2 = 1.0 / (12.0 * L.h * L.h);
-    for (int a = 0; a < 6; ++a) D.st.bc[a] = L.wall_bc[a];
+    for (int a = 0; a < 6; ++a) {
+      D.st.bc[a] = L.wall_bc[a];
+      for (int ly = 0; ly < 2; ++ly)
+        for (int q = 0; q < 4; ++q) D.st.rob[a][ly][q] = L.wall[a].lay[ly][q];
+    }
     D.st.type = B.upload(L.type);
     default_stencil_schedule(L.n, D.st.march, D.st.kz);
     // zone 1: phi_2 cells, and phi_1 cells with a phi_2 cell within 3 cells along
@@ -1222,6 +1221,17 @@ double face_average(const LevelHost& L, const FieldDesc& g, int cell, int axis, 
   return 0.25 * acc;
 }
 
+// The datum of the wall face of `cell` on wall (axis, side): Dirichlet <g>,
+// Neumann <dg/dn>, Robin <alpha g + beta dg/dn> (n out of the box).
+double wall_datum(const LevelHost& L, const FieldDesc& g, int cell, int axis, int side) {
+  const int w = 2 * axis + (side > 0 ? 1 : 0);
+  const int bc = L.wall_bc[w];
+  if (bc == CC_DIRICHLET) return face_average(L, g, cell, axis, side, false);
+  if (bc == CC_NEUMANN) return face_average(L, g, cell, axis, side, true);
+  const double* ab = L.dom->wall_robin[w];
+  return ab[0] * face_average(L, g, cell, axis, side, false) + ab[1] * face_average(L, g, cell, axis, side, true);
+}
+
 }  // namespace
 }  // namespace cc
 
@@ -1283,8 +1293,15 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     if (prm->krylov < 0 || prm->krylov > 64) fail(CC_EINVAL, "krylov must lie in [0, 64]");
     if (!(prm->pivot_tol > 0 && prm->pivot_tol <= 1e6)) fail(CC_EINVAL, "pivot_tol must lie in (0, 1e6]");
     if (prm->fit_on_device != 0 && prm->fit_on_device != 1) fail(CC_EINVAL, "fit_on_device must be 0 or 1");
-    for (int a = 0; a < 6; ++a)
-      if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN) fail(CC_EINVAL, "bad wall bc");
+    for (int a = 0; a < 6; ++a) {
+      if (dom->wall_bc[a] != CC_DIRICHLET && dom->wall_bc[a] != CC_NEUMANN && dom->wall_bc[a] != CC_ROBIN)
+        fail(CC_EINVAL, "bad wall bc");
+      if (dom->wall_bc[a] == CC_ROBIN) {
+        const double al = dom->wall_robin[a][0], be = dom->wall_robin[a][1];
+        if (!(std::isfinite(al) && std::isfinite(be)) || (al == 0.0 && be == 0.0))
+          fail(CC_EINVAL, "a Robin wall needs finite (alpha, beta), not both 0");
+      }
+    }
     auto P = std::make_unique<cc_problem>();
     P->prm = *prm;
     P->device = prm->device;
@@ -1292,7 +1309,11 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     D.n = dom->n;
     D.h = dom->h;
     for (int a = 0; a < 3; ++a) D.origin[a] = dom->origin[a];
-    for (int a = 0; a < 6; ++a) D.wall_bc[a] = dom->wall_bc[a];
+    for (int a = 0; a < 6; ++a) {
+      D.wall_bc[a] = dom->wall_bc[a];
+      D.wall_robin[a][0] = dom->wall_bc[a] == CC_ROBIN ? dom->wall_robin[a][0] : 0.0;
+      D.wall_robin[a][1] = dom->wall_bc[a] == CC_ROBIN ? dom->wall_robin[a][1] : 0.0;
+    }
     for (int t = 0; t < dom->n_obst; ++t) {
       const cc_obstacle& o = dom->obst[t];
       Obstacle ob;
@@ -1667,9 +1688,8 @@ static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<Fie
         for (int side : {-1, 1}) {
           int layer = side > 0 ? n - 1 - ii[d] : ii[d];
           if (layer > 1) continue;
-          int bc = L.wall_bc[2 * d + (side > 0 ? 1 : 0)];
-          double dat = face_average(L, gds[k], c, d, side, bc == CC_NEUMANN);
-          corr += wall_coef(layer, bc, h) * s12 * dat;
+          const int w = 2 * d + (side > 0 ? 1 : 0);
+          corr += L.wall[w].dat[layer] * s12 * wall_datum(L, gds[k], c, d, side);
         }
       add_vals[t * nf + k] = -corr;
     }
@@ -1685,8 +1705,13 @@ static void assemble_rhs(cc_problem* p, int level, int nf, const std::vector<Fie
         const Site& st = L.sites[si];
         double dat;
         if (st.kind == 'W') {
-          dat = face_average(L, gds[k], st.cell, st.axis, st.side, st.bc == CC_NEUMANN);
-          if (st.bc == CC_NEUMANN) dat *= h;
+          dat = wall_datum(L, gds[k], st.cell, st.axis, st.side);
+          if (st.bc == CC_NEUMANN) {
+            dat *= h;
+          } else if (st.bc == CC_ROBIN) {
+            const double* ab = L.dom->wall_robin[2 * st.axis + (st.side > 0 ? 1 : 0)];
+            dat *= h / (std::fabs(ab[0]) * h + std::fabs(ab[1]));
+          }
         } else {
           dat = cut_dat[cut_pos.at(st.cell) * nf + k];
         }

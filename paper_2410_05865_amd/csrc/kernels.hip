@@ -65,15 +65,22 @@ __device__ __forceinline__ double block_max(double v) {
 
 // One axis of the assembled regular row (times 12 h^2): the 5-point
 // fourth-order stencil, with the ghost-substituted forms in the two cell layers
-// next to a Dirichlet (bc 0) or Neumann (bc 1) wall.  x(d) is the operand at
-// offset d (-3..3) along the axis; adds the diagonal to diag.
+// next to a Dirichlet (bc 0), Neumann (bc 1) or Robin (bc 2: the level's
+// assembled rows L.rob) wall.  x(d) is the operand at offset d (-3..3) along
+// axis `ax`; adds the diagonal to diag.
 template <class T, class X>
-__device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& diag) {
+__device__ __forceinline__ T axis_op_at(X x, int t, int n, const StencilLevel& L, int ax, T& diag) {
+  const int blo = L.bc[2 * ax], bhi = L.bc[2 * ax + 1];
   if (t >= 2 && t <= n - 3) {
     diag += T(-30.0);
     return -x(-2) + T(16.0) * x(-1) - T(30.0) * x(0) + T(16.0) * x(1) - x(2);
   }
   if (t == n - 1) {
+    if (bhi == 2) {
+      const double* r = L.rob[2 * ax + 1][0];
+      diag += T(r[0]);
+      return T(r[0]) * x(0) + T(r[1]) * x(-1) + T(r[2]) * x(-2) + T(r[3]) * x(-3);
+    }
     if (bhi == 0) {
       diag += T(-1087.0 / 12.0);
       return (T(21.0) * x(-3) - T(139.0) * x(-2) + T(545.0) * x(-1) - T(1087.0) * x(0)) / T(12.0);
@@ -82,6 +89,11 @@ __device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& 
     return T(0.1) * x(-3) - T(1.5) * x(-2) + T(15.9) * x(-1) - T(14.5) * x(0);
   }
   if (t == n - 2) {
+    if (bhi == 2) {
+      const double* r = L.rob[2 * ax + 1][1];
+      diag += T(r[1]);
+      return T(r[0]) * x(1) + T(r[1]) * x(0) + T(r[2]) * x(-1) + T(r[3]) * x(-2);
+    }
     if (bhi == 0) {
       diag += T(-403.0 / 12.0);
       return (T(-15.0) * x(-2) + T(209.0) * x(-1) - T(403.0) * x(0) + T(269.0) * x(1)) / T(12.0);
@@ -90,6 +102,11 @@ __device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& 
     return T(-1.1) * x(-2) + T(16.5) * x(-1) - T(30.9) * x(0) + T(15.5) * x(1);
   }
   if (t == 0) {
+    if (blo == 2) {
+      const double* r = L.rob[2 * ax][0];
+      diag += T(r[0]);
+      return T(r[0]) * x(0) + T(r[1]) * x(1) + T(r[2]) * x(2) + T(r[3]) * x(3);
+    }
     if (blo == 0) {
       diag += T(-1087.0 / 12.0);
       return (T(21.0) * x(3) - T(139.0) * x(2) + T(545.0) * x(1) - T(1087.0) * x(0)) / T(12.0);
@@ -98,6 +115,11 @@ __device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& 
     return T(0.1) * x(3) - T(1.5) * x(2) + T(15.9) * x(1) - T(14.5) * x(0);
   }
   // t == 1
+  if (blo == 2) {
+    const double* r = L.rob[2 * ax][1];
+    diag += T(r[1]);
+    return T(r[0]) * x(-1) + T(r[1]) * x(0) + T(r[2]) * x(1) + T(r[3]) * x(2);
+  }
   if (blo == 0) {
     diag += T(-403.0 / 12.0);
     return (T(-15.0) * x(2) + T(209.0) * x(1) - T(403.0) * x(0) + T(269.0) * x(-1)) / T(12.0);
@@ -108,9 +130,9 @@ __device__ __forceinline__ T axis_op_at(X x, int t, int n, int blo, int bhi, T& 
 
 // The same axis with the operand read from x at stride s around cell c.
 template <class T>
-__device__ __forceinline__ T axis_op(const T* __restrict__ x, long c, long s, int t, int n, int blo, int bhi,
-                                     T& diag) {
-  return axis_op_at<T>([&](int d) { return x[c + d * s]; }, t, n, blo, bhi, diag);
+__device__ __forceinline__ T axis_op(const T* __restrict__ x, long c, long s, int t, int n, const StencilLevel& L,
+                                     int ax, T& diag) {
+  return axis_op_at<T>([&](int d) { return x[c + d * s]; }, t, n, L, ax, diag);
 }
 
 // (L x)_c * 12 h^2 for a phi_1 cell and its diagonal.
@@ -120,9 +142,9 @@ __device__ __forceinline__ T regular_row(const StencilLevel& L, const T* __restr
   const int n = L.n;
   const long nn = (long)n * n;
   diag = T(0);
-  T a = axis_op<T>(x, c, 1, i, n, L.bc[0], L.bc[1], diag);
-  a += axis_op<T>(x, c, n, j, n, L.bc[2], L.bc[3], diag);
-  a += axis_op<T>(x, c, nn, k, n, L.bc[4], L.bc[5], diag);
+  T a = axis_op<T>(x, c, 1, i, n, L, 0, diag);
+  a += axis_op<T>(x, c, n, j, n, L, 1, diag);
+  a += axis_op<T>(x, c, nn, k, n, L, 2, diag);
   return a;
 }
 
@@ -309,13 +331,13 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
         T v = (Mode == kMarchSmo || Mode == kMarchSmoFar) ? q[kHalo] : T(0);
         if (valid && cur.type == 1) {
           T diag = T(0);
-          T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L.bc[0], L.bc[1], diag);
+          T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L, 0, diag);
           a += axis_op_at<T>(
               [&](int d) {
                 return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : cur.y[d < 0 ? d + 2 : d + 1];
               },
-              j, n, L.bc[2], L.bc[3], diag);
-          a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L.bc[4], L.bc[5], diag);
+              j, n, L, 1, diag);
+          a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L, 2, diag);
           if constexpr (Mode == kMarchSmo || Mode == kMarchSmoFar)
             v += omega * (cur.b - a * inv) / (diag * inv);
           else if constexpr (Mode == kMarchResidual)
@@ -358,12 +380,13 @@ __global__ __launch_bounds__(256) void k_stencil_apply_z(StencilLevel L, const d
 // Diagonal of the assembled regular row (times 12 h^2), summed over the axes in
 // the order regular_row uses.
 template <class T>
-__device__ __forceinline__ T axis_diag(int t, int n, int blo, int bhi) {
+__device__ __forceinline__ T axis_diag(int t, int n, const StencilLevel& L, int ax) {
+  const int blo = L.bc[2 * ax], bhi = L.bc[2 * ax + 1];
   if (t >= 2 && t <= n - 3) return T(-30.0);
-  if (t == n - 1) return bhi == 0 ? T(-1087.0 / 12.0) : T(-14.5);
-  if (t == n - 2) return bhi == 0 ? T(-403.0 / 12.0) : T(-30.9);
-  if (t == 0) return blo == 0 ? T(-1087.0 / 12.0) : T(-14.5);
-  return blo == 0 ? T(-403.0 / 12.0) : T(-30.9);
+  if (t == n - 1) return bhi == 2 ? T(L.rob[2 * ax + 1][0][0]) : bhi == 0 ? T(-1087.0 / 12.0) : T(-14.5);
+  if (t == n - 2) return bhi == 2 ? T(L.rob[2 * ax + 1][1][1]) : bhi == 0 ? T(-403.0 / 12.0) : T(-30.9);
+  if (t == 0) return blo == 2 ? T(L.rob[2 * ax][0][0]) : blo == 0 ? T(-1087.0 / 12.0) : T(-14.5);
+  return blo == 2 ? T(L.rob[2 * ax][1][1]) : blo == 0 ? T(-403.0 / 12.0) : T(-30.9);
 }
 
 // The first SMO-1 sweep of a V-cycle level, from e = 0: e' = omega s / D on
@@ -381,9 +404,9 @@ __global__ void k_smo1_first(StencilLevel L, T omega, const T* __restrict__ s, T
   T v = T(0);
   if (L.type[c] == 1) {
     T diag = T(0);
-    diag += axis_diag<T>(i, n, L.bc[0], L.bc[1]);
-    diag += axis_diag<T>(j, n, L.bc[2], L.bc[3]);
-    diag += axis_diag<T>(k, n, L.bc[4], L.bc[5]);
+    diag += axis_diag<T>(i, n, L, 0);
+    diag += axis_diag<T>(j, n, L, 1);
+    diag += axis_diag<T>(k, n, L, 2);
     const T inv = T(L.inv12h2);
     v += omega * (ld_stream(s + c) - T(0) * inv) / (diag * inv);
   }

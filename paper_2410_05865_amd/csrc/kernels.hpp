@@ -16,7 +16,9 @@ namespace cc {
 struct StencilLevel {
   int n;
   double inv12h2;        // 1 / (12 h^2)
-  int bc[6];             // wall conditions -x,+x,-y,+y,-z,+z
+  int bc[6];             // wall conditions -x,+x,-y,+y,-z,+z (0 Dirichlet, 1 Neumann, 2 Robin)
+  double rob[6][2][4];   // Robin walls: the assembled rows (times 12 h^2) of layer 0 and 1 on the 4
+                         // cells nearest the wall, nearest first
   const uint8_t* type;   // 0 no unknown, 1 phi_1, 2 phi_2
   int march;             // regular-row kernels (SMO-1, residual, apply): 1 march in z, 2 march in z with the
                          // XCD-aware tile order, 0 one cell per thread

@@ -104,7 +104,10 @@ void LevelHost::build(const DomainSpec& d, int n_level, double theta, PlgLsqSolv
   n = n_level;
   h = 1.0 / n;
   for (int i = 0; i < 3; ++i) origin[i] = d.origin[i];
-  for (int i = 0; i < 6; ++i) wall_bc[i] = d.wall_bc[i];
+  for (int i = 0; i < 6; ++i) {
+    wall_bc[i] = d.wall_bc[i];
+    wall[i] = wall_rows(d.wall_bc[i], d.wall_robin[i][0], d.wall_robin[i][1], h);
+  }
   size_t n3 = (size_t)n * n * n;
   // away from the obstacles' claimed cells: interior in the box minus the
   // obstacles, exterior for the interior of one obstacle
@@ -658,10 +661,18 @@ void LevelHost::plg_system(int p, int row, const int cells[kPLG], std::vector<do
             inplane *= (std::pow(dd + 0.5, k + 1) - std::pow(dd - 0.5, k + 1)) / (k + 1);
           }
         int ed = T.e4[j][d];
-        if (st.bc == CC_DIRICHLET)
-          rowp[j] = inplane * ipow(xf, ed);
-        else
-          rowp[j] = ed > 0 ? st.side * ed * ipow(xf, ed - 1) * inplane : 0.0;
+        const double dir = inplane * ipow(xf, ed);
+        const double neu = ed > 0 ? st.side * ed * ipow(xf, ed - 1) * inplane : 0.0;
+        if (st.bc == CC_DIRICHLET) {
+          rowp[j] = dir;
+        } else if (st.bc == CC_NEUMANN) {
+          rowp[j] = neu;
+        } else {
+          // Robin wall: s (alpha <xi^a> + (beta / h) <n . grad_xi xi^a>), s = h / (|alpha| h + |beta|)
+          const double* ab = dom->wall_robin[2 * d + (st.side > 0 ? 1 : 0)];
+          const double sc = h / (std::fabs(ab[0]) * h + std::fabs(ab[1]));
+          rowp[j] = sc * (ab[0] * dir + (ab[1] / h) * neu);
+        }
       }
     }
     sw[kPLG + s] = std::sqrt(weight(st.cell));
@@ -762,6 +773,59 @@ void LevelHost::rows(PlgLsqSolver* lsq) {
   if (err_code) fail(err_code, err_msg);
   sites.clear();
   for (auto& v : tsites) sites.insert(sites.end(), v.begin(), v.end());
+}
+
+// Ghost cells beyond a wall, in units of h along its normal (the wall at 0,
+// interior cells [j-1, j] with averages A_1..A_4, ghost g = [-g, 1-g]): the
+// averages of the quartic P that matches the A_j and the wall condition
+// (Dirichlet P(0) = D, Neumann -P'(0)/h = D, Robin alpha P(0) - (beta/h) P'(0) = D).
+// G_g = sum_j r_g[j] A_j + r_g[4] D, from M^T r_g = m_g with M the 5 x 5 system
+// and m_g the ghost averages of the monomials.  The rows follow by substituting
+// G_1, G_2 into the 5-point stencil of the two cells next to the wall.
+WallRows wall_rows(int bc, double alpha, double beta, double h) {
+  // Dirichlet and Neumann: the exact tables the stencil kernels use
+  if (bc == CC_DIRICHLET)
+    return WallRows{{{-1087.0 / 12, 545.0 / 12, -139.0 / 12, 21.0 / 12}, {269.0 / 12, -403.0 / 12, 209.0 / 12, -15.0 / 12}},
+                    {55.0, -5.0}};
+  if (bc == CC_NEUMANN)
+    return WallRows{{{-14.5, 15.9, -1.5, 0.1}, {15.5, -30.9, 16.5, -1.1}}, {13.2 * h, -1.2 * h}};
+  auto avg = [](int k, double a, double b) { return (std::pow(b, k + 1) - std::pow(a, k + 1)) / ((k + 1) * (b - a)); };
+  double r[2][5];
+  for (int g = 1; g <= 2; ++g) {
+    // solve M^T r = m by Gaussian elimination with partial pivoting (5 x 5)
+    double A[5][6];
+    for (int k = 0; k < 5; ++k) {       // row k of M^T = column k of M
+      for (int j = 0; j < 4; ++j) A[k][j] = avg(k, j, j + 1);
+      A[k][4] = (k == 0 ? alpha : 0.0) + (k == 1 ? -beta / h : 0.0);
+      A[k][5] = avg(k, -g, 1 - g);
+    }
+    for (int c = 0; c < 5; ++c) {
+      int piv = c;
+      for (int q = c + 1; q < 5; ++q)
+        if (std::fabs(A[q][c]) > std::fabs(A[piv][c])) piv = q;
+      if (piv != c)
+        for (int t = 0; t < 6; ++t) std::swap(A[c][t], A[piv][t]);
+      for (int q = c + 1; q < 5; ++q) {
+        const double f = A[q][c] / A[c][c];
+        for (int t = c; t < 6; ++t) A[q][t] -= f * A[c][t];
+      }
+    }
+    for (int c = 4; c >= 0; --c) {
+      double v = A[c][5];
+      for (int t = c + 1; t < 5; ++t) v -= A[c][t] * r[g - 1][t];
+      r[g - 1][c] = v / A[c][c];
+    }
+  }
+  WallRows w;
+  // layer 0: -G_2 + 16 G_1 - 30 A_1 + 16 A_2 - A_3
+  const double base0[4] = {-30.0, 16.0, -1.0, 0.0};
+  for (int j = 0; j < 4; ++j) w.lay[0][j] = base0[j] + 16.0 * r[0][j] - r[1][j];
+  w.dat[0] = 16.0 * r[0][4] - r[1][4];
+  // layer 1: -G_1 + 16 A_1 - 30 A_2 + 16 A_3 - A_4
+  const double base1[4] = {16.0, -30.0, 16.0, -1.0};
+  for (int j = 0; j < 4; ++j) w.lay[1][j] = base1[j] - r[0][j];
+  w.dat[1] = -r[0][4];
+  return w;
 }
 
 }  // namespace cc

@@ -27,6 +27,7 @@ struct DomainSpec {
   double origin[3];
   double h;
   int wall_bc[6];
+  double wall_robin[6][2] = {};  // (alpha, beta) of CC_ROBIN walls
   std::vector<Obstacle> obst;
   bool inside = false;  // Omega = interior of obst[0] (its quadric negated: Omega = {ls > 0} either way)
 };
@@ -66,10 +67,22 @@ struct PlgLsqSolver {
   virtual ~PlgLsqSolver() = default;
 };
 
+// The assembled regular row next to one wall (coefficients times 12 h^2):
+// layer 0 (the cell on the wall) and layer 1, each on the 4 cells nearest the
+// wall (nearest first, A_1..A_4), and the coefficient of the wall datum
+// (Dirichlet <g>, Neumann <dphi/dn>, Robin <alpha g + beta dg/dn>; n outward).
+// Built from the two ghost-cell formulas beyond the wall (Sec. 2.3).
+struct WallRows {
+  double lay[2][4];
+  double dat[2];
+};
+WallRows wall_rows(int bc, double alpha, double beta, double h);
+
 struct LevelHost {
   int n = 0;
   double h = 0, origin[3] = {0, 0, 0};
   int wall_bc[6] = {};
+  WallRows wall[6] = {};
   const DomainSpec* dom = nullptr;
 
   std::vector<int8_t> cls;       // n^3

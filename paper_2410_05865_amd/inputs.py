@@ -26,7 +26,7 @@ import numpy as np
 
 DIRICHLET = 0
 NEUMANN = 1
-ROBIN = 2                       # alpha phi + beta dphi/dn = g (obstacle surfaces only)
+ROBIN = 2                       # alpha phi + beta dphi/dn = g (obstacle surfaces and box walls)
 
 ELLIPSOID = 0                   # obstacle kinds
 TORUS = 1
@@ -57,6 +57,7 @@ class Domain:
     origin: Sequence[float] = (0.0, 0.0, 0.0)
     n_min: int = 16             # coarsest grid size of the multigrid hierarchy
     inside: bool = False        # Omega = the interior of obstacles[0] instead of the box minus the obstacles
+    wall_robin: Sequence[Tuple[float, float]] = ((1.0, 0.0),) * 6   # (alpha, beta) of ROBIN walls
 
     @property
     def h(self) -> float:

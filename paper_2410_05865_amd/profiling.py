@@ -20,13 +20,16 @@ SMO_KERNEL = "k_smo1_z<double>"
 
 def _last_run(seq, key):
     """Indices of the trailing run of consecutive entries of `seq` (dispatch
-    order) whose kernel is `key`: the timing hook's back-to-back launches,
-    which come after the build-time schedule trials of the same kernel."""
+    order; entries (kernel, grid, ...)) whose kernel is `key` and whose grid is
+    that of the last one: the timing hook's back-to-back launches, which can
+    follow the build-time schedule trials of the same kernel on other levels
+    directly (other grids)."""
     idx = [i for i, (k, *_rest) in enumerate(seq) if k == key]
     if not idx:
         return []
     run = [idx[-1]]
-    while run[-1] - 1 >= 0 and seq[run[-1] - 1][0] == key:
+    grid = seq[idx[-1]][1]
+    while run[-1] - 1 >= 0 and seq[run[-1] - 1][0] == key and seq[run[-1] - 1][1] == grid:
         run.append(run[-1] - 1)
     return run[::-1]
 

@@ -78,6 +78,25 @@ def test_traffic_summary_calibrates_with_the_copy_kernel(tmp_path):
     assert "fetch x2.0000, write x1.0000" in text
 
 
+def test_hook_run_is_split_from_trials_on_other_levels(tmp_path):
+    """The build's last schedule trials (a coarser level: another grid) can
+    directly precede the timing hook's launches of the same kernel."""
+    n = 64
+    n3 = n ** 3
+    true_kib = 8.0 * n3 / 1024.0
+    fe = [(1, SMO, n3 // 64, "FETCH_SIZE", 1.0), (2, SMO, n3 // 64, "FETCH_SIZE", 1.0),
+          (3, SMO, n3 // 4, "FETCH_SIZE", 1.5 * true_kib), (4, SMO, n3 // 4, "FETCH_SIZE", 1.5 * true_kib),
+          (5, COPY, n3 // 4, "FETCH_SIZE", true_kib / 2)]
+    wr = [(1, SMO, n3 // 64, "WRITE_SIZE", 1.0), (2, SMO, n3 // 64, "WRITE_SIZE", 1.0),
+          (3, SMO, n3 // 4, "WRITE_SIZE", true_kib), (4, SMO, n3 // 4, "WRITE_SIZE", true_kib),
+          (5, COPY, n3 // 4, "WRITE_SIZE", true_kib)]
+    _counter_db(tmp_path / "f.db", fe)
+    _counter_db(tmp_path / "w.db", wr)
+    text = profiling.traffic_summary(str(tmp_path / "f.db"), str(tmp_path / "w.db"), n, "abc")
+    assert "(2 dispatches, grid" in text
+    assert "measured/algorithmic = 1.280" in text
+
+
 def test_kernel_stats_take_the_timing_hooks_dispatches(tmp_path):
     con = sqlite3.connect(tmp_path / "t.db")
     con.execute("create table kernels (name text, start int, end int, grid_x int, grid_y int, grid_z int)")

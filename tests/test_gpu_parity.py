@@ -29,10 +29,18 @@ def _workloads():
     for ob, ab in zip(rob.obstacles, [(1.0, 0.3), (0.2, 1.0)]):     # Robin on both surfaces
         ob.bc = inputs.ROBIN
         ob.robin = ab
+    rw = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    rw.n_min = 16
+    for ob in rw.obstacles:
+        ob.bc = inputs.DIRICHLET
+    R = inputs.ROBIN
+    rw.wall_bc = (R, 0, R, 0, 0, R)            # Robin walls; 234 Robin wall sites in FV-PLG rows
+    rw.wall_robin = ((1.0, 0.5), (1.0, 0.0), (2.0, 0.05), (1.0, 0.0), (1.0, 0.0), (0.7, 0.7))
     small = inputs.sphere_domain(n=96, radius=0.1, n_min=24)   # ragged tiles, 3 levels
     return {"sphere32": (sph, inputs.sinprod_field()),
             "ellipsoid32_neumann": (ell, inputs.expcos_field()),
             "ellipsoid32_robin": (rob, inputs.expcos_field()),
+            "ellipsoid32_robin_walls": (rw, inputs.expcos_field()),
             "sphere96_ragged": (small, inputs.sinprod_field())}
 
 

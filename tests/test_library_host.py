@@ -60,7 +60,22 @@ CASES = {
     "ellipsoid32_neumann": lambda: _ell32(),
     "sphere_interior32": lambda: inputs.sphere_interior_problem(32, n_min=16)[0],
     "ellipsoid32_robin": lambda: _ell32(robin=True),
+    "ellipsoid32_robin_walls": lambda: _ell32_robin_walls(),
+    "torus16": lambda: inputs.torus_problem(16, n_min=16)[0],
 }
+
+
+def _ell32_robin_walls():
+    """Dirichlet ellipsoids, Robin conditions on three walls (FV-PLG rows with
+    Robin wall sites)."""
+    d = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
+    d.n_min = 16
+    for ob in d.obstacles:
+        ob.bc = inputs.DIRICHLET
+    R = inputs.ROBIN
+    d.wall_bc = (R, 0, R, 0, 0, R)
+    d.wall_robin = ((1.0, 0.5), (1.0, 0.0), (2.0, 0.05), (1.0, 0.0), (1.0, 0.0), (0.7, 0.7))
+    return d
 
 
 def _ell32(robin=False):
@@ -153,6 +168,17 @@ def test_errors_are_status_codes():
     bad.obstacles[0].robin = (0.0, 0.0)     # no condition at all
     with pytest.raises(L.CutCellError) as e:
         L.Problem(bad, device=-1)
+    assert e.value.code == L.CC_EINVAL
+    for ab in ((0.0, 0.0), (float("inf"), 1.0)):  # a Robin wall with no condition, or a non-finite one
+        badw = _ell32_robin_walls()
+        badw.wall_robin = (ab,) + tuple(badw.wall_robin[1:])
+        with pytest.raises(L.CutCellError) as e:
+            L.Problem(badw, device=-1)
+        assert e.value.code == L.CC_EINVAL and "Robin wall" in str(e.value)
+    wild = _ell32()
+    wild.wall_bc = (0, 1, 0, 0, 7, 0)
+    with pytest.raises(L.CutCellError) as e:
+        L.Problem(wild, device=-1)
     assert e.value.code == L.CC_EINVAL
     with L.Problem(dom, device=-1) as Q:          # the handle is released on leaving the block
         assert Q.num_levels >= 2

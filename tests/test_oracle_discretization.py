@@ -53,6 +53,31 @@ def test_ghost_formulas_exact_on_quartics(row):
         assert ok
 
 
+@pytest.mark.parametrize("alpha,beta,h", [(1.0, 0.5, 0.1), (0.3, 1.0, 0.05), (2.0, 0.01, 1 / 32), (1.0, 0.0, 0.1),
+                                          (0.0, 1.0, 0.1)])
+def test_robin_wall_ghosts_exact_on_quartics(alpha, beta, h):
+    """Robin wall alpha phi + beta dphi/dn = D (n out of the box): with the
+    wall at t = 0 and interior cells [j-1, j] in units of h, the ghost averages
+    over [-1, 0] and [-2, -1] of t^k (k <= 4) follow from the 4 interior
+    averages and D = alpha P(0) - (beta/h) P'(0) exactly."""
+    rule = D.robin_ghost_rule(alpha, beta, h)
+    for k in range(5):
+        cells = [_avg_monomial(k, j - 1, j) for j in (4, 3, 2, 1)]      # farthest first
+        datum = alpha * (0.0 ** k) - (beta / h) * float(k == 1)
+        for g in (1, 2):
+            coefs, dc = rule[g]
+            assert np.dot(coefs, cells) + dc * datum == pytest.approx(_avg_monomial(k, -g, 1 - g), abs=1e-11)
+
+
+def test_robin_wall_ghosts_reduce_to_dirichlet_and_neumann():
+    for h in (0.1, 1 / 64):
+        for robin, bc in (((1.0, 0.0), D.DIRICHLET), ((0.0, 1.0), D.NEUMANN)):
+            a, b = D.robin_ghost_rule(*robin, h), D.ghost_rule(bc, None, h)
+            for g in (1, 2):
+                assert np.max(np.abs(np.array(a[g][0]) - b[g][0])) < 1e-12
+                assert a[g][1] == pytest.approx(b[g][1], rel=1e-12)
+
+
 def test_regular_stencil_exact_to_degree_five():
     for k in range(7):
         cells = [_avg_monomial(k, a - 0.5, a + 0.5) for a in (-2, -1, 0, 1, 2)]
@@ -84,13 +109,22 @@ def torus16():
 
 
 @pytest.fixture(scope="module")
+def sphere16_robin_walls():
+    """The 16^3 sphere workload with Robin conditions on four walls."""
+    dom, _ = inputs.sphere_workload(16)
+    dom.wall_bc = (inputs.ROBIN, inputs.ROBIN, inputs.DIRICHLET, inputs.ROBIN, inputs.NEUMANN, inputs.ROBIN)
+    dom.wall_robin = ((1.0, 0.5), (0.3, 1.0), (1.0, 0.0), (2.0, 0.05), (1.0, 0.0), (0.7, 0.7))
+    return D.Level(dom, 16)
+
+
+@pytest.fixture(scope="module")
 def ellipsoid32_mixed():
     dom = inputs.ellipsoid_domain(n=32, seed=7, count=2, axes_range=(0.08, 0.14), h_coarse=1 / 16)
     dom.wall_bc = (0, 1, 0, 0, 1, 0)      # two Neumann walls
     return D.Level(dom, 32)
 
 
-@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed", "torus16"])
+@pytest.mark.parametrize("which", ["sphere16", "ellipsoid32_mixed", "torus16", "sphere16_robin_walls"])
 def test_every_row_exact_on_quartics(which, request):
     lv = request.getfixturevalue(which)
     P = _quartic()

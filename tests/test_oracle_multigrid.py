@@ -149,3 +149,52 @@ def test_polynomial_reproduction_robin():
     x, hist = H.solve(r, MGParams(tol=1e-13, max_iter=300))
     ex = lv.region_average(P)
     assert np.max(np.abs(x - ex)) < 1e-10 * np.max(np.abs(ex))
+
+
+def _sphere_robin_walls(n, robin, bcs):
+    dom, phi = inputs.sphere_workload(n)
+    dom.n_min = 8 if n == 16 else 16
+    dom.wall_bc = bcs
+    dom.wall_robin = robin
+    return dom, phi
+
+
+def test_robin_walls_reduce_to_dirichlet_and_neumann():
+    """Robin walls with (1, 0) give the Dirichlet walls' operator and
+    right-hand side, with (0, 1) the Neumann walls' (same data)."""
+    from oracle.discretize import Level
+    F = Field(inputs.expcos_field())
+    for robin, plain in (((1.0, 0.0), inputs.DIRICHLET), ((0.0, 1.0), inputs.NEUMANN)):
+        a = Level(_sphere_robin_walls(16, (robin,) * 6, (inputs.ROBIN,) * 6)[0], 16)
+        b = Level(_sphere_robin_walls(16, ((1.0, 0.0),) * 6, (plain,) * 6)[0], 16)
+        assert np.array_equal(a.unknowns, b.unknowns) and np.array_equal(a.phi2, b.phi2)
+        d = abs(a.L - b.L)
+        assert d.max() <= 1e-12 * abs(b.L).max()
+        ra, rb = a.rhs(F.laplacian_desc(), F), b.rhs(F.laplacian_desc(), F)
+        assert np.max(np.abs(ra - rb)) <= 1e-12 * np.max(np.abs(rb))
+
+
+def test_polynomial_reproduction_robin_walls():
+    """With Robin conditions on four walls every row is exact on quartics, so
+    the solve returns their exact cell averages; a smooth solution converges at
+    fourth order (16^3 -> 32^3).  (The sphere workload: the two-ellipsoid 32^3
+    domain above has a 16^3 coarse level on which its ellipsoids span 1-2
+    cells, and the plain iteration stalls there already with Neumann walls.)"""
+    mixed = (inputs.ROBIN, inputs.ROBIN, inputs.DIRICHLET, inputs.ROBIN, inputs.NEUMANN, inputs.ROBIN)
+    robin = ((1.0, 0.5), (0.3, 1.0), (1.0, 0.0), (2.0, 0.05), (1.0, 0.0), (0.7, 0.7))
+    H = Hierarchy(_sphere_robin_walls(16, robin, mixed)[0])
+    P = Field(inputs.poly_field([(4, 0, 0, 1.0), (0, 2, 2, -2.0), (1, 1, 1, 1.0), (0, 0, 0, 1.0),
+                                 (2, 0, 1, 0.4)]))
+    lv = H.fine
+    r = lv.rhs(P.laplacian_desc(), P)
+    x, hist = H.solve(r, MGParams(tol=1e-13, max_iter=300))
+    ex = lv.region_average(P)
+    assert np.max(np.abs(x - ex)) < 1e-10 * np.max(np.abs(ex))
+    errs = []
+    for n in (16, 32):
+        dom, phi = _sphere_robin_walls(n, robin, mixed)
+        Hn = Hierarchy(dom)
+        Fn = Field(phi)
+        xn, _ = Hn.solve(Hn.fine.rhs(Fn.laplacian_desc(), Fn), MGParams(tol=1e-12, max_iter=300))
+        errs.append(np.max(np.abs(xn - Hn.fine.region_average(Fn))))
+    assert errs[0] / errs[1] > 11.0, errs
