@@ -284,8 +284,27 @@ def _multi_leg(args):
 
     s_seq, i_seq = _timed(seq, 1, 1)
     s_con, i_con = _timed(conc, 1, 1)
+    # the plain multigrid iteration: one after the other, on host threads and
+    # streams, and in lockstep with one graph launch per iteration for all
     for P in probs:
+        P.set_krylov(0)
+
+    def graph():
+        for x in phis:
+            x.zero_()
+        torch.cuda.synchronize()
+        return _lib.solve_multi_graph(probs, rs, phis)
+    p_seq, pi_seq = _timed(seq, 1, 1)
+    p_con, pi_con = _timed(conc, 1, 1)
+    p_gr, pi_gr = _timed(graph, 1, 1)
+    for P in probs:
+        P.set_krylov(args.krylov)
         P.close()
+    plain = {"sequential_s": p_seq, "threads_streams_s": p_con, "one_graph_s": p_gr,
+             "all_converged": all(i["converged"] for i in pi_gr), "v_cycles": [i["iterations"] for i in pi_gr]}
+    print(f"[bench {time.perf_counter() - T_START:6.1f} s] {MULTI_COUNT} geometries, plain iteration: sequential "
+          f"{p_seq * 1e3:.0f} ms, threads {p_con * 1e3:.0f} ms, one graph {p_gr * 1e3:.0f} ms", file=sys.stderr,
+          flush=True)
     print(f"[bench {time.perf_counter() - T_START:6.1f} s] {MULTI_COUNT} geometries: sequential {s_seq * 1e3:.0f} ms, "
           f"concurrent {s_con * 1e3:.0f} ms (set-up {t_setup:.0f} s)", file=sys.stderr, flush=True)
     return {"problems": f"{MULTI_COUNT} ellipsoid geometries of sizes {', '.join(f'{m}^3' for m in MULTI_SIZES)} in turn "
@@ -293,7 +312,7 @@ def _multi_leg(args):
                         f"GMRES({args.krylov}) with the V-cycle",
             "unknowns": dofs, "setup_s": t_setup, "sequential_s": s_seq, "concurrent_s": s_con,
             "speedup": s_seq / s_con, "all_converged": all(i["converged"] for i in i_con),
-            "v_cycles": [i["iterations"] for i in i_con]}
+            "v_cycles": [i["iterations"] for i in i_con], "plain_iteration": plain}
 
 
 def _learned_leg(P, dom, phi, r_plain, coarse, args, stream):

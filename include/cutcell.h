@@ -225,6 +225,20 @@ int cc_solve(cc_problem* p, const double* r_dev, double* phi_dev, cc_solve_info*
 int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r_dev,
                    double* const* phi_dev, cc_solve_info* info);
 
+/* The same as cc_solve_multi for the plain multigrid iteration (Sec. 5.3;
+ * FP64 or CC_MIXED per problem, krylov 0), with all problems in lockstep on
+ * one stream: after each problem's prologue on its own stream, every iteration
+ * is one launch of a graph that holds each unconverged problem's captured outer
+ * step as an independent child graph, followed by one read-back of all their
+ * residual norms; the graph is rebuilt whenever a problem converges.  The
+ * problems live on one device and appear once each; they may share a stream.
+ * Launches on probs[0]'s stream.  info[i] (optional) as for cc_solve, with the
+ * whole call's time.  Errors: CC_EINVAL (empty list, null or host-only problem,
+ * two devices, a repeated problem, krylov > 0), CC_ENOCONV (some problem hit
+ * max_iter; all outputs filled), CC_EDEVICE. */
+int cc_solve_multi_graph(int nprob, cc_problem* const* probs, const double* const* r, double* const* phi,
+                         cc_solve_info* info);
+
 /* Switch the precision of later cc_solve / cc_solve_batched calls (CC_FP64 or
  * CC_MIXED); the build-time value is cc_params.precision. */
 int cc_set_precision(cc_problem* p, int precision);

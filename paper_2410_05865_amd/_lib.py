@@ -34,7 +34,7 @@ EXPORTED = [
     "cc_destroy", "cc_last_error", "cc_solve_batched", "cc_set_precision", "cc_set_krylov", "cc_solve_multi",
     "cc_set_lu_schedule", "cc_fmg", "cc_fmg_restrict", "cc_fmg_prolong", "cc_assemble_rhs_level",
     "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc", "cc_set_overlap", "cc_net_pairs",
-    "cc_assemble_rhs_batched", "cc_fit_patches",
+    "cc_assemble_rhs_batched", "cc_fit_patches", "cc_solve_multi_graph",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
     "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
 ]
@@ -129,6 +129,8 @@ def load() -> C.CDLL:
     lib.cc_fmg_restrict.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_fmg_prolong.argtypes = [vp, C.c_int, vp, vp]
     lib.cc_solve_multi.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
+    lib.cc_solve_multi_graph.argtypes = [C.c_int, P(vp), P(vp), P(vp), P(CcSolveInfo)]
+    lib.cc_fit_patches.argtypes = [vp, C.c_int, P(CcField), vp, vp, vp, vp, vp]
     lib.cc_net_create.argtypes = [C.c_int, C.c_int, C.c_ulonglong, vp, P(vp)]
     lib.cc_net_num_params.argtypes = [vp]
     lib.cc_net_num_params.restype = C.c_longlong
@@ -212,6 +214,23 @@ def solve_multi(problems, rs, phis) -> list:
     pp = (C.c_void_p * k)(*[_ptr(x, p.n() ** 3).value for p, x in zip(problems, phis)])
     infos = (CcSolveInfo * k)()
     rc = load().cc_solve_multi(k, hs, rp, pp, infos)
+    if rc not in (CC_OK, CC_ENOCONV):
+        _check(rc)
+    return [dict(Problem._info(infos[i], CC_OK), converged=infos[i].rel_residual < problems[i].params.tol)
+            for i in range(k)]
+
+
+def solve_multi_graph(problems, rs, phis) -> list:
+    """The plain multigrid iterations of several problems in lockstep, one
+    graph launch per iteration for all of them (cc_solve_multi_graph)."""
+    import torch
+    torch.cuda.current_stream().synchronize()
+    k = len(problems)
+    hs = (C.c_void_p * k)(*[p._h.value for p in problems])
+    rp = (C.c_void_p * k)(*[_ptr(r, p.n() ** 3).value for p, r in zip(problems, rs)])
+    pp = (C.c_void_p * k)(*[_ptr(x, p.n() ** 3).value for p, x in zip(problems, phis)])
+    infos = (CcSolveInfo * k)()
+    rc = load().cc_solve_multi_graph(k, hs, rp, pp, infos)
     if rc not in (CC_OK, CC_ENOCONV):
         _check(rc)
     return [dict(Problem._info(infos[i], CC_OK), converged=infos[i].rel_residual < problems[i].params.tol)

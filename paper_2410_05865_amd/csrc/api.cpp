@@ -926,15 +926,32 @@ struct SolveRec {
   std::vector<double> hist;
 };
 
-// The multigrid iteration of Sec. 5.3 on nb right-hand sides at once (r, phi:
-// nb * n^3, batch-major) until every relative residual is below tol or max_iter.
+// The prologue of the multigrid iteration (Sec. 5.3) on nb right-hand sides:
+// the right-hand side norms rn (a zero one sets its phi to 0), phi masked to
+// the unknowns, the residual and its norms sn; records started.  Returns
+// whether every member has converged already.
+bool update_rec(cc_problem* P, const std::vector<double>& rn, const std::vector<double>& sn, std::vector<SolveRec>& rec,
+                bool first) {
+  bool all = true;
+  for (size_t b = 0; b < rn.size(); ++b) {
+    double rel = rn[b] > 0 ? sn[b] / rn[b] : 0.0;
+    rec[b].rel = rel;
+    rec[b].hist.push_back(rel);
+    if (!first) ++rec[b].iterations;
+    if (!(rel < P->prm.tol)) all = false;
+    if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
+  }
+  return all;
+}
+
 template <class T>
-void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb, std::vector<SolveRec>& rec) {
+bool loop_prologue(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb, std::vector<double>& rn,
+                   std::vector<SolveRec>& rec) {
   DevLevel& D0 = P->dev[0];
   const long long n3 = cube(D0.st.n);
   launch_zero_u64(W.norm, nb, P->stream);
   launch_maxabs(r, n3, nb, W.norm, P->d_partial, P->stream);
-  std::vector<double> rn = read_norms(P, W.norm, nb);
+  rn = read_norms(P, W.norm, nb);
   for (int b = 0; b < nb; ++b) {
     if (!std::isfinite(rn[b])) fail(CC_EINVAL, "non-finite right-hand side");
     // L is nonsingular: r = 0 has the solution 0, whatever the guess (the relative
@@ -947,39 +964,42 @@ void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb,
   launch_maxabs(W.s0, n3, nb, W.norm, P->d_partial, P->stream);
   std::vector<double> sn = read_norms(P, W.norm, nb);
   rec.assign(nb, SolveRec{});
-  auto update = [&](bool first) {
-    bool all = true;
-    for (int b = 0; b < nb; ++b) {
-      double rel = rn[b] > 0 ? sn[b] / rn[b] : 0.0;
-      rec[b].rel = rel;
-      rec[b].hist.push_back(rel);
-      if (!first) ++rec[b].iterations;
-      if (!(rel < P->prm.tol)) all = false;
-      if (!std::isfinite(rel)) fail(CC_ENOCONV, "non-finite residual");
-    }
-    return all;
-  };
-  bool done = update(true);
+  return update_rec(P, rn, sn, rec, true);
+}
+
+// The captured outer step for (r, phi, nb), kept across solves with the same arrays.
+template <class T>
+void ensure_graph(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb) {
+  if (W.g_r == r && W.g_phi == phi && W.g_nb == nb && W.gexec) return;
+  W.drop_graph();
+  HIPCHK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+  outer_step<T>(P, W, r, phi, nb);
+  HIPCHK(hipStreamEndCapture(P->stream, &W.graph));
+  HIPCHK(hipGraphInstantiate(&W.gexec, W.graph, nullptr, nullptr, 0));
+  W.g_r = r;
+  W.g_phi = phi;
+  W.g_nb = nb;
+}
+
+// The multigrid iteration of Sec. 5.3 on nb right-hand sides at once (r, phi:
+// nb * n^3, batch-major) until every relative residual is below tol or max_iter.
+template <class T>
+void solve_loop(cc_problem* P, Work<T>& W, const double* r, double* phi, int nb, std::vector<SolveRec>& rec) {
+  DevLevel& D0 = P->dev[0];
+  const long long n3 = cube(D0.st.n);
+  std::vector<double> rn;
+  bool done = loop_prologue<T>(P, W, r, phi, nb, rn, rec);
   const bool use_graph = P->prm.use_graph != 0;
-  if (use_graph && !done && (W.g_r != r || W.g_phi != phi || W.g_nb != nb || !W.gexec)) {
-    W.drop_graph();
-    HIPCHK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
-    outer_step<T>(P, W, r, phi, nb);
-    HIPCHK(hipStreamEndCapture(P->stream, &W.graph));
-    HIPCHK(hipGraphInstantiate(&W.gexec, W.graph, nullptr, nullptr, 0));
-    W.g_r = r;
-    W.g_phi = phi;
-    W.g_nb = nb;
-  }
+  if (use_graph && !done) ensure_graph<T>(P, W, r, phi, nb);
   int it = 0;
   while (!done && it < P->prm.max_iter) {
     if (use_graph)
       HIPCHK(hipGraphLaunch(W.gexec, P->stream));
     else
       outer_step<T>(P, W, r, phi, nb);
-    sn = read_norms(P, W.norm, nb);
+    std::vector<double> sn = read_norms(P, W.norm, nb);
     ++it;
-    done = update(false);
+    done = update_rec(P, rn, sn, rec, false);
   }
   launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, phi, n3, nb, P->stream);
   HIPSYNC(P->stream);
@@ -2084,6 +2104,117 @@ int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r, 
       set_last_error("problem " + std::to_string(i) + ": " + msg[i]);
     }
   return worst;
+}
+
+namespace {
+
+// One problem of a lockstep multi-problem iteration.
+struct MultiSlot {
+  cc_problem* P = nullptr;
+  const double* r = nullptr;
+  double* phi = nullptr;
+  bool mixed = false;
+  std::vector<double> rn;
+  std::vector<SolveRec> rec;
+  bool done = false;
+  int it = 0;
+  hipGraph_t graph() const { return mixed ? P->w32.graph : P->w64.graph; }
+  unsigned long long* norm() const { return mixed ? P->w32.norm : P->w64.norm; }
+};
+
+struct ParentGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+  void drop() {
+    if (e) (void)hipGraphExecDestroy(e);
+    if (g) (void)hipGraphDestroy(g);
+    e = nullptr;
+    g = nullptr;
+  }
+  ~ParentGraph() { drop(); }
+};
+
+}  // namespace
+
+int cc_solve_multi_graph(int nprob, cc_problem* const* probs, const double* const* r, double* const* phi,
+                         cc_solve_info* info) {
+  int all_conv = 1;
+  int rc = guard([&] {
+    if (nprob < 1 || !probs || !r || !phi) fail(CC_EINVAL, "bad argument");
+    std::vector<MultiSlot> S(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      if (!probs[i] || !r[i] || !phi[i] || probs[i]->device < 0) fail(CC_EINVAL, "null or host-only problem in the list");
+      if (probs[i]->device != probs[0]->device) fail(CC_EINVAL, "every problem must live on one device");
+      if (probs[i]->prm.krylov > 0) fail(CC_EINVAL, "the lockstep iteration is the plain multigrid iteration (krylov 0)");
+      for (int j = 0; j < i; ++j)
+        if (probs[j] == probs[i]) fail(CC_EINVAL, "a problem appears twice in the list");
+      S[i].P = probs[i];
+      S[i].r = r[i];
+      S[i].phi = phi[i];
+      S[i].mixed = probs[i]->prm.precision == CC_MIXED;
+    }
+    HIPCHK(hipSetDevice(probs[0]->device));
+    const double t0 = now_s();
+    // each problem's prologue and captured outer step, on its own stream
+    for (MultiSlot& m : S) {
+      if (m.mixed) {
+        if (m.P->w32.nb < 1) alloc_work(m.P, m.P->w32, 1);
+        m.done = loop_prologue<float>(m.P, m.P->w32, m.r, m.phi, 1, m.rn, m.rec);
+        if (!m.done) ensure_graph<float>(m.P, m.P->w32, m.r, m.phi, 1);
+      } else {
+        m.done = loop_prologue<double>(m.P, m.P->w64, m.r, m.phi, 1, m.rn, m.rec);
+        if (!m.done) ensure_graph<double>(m.P, m.P->w64, m.r, m.phi, 1);
+      }
+      HIPSYNC(m.P->stream);
+    }
+    // every iteration: one launch of a graph holding the unconverged problems'
+    // outer steps as independent child graphs, then their residual norms
+    hipStream_t st = probs[0]->stream;
+    ParentGraph pg;
+    std::vector<int> act, prev;
+    std::vector<unsigned long long> bits(nprob);
+    while (true) {
+      act.clear();
+      for (int i = 0; i < nprob; ++i)
+        if (!S[i].done && S[i].it < S[i].P->prm.max_iter) act.push_back(i);
+      if (act.empty()) break;
+      if (act != prev) {
+        pg.drop();
+        HIPCHK(hipGraphCreate(&pg.g, 0));
+        for (int i : act) {
+          hipGraphNode_t nd;
+          HIPCHK(hipGraphAddChildGraphNode(&nd, pg.g, nullptr, 0, S[i].graph()));
+        }
+        HIPCHK(hipGraphInstantiate(&pg.e, pg.g, nullptr, nullptr, 0));
+        prev = act;
+      }
+      HIPCHK(hipGraphLaunch(pg.e, st));
+      for (int i : act)
+        HIPCHK(hipMemcpyAsync(&bits[i], S[i].norm(), sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      HIPSYNC(st);
+      for (int i : act) {
+        double v;
+        std::memcpy(&v, &bits[i], sizeof(double));
+        ++S[i].it;
+        S[i].done = update_rec(S[i].P, S[i].rn, std::vector<double>{v}, S[i].rec, false);
+      }
+    }
+    for (MultiSlot& m : S) {
+      DevLevel& D0 = m.P->dev[0];
+      launch_copy_pairs<double>(D0.n_absorbed, D0.absorbed, m.phi, cube(D0.st.n), 1, m.P->stream);
+      HIPSYNC(m.P->stream);
+    }
+    const double dt = now_s() - t0;
+    for (int i = 0; i < nprob; ++i) {
+      if (info) fill_info(S[i].rec[0], dt, info + i);
+      if (!(S[i].rec[0].rel < S[i].P->prm.tol)) all_conv = 0;
+    }
+  });
+  if (rc == CC_OK && !all_conv) {
+    set_last_error("max_iter reached before tol on at least one problem");
+    return CC_ENOCONV;
+  }
+  return rc;
 }
 
 int cc_set_overlap(cc_problem* p, int on) {

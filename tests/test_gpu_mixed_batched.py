@@ -240,6 +240,43 @@ def test_solve_multi_matches_single_solves():
         P.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_solve_multi_graph_matches_single_solves(mixed):
+    """The lockstep iteration (one graph launch per iteration for all
+    problems, rebuilt as problems converge) gives each problem's single-solve
+    iteration count and solution, FP64 and mixed."""
+    L = _lib()
+    doms = [inputs.sphere_domain(n=16, radius=0.25, n_min=8), WORK["sphere32"](), _ell32(),
+            inputs.sphere_domain(n=48, radius=0.2, n_min=12)]
+    probs, rs, singles = [], [], []
+    for i, d in enumerate(doms):
+        P = L.Problem(d, precision=L.CC_MIXED if mixed else L.CC_FP64)
+        n3 = d.n ** 3
+        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(inputs.gaussian_rhs(d, seed=70 + i), None, r)
+        x = torch.zeros_like(r)
+        singles.append((P.solve(r, x), x.clone()))
+        probs.append(P)
+        rs.append(r)
+    phis = [torch.zeros_like(r) for r in rs]
+    infos = L.solve_multi_graph(probs, rs, phis)
+    its = [i["iterations"] for i in infos]
+    assert len(set(its)) > 1            # the problems converge at different iterations
+    for (i1, x1), i2, x2 in zip(singles, infos, phis):
+        assert i2["converged"] and i2["iterations"] == i1["iterations"]
+        assert float((x2 - x1).abs().max() / x1.abs().max()) < 1e-11
+    # a second call reuses the captured steps
+    for x in phis:
+        x.zero_()
+    infos2 = L.solve_multi_graph(probs, rs, phis)
+    assert [i["iterations"] for i in infos2] == its
+    with pytest.raises(L.CutCellError) as e:
+        L.solve_multi_graph([probs[0], probs[0]], [rs[0], rs[0]], [phis[0], phis[0]])
+    assert e.value.code == L.CC_EINVAL
+    for P in probs:
+        P.close()
+
+
 def test_batched_rhs_assembly_matches_single_and_oracle():
     """cc_assemble_rhs_batched (one quadrature rule per cut cell for all fields)
     gives each field's right-hand side bit for bit as the one-field call, on
