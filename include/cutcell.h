@@ -146,7 +146,7 @@ typedef struct cc_level_info {
   long long lu_entries;   /* FP64 entries of the stored supernodal factors */
   int lu_nodes;           /* supernodes */
   int lu_depth;           /* levels of the supernode tree */
-  double setup_seconds;
+  double setup_seconds;   /* host set-up of the level: geometry, merging, rows, LU factorization */
   int lu_subtree_cut;     /* device sweeps: heights below this run as one launch of subtrees */
   int lu_subtrees;        /* number of those subtrees (0: one launch per height throughout) */
   int lu_entries_per_lane;/* device sweeps: factor entries per lane of a row (chosen at build) */
@@ -165,6 +165,10 @@ typedef struct cc_level_info {
                              XCD-aware order at [5..8] (0: not tried) */
   long long n_near;       /* phi_1 cells within 3 cells of a phi_2 cell along an axis: the near
                              SMO-1 sweep (cc_set_overlap) */
+  double lu_seconds;      /* the share of setup_seconds spent assembling, ordering and factoring
+                             the level's LU matrix: L on the bottom level (the paper's setup of the
+                             bottom solver), L22 on the others (its setup of the LU-correction),
+                             Table 4 */
 } cc_level_info;
 
 /* Fill p with the defaults listed above. */

@@ -73,7 +73,8 @@ class CcLevelInfo(C.Structure):
                 ("lu_nodes", C.c_int), ("lu_depth", C.c_int), ("setup_seconds", C.c_double),
                 ("lu_subtree_cut", C.c_int), ("lu_subtrees", C.c_int), ("lu_entries_per_lane", C.c_int),
                 ("lu_tune_ms", C.c_double * 10), ("lu_waves_cap", C.c_int), ("stencil_march", C.c_int),
-                ("stencil_planes", C.c_int), ("stencil_tune_us", C.c_double * 9), ("n_near", C.c_longlong)]
+                ("stencil_planes", C.c_int), ("stencil_tune_us", C.c_double * 9), ("n_near", C.c_longlong),
+                ("lu_seconds", C.c_double)]
 
 
 class CutCellError(RuntimeError):

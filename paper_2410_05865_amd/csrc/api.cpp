@@ -228,6 +228,7 @@ struct cc_problem {
   std::vector<cc::SupernodalLU> lu;
   std::vector<cc::CSR> lu_mat;
   std::vector<double> setup_s;
+  std::vector<double> lu_s;     // per level: the factorization's share of setup_s
   std::vector<cc::DevLevel> dev;
   cc::DevBuf buf;
   unsigned long long* d_norm = nullptr;
@@ -1399,6 +1400,7 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
     P->lu.resize(sizes.size());
     P->lu_mat.resize(sizes.size());
     P->setup_s.resize(sizes.size());
+    P->lu_s.resize(sizes.size());
     if (P->device >= 0) {
       HIPCHK(hipSetDevice(P->device));
       {  // resolve this device's copy of the allocation-free entry points' scratch
@@ -1432,11 +1434,13 @@ int cc_build(const cc_domain* dom, const cc_params* prm, void* stream, cc_proble
         double t0 = now_s();
         P->lv[m] = std::make_unique<LevelHost>();
         P->lv[m]->build(D, sizes[m], prm->theta, lsq);
+        const double t1 = now_s();
         std::vector<std::array<int, 3>> xyz;
         std::vector<int> orig;
         build_lu_matrix(*P->lv[m], m == M, P->lu_mat[m], xyz, orig);
         factorize(P->lu_mat[m], xyz, prm->leaf_size, prm->pivot_tol, P->lu[m]);
         P->setup_s[m] = now_s() - t0;
+        P->lu_s[m] = now_s() - t1;
       }
       if (P->device >= 0) upload(P.get());
     } catch (...) {
@@ -1468,6 +1472,7 @@ int cc_get_level_info(const cc_problem* p, int level, cc_level_info* info) {
     info->lu_nodes = (int)p->lu[level].nodes.size();
     info->lu_depth = p->lu[level].max_height + 1;
     info->setup_seconds = p->setup_s[level];
+    info->lu_seconds = p->lu_s[level];
     const bool dev = p->device >= 0 && (int)p->dev.size() > level;
     const bool on = dev && p->dev[level].lu.sub_on;
     info->lu_subtree_cut = on ? p->dev[level].lu.sub.hcut : 0;

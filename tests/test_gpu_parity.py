@@ -47,13 +47,15 @@ def _workloads():
 WORK = _workloads()
 
 # Sensitivity of the V-cycle and of the solution to the FV-PLG coefficients,
-# which the two sides compute by different least-squares methods (QR, SVD)
-# and which agree to ~1e-13..1e-12 relative: on the oracle, perturbing them by
+# which the two sides compute by different least-squares methods (QR on the
+# device, SVD in the oracle) and which agree to 1e-12 relative (the device fits
+# against the host fits, asserted above): on the oracle, perturbing them by
 # 1e-12 relative moves one V-cycle by 9.7e-11 and the direct solution by
 # 1.7e-11 on the Robin-wall workload (cond L22 = 756), against 1.1e-11 and
 # 3.1e-12 on the Robin-obstacle workload (cond L22 = 64).  The tolerances of the
-# V-cycle and solution comparisons scale with it.
-SENS = {"ellipsoid32_robin_walls": 10.0}
+# V-cycle and of the solution comparisons scale with it.
+SENS_VCYCLE = {"ellipsoid32_robin_walls": 100.0}
+SENS_SOLUTION = {"ellipsoid32_robin_walls": 10.0}
 
 
 @pytest.fixture(scope="module", params=sorted(WORK))
@@ -195,7 +197,7 @@ def test_one_vcycle(pair):
     e = _dev(np.zeros(lv.n ** 3))
     P.vcycle(0, _dev(lv.to_grid(s)), e)
     ref = H.vcycle(0, s, MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
-    assert _rel(_host(e)[lv.unknowns], ref) < 1e-12 * SENS.get(name, 1.0)
+    assert _rel(_host(e)[lv.unknowns], ref) < 1e-12 * SENS_VCYCLE.get(name, 1.0)
 
 
 def test_overlap_matches_whole_sweeps(pair):
@@ -215,7 +217,7 @@ def test_overlap_matches_whole_sweeps(pair):
     P.set_overlap(0)
     assert _rel(out[1], out[0]) < 1e-13
     ref = H.vcycle(0, _host(s)[lv.unknowns], MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
-    assert _rel(out[1], ref) < 1e-12 * SENS.get(name, 1.0)
+    assert _rel(out[1], ref) < 1e-12 * SENS_VCYCLE.get(name, 1.0)
     r_or, x_or, hist = _oracle_solution(name, H, F)
     sols = {}
     for on in (0, 1):
@@ -226,7 +228,7 @@ def test_overlap_matches_whole_sweeps(pair):
         sols[on] = _host(phi)[lv.unknowns]
     P.set_overlap(0)
     assert _rel(sols[1], sols[0]) < 1e-12
-    assert _rel(sols[1], x_or) < 1e-11 * SENS.get(name, 1.0)
+    assert _rel(sols[1], x_or) < 1e-11 * SENS_SOLUTION.get(name, 1.0)
 
 
 # regular-row kernel schedules: (march, planes per workgroup); march 0 is one
@@ -279,12 +281,12 @@ def test_stencil_schedules_match_oracle(pair, sched):
         e = _dev(np.zeros(lv.n ** 3))
         P.vcycle(0, _dev(lv.to_grid(s)), e)
         ref = H.vcycle(0, s, MGParams(omega=P.params.omega, nu1=P.params.nu1, nu2=P.params.nu2))
-        assert _rel(_host(e)[lv.unknowns], ref) < 1e-12 * SENS.get(name, 1.0)
+        assert _rel(_host(e)[lv.unknowns], ref) < 1e-12 * SENS_VCYCLE.get(name, 1.0)
         r_or, x_or, hist = _oracle_solution(name, H, F)
         phi = _dev(np.zeros(lv.n ** 3))
         info = P.solve(_dev(lv.to_grid(r_or)), phi)
         assert info["converged"] and info["iterations"] == len(hist) - 1
-        assert _rel(_host(phi)[lv.unknowns], x_or) < 1e-11 * SENS.get(name, 1.0)
+        assert _rel(_host(phi)[lv.unknowns], x_or) < 1e-11 * SENS_SOLUTION.get(name, 1.0)
     finally:
         P.set_stencil_schedule(-1, -1, 0)
 
@@ -306,7 +308,7 @@ def test_converged_solve_matches_oracle(pair, graph):
     assert info["converged"] and info["rel_residual"] < 1e-10
     assert info["iterations"] == len(hist) - 1
     got = _host(phi)
-    assert _rel(got[lv.unknowns], x_or) < 1e-11 * SENS.get(name, 1.0)
+    assert _rel(got[lv.unknowns], x_or) < 1e-11 * SENS_SOLUTION.get(name, 1.0)
     for a, b in zip(info["history"], hist):
         assert a == pytest.approx(b, rel=1e-5, abs=1e-14)
     # the GPU solution satisfies the oracle's discrete system
@@ -334,7 +336,7 @@ def test_tight_solve_matches_direct_solve(pair):
         xd = spla.splu(lv.L.tocsc()).solve(r_or)
     else:   # a 3D sparse LU of this size is out of reach on the CPU: oracle multigrid
         xd, _ = H.solve(r_or, MGParams(tol=1e-13))
-    assert _rel(_host(phi)[lv.unknowns], xd) < 1e-11 * SENS.get(name, 1.0)
+    assert _rel(_host(phi)[lv.unknowns], xd) < 1e-11 * SENS_SOLUTION.get(name, 1.0)
     # fourth-order accurate against the exact cell averages (discretisation error)
     err = np.max(np.abs(_host(phi)[lv.unknowns] - lv.region_average(F)))
     assert err < 1e-3
