@@ -61,7 +61,6 @@ CASES = {
     "sphere_interior32": lambda: inputs.sphere_interior_problem(32, n_min=16)[0],
     "ellipsoid32_robin": lambda: _ell32(robin=True),
     "ellipsoid32_robin_walls": lambda: _ell32_robin_walls(),
-    "torus16": lambda: inputs.torus_problem(16, n_min=16)[0],
 }
 
 
