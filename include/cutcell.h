@@ -160,9 +160,10 @@ typedef struct cc_level_info {
                              1 z-marching, 2 z-marching in the XCD-aware tile order (chosen at build
                              by timing, or cc_set_stencil_schedule) */
   int stencil_planes;     /* z-planes per workgroup of the marching kernels */
-  double stencil_tune_us[9]; /* the build-time trials: us per FP64 SMO-1 sweep, one cell per thread
-                             at [0], marching with 4, 8, 16, 32 planes at [1..4], the same in the
-                             XCD-aware order at [5..8] (0: not tried) */
+  double stencil_tune_us[9]; /* the build-time trials: us per FP64 SMO-1 sweep (the best of 3
+                             interleaved rounds of 5 sweeps), one cell per thread at [0], marching
+                             with 4, 8, 16, 32 planes at [1..4], the same in the XCD-aware order
+                             at [5..8] (0: not tried); the smallest decides */
   long long n_near;       /* phi_1 cells within 3 cells of a phi_2 cell along an axis: the near
                              SMO-1 sweep (cc_set_overlap) */
   double lu_seconds;      /* the share of setup_seconds spent assembling, ordering and factoring

@@ -32,10 +32,13 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_lookup_checks_size_and_source(monkeypatch, tmp_path):
     f = tmp_path / "traffic.md"
     f.write_text("- grid: `256^3`\n- kernels.hip sha256[:16]: `0123456789abcdef`\n"
-                 "- SMO-1 bytes per launch (calibrated): `5.0e+08`\n")
+                 "- k_smo1_z<double>: FETCH_SIZE 1 KiB, WRITE_SIZE 1 KiB per dispatch (6 dispatches, grid 1048576 "
+                 "work-items)\n- SMO-1 bytes per launch (calibrated): `5.0e+08`\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     monkeypatch.setattr(bench, "_src_hash", lambda: "0123456789abcdef")
     assert bench._traffic(256) == pytest.approx(5.0e8)
+    assert bench._traffic(256, 1048576) == pytest.approx(5.0e8)   # the hook's schedule (16 planes)
+    assert bench._traffic(256, 2097152) is None                    # another schedule (8 planes)
     assert bench._traffic(128) is None                     # another grid
     monkeypatch.setattr(bench, "_src_hash", lambda: "fedcba9876543210")
     assert bench._traffic(256) is None                     # the kernels changed since
