@@ -231,16 +231,16 @@ int cc_solve_multi(int nprob, cc_problem* const* probs, const double* const* r_d
                    double* const* phi_dev, cc_solve_info* info);
 
 /* The same as cc_solve_multi for the plain multigrid iteration (Sec. 5.3;
- * FP64 or CC_MIXED per problem, krylov 0), with all problems in lockstep on
- * one stream: after each problem's prologue on its own stream, every iteration
- * is one launch of a graph that holds each unconverged problem's captured outer
- * step as an independent child graph, followed by one read-back of all their
- * residual norms; the graph is rebuilt whenever a problem converges.  The
- * problems live on one device and appear once each; they may share a stream.
- * Launches on probs[0]'s stream.  info[i] (optional) as for cc_solve, with the
- * whole call's time.  Errors: CC_EINVAL (empty list, null or host-only problem,
- * two devices, a repeated problem, krylov > 0), CC_ENOCONV (some problem hit
- * max_iter; all outputs filled), CC_EDEVICE. */
+ * FP64 or CC_MIXED per problem, krylov 0), from the calling thread alone: after
+ * each problem's prologue, every iteration launches each unconverged problem's
+ * captured outer step (a hipGraph kept by the problem) on the problem's own
+ * stream, then reads back all their residual norms; problems on different
+ * streams overlap on the device, problems sharing a stream run one after the
+ * other.  The problems live on one device and appear once each.  info[i]
+ * (optional) as for cc_solve, with the whole call's time.  Errors: CC_EINVAL
+ * (empty list, null or host-only problem, two devices, a repeated problem,
+ * krylov > 0), CC_ENOCONV (some problem hit max_iter; all outputs filled),
+ * CC_EDEVICE. */
 int cc_solve_multi_graph(int nprob, cc_problem* const* probs, const double* const* r, double* const* phi,
                          cc_solve_info* info);
 

@@ -222,8 +222,9 @@ def solve_multi(problems, rs, phis) -> list:
 
 
 def solve_multi_graph(problems, rs, phis) -> list:
-    """The plain multigrid iterations of several problems in lockstep, one
-    graph launch per iteration for all of them (cc_solve_multi_graph)."""
+    """The plain multigrid iterations of several problems in lockstep from the
+    calling thread: per iteration each problem's captured step on its own
+    stream (cc_solve_multi_graph)."""
     import torch
     torch.cuda.current_stream().synchronize()
     k = len(problems)

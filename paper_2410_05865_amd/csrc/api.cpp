@@ -2135,21 +2135,11 @@ struct MultiSlot {
   std::vector<SolveRec> rec;
   bool done = false;
   int it = 0;
-  hipGraph_t graph() const { return mixed ? P->w32.graph : P->w64.graph; }
+  hipGraphExec_t gexec() const { return mixed ? P->w32.gexec : P->w64.gexec; }
   unsigned long long* norm() const { return mixed ? P->w32.norm : P->w64.norm; }
 };
 
-struct ParentGraph {
-  hipGraph_t g = nullptr;
-  hipGraphExec_t e = nullptr;
-  void drop() {
-    if (e) (void)hipGraphExecDestroy(e);
-    if (g) (void)hipGraphDestroy(g);
-    e = nullptr;
-    g = nullptr;
-  }
-  ~ParentGraph() { drop(); }
-};
+
 
 }  // namespace
 
@@ -2184,31 +2174,21 @@ int cc_solve_multi_graph(int nprob, cc_problem* const* probs, const double* cons
       }
       HIPSYNC(m.P->stream);
     }
-    // every iteration: one launch of a graph holding the unconverged problems'
-    // outer steps as independent child graphs, then their residual norms
-    hipStream_t st = probs[0]->stream;
-    ParentGraph pg;
-    std::vector<int> act, prev;
+    // every iteration: each unconverged problem's captured outer step launched
+    // on its own stream from this one host thread (the problems' kernels
+    // overlap on the device), then all their residual norms read back
+    std::vector<int> act;
     std::vector<unsigned long long> bits(nprob);
     while (true) {
       act.clear();
       for (int i = 0; i < nprob; ++i)
         if (!S[i].done && S[i].it < S[i].P->prm.max_iter) act.push_back(i);
       if (act.empty()) break;
-      if (act != prev) {
-        pg.drop();
-        HIPCHK(hipGraphCreate(&pg.g, 0));
-        for (int i : act) {
-          hipGraphNode_t nd;
-          HIPCHK(hipGraphAddChildGraphNode(&nd, pg.g, nullptr, 0, S[i].graph()));
-        }
-        HIPCHK(hipGraphInstantiate(&pg.e, pg.g, nullptr, nullptr, 0));
-        prev = act;
-      }
-      HIPCHK(hipGraphLaunch(pg.e, st));
+      for (int i : act) HIPCHK(hipGraphLaunch(S[i].gexec(), S[i].P->stream));
       for (int i : act)
-        HIPCHK(hipMemcpyAsync(&bits[i], S[i].norm(), sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-      HIPSYNC(st);
+        HIPCHK(hipMemcpyAsync(&bits[i], S[i].norm(), sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              S[i].P->stream));
+      for (int i : act) HIPSYNC(S[i].P->stream);
       for (int i : act) {
         double v;
         std::memcpy(&v, &bits[i], sizeof(double));

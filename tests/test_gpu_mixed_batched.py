@@ -242,8 +242,8 @@ def test_solve_multi_matches_single_solves():
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_solve_multi_graph_matches_single_solves(mixed):
-    """The lockstep iteration (one graph launch per iteration for all
-    problems, rebuilt as problems converge) gives each problem's single-solve
+    """The lockstep iteration from one host thread (each problem's captured
+    step on its own stream, per iteration) gives each problem's single-solve
     iteration count and solution, FP64 and mixed."""
     L = _lib()
     doms = [inputs.sphere_domain(n=16, radius=0.25, n_min=8), WORK["sphere32"](), _ell32(),
