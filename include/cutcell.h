@@ -484,6 +484,18 @@ int cc_net_pairs(cc_problem* p, int level, int nrhs, const double* r_dev, const 
 int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r_dev,
                      double* phi_dev);
 
+/* The network's output fed in at the coarse level, as the iterate the full
+ * multigrid ascent (Sec. 5, algorithm FMG) starts from: the features of r on
+ * `level` (as for cc_learned_guess), the network's prediction scaled by
+ * max|r| / phi_scale there (0 on cells without an unknown), `cycles` V-cycles on
+ * that level, then for each finer level the FMG interpolation and `cycles`
+ * V-cycles, as cc_fmg does above its coarsest level.  coarse_rhs as for cc_fmg
+ * (NULL: restrictions of r).  level in [1, levels - 1), cycles in [1, 16].
+ * Device arrays; phi (n^3) receives the level-0 iterate.  Errors: CC_EINVAL,
+ * CC_EDEVICE. */
+int cc_learned_fmg(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r_dev,
+                   const double* const* coarse_rhs, double* phi_dev, int cycles);
+
 #ifdef __cplusplus
 }
 #endif

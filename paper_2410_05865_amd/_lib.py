@@ -36,7 +36,7 @@ EXPORTED = [
     "cc_fmg_batched", "cc_set_stencil_schedule", "cc_get_stencil_schedule", "cc_fmg_noalloc", "cc_set_overlap", "cc_net_pairs",
     "cc_assemble_rhs_batched", "cc_fit_patches", "cc_solve_multi_graph",
     "cc_net_create", "cc_net_num_params", "cc_net_get_params", "cc_net_set_params", "cc_net_forward",
-    "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess",
+    "cc_net_loss_grad", "cc_net_adam_step", "cc_net_destroy", "cc_learned_guess", "cc_learned_fmg",
 ]
 
 
@@ -141,6 +141,7 @@ def load() -> C.CDLL:
     lib.cc_net_loss_grad.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, P(C.c_double), vp]
     lib.cc_net_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.cc_learned_guess.argtypes = [vp, vp, C.c_int, C.c_double, vp, vp]
+    lib.cc_learned_fmg.argtypes = [vp, vp, C.c_int, C.c_double, vp, P(vp), vp, C.c_int]
     lib.cc_net_pairs.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_double, vp, vp, vp]
     lib.cc_net_destroy.argtypes = [vp]
     lib.cc_net_destroy.restype = None
@@ -570,6 +571,18 @@ class Problem:
         self._order()
         n3 = self.n() ** 3
         _check(load().cc_learned_guess(self._h, net._h, level, phi_scale, _ptr(r, n3), _ptr(phi, n3)))
+
+    def learned_fmg(self, net: "Net", level: int, phi_scale: float, r, phi, cycles: int = 2, coarse_rhs=None):
+        """phi <- the full multigrid ascent from the network's prediction on
+        `level` (see cc_learned_fmg); coarse_rhs as for fmg()."""
+        self._order()
+        n3 = self.n() ** 3
+        arr = None
+        if coarse_rhs is not None:
+            if len(coarse_rhs) != self.num_levels - 1:
+                raise ValueError("one right-hand side per coarser level expected")
+            arr = (C.c_void_p * len(coarse_rhs))(*[_ptr(t, self.n(m + 1) ** 3) for m, t in enumerate(coarse_rhs)])
+        _check(load().cc_learned_fmg(self._h, net._h, level, phi_scale, _ptr(r, n3), arr, _ptr(phi, n3), cycles))
 
     def time_kernel(self, which: int, reps: int = 20):
         """(ms per launch, algorithmic bytes per launch) of a timing hook."""

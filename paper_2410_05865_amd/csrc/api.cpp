@@ -857,10 +857,14 @@ void residual(cc_problem* P, int m, const double* r, const double* x, double* s,
 // group start coarse_off arrays into coarse_rhs[m - 1].
 // crhs[m], cx[m] (m = 1..M, nb * n_m^3 doubles each): the coarse levels'
 // right-hand side (used only without coarse_rhs) and solution arrays; every
-// cell of each is written before it is read.
+// cell of each is written before it is read.  With start in [1, M), the
+// ascent begins at level `start` from the iterate cx[start] holds (improved
+// by `cycles` V-cycles there) instead of the coarsest level's LU solution.
 void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* const* coarse_rhs, long long coarse_off,
-         double* phi, int cycles, int nb, const std::vector<double*>& crhs, const std::vector<double*>& cx) {
+         double* phi, int cycles, int nb, const std::vector<double*>& crhs, const std::vector<double*>& cx,
+         int start = -1) {
   const int M = (int)P->dev.size() - 1;
+  const int s0 = (start >= 1 && start < M) ? start : M;
   std::vector<const double*> rhs(M + 1);
   std::vector<double*> x(M + 1);
   rhs[0] = r;
@@ -870,10 +874,18 @@ void fmg(cc_problem* P, const Work<double>& W, const double* r, const double* co
     x[m] = cx[m];
   }
   if (!coarse_rhs)
-    for (int m = 0; m < M; ++m)
+    for (int m = 0; m < s0; ++m)
       launch_fmg_restrict(P->dev[m].st, P->dev[m + 1].st, rhs[m], crhs[m + 1], nb, P->stream);
-  bottom<double>(P, W, rhs[M], x[M], nb);
-  for (int m = M - 1; m >= 0; --m) {
+  if (s0 == M) {
+    bottom<double>(P, W, rhs[M], x[M], nb);
+  } else {
+    for (int c = 0; c < cycles; ++c) {
+      residual(P, s0, rhs[s0], x[s0], W.s[s0], nb);
+      vcycle<double>(P, W, s0, W.s[s0], W.e[s0], W.et[s0], nb);
+      launch_add_unknowns<double>(P->dev[s0].st, W.e[s0], nullptr, x[s0], nb, P->stream);
+    }
+  }
+  for (int m = s0 - 1; m >= 0; --m) {
     DevLevel& D = P->dev[m];
     launch_fmg_prolong(D.st, P->dev[m + 1].st, x[m + 1], x[m], nb, P->stream);
     for (int c = 0; c < cycles; ++c) {
@@ -2075,6 +2087,45 @@ int cc_learned_guess(cc_problem* p, cc_net* net, int level, double phi_scale, co
     int rc = cc_net_forward(net, m, 1, p->net_x, p->net_y);
     if (rc != CC_OK) fail(rc, cc_last_error());
     launch_prolong_trilinear(p->dev[0].st, m, p->net_y, rn / phi_scale, phi, p->stream);
+    HIPSYNC(p->stream);
+  });
+}
+
+int cc_learned_fmg(cc_problem* p, cc_net* net, int level, double phi_scale, const double* r,
+                   const double* const* coarse_rhs, double* phi, int cycles) {
+  return guard([&] {
+    if (!p || !net || !r || !phi) fail(CC_EINVAL, "null argument");
+    need_device(p);
+    check_level(p, level);
+    const int M = (int)p->lv.size() - 1;
+    if (level < 1 || level >= M) fail(CC_EINVAL, "level must lie in [1, levels - 1)");
+    if (!(phi_scale > 0)) fail(CC_EINVAL, "phi_scale must be positive");
+    if (cycles < 1 || cycles > 16) fail(CC_EINVAL, "cycles must lie in [1, 16]");
+    if (coarse_rhs)
+      for (int m = 1; m <= M; ++m)
+        if (!coarse_rhs[m - 1]) fail(CC_EINVAL, "null coarse right-hand side");
+    const LevelHost& Lm = *p->lv[level];
+    const int m = Lm.n, n0 = p->lv[0]->n;
+    const long long m3 = cube(m);
+    level_volfrac(p, level);
+    if (p->net_cells < m3) {
+      p->net_x = p->buf.alloc<float>(2 * m3);
+      p->net_y = p->buf.alloc<float>(m3);
+      p->net_cells = m3;
+    }
+    if (p->w64.nb < 1) alloc_work(p, p->w64, 1);
+    fmg_alloc(p, 1);
+    launch_zero_u64(p->d_norm, 1, p->stream);
+    launch_maxabs(r, cube(n0), 1, p->d_norm, p->d_partial, p->stream);
+    const double rn = read_norm(p);
+    if (!std::isfinite(rn)) fail(CC_EINVAL, "non-finite right-hand side");
+    const double inv = rn > 0 ? 1.0 / rn : 0.0;
+    launch_net_features(n0, m, r, inv, p->volfrac[level], p->net_x, p->stream);
+    HIPSYNC(p->stream);
+    int rc = cc_net_forward(net, m, 1, p->net_x, p->net_y);
+    if (rc != CC_OK) fail(rc, cc_last_error());
+    launch_net_to_level(p->dev[level].st, p->net_y, rn / phi_scale, p->fmg_x[level], p->stream);
+    fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1, p->fmg_rhs, p->fmg_x, level);
     HIPSYNC(p->stream);
   });
 }

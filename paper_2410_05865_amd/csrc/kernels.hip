@@ -1258,6 +1258,15 @@ __global__ void k_prolong_trilinear(StencilLevel L0, int m, const float* __restr
   phi[c] = scale * v;
 }
 
+// x = scale y on the cells of level Lm that carry an unknown, 0 elsewhere (a
+// network output on that level's grid as the level's iterate)
+__global__ void k_net_to_level(StencilLevel Lm, const float* __restrict__ y, double scale, double* __restrict__ x) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long m3 = (long long)Lm.n * Lm.n * Lm.n;
+  if (c >= m3) return;
+  x[c] = Lm.type[c] != 0 ? scale * (double)y[c] : 0.0;
+}
+
 // per-block partial sums of (w, V_i), i < NV, and (w, w) into
 // partial[block * (NV + 1) + i]: w is read once for all the vectors
 template <int NV>
@@ -1643,6 +1652,9 @@ void launch_net_features(int n0, int m, const double* r, double inv_norm, const 
 void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_prolong_trilinear, dim3(blocks(cube(L0.n), 256)), dim3(256), 0, st, L0, m, y, scale, phi);
+}
+void launch_net_to_level(const StencilLevel& Lm, const float* y, double scale, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_to_level, dim3(blocks(cube(Lm.n), 256)), dim3(256), 0, st, Lm, y, scale, x);
 }
 void launch_combo(long long n3, const double* V, long long stride, int nv, const double* coef, double* out, int mode,
                   unsigned long long* amax, double* sumsq, double* partial, hipStream_t st) {

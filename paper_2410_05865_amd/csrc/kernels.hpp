@@ -223,6 +223,8 @@ void launch_net_pairs(int n0, int m, int nb, const double* r, const double* phi,
                       uint8_t* mask, hipStream_t st);
 void launch_prolong_trilinear(const StencilLevel& L0, int m, const float* y, double scale, double* phi,
                               hipStream_t st);
+// x = scale y on the unknown cells of level Lm (n_m^3 cells), 0 elsewhere
+void launch_net_to_level(const StencilLevel& Lm, const float* y, double scale, double* x, hipStream_t st);
 
 // FV-PLG weighted least-squares fits on the device (setup): nsys systems, system
 // s the rows off[s] .. off[s+1] of A (35 doubles each, weighted); y receives the

@@ -9,8 +9,10 @@ works on (m cells per axis):
   target    t[V] = PHI_SCALE * (mean of phi over the unknown cells of V) / max|r|
   mask      V holds at least one unknown cell.
 The network (cc_net_*, the library's BF16-MFMA kernels) is trained with Adam
-on the masked mean-square loss; at solve time `Problem.learned_guess` builds
-the same features on the device and interpolates the output to the fine grid.
+on the masked mean-square loss; at solve time `Problem.learned_fmg` builds the
+same features on the device and starts the full multigrid ascent from the
+network's output on that level (`Problem.learned_guess` instead interpolates
+the output to the fine grid).
 PyTorch only holds the device arrays and picks the mini-batches.
 """
 from __future__ import annotations

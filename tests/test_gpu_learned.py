@@ -138,3 +138,46 @@ def test_learned_guess_in_solve():
     log(f"[learned] V-cycles saved per solve: {gains}")
     assert np.mean(gains) > 0
     net.close()
+
+
+def test_learned_fmg_start_saves_vcycles():
+    """The network's output fed in at a coarse level (cc_learned_fmg): trained
+    on pairs at the 64^3 level of 128^3 problems, its prediction there is the
+    iterate the full multigrid ascent starts from (2 V-cycles per level).  On
+    held-out problems the solve from that iterate takes fewer V-cycles than
+    from the zero guess, every time; FMG(2) from the exact coarsest solve is
+    reported beside it."""
+    L = _lib()
+    from paper_2410_05865_amd import inputs, learned
+    log = lambda s: print(s, flush=True)
+    net, info = learned.fit(n_fine=128, level=1, geometries=3, rhs_per_geometry=32, steps=600, batch=4, seed=5,
+                            log=log)
+    log(f"[learned-fmg] {info}")
+    rows = []
+    for s in range(3):
+        dom = inputs.ellipsoid_domain(n=128, seed=888 + s)
+        P = L.Problem(dom)
+        f = inputs.gaussian_rhs(dom, seed=5151 + s)
+        r = torch.zeros(128 ** 3, dtype=torch.float64, device="cuda")
+        P.assemble_rhs(f, None, r)
+        coarse = []
+        for m in range(1, P.num_levels):
+            rm = torch.zeros(P.n(m) ** 3, dtype=torch.float64, device="cuda")
+            P.assemble_rhs(f, None, rm, level=m)
+            coarse.append(rm)
+        x0 = torch.zeros_like(r)
+        i0 = P.solve(r, x0)
+        x1 = torch.zeros_like(r)
+        P.learned_fmg(net, 1, learned.PHI_SCALE, r, x1, cycles=2, coarse_rhs=coarse)
+        i1 = P.solve(r, x1)
+        x2 = torch.zeros_like(r)
+        P.fmg(r, x2, 2, coarse_rhs=coarse)
+        i2 = P.solve(r, x2)
+        assert i0["converged"] and i1["converged"] and i2["converged"]
+        assert float((x1 - x0).abs().max() / x0.abs().max()) < 1e-8
+        rows.append((i0["iterations"], i1["iterations"], i2["iterations"]))
+        log(f"[learned-fmg] held-out {s}: V-cycles zero guess {i0['iterations']}, learned FMG start "
+            f"{i1['iterations']}, FMG(2) {i2['iterations']}")
+        P.close()
+    assert all(a > b for a, b, _ in rows), rows
+    net.close()
