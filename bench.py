@@ -684,6 +684,10 @@ def main():
              "subtrees": li["lu_subtrees"], "subtree_cut": li["lu_subtree_cut"], "waves_cap": li["lu_waves_cap"],
              "trial_ms": [round(v, 4) for v in li["lu_tune_ms"]]}
             for m, li in ((m, P.level_info(m)) for m in range(P.num_levels))],
+        "stencil_schedule": [
+            {"level": m, "n": li["n"], "march": li["stencil_march"], "planes": li["stencil_planes"],
+             "trial_us": [round(v, 1) for v in li["stencil_tune_us"]]}
+            for m, li in ((m, P.level_info(m)) for m in range(P.num_levels))],
         "mixed": out_mixed,
         "krylov": out_krylov,
         "fmg": out_fmg,
