@@ -226,14 +226,20 @@ __global__ void k_smo1_list(StencilLevel L, T omega, const T* __restrict__ s, co
 }
 
 // The regular-row kernels marching in z: a workgroup takes a 64 x 4 cell tile
-// of (x, y) columns through kz consecutive planes.  Each thread keeps its
-// column's operand at planes k-3 .. k+3 in registers (one new plane loaded per
-// step); each wavefront (one x row) shares its row of the current plane, with 3
-// halo cells on either side, through LDS for the x-neighbours; the
-// y-neighbours (+-1, +-2; +-3 only in the wall rows), the cell type and the
-// right-hand side of plane k+1 are loaded while plane k is computed.  All loads
+// of (x, y) columns through kz consecutive planes, one wavefront per x row.
+// Each thread keeps its column's operand at planes k-3 .. k+3 in registers
+// (one new plane loaded per step).  The workgroup shares the current plane of
+// its tile and of the 2 rows on either side (8 rows; the tile rows with their
+// 3 x-halo cells) through LDS for the x- and y-neighbours, double-buffered by
+// plane parity: one workgroup barrier per plane orders the writes of a plane
+// before its reads, and the reads of a plane before the writes two planes
+// later.  Per plane each thread loads its column's value 3 planes ahead, the
+// cell type and the right-hand side, and one value of the 4 y-halo rows (row
+// j0 - 2 + w for wavefront w < 2, j0 + 2 + w for w >= 2); lanes 0 .. 5 also
+// load the x-halo; the y-neighbours at +-3 (wall rows only) come from memory.
+// The loads of plane k+1 are in flight while plane k is computed.  All loads
 // are unconditional at clamped addresses (a clamped value is never used: every
-// stencil reference of a cell in the grid stays in the grid).  About 8 vector
+// stencil reference of a cell in the grid stays in the grid).  About 4 vector
 // memory instructions per cell against 15 for the one-cell-per-thread kernels,
 // in the same arithmetic order (identical results).
 //   kMarchSmo:      eout = e + omega (b - A e) / D on phi_1 cells, e elsewhere
@@ -244,9 +250,9 @@ constexpr int kHalo = 3;
 enum { kMarchSmo = 0, kMarchResidual = 1, kMarchApply = 2, kMarchSmoFar = 3 };
 template <class T>
 struct MarchPlane {
-  T y[4];      // operand at y offsets -2, -1, +1, +2
+  T yh;        // this thread's y-halo row value
   T b;         // right-hand side
-  T h;         // halo cell (lanes 0 .. 5)
+  T h;         // x-halo cell (lanes 0 .. 5)
   int type;
 };
 // Workgroups go to the 8 XCDs round-robin (workgroup w to XCD w mod 8).  The
@@ -262,7 +268,8 @@ __device__ __forceinline__ int xcd_tile(int w, int T) {
 template <class T, int Mode>
 __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const T* __restrict__ bv,
                                            const T* __restrict__ ein, T* __restrict__ eout, int kz) {
-  __shared__ T row[4][64 + 2 * kHalo];
+  constexpr int kW = 64 + 2 * kHalo;
+  __shared__ T pl[2][8][kW];
   const int n = L.n;
   const int nzb = (n + kz - 1) / kz;
   int blk = L.march == 2 ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -270,7 +277,8 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
   blk /= nzb;
   const int ny = (n + 3) / 4;
   const int l = threadIdx.x, w = threadIdx.y;
-  const int j = (blk % ny) * 4 + w;
+  const int j0 = (blk % ny) * 4;
+  const int j = j0 + w;
   const int i0 = (blk / ny) * 64;
   const int i = i0 + l;
   const bool valid = i < n && j < n;
@@ -281,22 +289,19 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
   const long nn = (long)n * n;
   const int ic = min(i, n - 1), jc = min(j, n - 1);
   const long col = ic + (long)n * jc;
-  long ycol[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int dy = m < 2 ? m - 2 : m - 1;
-    ycol[m] = ic + (long)n * min(max(jc + dy, 0), n - 1);
-  }
+  // LDS rows: 0, 1 hold j0 - 2, j0 - 1; 2 .. 5 the tile; 6, 7 hold j0 + 4, j0 + 5
+  const int trow = 2 + w;
+  const int hrow = w < 2 ? w : w + 4;
+  const long hycol = ic + (long)n * min(max(j0 + hrow - 2, 0), n - 1);
   // lanes 0..2 hold x = i0-3 .. i0-1, lanes 3..5 x = i0+64 .. i0+66, stored at
-  // row index x - i0 + 3
+  // column x - i0 + 3
   const int hl = l < kHalo ? l : l + 64;
   const long hcol = min(max(i0 + hl - kHalo, 0), n - 1) + (long)n * jc;
   const int k0 = zb * kz, k1 = min(k0 + kz, n);
   auto load = [&](int kp) {
     MarchPlane<T> P;
     const long po = kp * nn;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) P.y[m] = ein[ycol[m] + po];
+    P.yh = ein[hycol + po];
     P.type = L.type[col + po];
     if constexpr (Mode != kMarchApply)
       P.b = ld_stream(bv + col + po);
@@ -312,29 +317,29 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
   const T inv = T(L.inv12h2);
   // Planes in chunks of 8 with the steps unrolled: the register queue and the
   // plane buffers then rotate by renaming, not by moves (a move out of a
-  // register whose load is in flight waits for that load).  The chunked form
-  // has a constant inner trip count, which the wavefront barriers require for
-  // unrolling; the guard is uniform over the workgroup.
+  // register whose load is in flight waits for that load), and the LDS buffer
+  // of step u is the constant u & 1.  The guard is uniform over the
+  // workgroup, so every wavefront takes the same barriers.
   for (int kc = k0; kc < k1; kc += 8) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = kc + u;
       if (k < k1) {
+        T(*P)[kW] = pl[u & 1];
         q[2 * kHalo] = ein[col + min(k + kHalo, n - 1) * nn];
         const MarchPlane<T> nxt = load(min(k + 1, k1 - 1));
         const long c = col + k * nn;
-        row[w][kHalo + l] = q[kHalo];
-        if (l < 2 * kHalo) row[w][hl] = cur.h;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        P[trow][kHalo + l] = q[kHalo];
+        if (l < 2 * kHalo) P[trow][hl] = cur.h;
+        P[hrow][kHalo + l] = cur.yh;
+        __syncthreads();
         T v = (Mode == kMarchSmo || Mode == kMarchSmoFar) ? q[kHalo] : T(0);
         if (valid && cur.type == 1) {
           T diag = T(0);
-          T a = axis_op_at<T>([&](int d) { return row[w][kHalo + l + d]; }, i, n, L, 0, diag);
+          T a = axis_op_at<T>([&](int d) { return P[trow][kHalo + l + d]; }, i, n, L, 0, diag);
           a += axis_op_at<T>(
               [&](int d) {
-                return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : cur.y[d < 0 ? d + 2 : d + 1];
+                return d == 0 ? q[kHalo] : (d == -3 || d == 3) ? ein[c + d * (long)n] : P[trow + d][kHalo + l];
               },
               j, n, L, 1, diag);
           a += axis_op_at<T>([&](int d) { return q[kHalo + d]; }, k, n, L, 2, diag);
@@ -346,10 +351,6 @@ __device__ __forceinline__ void march_body(const StencilLevel& L, T omega, const
             v = a * inv;
         }
         if (valid && (Mode != kMarchSmoFar || L.zone[c] == 0)) st_stream(v, eout + c);
-        // every lane's reads of this row precede the next plane's writes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int d = 0; d < 2 * kHalo; ++d) q[d] = q[d + 1];
         cur = nxt;
@@ -1421,7 +1422,7 @@ inline int blocks(long long count, int bs) { return (int)((count + bs - 1) / bs)
 constexpr int kSmoMarchMin = 96;
 inline int smo_march_planes(int n) {
   const long long tiles = (long long)((n + 63) / 64) * ((n + 3) / 4);
-  const long long want = 4096;   // workgroups
+  const long long want = 8192;   // workgroups
   int kz = (int)std::min<long long>(32, std::max<long long>(8, (long long)n * tiles / want));
   return kz;
 }

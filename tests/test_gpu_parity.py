@@ -118,11 +118,11 @@ def test_device_fits_match_host_fits(pair):
 def _default_schedule(n):
     """The grid-size default of the regular-row kernels: one cell per thread
     below 96^3, else the linear-order z-march with the plane count that gives
-    about 4096 workgroups (8 to 32 planes)."""
+    about 8192 workgroups (8 to 32 planes)."""
     if n < 96:
         return 0, None
     tiles = ((n + 63) // 64) * ((n + 3) // 4)
-    return 1, min(32, max(8, n * tiles // 4096))
+    return 1, min(32, max(8, n * tiles // 8192))
 
 
 def test_stencil_autotuner_choice(pair):
