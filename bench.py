@@ -356,7 +356,7 @@ def _learned_leg(P, dom, phi, r_plain, coarse, args, stream):
     log = lambda s_: print(s_, file=sys.stderr, flush=True)
     net, info = learned.fit(n_fine=128, level=1, geometries=args.learned_geometries,
                             rhs_per_geometry=args.learned_rhs, steps=args.learned_steps, base_channels=32, depth=4,
-                            seed=3, log=log)
+                            seed=3, log=log, max_attempts=2 * args.learned_geometries + 4)
     level = next(m for m in range(P.num_levels) if P.n(m) == 64)
     n3 = args.n ** 3
     out = {"train": info, "rhs": "f = sum of 16 seeded Gaussians (seeds 9000 ..), g = 0", "held_out": []}
@@ -429,7 +429,7 @@ def main():
     ap.add_argument("--krylov", type=int, default=20)
     ap.add_argument("--learned-steps", type=int, default=2000)
     ap.add_argument("--learned-geometries", type=int, default=16,
-                    help="128^3 geometries the training pairs come from")
+                    help="128^3 geometries the training pairs come from (drawn until this many converge)")
     ap.add_argument("--learned-rhs", type=int, default=125, help="right-hand sides per training geometry")
     ap.add_argument("--learned-eval", type=int, default=10, help="held-out right-hand sides at the benchmark size")
     ap.add_argument("--no-cpu-baseline", action="store_true")

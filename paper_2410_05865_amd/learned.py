@@ -27,16 +27,22 @@ PHI_SCALE = 100.0
 
 
 def make_pairs(n_fine: int = 128, level: int = 2, geometries: int = 8, rhs_per_geometry: int = 64,
-               seed: int = 0, log=None):
+               seed: int = 0, log=None, max_attempts: int = None):
     """Solver-generated (features, target, mask) at level `level` of n_fine
     problems (geometry seeds 10000 + 100 seed + g, right-hand-side seeds drawn
     from `seed`); returns float32/uint8 CUDA tensors (S, m^3, 2), (S, m^3),
-    (S, m^3) and the number of geometries used."""
+    (S, m^3) and the number of geometries used.  Geometries on which the
+    plain iteration does not converge give no pairs; up to max_attempts
+    geometries (default: `geometries`, at most 100) are drawn to collect
+    `geometries` that do."""
     import torch
     xs, ts, ms = [], [], []
     rng = np.random.default_rng(seed)
     used = 0
-    for g in range(geometries):
+    attempts = min(100, geometries if max_attempts is None else max_attempts)
+    for g in range(attempts):
+        if used == geometries:
+            break
         t0 = time.perf_counter()
         dom = inputs.ellipsoid_domain(n=n_fine, seed=10_000 + seed * 100 + g)
         P = _lib.Problem(dom)
@@ -97,11 +103,14 @@ def relative_error(net, x, t, mask, m: int):
 
 
 def fit(n_fine: int = 128, level: int = 2, geometries: int = 8, rhs_per_geometry: int = 64, steps: int = 2000,
-        batch: int = 8, lr: float = 1e-3, base_channels: int = 16, depth: int = 3, seed: int = 0, log=None):
-    """Generate pairs and train a network (Adam, learning rate lr for half of
-    the steps, lr/3 and lr/10 for a quarter each).  Returns (net, info)."""
+        batch: int = 8, lr: float = 1e-3, base_channels: int = 16, depth: int = 3, seed: int = 0, log=None,
+        max_attempts: int = None):
+    """Generate pairs (make_pairs) and train a network (Adam, learning rate lr
+    for half of the steps, lr/3 and lr/10 for a quarter each).  Returns
+    (net, info)."""
     t0 = time.perf_counter()
-    x, t, mask, used = make_pairs(n_fine, level, geometries, rhs_per_geometry, seed=seed, log=log)
+    x, t, mask, used = make_pairs(n_fine, level, geometries, rhs_per_geometry, seed=seed, log=log,
+                                  max_attempts=max_attempts)
     t_data = time.perf_counter() - t0
     m = round(x.shape[1] ** (1.0 / 3.0))
     net = _lib.Net(base_channels, seed=seed + 1, depth=depth)
