@@ -130,6 +130,8 @@ struct DevLU {
   int height = 0;
   float tune_ms[10] = {};      // build-time trials: ms per solve, [2k + subtree on] for 2^(k+1) entries
   int wcap = 1 << 30;          // single RHS: wavefronts per height launch at most (chosen by timing)
+  LuFlow flow;                 // the one-launch sweeps of a single right-hand side
+  bool flow_on = false;        // single-RHS solves use them (cc_set_lu_schedule)
 };
 
 // One LU solve with a level's factorization: forward then backward sweeps,
@@ -137,6 +139,10 @@ struct DevLU {
 // height above; the backward sweep writes the solution to `out`.
 template <class T, class TO>
 void lu_sweeps(hipStream_t st, const DevLU& L, const LuDev& F, TO* out, long long ostride, int nb) {
+  if (L.flow_on && nb == 1) {
+    launch_lu_flow<T, TO>(F, L.flow, out, st);
+    return;
+  }
   const int h0 = L.sub_on ? L.sub.hcut : 0;
   if (L.sub_on) launch_lu_forward_sub<T>(F, L.sub, nb, st);
   for (int h = h0; h <= L.height; ++h) launch_lu_forward<T>(F, L.tasks[h], nb, st);
@@ -511,6 +517,82 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     T.nBm = (int)bm.size();
     T.ftask_m = B.upload(fm);
     T.btask_m = B.upload(bm);
+  }
+  // the one-launch sweeps: the same single-RHS tasks, every height in ticket
+  // order (forward ascending, backward descending), with the node of each
+  // task, the tasks per node, and the nodes each waits on (forward: children;
+  // backward: the parent)
+  {
+    std::vector<LuTask> ft, bt;
+    std::vector<int> fn, bn, needf(ns, 0), needb(ns, 0);
+    for (int h = 0; h <= F.max_height; ++h)
+      for (int s = 0; s < ns; ++s) {
+        const SnNode& nd = F.nodes[s];
+        if (nd.height != h) continue;
+        const int gf = lanes_for(nd.p), lgf = log2i(gf);
+        for (int r = 0; r < nd.p + nd.q; r += 64 / gf) {
+          ft.push_back(LuTask{nd.offM, nd.offV, nd.offU, nd.base, nd.p, nd.q, r, lgf, 0});
+          fn.push_back(s);
+          ++needf[s];
+        }
+      }
+    for (int h = F.max_height; h >= 0; --h)
+      for (int s = 0; s < ns; ++s) {
+        const SnNode& nd = F.nodes[s];
+        if (nd.height != h) continue;
+        const int gb = lanes_for(0.5 * nd.p + nd.q), lgb = log2i(gb);
+        for (int r = 0; r < nd.p; r += 64 / gb) {
+          bt.push_back(LuTask{nd.offM, nd.offW, nd.offU, nd.base, nd.p, nd.q, r, lgb, 0});
+          bn.push_back(s);
+          ++needb[s];
+        }
+      }
+    std::vector<std::vector<int>> kids(ns);
+    for (int s = 0; s < ns; ++s) {
+      const int par = F.nodes[s].parent;
+      if (par >= 0) {
+        if (F.nodes[par].height <= F.nodes[s].height) fail(CC_EDEVICE, "supernode tree: parent not above child");
+        kids[par].push_back(s);
+      }
+    }
+    std::vector<int> fptr(ns + 1, 0), fw, bptr(ns + 1, 0), bw;
+    for (int s = 0; s < ns; ++s) {
+      fptr[s + 1] = fptr[s] + (int)kids[s].size();
+      for (int c : kids[s]) fw.push_back(c);
+      const int par = F.nodes[s].parent;
+      bptr[s + 1] = bptr[s] + (par >= 0 ? 1 : 0);
+      if (par >= 0) bw.push_back(par);
+    }
+    LuFlow& W = D.flow;
+    W.ncounters = 2 * ns + 2;
+    W.counters = B.alloc<int>((size_t)W.ncounters);
+    W.err = B.alloc<int>(1);
+    HIPCHK(hipMemset(W.err, 0, sizeof(int)));
+    W.ftask = B.upload(ft);
+    W.btask = B.upload(bt);
+    W.fwd.ntask = (int)ft.size();
+    W.fwd.node = B.upload(fn);
+    W.fwd.wait_ptr = B.upload(fptr);
+    W.fwd.wait = fw.empty() ? B.alloc<int>(1) : B.upload(fw);
+    W.fwd.need = B.upload(needf);
+    W.fwd.done = W.counters;
+    W.fwd.ticket = W.counters + 2 * ns;
+    W.fwd.err = W.err;
+    W.bwd.ntask = (int)bt.size();
+    W.bwd.node = B.upload(bn);
+    W.bwd.wait_ptr = B.upload(bptr);
+    W.bwd.wait = bw.empty() ? B.alloc<int>(1) : B.upload(bw);
+    W.bwd.need = B.upload(needb);
+    W.bwd.done = W.counters + ns;
+    W.bwd.ticket = W.counters + 2 * ns + 1;
+    W.bwd.err = W.err;
+    W.kc = kc;
+    // waits give up after 50 ms of the device's wall clock (a sweep takes well
+    // under a millisecond; the bound only ends a launch that cannot progress)
+    int dev = 0, khz = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    W.limit = (long long)std::max(khz, 1) * 50;
   }
 }
 
@@ -1867,6 +1949,21 @@ int cc_smo1(cc_problem* p, int level, const double* s, double* e) {
   });
 }
 
+// A wait of a one-launch LU sweep that gave up (the launch then finished with
+// wrong values) is reported by the next call that checks, and cleared.
+static void flow_check(cc_problem* p) {
+  for (size_t m = 0; m < p->dev.size(); ++m) {
+    const DevLU& L = p->dev[m].lu;
+    if (!L.flow_on || !L.flow.err) continue;
+    int e = 0;
+    HIPCHK(hipMemcpy(&e, L.flow.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) {
+      HIPCHK(hipMemset(L.flow.err, 0, sizeof(int)));
+      fail(CC_EDEVICE, "a wait of the one-launch LU sweep gave up on level " + std::to_string(m));
+    }
+  }
+}
+
 int cc_smo2(cc_problem* p, int level, const double* s, double* e) {
   return guard([&] {
     check_level(p, level);
@@ -1875,6 +1972,7 @@ int cc_smo2(cc_problem* p, int level, const double* s, double* e) {
     if (level == (int)p->lv.size() - 1) fail(CC_EINVAL, "the coarsest level has no LU-correction");
     smo2<double>(p, p->w64, level, s, e, 1);
     HIPSYNC(p->stream);
+    flow_check(p);
   });
 }
 
@@ -1911,6 +2009,7 @@ int cc_fmg(cc_problem* p, const double* r, const double* const* coarse_rhs, doub
     fmg_alloc(p, 1);
     fmg(p, p->w64, r, coarse_rhs, 0, phi, cycles, 1, p->fmg_rhs, p->fmg_x);
     HIPSYNC(p->stream);
+    flow_check(p);
   });
 }
 
@@ -2000,6 +2099,7 @@ int cc_bottom_solve(cc_problem* p, const double* s, double* e) {
     need_device(p);
     bottom<double>(p, p->w64, s, e, 1);
     HIPSYNC(p->stream);
+    flow_check(p);
   });
 }
 
@@ -2010,6 +2110,7 @@ int cc_vcycle(cc_problem* p, int level, const double* s, double* e) {
     if (!s || !e) fail(CC_EINVAL, "null array");
     vcycle<double>(p, p->w64, level, s, e, p->dev[level].et, 1);
     HIPSYNC(p->stream);
+    flow_check(p);
   });
 }
 
@@ -2029,6 +2130,7 @@ int cc_solve(cc_problem* p, const double* r, double* phi, cc_solve_info* info) {
     } else {
       solve_loop<double>(p, p->w64, r, phi, 1, rec);
     }
+    flow_check(p);
     fill_info(rec[0], now_s() - t0, info);
     conv = (rec[0].rel < p->prm.tol) ? 1 : 0;
   });
@@ -2309,7 +2411,7 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     if (entries_per_lane != 2 && entries_per_lane != 4 && entries_per_lane != 8 && entries_per_lane != 16 &&
         entries_per_lane != 32)
       fail(CC_EINVAL, "entries_per_lane must be 2, 4, 8, 16 or 32");
-    if (subtree != 0 && subtree != 1) fail(CC_EINVAL, "subtree must be 0 or 1");
+    if (subtree < 0 || subtree > 2) fail(CC_EINVAL, "subtree must be 0, 1 or 2");
     if (waves_cap != 0 && waves_cap < 4) fail(CC_EINVAL, "waves_cap must be 0 or at least 4");
     HIPCHK(hipSetDevice(p->device));
     HIPSYNC(p->stream);  // no launch in flight reads the old task lists
@@ -2317,11 +2419,12 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     DevBuf nb;
     DevLU L = D.lu;
     make_schedule(p->lu[level], L, (double)entries_per_lane, nb);
-    if (subtree && L.sub.nsub == 0) {
+    if (subtree == 1 && L.sub.nsub == 0) {
       nb.release();
       fail(CC_EINVAL, "this factorization has no subtree launch (cc_level_info.lu_subtrees is 0)");
     }
-    L.sub_on = subtree != 0;
+    L.sub_on = subtree == 1;
+    L.flow_on = subtree == 2;
     L.epl = entries_per_lane;
     L.wcap = waves_cap == 0 ? (1 << 30) : waves_cap;
     for (LuTasks& T : L.tasks) T.wcap = L.wcap;
@@ -2497,6 +2600,7 @@ int cc_time_kernel(cc_problem* p, int which, int reps, double* ms, double* bytes
     HIPCHK(hipEventSynchronize(b));
     float t = 0.f;
     HIPCHK(hipEventElapsedTime(&t, a, b));
+    flow_check(p);
     *ms = t / reps;
     if (bytes) *bytes = by;
     (void)hipEventDestroy(a);

@@ -1035,6 +1035,59 @@ __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __re
   }
 }
 
+// Both sweeps of an LU solve as one launch each (lu_flow.hpp).  The unit of
+// the protocol is a wavefront: lane 0 takes tickets and signals completion,
+// every lane polls the (uniform) counters.  Polls are relaxed agent-scope
+// loads (they read the counter at the coherence point, not a stale L2 line);
+// the acquire fence after the waits and the release fence before the signal
+// order the task's data across the XCDs (fence plus relaxed access is the
+// acquire load / release increment of the host model).
+struct DevSync {
+  static __device__ int next_ticket(int* t) {
+    int v = 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) v = __hip_atomic_fetch_add(t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __shfl(v, 0, kWave);
+  }
+  static __device__ int load_acquire(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ int load_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ void set_err(int* p) {
+    if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ long long now() { return wall_clock64(); }
+  static __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
+  static __device__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+  static __device__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+  static __device__ void signal(int* p) {
+    if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+template <int K, class T>
+__global__ void __launch_bounds__(256) k_lu_forward_flow(LuDev F, const LuTask* __restrict__ tasks, FlowGraph G,
+                                                         long long limit) {
+  const int lane = threadIdx.x & (kWave - 1);
+  flow_run<DevSync>(G, limit, [&](int t) {
+    const LuTask tk = tasks[t];
+    FwdRound<K, T> r;
+    fwd_issue<K, T>(F, tk, lane, r);
+    fwd_finish<K, T>(F, tk, lane, r);
+  });
+}
+template <int K, class T, class TO>
+__global__ void __launch_bounds__(256) k_lu_backward_flow(LuDev F, const LuTask* __restrict__ tasks, FlowGraph G,
+                                                          long long limit, TO* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  flow_run<DevSync>(G, limit, [&](int t) {
+    const LuTask tk = tasks[t];
+    BwdRound<K, T> r;
+    bwd_issue<K, T>(F, tk, lane, r);
+    bwd_finish<K, T, TO>(F, tk, lane, r, out);
+  });
+}
+
 // The lower heights of the tree in one launch: workgroup s takes subtree s
 // through all its heights (levels lptr[s] .. lptr[s+1] of the list, each a
 // range of tasks), its kSubWaves wavefronts sharing each height's tasks, with a
@@ -1591,6 +1644,29 @@ void launch_zero(T* p, long long count, hipStream_t st) {
   int nb = (int)std::min<long long>(blocks(count, 256), 8192);
   hipLaunchKernelGGL(k_zero<T>, dim3(nb), dim3(256), 0, st, p, count);
 }
+// Workgroups of the one-launch sweeps: enough wavefronts to fill the chip
+// (each loops over tickets); at most one per task.
+constexpr int kFlowBlocks = 2048;
+template <class T, class TO>
+void launch_lu_flow(const LuDev& F, const LuFlow& W, TO* out, hipStream_t st) {
+  launch_zero<int>(W.counters, W.ncounters, st);
+  const int gf = std::max(1, std::min(kFlowBlocks, blocks(W.fwd.ntask, 256 / kWave)));
+  const int gb = std::max(1, std::min(kFlowBlocks, blocks(W.bwd.ntask, 256 / kWave)));
+  if (W.fwd.ntask > 0) {
+    if (W.kc <= 4)
+      hipLaunchKernelGGL((k_lu_forward_flow<4, T>), dim3(gf), dim3(256), 0, st, F, W.ftask, W.fwd, W.limit);
+    else
+      hipLaunchKernelGGL((k_lu_forward_flow<8, T>), dim3(gf), dim3(256), 0, st, F, W.ftask, W.fwd, W.limit);
+  }
+  if (W.bwd.ntask > 0) {
+    if (W.kc <= 4)
+      hipLaunchKernelGGL((k_lu_backward_flow<4, T, TO>), dim3(gb), dim3(256), 0, st, F, W.btask, W.bwd, W.limit,
+                         out);
+    else
+      hipLaunchKernelGGL((k_lu_backward_flow<8, T, TO>), dim3(gb), dim3(256), 0, st, F, W.btask, W.bwd, W.limit,
+                         out);
+  }
+}
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(blocks(count, 64)), dim3(64), 0, st, p, count);
 }
@@ -1750,6 +1826,10 @@ CC_INST(float)
 #undef CC_INST
 template void launch_lu_backward<double, double>(const LuDev&, const LuTasks&, double*, long long, int,
                                                  hipStream_t);
+template void launch_zero<int>(int*, long long, hipStream_t);
+template void launch_lu_flow<double, double>(const LuDev&, const LuFlow&, double*, hipStream_t);
+template void launch_lu_flow<double, float>(const LuDev&, const LuFlow&, float*, hipStream_t);
+template void launch_lu_flow<float, float>(const LuDev&, const LuFlow&, float*, hipStream_t);
 template void launch_lu_backward<double, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
 template void launch_lu_backward<float, float>(const LuDev&, const LuTasks&, float*, long long, int, hipStream_t);
 template void launch_lu_backward_sub<double, double>(const LuDev&, const LuSub&, double*, long long, int, hipStream_t);

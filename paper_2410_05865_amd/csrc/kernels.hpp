@@ -9,6 +9,7 @@
 #include <cstdint>
 
 #include "fields.hpp"
+#include "lu_flow.hpp"
 
 namespace cc {
 
@@ -110,6 +111,21 @@ struct LuSub {
   LuSubList single{}, multi{};
 };
 
+// One launch per sweep (single right-hand side; protocol in lu_flow.hpp): the
+// forward tasks of every height in ascending height order, each waiting on its
+// node's children; the backward tasks in descending order, each waiting on its
+// node's parent.
+struct LuFlow {
+  FlowGraph fwd{}, bwd{};
+  const LuTask* ftask = nullptr;  // fwd.ntask tasks in ticket order
+  const LuTask* btask = nullptr;  // bwd.ntask tasks in ticket order
+  int* counters = nullptr;        // fwd.done, bwd.done and the two tickets: zeroed before each solve
+  int ncounters = 0;
+  int* err = nullptr;             // nonzero once a wait gave up (checked and cleared by the host)
+  int kc = 8;                     // entries per lane per load round
+  long long limit = 0;            // wait bound in wall-clock ticks
+};
+
 // ---- stencil work (T = double or float), nb arrays at stride n^3
 template <class T>
 void launch_smo1(const StencilLevel& L, double omega, const T* s, const T* e_in, T* e_out, int nb, hipStream_t st);
@@ -162,6 +178,9 @@ template <class T>
 void launch_lu_forward_sub(const LuDev& F, const LuSub& S, int nb, hipStream_t st);
 template <class T, class TO>
 void launch_lu_backward_sub(const LuDev& F, const LuSub& S, TO* out, long long out_stride, int nb, hipStream_t st);
+// one LU solve as a counter reset and two launches (single right-hand side)
+template <class T, class TO>
+void launch_lu_flow(const LuDev& F, const LuFlow& W, TO* out, hipStream_t st);
 
 // ---- norms, updates, fills (nb arrays; norms are nb u64 bit patterns of
 // non-negative doubles, combined by atomicMax)
