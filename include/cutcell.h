@@ -265,7 +265,8 @@ int cc_set_krylov(cc_problem* p, int krylov);
  * factorization (the LU-correction of Sec. 5.3 on levels m < M, the bottom
  * solve on level M): entries_per_lane in {2, 4, 8, 16, 32} sets the lanes per
  * row of a task, subtree = 1 runs the low heights as one launch of subtrees
- * (only where cc_level_info.lu_subtrees > 0), waves_cap caps the wavefronts of
+ * (only where cc_level_info.lu_subtrees > 0; subtree = 2, one launch per
+ * sweep, is switched off and rejected), waves_cap caps the wavefronts of
  * a height launch (0: no cap; else at least 4).  Waits for the problem's
  * stream, rebuilds the task lists (device allocation) and drops captured
  * iterations.  The solution does not depend on the schedule beyond rounding.
