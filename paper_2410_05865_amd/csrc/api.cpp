@@ -518,10 +518,25 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     T.ftask_m = B.upload(fm);
     T.btask_m = B.upload(bm);
   }
-  // the one-launch sweeps: the same single-RHS tasks, every height in ticket
-  // order (forward ascending, backward descending), with the node of each
-  // task, the tasks per node, and the nodes each waits on (forward: children;
-  // backward: the parent)
+}
+
+// The one-launch sweeps of a factorization (lu_flow.hpp): the same
+// single-RHS tasks as make_schedule's, every height in ticket order (forward
+// ascending, backward descending), with the node of each task, the tasks per
+// node, and the nodes each waits on (forward: children; backward: the parent).
+void make_flow(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
+  const int ns = (int)F.nodes.size();
+  auto lanes_for = [epl](double len) {
+    int g = 1;
+    while (g < 64 && 2.0 * epl * g <= len) g <<= 1;
+    return g;
+  };
+  auto log2i = [](int g) {
+    int l = 0;
+    while ((1 << l) < g) ++l;
+    return l;
+  };
+  const int kc = epl <= 2.0 ? 4 : 8;
   {
     std::vector<LuTask> ft, bt;
     std::vector<int> fn, bn, needf(ns, 0), needb(ns, 0);
@@ -595,6 +610,7 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     W.limit = (long long)std::max(khz, 1) * 50;
   }
 }
+
 
 // Allocate a Work for nb right-hand sides (FP64 outer arrays, level arrays in
 // T, factorization vectors in T on levels m < M and FP64 on the coarsest).
@@ -2429,6 +2445,7 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     }
     L.sub_on = subtree == 1;
     L.flow_on = subtree == 2;
+    if (L.flow_on) make_flow(p->lu[level], L, (double)entries_per_lane, nb);
     L.epl = entries_per_lane;
     L.wcap = waves_cap == 0 ? (1 << 30) : waves_cap;
     for (LuTasks& T : L.tasks) T.wcap = L.wcap;
