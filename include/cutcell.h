@@ -265,9 +265,10 @@ int cc_set_krylov(cc_problem* p, int krylov);
  * factorization (the LU-correction of Sec. 5.3 on levels m < M, the bottom
  * solve on level M): entries_per_lane in {2, 4, 8, 16, 32} sets the lanes per
  * row of a task, subtree = 1 runs the low heights as one launch of subtrees
- * (only where cc_level_info.lu_subtrees > 0; subtree = 2, one launch per
- * sweep, is switched off and rejected), waves_cap caps the wavefronts of
- * a height launch (0: no cap; else at least 4).  Waits for the problem's
+ * (only where cc_level_info.lu_subtrees > 0), subtree = 2 runs each sweep
+ * as one launch (single right-hand side; every wait bounded in time, a wait
+ * that gave up makes the next call fail with CC_EDEVICE), waves_cap caps the
+ * wavefronts of a height launch (0: no cap; else at least 4).  Waits for the problem's
  * stream, rebuilds the task lists (device allocation) and drops captured
  * iterations.  The solution does not depend on the schedule beyond rounding.
  * Errors: CC_EINVAL for a bad level or value. */

@@ -2427,11 +2427,7 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     if (entries_per_lane != 2 && entries_per_lane != 4 && entries_per_lane != 8 && entries_per_lane != 16 &&
         entries_per_lane != 32)
       fail(CC_EINVAL, "entries_per_lane must be 2, 4, 8, 16 or 32");
-    if (subtree < 0 || subtree > 2) fail(CC_EINVAL, "subtree must be 0 or 1");
-    // the one-launch sweeps (subtree = 2) are switched off: their first device
-    // run did not finish (the cause is not known; the protocol passes its host
-    // model under the thread sanitizer)
-    if (subtree == 2) fail(CC_EINVAL, "the one-launch LU sweeps are switched off: a device run did not finish");
+    if (subtree < 0 || subtree > 2) fail(CC_EINVAL, "subtree must be 0, 1 or 2");
     if (waves_cap != 0 && waves_cap < 4) fail(CC_EINVAL, "waves_cap must be 0 or at least 4");
     HIPCHK(hipSetDevice(p->device));
     HIPSYNC(p->stream);  // no launch in flight reads the old task lists

@@ -1036,33 +1036,36 @@ __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __re
 }
 
 // Both sweeps of an LU solve as one launch each (lu_flow.hpp).  The unit of
-// the protocol is a wavefront: lane 0 takes tickets and signals completion,
-// every lane polls the (uniform) counters.  Polls are relaxed agent-scope
-// loads (they read the counter at the coherence point, not a stale L2 line);
-// the acquire fence after the waits and the release fence before the signal
-// order the task's data across the XCDs (fence plus relaxed access is the
-// acquire load / release increment of the host model).
+// the protocol is a wavefront, and the protocol's control flow is uniform over
+// it: every lane takes part in the ticket and completion atomics (lane 0 adds
+// 1, the others 0) and every value that steers the loop (ticket, counts, error
+// word) is read through readfirstlane, so the loop and its waits branch on
+// scalars.  (A lane-0-only ticket and signal let the compiler route lanes
+// 1..63 past the ticket back to the broadcast of lane 0's register while lane
+// 0 was inactive, where they re-ran task 0 for ever.)  Polls are relaxed
+// agent-scope loads (they read the counter at the coherence point, not a stale
+// L2 line); the acquire fence after the waits and the release fence before
+// the signal order the task's data across the XCDs (fence plus relaxed access
+// is the acquire load / release increment of the host model).
 struct DevSync {
+  static __device__ int lane0() { return (threadIdx.x & (kWave - 1)) == 0 ? 1 : 0; }
   static __device__ int next_ticket(int* t) {
-    int v = 0;
-    if ((threadIdx.x & (kWave - 1)) == 0) v = __hip_atomic_fetch_add(t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __shfl(v, 0, kWave);
+    const int v = __hip_atomic_fetch_add(t, lane0(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(v);
   }
   static __device__ int load_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
   static __device__ int load_relaxed(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
-  static __device__ void set_err(int* p) {
-    if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  static __device__ void set_err(int* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
   static __device__ long long now() { return wall_clock64(); }
   static __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
   static __device__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
   static __device__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
   static __device__ void signal(int* p) {
-    if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(p, lane0(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 template <int K, class T>
