@@ -2441,7 +2441,10 @@ int cc_set_lu_schedule(cc_problem* p, int level, int entries_per_lane, int subtr
     }
     L.sub_on = subtree == 1;
     L.flow_on = subtree == 2;
-    if (L.flow_on) make_flow(p->lu[level], L, (double)entries_per_lane, nb);
+    if (L.flow_on) {
+      make_flow(p->lu[level], L, (double)entries_per_lane, nb);
+      L.flow.max_waves = waves_cap;
+    }
     L.epl = entries_per_lane;
     L.wcap = waves_cap == 0 ? (1 << 30) : waves_cap;
     for (LuTasks& T : L.tasks) T.wcap = L.wcap;

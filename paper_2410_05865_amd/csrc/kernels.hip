@@ -655,7 +655,24 @@ struct LuArr<float> {
 // so a row of at most K g entries costs one memory round trip.  Indices past
 // the row are clamped to its last entry (an in-bounds load) and their products
 // dropped.
-template <int K, class T>
+// Loads and stores of the work vectors that other tasks of the same launch
+// write (C: the one-launch sweeps): relaxed agent-scope atomics, coherent
+// across the XCDs without cache maintenance; plain accesses otherwise.
+template <bool C, class T>
+__device__ __forceinline__ T ld_c(const T* p) {
+  if constexpr (C)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool C, class T>
+__device__ __forceinline__ void st_c(T* p, T v) {
+  if constexpr (C)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+template <int K, class T, bool C = false>
 __device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restrict__ b, int j0, int j1, int gl,
                                       int g) {
   T s0 = T(0), s1 = T(0);
@@ -665,7 +682,7 @@ __device__ __forceinline__ T lane_dot(const T* __restrict__ a, const T* __restri
     for (int u = 0; u < K; ++u) {
       const int j = min(jb + u * g, j1 - 1);
       va[u] = a[j];
-      vb[u] = b[j];
+      vb[u] = ld_c<C>(b + j);
     }
 #pragma unroll
     for (int u = 0; u < K; u += 2) {
@@ -703,13 +720,13 @@ template <class T>
 __device__ __forceinline__ const T* fwd_row(const LuDev& F, const LuTask& t, int ii) {
   return ii < t.p ? LuArr<T>::M(F) + t.offM + (long)ii * t.p : LuArr<T>::V(F) + t.offVW + (long)(ii - t.p) * t.p;
 }
-template <int K, class T>
+template <int K, class T, bool C = false>
 __device__ __forceinline__ void fwd_issue(const LuDev& F, const LuTask& t, int lane, FwdRound<K, T>& r) {
   const TaskLanes L(t, lane);
   const int p = t.p, q = t.q;
   const int ii = min(L.i, p + q - 1);
   const T* yF = LuArr<T>::y(F) + t.base;
-  r.yi = yF[min(ii, p - 1)];
+  r.yi = ld_c<C>(yF + min(ii, p - 1));
   r.dst = F.Uf[t.offU + max(ii - p, 0)];
   const T* row = fwd_row<T>(F, t, ii);
   const int jend = L.i < p + q ? (ii < p ? ii : p) : 0;
@@ -718,10 +735,10 @@ __device__ __forceinline__ void fwd_issue(const LuDev& F, const LuTask& t, int l
   for (int u = 0; u < K; ++u) {
     const int j = min(L.gl + u * L.g, jmax);
     r.va[u] = row[j];
-    r.vb[u] = yF[j];
+    r.vb[u] = ld_c<C>(yF + j);
   }
 }
-template <int K, class T>
+template <int K, class T, bool C = false>
 __device__ __forceinline__ void fwd_finish(const LuDev& F, const LuTask& t, int lane, const FwdRound<K, T>& r) {
   const TaskLanes L(t, lane);
   const int p = t.p, q = t.q;
@@ -736,7 +753,7 @@ __device__ __forceinline__ void fwd_finish(const LuDev& F, const LuTask& t, int 
   }
   T acc = s0 + s1;
   if (L.gl + K * L.g < jend)
-    acc += lane_dot<K, T>(fwd_row<T>(F, t, ii), LuArr<T>::y(F) + t.base, K * L.g, jend, L.gl, L.g);
+    acc += lane_dot<K, T, C>(fwd_row<T>(F, t, ii), LuArr<T>::y(F) + t.base, K * L.g, jend, L.gl, L.g);
   for (int o = L.g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (valid && L.gl == 0) {
     if (L.i < p)
@@ -794,7 +811,7 @@ __device__ __forceinline__ void bwd_issue(const LuDev& F, const LuTask& t, int l
     r.vb[u] = z[j];
   }
 }
-template <int K, class T, class TO>
+template <int K, class T, class TO, bool C = false>
 __device__ __forceinline__ void bwd_finish(const LuDev& F, const LuTask& t, int lane, const BwdRound<K, T>& r,
                                            TO* __restrict__ out) {
   const TaskLanes L(t, lane);
@@ -811,7 +828,7 @@ __device__ __forceinline__ void bwd_finish(const LuDev& F, const LuTask& t, int 
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     w[u] = Wr[min(L.gl + u * L.g, qmax)];
-    vx[u] = x[r.uu[u]];
+    vx[u] = ld_c<C>(x + r.uu[u]);
   }
   T s0 = T(0), s1 = T(0);
 #pragma unroll
@@ -838,7 +855,7 @@ __device__ __forceinline__ void bwd_finish(const LuDev& F, const LuTask& t, int 
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       w[u] = Wr[min(jb + u * L.g, q - 1)];
-      vx[u] = x[uu[u]];
+      vx[u] = ld_c<C>(x + uu[u]);
     }
 #pragma unroll
     for (int u = 0; u < K; u += 2) {
@@ -849,7 +866,7 @@ __device__ __forceinline__ void bwd_finish(const LuDev& F, const LuTask& t, int 
   acc -= s0 + s1;
   for (int o = L.g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (valid && L.gl == 0) {
-    x[t.base + L.i] = acc;
+    st_c<C>(x + t.base + L.i, acc);
     out[r.cell] = TO(acc);
   }
 }
@@ -1061,9 +1078,15 @@ struct DevSync {
   }
   static __device__ void set_err(int* p) { __hip_atomic_store(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
   static __device__ long long now() { return wall_clock64(); }
-  static __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
-  static __device__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-  static __device__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+  // about 0.2 us between polls: waiting wavefronts leave the memory system
+  // to the working ones
+  static __device__ void pause() { __builtin_amdgcn_s_sleep(8); }
+  // every access to data another task of the launch writes is a coherent
+  // agent-scope atomic (ld_c / st_c, atomicAdd), so no cache maintenance is
+  // needed: the reader issues those loads only after its poll saw the count,
+  // and the writer's accesses have completed before its count is raised
+  static __device__ void acquire_fence() {}
+  static __device__ void release_fence() { __builtin_amdgcn_s_waitcnt(0); }
   static __device__ void signal(int* p) {
     __hip_atomic_fetch_add(p, lane0(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -1075,8 +1098,8 @@ __global__ void __launch_bounds__(256) k_lu_forward_flow(LuDev F, const LuTask* 
   flow_run<DevSync>(G, limit, [&](int t) {
     const LuTask tk = tasks[t];
     FwdRound<K, T> r;
-    fwd_issue<K, T>(F, tk, lane, r);
-    fwd_finish<K, T>(F, tk, lane, r);
+    fwd_issue<K, T, true>(F, tk, lane, r);
+    fwd_finish<K, T, true>(F, tk, lane, r);
   });
 }
 template <int K, class T, class TO>
@@ -1087,7 +1110,7 @@ __global__ void __launch_bounds__(256) k_lu_backward_flow(LuDev F, const LuTask*
     const LuTask tk = tasks[t];
     BwdRound<K, T> r;
     bwd_issue<K, T>(F, tk, lane, r);
-    bwd_finish<K, T, TO>(F, tk, lane, r, out);
+    bwd_finish<K, T, TO, true>(F, tk, lane, r, out);
   });
 }
 
@@ -1653,8 +1676,9 @@ constexpr int kFlowBlocks = 2048;
 template <class T, class TO>
 void launch_lu_flow(const LuDev& F, const LuFlow& W, TO* out, hipStream_t st) {
   launch_zero<int>(W.counters, W.ncounters, st);
-  const int gf = std::max(1, std::min(kFlowBlocks, blocks(W.fwd.ntask, 256 / kWave)));
-  const int gb = std::max(1, std::min(kFlowBlocks, blocks(W.bwd.ntask, 256 / kWave)));
+  const int cap = W.max_waves > 0 ? std::max(1, W.max_waves / (256 / kWave)) : kFlowBlocks;
+  const int gf = std::max(1, std::min(cap, blocks(W.fwd.ntask, 256 / kWave)));
+  const int gb = std::max(1, std::min(cap, blocks(W.bwd.ntask, 256 / kWave)));
   if (W.fwd.ntask > 0) {
     if (W.kc <= 4)
       hipLaunchKernelGGL((k_lu_forward_flow<4, T>), dim3(gf), dim3(256), 0, st, F, W.ftask, W.fwd, W.limit);

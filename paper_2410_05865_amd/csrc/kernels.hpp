@@ -124,6 +124,7 @@ struct LuFlow {
   int* err = nullptr;             // nonzero once a wait gave up (checked and cleared by the host)
   int kc = 8;                     // entries per lane per load round
   long long limit = 0;            // wait bound in wall-clock ticks
+  int max_waves = 0;              // wavefronts of a sweep launch at most (0: enough to fill the chip)
 };
 
 // ---- stencil work (T = double or float), nb arrays at stride n^3
