@@ -520,6 +520,10 @@ void make_schedule(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
   }
 }
 
+// Tickets a wavefront of the one-launch sweeps takes at a time (one atomic on
+// the shared ticket counter per batch).
+constexpr int kFlowBatch = 4;
+
 // The one-launch sweeps of a factorization (lu_flow.hpp): the same
 // single-RHS tasks as make_schedule's, every height in ticket order (forward
 // ascending, backward descending), with the node of each task, the tasks per
@@ -601,6 +605,7 @@ void make_flow(const SupernodalLU& F, DevLU& D, double epl, DevBuf& B) {
     W.bwd.done = W.counters + ns;
     W.bwd.ticket = W.counters + 2 * ns + 1;
     W.bwd.err = W.err;
+    W.fwd.batch = W.bwd.batch = kFlowBatch;
     W.kc = kc;
     // waits give up after 50 ms of the device's wall clock (a sweep takes well
     // under a millisecond; the bound only ends a launch that cannot progress)

@@ -1066,8 +1066,8 @@ __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __re
 // is the acquire load / release increment of the host model).
 struct DevSync {
   static __device__ int lane0() { return (threadIdx.x & (kWave - 1)) == 0 ? 1 : 0; }
-  static __device__ int next_ticket(int* t) {
-    const int v = __hip_atomic_fetch_add(t, lane0(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  static __device__ int next_ticket(int* t, int n) {
+    const int v = __hip_atomic_fetch_add(t, lane0() * n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_amdgcn_readfirstlane(v);
   }
   static __device__ int load_acquire(const int* p) {

@@ -7,11 +7,13 @@
 // Tickets follow the tree order of the sweep (forward: heights ascending,
 // backward: descending), and a task depends only on nodes whose tasks all come
 // earlier in that order (forward: the node's children; backward: its parent).
+// A unit takes `batch` consecutive tickets at a time and runs them in order.
 // A unit holding ticket t therefore waits only on tickets below t, which units
-// already running hold, and those never wait on a ticket above their own: the
-// smallest unfinished ticket always makes progress, so the sweep cannot
-// deadlock as long as a unit that took a ticket keeps running (nothing
-// preempts a running wavefront), however many units the grid has.
+// already running hold, and those never wait on a ticket above their own (a
+// unit's own earlier tickets are smaller): the smallest unfinished ticket
+// always makes progress, so the sweep cannot deadlock as long as a unit that
+// took a ticket keeps running (nothing preempts a running wavefront), however
+// many units the grid has.
 //
 // Memory ordering: a task's writes (plain stores and atomic additions into
 // later equations) are made visible by a release fence before its node's
@@ -44,10 +46,11 @@ struct FlowGraph {
   int* done;              // per node: tasks completed (zero before the sweep)
   int* ticket;            // next ticket (zero before the sweep)
   int* err;               // nonzero once a wait gave up
+  int batch;              // tickets taken at a time (at least 1)
 };
 
 // Runs tasks until the tickets are exhausted; work(t) runs task t.
-// S::next_ticket(int*)        relaxed fetch-add, the value uniform over the unit
+// S::next_ticket(int*, int n) relaxed fetch-add of n, the value uniform over the unit
 // S::load_acquire(const int*) acquire load of a counter
 // S::load_relaxed(const int*) relaxed load of the error word
 // S::set_err(int*)            relaxed store of 1
@@ -58,26 +61,29 @@ struct FlowGraph {
 template <class S, class Work>
 CC_FLOW_HD inline void flow_run(const FlowGraph& G, long long limit, Work&& work) {
   for (;;) {
-    const int t = S::next_ticket(G.ticket);
-    if (t >= G.ntask) return;
-    const int v = G.node[t];
-    for (int k = G.wait_ptr[v]; k < G.wait_ptr[v + 1]; ++k) {
-      const int u = G.wait[k];
-      const int need = G.need[u];
-      const long long t0 = S::now();
-      while (S::load_acquire(G.done + u) < need) {
-        if (S::load_relaxed(G.err) != 0) break;
-        if (S::now() - t0 > limit) {
-          S::set_err(G.err);
-          break;
+    const int tb = S::next_ticket(G.ticket, G.batch);
+    if (tb >= G.ntask) return;
+    const int te = tb + G.batch < G.ntask ? tb + G.batch : G.ntask;
+    for (int t = tb; t < te; ++t) {
+      const int v = G.node[t];
+      for (int k = G.wait_ptr[v]; k < G.wait_ptr[v + 1]; ++k) {
+        const int u = G.wait[k];
+        const int need = G.need[u];
+        const long long t0 = S::now();
+        while (S::load_acquire(G.done + u) < need) {
+          if (S::load_relaxed(G.err) != 0) break;
+          if (S::now() - t0 > limit) {
+            S::set_err(G.err);
+            break;
+          }
+          S::pause();
         }
-        S::pause();
       }
+      S::acquire_fence();
+      work(t);
+      S::release_fence();
+      S::signal(G.done + v);
     }
-    S::acquire_fence();
-    work(t);
-    S::release_fence();
-    S::signal(G.done + v);
   }
 }
 

@@ -9,8 +9,9 @@
 //     sweeps (a task waits on its node's parent and reads the plain outputs of
 //     the parent's and grandparent's tasks) give the sequential results;
 //   * trees: random forests, a chain, a star, one node; 1, 2, 7 and 33 threads,
-//     threads starting late; repeated sweeps with the counters reset between
-//     them (the replays of a captured graph);
+//     threads starting late; 1, 2, 4 or 5 tickets taken at a time; repeated
+//     sweeps with the counters reset between them (the replays of a captured
+//     graph);
 //   * a node that never completes (its count one short): every wait on it
 //     gives up within the bound, the error word is set and the run ends.
 // Exit status 0 and a line "all ok" on success.  Built with PLANT_RELAXED_SIGNAL
@@ -33,7 +34,7 @@ namespace {
 // the sanitizer does not model standalone fences, so the host states the
 // equivalent release RMW and acquire load directly.
 struct HostSync {
-  static int next_ticket(int* t) { return __atomic_fetch_add(t, 1, __ATOMIC_RELAXED); }
+  static int next_ticket(int* t, int n) { return __atomic_fetch_add(t, n, __ATOMIC_RELAXED); }
   static int load_acquire(const int* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
   static int load_relaxed(const int* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
   static void set_err(int* p) { __atomic_store_n(p, 1, __ATOMIC_RELAXED); }
@@ -91,7 +92,7 @@ Tree star(int n, std::mt19937& rng) {
 
 struct Sweep {
   std::vector<int> node, wait_ptr, wait, need, done, first;  // first: first ticket of each node
-  int ticket = 0, err = 0;
+  int ticket = 0, err = 0, batch = 1;
   cc::FlowGraph graph() {
     cc::FlowGraph G;
     G.ntask = (int)node.size();
@@ -102,6 +103,7 @@ struct Sweep {
     G.done = done.data();
     G.ticket = &ticket;
     G.err = &err;
+    G.batch = batch;
     return G;
   }
 };
@@ -148,10 +150,12 @@ void check(bool ok, const char* what, int a, int b) {
   }
 }
 
-// one forward and one backward sweep with `threads` threads; `replays` times
-void run_case(const char* name, const Tree& T, int threads, int replays, std::mt19937& rng) {
+// one forward and one backward sweep with `threads` threads, `batch` tickets
+// taken at a time; `replays` times
+void run_case(const char* name, const Tree& T, int threads, int replays, std::mt19937& rng, int batch = 1) {
   const int n = (int)T.parent.size();
   Sweep F = make_sweep(T, true), B = make_sweep(T, false);
+  F.batch = B.batch = batch;
   const int nt = (int)F.node.size();
   std::vector<long long> acc(n), fout(nt), bout(nt);
   std::vector<long long> acc_ref(n, 0), fout_ref(nt), bout_ref(nt);
@@ -220,13 +224,15 @@ void run_case(const char* name, const Tree& T, int threads, int replays, std::mt
       check(bout[t] == bout_ref[t], "backward result", t, rep);
     }
   }
-  std::printf("ok %s: %d nodes, %d tasks, %d threads, %d replays\n", name, n, nt, threads, replays);
+  std::printf("ok %s: %d nodes, %d tasks, %d threads, %d tickets at a time, %d replays\n", name, n, nt, threads,
+              batch, replays);
 }
 
 // a node one task short of its count: every wait on it must give up
 void run_give_up(std::mt19937& rng) {
   Tree T = chain(6, rng);
   Sweep F = make_sweep(T, true);
+  F.batch = 2;
   F.need[2] += 1;  // node 2 never completes
   cc::FlowGraph G = F.graph();
   const long long t0 = HostSync::now();
@@ -251,8 +257,13 @@ int main() {
     Tree f = random_forest(300, rng);
     run_case("random forest", f, threads, 3, rng);
   }
+  for (int batch : {2, 5}) {
+    Tree f = random_forest(300, rng);
+    run_case("random forest", f, 7, 3, rng, batch);
+  }
   Tree c = chain(120, rng);
   run_case("chain", c, 7, 3, rng);
+  run_case("chain", c, 7, 3, rng, 4);
   Tree s = star(400, rng);
   run_case("star", s, 7, 3, rng);
   run_give_up(rng);
