@@ -452,7 +452,7 @@ def main():
             print(profiling.kernel_stats_summary(args.summarize_trace, n=args.n))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
 
     import torch

@@ -428,7 +428,7 @@ const char* cc_last_error(void);
 
 /* ---------------------------------------------------------------------------
  * Learned initial guess (an addition on top of the paper's method: the
- * multigrid solve stays the judge, the network only supplies phi_0).
+ * multigrid solve still decides the result, the network only supplies phi_0).
  *
  * A 3D U-Net of `depth` levels (3 or 4) with base width C (16 or 32; encoder
  * channels C on the upper levels, 2C on the two coarsest): two input channels

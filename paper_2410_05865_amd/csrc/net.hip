@@ -1,7 +1,7 @@
 // Learned initial guess: a small 3D U-Net (BF16 activations and weights, FP32
 // accumulation on MFMA) that maps (scaled right-hand side, geometry) on a grid
-// to a scaled solution.  The multigrid solve stays the judge: the network only
-// supplies phi_0.  Not part of the paper's method; an addition on top of it.
+// to a scaled solution.  The multigrid solve still decides the result: the
+// network only supplies phi_0.  Not part of the paper's method; an addition on top of it.
 //
 // Architecture (C = base channels, D = 3 or 4 levels, grid n divisible by
 // 2^(D+1)); encoder channels w_l = C on the upper levels, 2C on the two coarsest:
