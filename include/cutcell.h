@@ -266,9 +266,12 @@ int cc_set_krylov(cc_problem* p, int krylov);
  * solve on level M): entries_per_lane in {2, 4, 8, 16, 32} sets the lanes per
  * row of a task, subtree = 1 runs the low heights as one launch of subtrees
  * (only where cc_level_info.lu_subtrees > 0), subtree = 2 runs each sweep
- * as one launch (single right-hand side; every wait bounded in time, a wait
- * that gave up makes the next call fail with CC_EDEVICE), waves_cap caps the
- * wavefronts of a height launch (0: no cap; else at least 4).  Waits for the problem's
+ * of a single right-hand side as one launch (opt-in; slower than the
+ * per-height launches on MI355X; every wait bounded in time, and a wait that
+ * gave up makes the next cc_solve, cc_vcycle, cc_fmg, cc_smo2,
+ * cc_bottom_solve or cc_time_kernel fail with CC_EDEVICE), waves_cap caps the
+ * wavefronts of a height launch, or of the one launch (0: no cap; else at
+ * least 4).  Waits for the problem's
  * stream, rebuilds the task lists (device allocation) and drops captured
  * iterations.  The solution does not depend on the schedule beyond rounding.
  * Errors: CC_EINVAL for a bad level or value. */
