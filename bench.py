@@ -20,6 +20,7 @@ bounded sample (`cpu_baseline`).
     python bench.py --summarize-pmc FETCH_DB WRITE_DB   # traffic table from rocprofv3 --pmc output
     python bench.py --summarize-trace TRACE_DB          # kernel table from rocprofv3 --kernel-trace output
     python bench.py --summarize-counters PMC_DB         # per-kernel counter averages from rocprofv3 --pmc output
+    python bench.py --summarize-lu FETCH_DB WRITE_DB TRACE_DB   # per-launch bytes and time of the LU-correction
 """
 from __future__ import annotations
 
@@ -439,7 +440,13 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DB")
     ap.add_argument("--summarize-counters", metavar="PMC_DB")
+    ap.add_argument("--summarize-lu", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "TRACE_DB"),
+                    help="per-launch bytes and durations of the level-0 LU-correction of the timing hook")
     args = ap.parse_args()
+    if args.summarize_lu:
+        from paper_2410_05865_amd import profiling
+        print(profiling.lu_launch_summary(*args.summarize_lu, n=args.n))
+        return
     if args.summarize_counters:
         from paper_2410_05865_amd import profiling
         print(profiling.counters_summary(args.summarize_counters))

@@ -145,6 +145,71 @@ def kernel_stats_summary(db: str, n: int, top: int = 14) -> str:
     return "\n".join(out)
 
 
+def _lu_corrections(names):
+    """(indices, launches per correction, corrections) of the trailing run of
+    consecutive k_lu_* entries of `names` (dispatch order), which holds whole
+    corrections of the same launch pattern (the timing hook's)."""
+    lu = [i for i, k in enumerate(names) if k.startswith("k_lu_")]
+    if not lu:
+        return [], 0, 0
+    tail = [lu[-1]]
+    while tail[-1] - 1 >= 0 and names[tail[-1] - 1].startswith("k_lu_"):
+        tail.append(tail[-1] - 1)
+    tail = tail[::-1]
+    seq = [names[i] for i in tail]
+    per = next((q for q in range(2, len(seq) // 2 + 1)
+                if len(seq) % q == 0 and seq == seq[:q] * (len(seq) // q)), len(seq))
+    return tail, per, len(seq) // per
+
+
+def lu_launch_summary(fetch_db: str, write_db: str, trace_db: str, n: int) -> str:
+    """Per launch of the level-0 LU-correction of the timing hook (forward
+    heights up, then backward heights down): mean duration from a
+    --kernel-trace database and mean HBM bytes from the FETCH_SIZE and
+    WRITE_SIZE databases of the same command, calibrated by the copy kernel
+    (the first correction, which warms up, left out of the means)."""
+    n3 = n ** 3
+    fe = _load(fetch_db, "FETCH_SIZE")
+    wr = _load(write_db, "WRITE_SIZE")
+
+    def hook_mean(rows, key):
+        seq = [(k, grid, v) for _, k, grid, v in rows]
+        run = _last_run(seq, key)
+        if not run:
+            raise ValueError(f"no dispatch of {key}")
+        return float(np.mean([seq[i][2] for i in run]))
+
+    f_fac = 8.0 * n3 / (hook_mean(fe, "k_copy") * 1024.0)
+    w_fac = 8.0 * n3 / (hook_mean(wr, "k_copy") * 1024.0)
+
+    def per_launch(names, vals):
+        idx, per, reps = _lu_corrections(names)
+        if not idx:
+            raise ValueError("no LU-correction dispatches")
+        a = np.array([vals[i] for i in idx]).reshape(reps, per)
+        return (a[1:].mean(axis=0) if reps > 1 else a[0]), [names[i] for i in idx[:per]], reps
+
+    fb, kn, reps = per_launch([k for _, k, _, _ in fe], [v * 1024.0 * f_fac for *_, v in fe])
+    wb, _, _ = per_launch([k for _, k, _, _ in wr], [v * 1024.0 * w_fac for *_, v in wr])
+    con = sqlite3.connect(trace_db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    tn, td = [], []
+    for name, st, en in rows:
+        m = re.search(r"(k_\w+)(<[^(]*>)?\(", name)
+        tn.append((m.group(1) + (m.group(2) or "")) if m else name.split("(")[0][:40])
+        td.append((en - st) / 1000.0)
+    dur, tkn, treps = per_launch(tn, td)
+    if len(dur) != len(fb) or tkn != kn:
+        raise ValueError("the trace and the counter runs hold different LU-correction launches")
+    by = fb + wb
+    out = [f"| launch | kernel | us | MB | GB/s |", "|---|---|---|---|---|"]
+    for i, k in enumerate(kn):
+        out.append(f"| {i} | {k} | {dur[i]:.1f} | {by[i] / 1e6:.1f} | {by[i] / (dur[i] * 1e-6) / 1e9:.0f} |")
+    out.append(f"| all | {len(kn)} launches ({reps} corrections in the counter runs, {treps} in the trace) | "
+               f"{dur.sum():.1f} | {by.sum() / 1e6:.1f} | {by.sum() / (dur.sum() * 1e-6) / 1e9:.0f} |")
+    return "\n".join(out)
+
+
 def counters_summary(db: str, kernels=(SMO_KERNEL, "k_copy")) -> str:
     """Per-dispatch averages of every counter of a rocprofv3 --pmc database for
     the named kernels (the timing hook's launches: the last run of

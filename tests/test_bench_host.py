@@ -123,3 +123,40 @@ def test_counter_summary_averages_the_timing_hooks_launches(tmp_path):
     text = profiling.counters_summary(str(tmp_path / "c.db"))
     assert "k_smo1_z<double> (grid 1000 work-items, 2 dispatches): TA_BUSY_avr 15" in text
     assert "k_copy (grid 500 work-items, 1 dispatches): TA_BUSY_avr 5" in text
+
+
+def test_lu_launch_summary_joins_bytes_and_durations(tmp_path):
+    """Per launch of the timing hook's LU-correction: calibrated bytes from the
+    counter runs and durations from the trace, the first correction left out."""
+    n = 64
+    n3 = n ** 3
+    true_kib = 8.0 * n3 / 1024.0
+    LB = "void cc::(anonymous namespace)::k_lu_backward<8, double, double>(cc::LuDev, cc::LuTasks)"
+    # a trial launch, the copy kernel, then 3 corrections of (forward, forward, backward, backward)
+    pat = [LU, LU, LB, LB]
+    fe = [(1, LU, 100, "FETCH_SIZE", 50.0), (2, COPY, n3 // 4, "FETCH_SIZE", true_kib / 2)]
+    wr = [(1, LU, 100, "WRITE_SIZE", 50.0), (2, COPY, n3 // 4, "WRITE_SIZE", true_kib)]
+    did = 3
+    for rep in range(3):
+        for j, k in enumerate(pat):
+            fe.append((did, k, 100, "FETCH_SIZE", 1000.0 * (j + 1) * (3 if rep == 0 else 1)))
+            wr.append((did, k, 100, "WRITE_SIZE", 100.0))
+            did += 1
+    _counter_db(tmp_path / "f.db", fe)
+    _counter_db(tmp_path / "w.db", wr)
+    con = sqlite3.connect(tmp_path / "t.db")
+    con.execute("create table kernels (name text, start int, end int, grid_x int, grid_y int, grid_z int)")
+    rows, t = [], 0
+    for rep in range(3):
+        for j, k in enumerate(pat):
+            d = (10_000 if j < 2 else 20_000) * (5 if rep == 0 else 1)
+            rows.append((k, t, t + d, 64, 1, 1))
+            t += d + 1000
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    text = profiling.lu_launch_summary(str(tmp_path / "f.db"), str(tmp_path / "w.db"), str(tmp_path / "t.db"), n)
+    # launch 0: fetch 1000 KiB x 2 + write 100 KiB = 2100 KiB = 2.15 MB in 10 us
+    assert "| 0 | k_lu_forward<8, double> | 10.0 | 2.2 | 215 |" in text
+    assert "| 3 | k_lu_backward<8, double, double> | 20.0 | 8.3 | 415 |" in text
+    assert "| all | 4 launches (3 corrections in the counter runs, 3 in the trace) | 60.0 |" in text
