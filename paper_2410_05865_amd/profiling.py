@@ -200,7 +200,8 @@ def lu_launch_summary(fetch_db: str, write_db: str, trace_db: str, n: int) -> st
         td.append((en - st) / 1000.0)
     dur, tkn, treps = per_launch(tn, td)
     if len(dur) != len(fb) or tkn != kn:
-        raise ValueError("the trace and the counter runs hold different LU-correction launches")
+        raise ValueError(f"the trace and the counter runs hold different LU-correction launches: "
+                         f"{len(tkn)} ({tkn[:3]} ...) against {len(kn)} ({kn[:3]} ...)")
     by = fb + wb
     out = [f"| launch | kernel | us | MB | GB/s |", "|---|---|---|---|---|"]
     for i, k in enumerate(kn):
