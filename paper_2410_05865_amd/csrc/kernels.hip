@@ -1055,15 +1055,18 @@ __global__ void __launch_bounds__(256) k_lu_backward(LuDev F, const LuTask* __re
 // Both sweeps of an LU solve as one launch each (lu_flow.hpp).  The unit of
 // the protocol is a wavefront, and the protocol's control flow is uniform over
 // it: every lane takes part in the ticket and completion atomics (lane 0 adds
-// 1, the others 0) and every value that steers the loop (ticket, counts, error
-// word) is read through readfirstlane, so the loop and its waits branch on
-// scalars.  (A lane-0-only ticket and signal let the compiler route lanes
-// 1..63 past the ticket back to the broadcast of lane 0's register while lane
-// 0 was inactive, where they re-ran task 0 for ever.)  Polls are relaxed
-// agent-scope loads (they read the counter at the coherence point, not a stale
-// L2 line); the acquire fence after the waits and the release fence before
-// the signal order the task's data across the XCDs (fence plus relaxed access
-// is the acquire load / release increment of the host model).
+// the batch or 1, the others 0) and every value that steers the loop (ticket,
+// counts, error word) is read through readfirstlane, so the loop and its
+// waits branch on scalars.  (A lane-0-only ticket and signal let the compiler
+// route lanes 1..63 past the ticket back to the broadcast of lane 0's register
+// while lane 0 was inactive, where they re-ran task 0 for ever.)  Polls are
+// relaxed agent-scope loads, which read the counter at the coherence point.
+// The data the tasks of one launch pass to each other are accessed only by
+// coherent agent-scope atomics (ld_c, st_c, atomicAdd), so the fences need no
+// cache maintenance: the writer waits for its own accesses before it raises
+// its count, and the reader issues its loads after its poll saw the count
+// (the host model states the same order as a release increment and an
+// acquire load).
 struct DevSync {
   static __device__ int lane0() { return (threadIdx.x & (kWave - 1)) == 0 ? 1 : 0; }
   static __device__ int next_ticket(int* t, int n) {
@@ -1081,10 +1084,6 @@ struct DevSync {
   // about 0.2 us between polls: waiting wavefronts leave the memory system
   // to the working ones
   static __device__ void pause() { __builtin_amdgcn_s_sleep(8); }
-  // every access to data another task of the launch writes is a coherent
-  // agent-scope atomic (ld_c / st_c, atomicAdd), so no cache maintenance is
-  // needed: the reader issues those loads only after its poll saw the count,
-  // and the writer's accesses have completed before its count is raised
   static __device__ void acquire_fence() {}
   static __device__ void release_fence() { __builtin_amdgcn_s_waitcnt(0); }
   static __device__ void signal(int* p) {
